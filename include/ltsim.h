@@ -1,0 +1,197 @@
+/*
+ * ltsim.h -- C ABI of the MI355X (gfx950) pixelated-LArTPC charge-simulation library (libltsim.so).
+ *
+ * The calls follow the statement of the problem in arXiv 2212.09807: a table of energy-deposit segments
+ * S_i = (r_s, r_e, E), r 4-dimensional (x, y, z, t) (Sec. 2), together with detector and response parameters
+ * (Sec. 3.1 recombination, Sec. 3.2 drift, Sec. 3.3.1 pixel field-response table, Sec. 3.4 front end), goes
+ * in; per-pixel induced currents (Sec. 3.3.2, eq. (current), summed over segments as in Sec. 3.4) and the
+ * digitised ADC counts with their timestamps per pixel (Sec. 3.4, last paragraph) come out.
+ *
+ * Conventions
+ *   - Units: cm, microseconds, MeV, electrons, kV/cm.  The anode plane is z = z_anode; charge drifts along -z.
+ *   - Pixel ids are tile-local: id = iy * n_x + ix, pixel (ix, iy) covering [x0 + ix*pitch, x0 + (ix+1)*pitch)
+ *     x [y0 + iy*pitch, ...).  Tick n covers [t_begin + n*tick, t_begin + (n+1)*tick).
+ *   - Currents are electrons per tick, FP32.  Charge reports are FP64.
+ *   - All pointers inside lts_segments / lts_outputs are DEVICE pointers (HIP global memory on the
+ *     context's device) unless a field says otherwise.  The caller owns them; the library never frees them.
+ *   - Stream arguments are hipStream_t values passed as void* (NULL = the null stream).  Entry points that
+ *     take a stream enqueue their work on it and return; results are valid after the stream is synchronised.
+ *     lts_simulate / lts_simulate_batch additionally synchronise that stream once (after sizing) to size
+ *     scratch and check output capacities, so a capacity error is returned synchronously.
+ *   - No call throws across the ABI.  Every call returns an lts_status; on failure lts_last_error() gives a
+ *     message.  A failed device call makes the context's status sticky (LTS_ERR_DEVICE).
+ *   - A context is not thread-safe: serialise calls on one context.  The server API is thread-safe.
+ */
+#ifndef LTSIM_H
+#define LTSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lts_status {
+    LTS_OK = 0,
+    LTS_ERR_INVALID_ARG = 1,   /* bad parameter, table shape, NaN/Inf, zero-length segment without dE/dx ... */
+    LTS_ERR_CAPACITY = 2,      /* an output buffer is too small; required sizes are written to counts[] */
+    LTS_ERR_OOM = 3,           /* device allocation failed */
+    LTS_ERR_DEVICE = 4,        /* a HIP call failed (sticky for the context) */
+    LTS_ERR_NOT_READY = 5,     /* server: the ticket has not finished */
+    LTS_ERR_CANCELLED = 6,     /* server: the ticket was dropped (server stopped or request failed) */
+    LTS_ERR_STATE = 7          /* call not valid in the current state (e.g. no response table set) */
+} lts_status;
+
+/* Charge-transport constants (Sec. 3.1, Sec. 3.2, Sec. 3.3.2). */
+typedef struct lts_physics {
+    int32_t recomb_model;      /* 0 = Birks, eq. (birks) (default); 1 = modified Box, eq. (box) */
+    double e_field;            /* kV/cm */
+    double lar_density;        /* g/cm^3; epsilon = e_field * lar_density */
+    double w_ion;              /* MeV per ionisation electron: Q_0 = E / w_ion */
+    double birks_ab, birks_kb; /* A_b, k_b */
+    double box_alpha, box_beta;/* alpha, beta */
+    double v_drift;            /* cm/us, eq. (drift) */
+    double lifetime;           /* us, eq. (lifetime) */
+    double d_long, d_tran;     /* cm^2/us, sigma = sqrt(2 D t_drift) */
+    double z_anode;            /* cm */
+    double sample_step;        /* cm; N = max(1, ceil(L / sample_step)) points per segment, eq. (rho) */
+    double n_sigma;            /* diffusion truncation in sigmas (>= 1) */
+} lts_physics;
+
+/* Pixel plane and time sampling. */
+typedef struct lts_readout {
+    double pitch;              /* cm */
+    int32_t n_x, n_y;          /* pixels */
+    double x0, y0;             /* cm, lower edge of pixel (0, 0) */
+    int32_t n_sub;             /* sub-pixel bins per pitch (even) = field-table granularity */
+    double tick;               /* us */
+    int32_t n_ticks;           /* readout window length (<= 8000) */
+    double t_begin;            /* us, lower edge of tick 0 */
+} lts_readout;
+
+/* LArPix-like front end (Sec. 3.4). */
+typedef struct lts_electronics {
+    double threshold;          /* electrons; a sample is triggered when integral + discriminator noise >= threshold */
+    int32_t hold_ticks;        /* ticks from the threshold crossing to digitisation (1.6 us = 16) */
+    int32_t min_spacing;       /* minimum ticks between consecutive samples (11) */
+    double q_lsb;              /* electrons per ADC count */
+    int32_t pedestal;          /* ADC counts added before clamping */
+    int32_t adc_bits;          /* ADC resolution (<= 16) */
+    double sigma_reset;        /* electrons: pedestal drawn at start and after each reset */
+    double sigma_disc;         /* electrons: per-tick noise on the discriminator comparison */
+    double sigma_unc;          /* electrons: per-sample uncorrelated noise */
+    int32_t max_packets;       /* per pixel (further samples are counted as overflow) */
+    uint64_t seed;             /* Philox4x32-10 key (low word, high word) */
+} lts_electronics;
+
+/* Segment table, structure of arrays, FP32, device pointers; n rows.  dedx may be NULL; it is read only
+ * for zero-length segments (and must then be finite). */
+typedef struct lts_segments {
+    const float *x0, *y0, *z0, *t0;   /* start point r_s (cm, cm, cm, us) */
+    const float *x1, *y1, *z1, *t1;   /* end point r_e */
+    const float *energy;              /* deposited energy E, MeV */
+    const float *dedx;                /* MeV/cm, optional */
+    int64_t n;
+} lts_segments;
+
+/* Outputs (caller-owned device buffers).
+ *   pixel_id[cap_pixels]           ascending tile-local ids of the active pixels (those whose table reach meets
+ *                                  some segment's charge cloud; their waveform may be all zero)
+ *   current[cap_pixels * n_ticks]  row-major [pixel slot][tick], electrons per tick
+ *   pkt_*[cap_packets]             packets ordered by (pixel slot, tick): pixel id, tick index of the
+ *                                  digitisation, ADC code, flags (bit0: ADC value within the FP32 error margin of
+ *                                  an LSB boundary; bit1: an earlier threshold decision of this pixel lay within
+ *                                  the FP32 error margin; bit2: ADC clamped)
+ *   counts[4]                      written: active pixels, packets, samples dropped past the window, packets over
+ *                                  max_packets.  On LTS_ERR_CAPACITY they hold the required sizes instead.
+ *   report[5 per event]            FP64: sum Q_R (after recombination), sum Q_a (after lifetime), sum of current
+ *                                  over pixels and ticks in the window, signed induction that fell outside the
+ *                                  tick window, charge whose cells lie outside the pixel grid.
+ *   event_pixel_offsets, event_packet_offsets  [n_events + 1] (batch only; may be NULL for one event):
+ *                                  slot / packet ranges of each event in the arrays above.
+ */
+typedef struct lts_outputs {
+    int32_t *pixel_id;
+    float *current;
+    int64_t cap_pixels;
+    int32_t *pkt_pixel;
+    int32_t *pkt_tick;
+    uint16_t *pkt_adc;
+    uint8_t *pkt_flags;
+    int64_t cap_packets;
+    int64_t *counts;
+    double *report;
+    int64_t *event_pixel_offsets;
+    int64_t *event_packet_offsets;
+} lts_outputs;
+
+typedef struct lts_context lts_context;
+
+/* Reduction variant for the per-pixel sum over segments (Sec. 3.4):
+ *   LTS_REDUCE_SORTED: pairs sorted pixel-major, one workgroup per pixel, Kahan-compensated FP32 accumulation in a
+ *                      fixed segment order (deterministic, batch-invariant; default);
+ *   LTS_REDUCE_ATOMIC: segment-major, per-pair currents added with FP32 atomics (order-dependent rounding). */
+enum { LTS_REDUCE_SORTED = 0, LTS_REDUCE_ATOMIC = 1 };
+
+/* Create a context on HIP device `device` with copies of the parameter sets.  Validates them
+ * (LTS_ERR_INVALID_ARG: non-positive v_drift / lifetime / pitch / tick / sample_step, negative diffusion,
+ * odd n_sub, n_sigma < 1, n_ticks outside [1, 8000], adc_bits outside [1, 16], ...). */
+lts_status lts_context_create(int device, const lts_physics *physics, const lts_readout *readout,
+                              const lts_electronics *electronics, lts_context **out);
+void lts_context_destroy(lts_context *ctx);
+
+/* Install the pixel field-response table (Sec. 3.3.1): host array R[t_r][b_x][b_y] (FP32, C order), entry
+ * [k][i][j] = electrons induced in tick k on a pad by one electron whose lateral offset from the pad centre is
+ * the centre of sub-pixel bin (i, j) of the quadrant (bin width pitch / n_sub); entry t_r-1 is the tick of
+ * arrival.  The table is copied to device memory (the caller keeps ownership of R_host).  Requires
+ * 1 <= t_r <= 8192 and 1 <= b_x, b_y <= 256. */
+lts_status lts_set_response(lts_context *ctx, const float *R_host, int32_t t_r, int32_t b_x, int32_t b_y);
+
+lts_status lts_set_reduce_mode(lts_context *ctx, int32_t mode);
+
+/* Sizing pass (synchronous on `stream`): need[4] = (segment-pixel pairs, active pixels, charge cells,
+ * packet upper bound = active pixels * max_packets).  Host pointer need. */
+lts_status lts_plan(lts_context *ctx, const lts_segments *segs, int64_t need[4], void *stream);
+
+/* Simulate one event (Sec. 3: recombination -> drift -> rasterisation -> induction -> per-pixel sum ->
+ * electronics, plus the FP64 charge report).  event_id keys the noise streams, so results do not depend on
+ * batch placement.  Capacity errors return LTS_ERR_CAPACITY with the needs in out->counts (device). */
+lts_status lts_simulate(lts_context *ctx, uint64_t event_id, const lts_segments *segs, const lts_outputs *out,
+                        void *stream);
+
+/* Simulate n_events independent events whose segments are concatenated in `segs` (event e owns rows
+ * [seg_offsets[e], seg_offsets[e+1]), host array of n_events + 1 entries) in one set of launches.  event_ids is a
+ * host array.  Outputs are concatenated event-major; out->event_pixel_offsets / event_packet_offsets must be
+ * provided; report holds 5 doubles per event. */
+lts_status lts_simulate_batch(lts_context *ctx, int32_t n_events, const uint64_t *event_ids,
+                              const int64_t *seg_offsets, const lts_segments *segs, const lts_outputs *out,
+                              void *stream);
+
+/* ---- stage entry points (test hooks; same kernels as the pipeline) ---------------------------------- */
+
+/* Steps of Sec. 3.1-3.2 per segment.  out_f[n * 6] (device): Q_R, Q_a, t_drift (us), sigma_T (cm),
+ * sigma_t (us), dE/dx; out_i[n * 2] (device): number of sample points N, flags (bit0 Box clamp, bit1 invalid). */
+lts_status lts_stage_quench_drift(lts_context *ctx, const lts_segments *segs, float *out_f, int32_t *out_i,
+                                  void *stream);
+
+/* Charge cells of the segments of the last lts_simulate call on this context (synchronous, host outputs):
+ * box[6] = (a0, na, u0, nu, v0, nv) in absolute tick / sub-pixel-bin indices, cells[na][nu][nv] if cap >= size. */
+lts_status lts_debug_cells(lts_context *ctx, int64_t segment, int64_t box[6], float *cells_host, int64_t cap);
+
+/* Front end alone on given currents: n_pix pixels with tile-local ids pixel_ids[] (device), currents
+ * current[n_pix * n_ticks] (device).  Packets as in lts_outputs (counts and packet arrays). */
+lts_status lts_stage_electronics(lts_context *ctx, uint64_t event_id, const int32_t *pixel_ids, const float *current,
+                                 int64_t n_pix, const lts_outputs *out, void *stream);
+
+/* Raw Philox4x32-10 blocks: ctr[n*4] (device) with key (k0, k1) -> out[n*4] (device). */
+lts_status lts_stage_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n, void *stream);
+
+const char *lts_status_str(lts_status s);
+const char *lts_last_error(const lts_context *ctx);
+const char *lts_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LTSIM_H */

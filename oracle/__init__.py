@@ -111,7 +111,7 @@ def lib():
         L.orc_electronics.argtypes = [C.POINTER(_Electronics), C.POINTER(_Readout), C.c_uint64, C.c_int64,
                                       C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_double, C.c_double,
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                      C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         L.orc_num_threads.restype = C.c_int
         _LIB = L
     return _LIB
@@ -203,8 +203,9 @@ def noise_normal(seed, pixel, tick, event_id, stream):
     return float(lib().orc_noise_normal(seed, pixel, tick, event_id, stream))
 
 
-def electronics(el, readout, event_id, pixels, wave, eps_rel=0.0, eps_abs=0.0):
-    """Packets per pixel: list of (tick, adc, flag) arrays; plus stats (dropped, over cap, flagged decisions)."""
+def electronics(el, readout, event_id, pixels, wave, eps_rel=0.0, eps_abs=0.0, with_uncertain=False):
+    """Packets per pixel: list of (tick, adc, flag) arrays; plus stats (dropped, over cap, flagged decisions) and,
+    if asked, per pixel the first tick whose threshold decision lay within eps (2**31-1 if none)."""
     pixels = np.ascontiguousarray(pixels, dtype=np.int32)
     wave = np.ascontiguousarray(wave, dtype=np.float64)
     n = len(pixels)
@@ -214,14 +215,16 @@ def electronics(el, readout, event_id, pixels, wave, eps_rel=0.0, eps_abs=0.0):
     flag = np.zeros(n * mp, np.int32)
     cnt = np.zeros(n, np.int32)
     stats = np.zeros(3, np.int64)
+    ufrom = np.zeros(n, np.int32)
     lib().orc_electronics(C.byref(_fill(_Electronics, el)), C.byref(_fill(_Readout, readout)), event_id, n,
                           _ptr(pixels, C.c_int32), _ptr(wave), eps_rel, eps_abs, _ptr(tick, C.c_int32),
-                          _ptr(adc, C.c_int32), _ptr(flag, C.c_int32), _ptr(cnt, C.c_int32), _ptr(stats, C.c_int64))
+                          _ptr(adc, C.c_int32), _ptr(flag, C.c_int32), _ptr(cnt, C.c_int32), _ptr(stats, C.c_int64),
+                          _ptr(ufrom, C.c_int32))
     out = []
     for q in range(n):
         s = slice(q * mp, q * mp + cnt[q])
         out.append((tick[s].copy(), adc[s].copy(), flag[s].copy()))
-    return out, stats
+    return (out, stats, ufrom) if with_uncertain else (out, stats)
 
 
 def simulate(workload, event_index=0, pixels=None, table=None, eps_rel=0.0, eps_abs=0.0, with_packets=True):
@@ -239,8 +242,9 @@ def simulate(workload, event_index=0, pixels=None, table=None, eps_rel=0.0, eps_
         res["report"] = {"q_after_quench": sums[0], "q_collected": sums[1], "q_induced": float(wave.sum()),
                          "q_clipped": float(clipped.sum()), "q_offgrid": sums[2]}
     if with_packets:
-        pk, st = electronics(workload.electronics, workload.readout, workload.event_ids[event_index], pixels, wave,
-                             eps_rel, eps_abs)
+        pk, st, uf = electronics(workload.electronics, workload.readout, workload.event_ids[event_index], pixels,
+                                 wave, eps_rel, eps_abs, with_uncertain=True)
         res["packets"] = pk
         res["electronics_stats"] = st
+        res["uncertain_from"] = uf
     return res

@@ -520,11 +520,13 @@ double orc_noise_normal(uint64_t seed, uint32_t pixel, uint32_t tick, uint64_t e
  *   threshold, so this packet's timing may legitimately differ from a finite-precision evaluation.
  *   eps = eps_abs + eps_rel * (running sum of |I| since the last reset + threshold).
  *   counts[n_pix]: packets emitted (capped); stats[3] += (samples dropped past the window, packets over
- *   the cap, decisions flagged).
+ *   the cap, decisions flagged); uncertain_from[n_pix] (may be NULL): first tick at which a threshold
+ *   decision lay within eps, INT32_MAX if none.
  */
 int orc_electronics(const orc_electronics_params *el, const orc_readout_params *ro, uint64_t event_id, int64_t n_pix,
                     const int32_t *pixels, const double *wave, double eps_rel, double eps_abs,
-                    int32_t *pkt_tick, int32_t *pkt_adc, int32_t *pkt_flag, int32_t *counts, int64_t *stats)
+                    int32_t *pkt_tick, int32_t *pkt_adc, int32_t *pkt_flag, int32_t *counts, int64_t *stats,
+                    int32_t *uncertain_from)
 {
     int64_t nt = ro->n_ticks;
     int64_t dropped = 0, over = 0, nflag = 0;
@@ -539,6 +541,7 @@ int orc_electronics(const orc_electronics_params *el, const orc_readout_params *
         int pending = 0, uncertain = 0;
         int64_t ns = 0, ready = 0, last_s = INT64_MIN / 4;
         int32_t cnt = 0;
+        int32_t ufrom = INT32_MAX;
         for (int64_t n = 0; n < nt; ++n) {
             Q += w[n];
             absum += fabs(w[n]);
@@ -548,7 +551,10 @@ int orc_electronics(const orc_electronics_params *el, const orc_readout_params *
                     disc = el->sigma_disc * orc_noise_normal(el->seed, pid, (uint32_t)n, event_id, ORC_STREAM_DISC);
                 double m = Q + disc - el->threshold;
                 double eps = eps_abs + eps_rel * (absum + fabs(Q) + el->threshold);
-                if (fabs(m) < eps) { if (!uncertain) ++nflag; uncertain = 1; }
+                if (fabs(m) < eps) {
+                    if (!uncertain) { ++nflag; ufrom = (int32_t)n; }
+                    uncertain = 1;
+                }
                 if (m >= 0.0) {
                     pending = 1;
                     ns = n + el->hold_ticks;
@@ -589,6 +595,7 @@ int orc_electronics(const orc_electronics_params *el, const orc_readout_params *
             }
         }
         counts[q] = cnt;
+        if (uncertain_from) uncertain_from[q] = ufrom;
     }
     stats[0] += dropped;
     stats[1] += over;

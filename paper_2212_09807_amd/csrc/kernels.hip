@@ -1,0 +1,884 @@
+// kernels.hip -- gfx950 kernels of the pixelated-LArTPC charge path (arXiv 2212.09807, Sec. 3).
+//
+// Stage map (one event, or a batch of events whose pixel spaces are concatenated):
+//   k_quench_drift   Sec. 3.1-3.2: recombination, lifetime, diffusion widths per segment; charge box in
+//                    (tick, sub-pixel bin) space; pixel rectangle the box reaches; per-pixel pair counts.
+//   scans            pair / cell offsets (exclusive scans), active-pixel compaction (slots).
+//   k_fill_pairs     pixel-major (pixel, segment) pair lists; k_sort_pairs orders each list by segment id.
+//   k_cells          Sec. 3.3.2 eq. (rho), expectation over the Gaussian perturbations: charge per
+//                    (tick, x-bin, y-bin) cell of each segment, as a sum over sample points of separable
+//                    truncated-Gaussian bin masses.
+//   k_induce_*       Sec. 3.3.2 eq. (current): per (segment, pixel) pair and tick, the cells in the pixel's table
+//                    reach convolved in time with the field-response column of their mirror-folded bin; summed
+//                    over the pixel's segments (Sec. 3.4) either in a fixed order with Kahan compensation
+//                    (sorted variant) or with FP32 atomics (atomic variant).
+//   k_electronics    Sec. 3.4: integrate, threshold (with discriminator noise), hold, digitise, reset, with
+//                    Philox4x32-10 noise; also the FP64 per-event sum of the currents.
+//   k_compact        packets of all pixels into the caller's arrays.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+#include "launch.hpp"
+
+namespace ltsim {
+
+constexpr uint64_t kMask40 = (1ull << 40) - 1;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// FP64 per-event report accumulation, aggregated over the wavefront when all valid lanes share the event.
+// Must be reached by all 64 lanes of the wavefront.
+__device__ __forceinline__ void add_report(double *rep, int e, int k, double v, bool valid) {
+    unsigned long long m = __ballot(valid);
+    if (m == 0) return;
+    int lead = __ffsll((long long)m) - 1;
+    int el = __shfl(e, lead);
+    bool same = __all(!valid || e == el);
+    if (same) {
+        double x = valid ? v : 0.0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (lane_id() == lead && x != 0.0) atomicAdd(&rep[(int64_t)el * 5 + k], x);
+    } else if (valid && v != 0.0) {
+        atomicAdd(&rep[(int64_t)e * 5 + k], v);
+    }
+}
+
+__device__ __forceinline__ int find_event(const int64_t *off, int n_ev, int64_t s) {
+    int lo = 0, hi = n_ev - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= s) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ================================================================================================= scans
+// Exclusive scan of int64 / uint64 arrays: per-tile reduce, scan of tile sums (one workgroup), per-tile scan.
+constexpr int kScanPT = 8;
+constexpr int kScanTile = kWG * kScanPT;
+
+template <typename T>
+__device__ __forceinline__ T block_exclusive(T v, T *lds, T &total) {
+    // wavefront inclusive scan
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    T x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int i = 0; i < kWG / 64; ++i) { T t = lds[i]; lds[i] = run; run += t; }
+        lds[kWG / 64] = run;
+    }
+    __syncthreads();
+    T res = x - v + lds[wv];
+    total = lds[kWG / 64];
+    __syncthreads();
+    return res;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_scan_reduce(const T *data, int64_t n, T *part) {
+    __shared__ T lds[kWG / 64 + 1];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPT;
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPT; ++i)
+        if (base + i < n) s += data[base + i];
+    T tot;
+    block_exclusive<T>(s, lds, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_scan_partials(T *part, int64_t nb) {
+    __shared__ T lds[kWG / 64 + 1];
+    T carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kWG) {
+        int64_t i = b0 + threadIdx.x;
+        T v = i < nb ? part[i] : 0;
+        T tot;
+        T ex = block_exclusive<T>(v, lds, tot);
+        if (i < nb) part[i] = ex + carry;
+        carry += tot;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_scan_apply(T *data, int64_t n, const T *part) {
+    __shared__ T lds[kWG / 64 + 1];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPT;
+    T v[kScanPT];
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPT; ++i) {
+        v[i] = base + i < n ? data[base + i] : 0;
+        s += v[i];
+    }
+    T tot;
+    T run = block_exclusive<T>(s, lds, tot) + part[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanPT; ++i)
+        if (base + i < n) { data[base + i] = run; run += v[i]; }
+}
+
+int64_t scan_tmp_needed(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+template <typename T>
+static void scan_exclusive(T *data, int64_t n, void *tmp, hipStream_t st) {
+    if (n <= 0) return;
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    T *part = (T *)tmp;
+    k_scan_reduce<T><<<(unsigned)nb, kWG, 0, st>>>(data, n, part);
+    k_scan_partials<T><<<1, kWG, 0, st>>>(part, nb);
+    k_scan_apply<T><<<(unsigned)nb, kWG, 0, st>>>(data, n, part);
+}
+
+void scan_exclusive_i64(int64_t *data, int64_t n, int64_t *, void *tmp, hipStream_t st) {
+    scan_exclusive<int64_t>(data, n, tmp, st);
+}
+void scan_exclusive_u64(uint64_t *data, int64_t n, void *tmp, hipStream_t st) {
+    scan_exclusive<unsigned long long>((unsigned long long *)data, n, tmp, st);
+}
+
+// ================================================================================================= quench / drift
+struct QDOut {
+    float q_r, q_a, t_drift, sigma_t, sigma_time, dedx;
+    int32_t n_points, flags;
+};
+
+// Recombination (Sec. 3.1) and drift (Sec. 3.2) of segment s, plus its local reference frame.
+__device__ __forceinline__ void segment_setup(const DevParams &P, const SegArrays &S, int64_t s, SegInfo &g, QDOut &o) {
+    const float x0 = S.x0[s], y0 = S.y0[s], z0 = S.z0[s], t0 = S.t0[s];
+    const float x1 = S.x1[s], y1 = S.y1[s], z1 = S.z1[s], t1 = S.t1[s];
+    const float E = S.energy[s];
+    int32_t flags = 0;
+    const float dx = __fsub_rn(x1, x0), dy = __fsub_rn(y1, y0), dz = __fsub_rn(z1, z0), dt = __fsub_rn(t1, t0);
+    // number of sample points (integer decided in IEEE single precision, no contraction)
+    const float L2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+    const float L = __fsqrt_rn(L2);
+    const float cN = ceilf(__fdiv_rn(L, P.step));
+    const int32_t N = cN >= 1.0f ? (int32_t)fminf(cN, 1.0e8f) : 1;
+    float dedx;
+    if (L > 0.0f) dedx = __fdiv_rn(E, L);                         // constant within the segment (Sec. 2)
+    else if (S.dedx && isfinite(S.dedx[s])) dedx = S.dedx[s];
+    else { dedx = 0.0f; flags |= SEG_INVALID; }
+    // finite, and small enough that bin / tick indices stay far from int32 limits (|coordinate| <= 1e6)
+    const float cmax = fmaxf(fmaxf(fmaxf(fabsf(x0), fabsf(y0)), fmaxf(fabsf(z0), fabsf(t0))),
+                             fmaxf(fmaxf(fabsf(x1), fabsf(y1)), fmaxf(fabsf(z1), fabsf(t1))));
+    const bool fin = isfinite(x0) && isfinite(y0) && isfinite(z0) && isfinite(t0) && isfinite(x1) && isfinite(y1) &&
+                     isfinite(z1) && isfinite(t1) && isfinite(E);       // (fmaxf would drop NaNs)
+    if (!(fin && cmax <= 1.0e6f && E >= 0.0f)) flags |= SEG_INVALID;
+    if (N > 65536) flags |= SEG_TOO_LONG;
+    float R;
+    if (P.recomb_model == 0) {
+        R = P.birks_ab / (1.0f + P.birks_kb_eps * dedx);           // eq. (birks)
+    } else {
+        const float xi = P.box_beta_eps * dedx;                    // eq. (box)
+        R = xi > 0.0f ? logf(P.box_alpha + xi) / xi : -1.0f;
+        if (!(R >= 0.0f)) { R = 0.0f; flags |= SEG_BOX_CLAMP; }
+    }
+    const float qr = R * (E * P.inv_w_ion);
+    const float zm = 0.5f * (z0 + z1);
+    const float td = fabsf(zm - P.za_hi) * P.inv_vd_hi;            // eq. (drift) at the midpoint
+    const float qa = qr * expf(-td * P.inv_lifetime);              // eq. (lifetime)
+    const float sT = sqrtf(P.two_dt * td);                         // sigma = sqrt(2 D t)
+    const float sL = sqrtf(P.two_dl * td) * P.inv_vd_hi;           // longitudinal, as time
+
+    g.q_r = qr; g.q_a = qa; g.q_pt = qa / (float)N; g.t_drift = td;
+    g.sigma_t = sT; g.sigma_time = sL; g.dedx = dedx;
+    g.n_points = N;
+    // local frame: reference bin / tick of the start point and exact offsets
+    ref_offset(x0, 0.0f, P.x0_hi, P.x0_lo, P.b_hi, P.b_lo, g.u_ref, g.ox);
+    ref_offset(y0, 0.0f, P.y0_hi, P.y0_lo, P.b_hi, P.b_lo, g.v_ref, g.oy);
+    float zh, zl;
+    two_sum(z0, -P.za_hi, zh, zl);
+    zl = __fsub_rn(zl, P.za_lo);
+    const float dh = fabsf(zh), dl = zh >= 0.0f ? zl : -zl;       // |z0 - z_anode| as hi + lo
+    const float q = __fmul_rn(dh, P.inv_vd_hi);
+    const float qe = __fadd_rn(fmaf(dh, P.inv_vd_hi, -q), __fadd_rn(__fmul_rn(dh, P.inv_vd_lo), __fmul_rn(dl, P.inv_vd_hi)));
+    float vh, ve;
+    two_sum(t0, q, vh, ve);
+    ref_offset(vh, __fadd_rn(ve, qe), P.tb_hi, P.tb_lo, P.tick_hi, P.tick_lo, g.a_ref, g.ot);
+    const float zz0 = __fsub_rn(z0, P.za_hi), zz1 = __fsub_rn(z1, P.za_hi);
+    const bool straddle = (zz0 < 0.0f && zz1 > 0.0f) || (zz0 > 0.0f && zz1 < 0.0f);
+    const float sg = (zz0 > 0.0f || (zz0 == 0.0f && zz1 >= 0.0f)) ? 1.0f : -1.0f;
+    g.dx = dx; g.dy = dy; g.dz = dz; g.dt = dt; g.zz0 = zz0;
+    g.dta = fmaf(sg * dz, P.inv_vd_hi, dt);
+    if (straddle) flags |= SEG_STRADDLE;
+    g.flags = flags;
+    o.q_r = qr; o.q_a = qa; o.t_drift = td; o.sigma_t = sT; o.sigma_time = sL; o.dedx = dedx;
+    o.n_points = N; o.flags = flags;
+}
+
+// Charge box (tick x bin x bin) that the truncated clouds of the sample points can reach, and the pixel
+// rectangle whose table reach meets it.
+__device__ __forceinline__ void segment_box(const DevParams &P, SegInfo &g) {
+    float lx0, ly0, lt0, lx1, ly1, lt1;
+    point_local(g, P, 0, lx0, ly0, lt0);
+    point_local(g, P, g.n_points - 1, lx1, ly1, lt1);
+    float tmin = fminf(lt0, lt1), tmax = fmaxf(lt0, lt1);
+    if ((g.flags & SEG_STRADDLE) && !(g.flags & (SEG_TOO_LONG | SEG_INVALID))) {
+        for (int32_t mu = 1; mu < g.n_points - 1; ++mu) {
+            float a, b, t;
+            point_local(g, P, mu, a, b, t);
+            tmin = fminf(tmin, t);
+            tmax = fmaxf(tmax, t);
+        }
+    }
+    const float ext = P.nsig * g.sigma_t, ext_t = P.nsig * g.sigma_time;
+    const int32_t ulo = (int32_t)floorf(__fdiv_rn(fminf(lx0, lx1) - ext, P.b_hi));
+    const int32_t uhi = (int32_t)floorf(__fdiv_rn(fmaxf(lx0, lx1) + ext, P.b_hi));
+    const int32_t vlo = (int32_t)floorf(__fdiv_rn(fminf(ly0, ly1) - ext, P.b_hi));
+    const int32_t vhi = (int32_t)floorf(__fdiv_rn(fmaxf(ly0, ly1) + ext, P.b_hi));
+    const int32_t alo = (int32_t)floorf(__fdiv_rn(tmin - ext_t, P.tick_hi));
+    const int32_t ahi = (int32_t)floorf(__fdiv_rn(tmax + ext_t, P.tick_hi));
+    g.u0 = g.u_ref + ulo; g.nu = uhi - ulo + 1;
+    g.v0 = g.v_ref + vlo; g.nv = vhi - vlo + 1;
+    g.a0 = g.a_ref + alo; g.na = ahi - alo + 1;
+    g.na_pad = (g.na + kAC - 1) / kAC * kAC;
+    if (!(g.nu >= 1 && g.nu <= kBoxMax && g.nv >= 1 && g.nv <= kBoxMax && g.na >= 1 && g.na <= kNaMax))
+        g.flags |= SEG_TOO_LONG;
+    // pixel ix reaches sub-pixel bins u in [ix*nsub + nsub/2 - bx, ix*nsub + nsub/2 + bx - 1]
+    const int32_t h = P.nsub / 2;
+    g.ix0 = max(ceil_div(g.u0 - h - P.bx + 1, P.nsub), 0);
+    g.ix1 = min(floor_div(g.u0 + g.nu - 1 - h + P.bx, P.nsub), P.nx - 1);
+    g.iy0 = max(ceil_div(g.v0 - h - P.by + 1, P.nsub), 0);
+    g.iy1 = min(floor_div(g.v0 + g.nv - 1 - h + P.by, P.nsub), P.ny - 1);
+    if (g.flags & (SEG_INVALID | SEG_TOO_LONG)) { g.ix1 = g.ix0 - 1; }
+    g.n_pairs = (g.ix1 >= g.ix0 && g.iy1 >= g.iy0) ? (g.ix1 - g.ix0 + 1) * (g.iy1 - g.iy0 + 1) : 0;
+}
+
+__global__ __launch_bounds__(kWG) void k_quench_drift(DevParams P, SegArrays S, int64_t n_seg, const int64_t *ev_off,
+                                                      int32_t n_ev, SegInfo *si, int64_t *cell_cnt, uint64_t *pix_cnt,
+                                                      DevHeader *H, double *report) {
+    const int64_t s = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    const bool valid = s < n_seg;
+    SegInfo g = {};
+    QDOut o;
+    int e = 0;
+    if (valid) {
+        e = find_event(ev_off, n_ev, s);
+        segment_setup(P, S, s, g, o);
+        segment_box(P, g);
+        g.event = e;
+        si[s] = g;
+        const bool skip = g.flags & (SEG_INVALID | SEG_TOO_LONG);
+        cell_cnt[s] = skip ? 0 : (int64_t)g.nu * g.nv * g.na_pad;
+        if (g.flags & SEG_INVALID) atomicOr(&H->status, ST_INVALID);
+        if (g.flags & SEG_TOO_LONG) atomicOr(&H->status, ST_TOO_LONG);
+        uint64_t *pc = pix_cnt + (int64_t)e * P.npx;
+        for (int32_t iy = g.iy0; iy <= g.iy1; ++iy)
+            for (int32_t ix = g.ix0; ix <= g.ix1; ++ix) atomicAdd((unsigned long long *)&pc[iy * P.nx + ix], 1ull);
+    }
+    add_report(report, e, 0, valid ? (double)g.q_r : 0.0, valid);
+    add_report(report, e, 1, valid ? (double)g.q_a : 0.0, valid);
+}
+
+// Mark active pixels (count > 0) in the high bits so one scan yields pair offsets and slot indices.
+__global__ void k_mark_active(uint64_t *pix_cnt, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        uint64_t v = pix_cnt[i];
+        pix_cnt[i] = v | (v ? (1ull << 40) : 0ull);
+    }
+}
+
+__global__ void k_totals(const uint64_t *pix_off, int64_t n_gp, const int64_t *cell_off, int64_t n_seg, DevHeader *H) {
+    uint64_t t = pix_off[n_gp];
+    H->n_pairs = (int64_t)(t & kMask40);
+    H->n_slots = (int64_t)(t >> 40);
+    H->n_cells = cell_off[n_seg];
+}
+
+void launch_quench_drift(const DevParams &P, const SegArrays &S, const Work &w, hipStream_t st) {
+    const int64_t n_gp = (int64_t)w.n_ev * P.npx;
+    if (w.n_seg > 0)
+        k_quench_drift<<<(unsigned)((w.n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, S, w.n_seg, w.seg_ev_off, w.n_ev, w.si,
+                                                                            w.cell_off, w.pix_cnt, w.hdr, w.report);
+    k_mark_active<<<(unsigned)((n_gp + kWG - 1) / kWG), kWG, 0, st>>>(w.pix_cnt, n_gp);
+    scan_exclusive<unsigned long long>((unsigned long long *)w.pix_cnt, n_gp + 1, w.scan_tmp, st);
+    scan_exclusive<int64_t>(w.cell_off, w.n_seg + 1, w.scan_tmp, st);
+    k_totals<<<1, 1, 0, st>>>(w.pix_cnt, n_gp, w.cell_off, w.n_seg, w.hdr);
+}
+
+__global__ void k_stage_qd(DevParams P, SegArrays S, int64_t n, float *out_f, int32_t *out_i) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    SegInfo g = {};
+    QDOut o;
+    segment_setup(P, S, s, g, o);
+    float *f = out_f + 6 * s;
+    f[0] = o.q_r; f[1] = o.q_a; f[2] = o.t_drift; f[3] = o.sigma_t; f[4] = o.sigma_time; f[5] = o.dedx;
+    out_i[2 * s] = o.n_points;
+    out_i[2 * s + 1] = o.flags & (SEG_BOX_CLAMP | SEG_INVALID);
+}
+
+void launch_stage_quench_drift(const DevParams &P, const SegArrays &S, int64_t n, float *out_f, int32_t *out_i,
+                               hipStream_t st) {
+    if (n > 0) k_stage_qd<<<(unsigned)((n + kWG - 1) / kWG), kWG, 0, st>>>(P, S, n, out_f, out_i);
+}
+
+// ================================================================================================= slots / pairs
+__global__ void k_slots(DevParams P, int64_t n_gp, const uint64_t *pix_off, int32_t *pix_slot, int32_t *slot_gp,
+                        int64_t *slot_off, int32_t *pixel_id_out, const DevHeader *H, int64_t cap_slots) {
+    int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gp > n_gp) return;
+    if (gp == n_gp) {
+        int64_t ns = H->n_slots;
+        if (ns <= cap_slots) slot_off[ns] = H->n_pairs;
+        return;
+    }
+    uint64_t v = pix_off[gp], vn = pix_off[gp + 1];
+    bool active = (vn >> 40) > (v >> 40);
+    int64_t slot = (int64_t)(v >> 40);
+    pix_slot[gp] = active ? (int32_t)slot : -1;
+    if (active && slot < cap_slots) {
+        slot_gp[slot] = (int32_t)gp;
+        slot_off[slot] = (int64_t)(v & kMask40);
+        if (pixel_id_out) pixel_id_out[slot] = (int32_t)(gp % P.npx);
+    }
+}
+
+__global__ void k_event_pixel_offsets(int32_t n_ev, int32_t npx, const uint64_t *pix_off, int64_t *ev_pix_off) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e <= n_ev) ev_pix_off[e] = (int64_t)(pix_off[(int64_t)e * npx] >> 40);
+}
+
+void launch_slots(const DevParams &P, const Work &w, int32_t *pixel_id_out, int64_t *ev_pix_off, hipStream_t st) {
+    const int64_t n_gp = (int64_t)w.n_ev * P.npx;
+    k_slots<<<(unsigned)((n_gp + 1 + kWG - 1) / kWG), kWG, 0, st>>>(P, n_gp, w.pix_cnt, w.pix_slot, w.slot_gp,
+                                                                   w.slot_off, pixel_id_out, w.hdr, INT64_MAX);
+    if (ev_pix_off)
+        k_event_pixel_offsets<<<(w.n_ev + 1 + kWG - 1) / kWG, kWG, 0, st>>>(w.n_ev, P.npx, w.pix_cnt, ev_pix_off);
+}
+
+__global__ __launch_bounds__(kWG) void k_fill_pairs(DevParams P, const SegInfo *si, int64_t n_seg, const uint64_t *pix_off,
+                                                    int32_t *cursor, int32_t *pairs) {
+    int64_t s = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (s >= n_seg) return;
+    const SegInfo &g = si[s];
+    const int64_t base = (int64_t)g.event * P.npx;
+    for (int32_t iy = g.iy0; iy <= g.iy1; ++iy)
+        for (int32_t ix = g.ix0; ix <= g.ix1; ++ix) {
+            int64_t gp = base + iy * P.nx + ix;
+            int64_t pos = (int64_t)(pix_off[gp] & kMask40) + atomicAdd(&cursor[gp], 1);
+            pairs[pos] = (int32_t)s;
+        }
+}
+
+void launch_fill_pairs(const DevParams &P, const Work &w, hipStream_t st) {
+    if (w.n_seg > 0)
+        k_fill_pairs<<<(unsigned)((w.n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.n_seg, w.pix_cnt, w.cursor,
+                                                                          w.pairs_unsorted);
+}
+
+// Each pixel's segment list in ascending segment id (ids are unique within a list): rank = number of smaller ids.
+constexpr int kSortLds = 4096;
+__global__ __launch_bounds__(kWG) void k_sort_pairs(const int64_t *slot_off, const DevHeader *H, const int32_t *in,
+                                                    int32_t *out) {
+    __shared__ int32_t lds[kSortLds];
+    const int64_t n_slots = H->n_slots;
+    for (int64_t slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
+        const int64_t off = slot_off[slot];
+        const int32_t cnt = (int32_t)(slot_off[slot + 1] - off);
+        const int32_t *src = in + off;
+        if (cnt <= kSortLds) {
+            for (int i = threadIdx.x; i < cnt; i += kWG) lds[i] = src[i];
+            __syncthreads();
+            for (int i = threadIdx.x; i < cnt; i += kWG) {
+                int32_t v = lds[i], r = 0;
+                for (int j = 0; j < cnt; ++j) r += lds[j] < v;
+                out[off + r] = v;
+            }
+            __syncthreads();
+        } else {
+            for (int i = threadIdx.x; i < cnt; i += kWG) {
+                int32_t v = src[i], r = 0;
+                for (int j = 0; j < cnt; ++j) r += src[j] < v;
+                out[off + r] = v;
+            }
+        }
+    }
+}
+
+void launch_sort_pairs(const Work &w, int64_t n_slots_host, hipStream_t st) {
+    int64_t g = n_slots_host < 1 ? 1 : (n_slots_host > 8192 ? 8192 : n_slots_host);
+    k_sort_pairs<<<(unsigned)g, kWG, 0, st>>>(w.slot_off, w.hdr, w.pairs_unsorted, w.pairs);
+}
+
+// ================================================================================================= charge cells
+// Masses of nk consecutive bins (edges (k0 + k) * width relative to the reference edge) for a point at local
+// offset l with width sigma, truncated at +-n sigma and renormalised.
+__device__ void axis_masses(float l, float sigma, int32_t k0, int32_t nk, float wh, float wl, const DevParams &P,
+                            float *out) {
+    if (!(sigma > 0.0f)) {
+        const int32_t kk = (int32_t)floorf(__fdiv_rn(l, wh)) - k0;
+        for (int32_t k = 0; k < nk; ++k) out[k] = (k == kk) ? 1.0f : 0.0f;
+        return;
+    }
+    const float inv = 1.0f / sigma;
+    float kf = (float)k0;
+    float e = __fadd_rn(fmaf(kf, wh, -l), __fmul_rn(kf, wl));
+    float za = fminf(fmaxf(e * inv, -P.nsig), P.nsig);
+    float ta = tail(za);
+    for (int32_t k = 0; k < nk; ++k) {
+        kf = (float)(k0 + k + 1);
+        e = __fadd_rn(fmaf(kf, wh, -l), __fmul_rn(kf, wl));
+        const float zb = fminf(fmaxf(e * inv, -P.nsig), P.nsig);
+        const float tb = tail(zb);
+        out[k] = tmass(za, ta, zb, tb, P.inv_norm);
+        za = zb;
+        ta = tb;
+    }
+}
+
+constexpr int kCellLds = 12288;   // floats (48 KB)
+
+__global__ __launch_bounds__(kWG) void k_cells(DevParams P, const SegInfo *si, int64_t n_seg, float *cells, double *report) {
+    __shared__ float sm[kCellLds];
+    __shared__ double red[kWG / 64];
+    const int tid = threadIdx.x;
+    for (int64_t s = blockIdx.x; s < n_seg; s += gridDim.x) {
+        const SegInfo g = si[s];
+        if (g.flags & (SEG_INVALID | SEG_TOO_LONG)) continue;
+        const int32_t nu = g.nu, nv = g.nv, na = g.na, nap = g.na_pad, N = g.n_points;
+        const int32_t row = nu + nv + nap;
+        const int32_t pc = min(64, kCellLds / row);
+        float *fx = sm, *fy = sm + pc * nu, *ft = fy + pc * nv;
+        const int64_t ncell = (int64_t)nu * nv * nap;
+        float *out = cells + g.cell_off;
+        for (int32_t mu0 = 0; mu0 < N; mu0 += pc) {
+            const int32_t np = min(pc, N - mu0);
+            for (int r = tid; r < np * 3; r += kWG) {
+                const int32_t m = r / 3, ax = r - 3 * (r / 3);
+                float lx, ly, lt;
+                point_local(g, P, mu0 + m, lx, ly, lt);
+                if (ax == 0) {
+                    axis_masses(lx, g.sigma_t, g.u0 - g.u_ref, nu, P.b_hi, P.b_lo, P, fx + m * nu);
+                } else if (ax == 1) {
+                    axis_masses(ly, g.sigma_t, g.v0 - g.v_ref, nv, P.b_hi, P.b_lo, P, fy + m * nv);
+                } else {
+                    axis_masses(lt, g.sigma_time, g.a0 - g.a_ref, na, P.tick_hi, P.tick_lo, P, ft + m * nap);
+                    for (int32_t a = na; a < nap; ++a) ft[m * nap + a] = 0.0f;
+                }
+            }
+            __syncthreads();
+            for (int64_t c = tid; c < ncell; c += kWG) {
+                const int32_t a = (int32_t)(c % nap);
+                const int32_t uv = (int32_t)(c / nap);
+                const int32_t v = uv % nv, u = uv / nv;
+                float acc = 0.0f;
+                for (int32_t m = 0; m < np; ++m) acc = fmaf(ft[m * nap + a] * fx[m * nu + u], fy[m * nv + v], acc);
+                acc *= g.q_pt;
+                if (mu0 == 0) out[c] = acc; else out[c] += acc;
+            }
+            __syncthreads();
+        }
+        // charge whose cells lie outside the pixel grid
+        const int32_t ug = P.nx * P.nsub, vg = P.ny * P.nsub;
+        if (g.u0 < 0 || g.u0 + nu > ug || g.v0 < 0 || g.v0 + nv > vg) {
+            double loc = 0.0;
+            for (int64_t c = tid; c < ncell; c += kWG) {
+                const int32_t uv = (int32_t)(c / nap);
+                const int32_t v = g.v0 + uv % nv, u = g.u0 + uv / nv;
+                if (u < 0 || u >= ug || v < 0 || v >= vg) loc += (double)out[c];
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) loc += __shfl_xor(loc, o);
+            if (lane_id() == 0) red[tid >> 6] = loc;
+            __syncthreads();
+            if (tid == 0) {
+                double t = 0.0;
+                for (int i = 0; i < kWG / 64; ++i) t += red[i];
+                if (t != 0.0) atomicAdd(&report[(int64_t)g.event * 5 + 4], t);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+void launch_cells(const DevParams &P, const Work &w, hipStream_t st) {
+    if (w.n_seg <= 0) return;
+    int64_t g = w.n_seg > 8192 ? 8192 : w.n_seg;
+    k_cells<<<(unsigned)g, kWG, 0, st>>>(P, w.si, w.n_seg, w.cells, w.report);
+}
+
+// ================================================================================================= induction
+// Current of one (segment, pixel) pair on RT consecutive ticks nb .. nb+RT-1 (eq. (current)):
+//   I[n] = sum over cells (a, u, v) in the pixel's reach of c[a,u,v] * R[n - a + T_R - 1, fold(u - uc), fold(v - vc)].
+// The table column is zero-padded by kPad on both sides, so no bounds test is needed in the inner loop; the cell
+// column is padded with zeros to a multiple of kAC ticks.
+template <int RT>
+__device__ __forceinline__ void pair_block(const DevParams &P, const float *__restrict__ cc0, int32_t nv, int32_t nap,
+                                           int32_t u0, int32_t v0, int32_t a0, const float *__restrict__ Rpad,
+                                           int32_t ulo, int32_t uhi, int32_t vlo, int32_t vhi, int32_t uc, int32_t vc,
+                                           int32_t nb, float (&acc)[RT]) {
+    const int32_t K0 = nb - a0 + P.t_r - 1 + kPad;
+    for (int32_t u = ulo; u <= uhi; ++u) {
+        const int32_t i = fold(u - uc);
+        const float *ccu = cc0 + (int64_t)(u - u0) * nv * nap;
+        for (int32_t v = vlo; v <= vhi; ++v) {
+            const int32_t j = fold(v - vc);
+            const float *col = Rpad + (int64_t)(i * P.by + j) * P.col_len + K0 - (kAC - 1);
+            const float *cc = ccu + (int64_t)(v - v0) * nap;
+            for (int32_t ac = 0; ac < nap; ac += kAC) {
+                float w[RT + kAC - 1];
+#pragma unroll
+                for (int m = 0; m < RT + kAC - 1; ++m) w[m] = col[m - ac];
+                float cv[kAC];
+#pragma unroll
+                for (int q = 0; q < kAC; ++q) cv[q] = cc[ac + q];
+#pragma unroll
+                for (int q = 0; q < kAC; ++q)
+#pragma unroll
+                    for (int r = 0; r < RT; ++r) acc[r] = fmaf(cv[q], w[r - q + kAC - 1], acc[r]);
+            }
+        }
+    }
+}
+
+// Signed induction of a pair's cells that falls outside the tick window [0, n_ticks), from FP64 prefix sums of
+// the table columns.  Threads of the workgroup split the cells; returns this thread's part.
+__device__ double pair_clipped(const DevParams &P, const float *cc0, int32_t nv, int32_t nap, int32_t na, int32_t u0,
+                               int32_t v0, int32_t a0, const double *prefix, int32_t ulo, int32_t uhi, int32_t vlo,
+                               int32_t vhi, int32_t uc, int32_t vc) {
+    double acc = 0.0;
+    const int32_t nuu = uhi - ulo + 1, nvv = vhi - vlo + 1;
+    const int64_t tot = (int64_t)nuu * nvv * na;
+    const int32_t T = P.t_r;
+    for (int64_t c = threadIdx.x; c < tot; c += kWG) {
+        const int32_t a = (int32_t)(c % na);
+        const int32_t uv = (int32_t)(c / na);
+        const int32_t v = vlo + uv % nvv, u = ulo + uv / nvv;
+        const float cval = cc0[((int64_t)(u - u0) * nv + (v - v0)) * nap + a];
+        if (cval == 0.0f) continue;
+        const int32_t aa = a0 + a;
+        const double *pf = prefix + (int64_t)(fold(u - uc) * P.by + fold(v - vc)) * (T + 1);
+        const int32_t klo = min(max(T - 1 - aa, 0), T);                 // first kept table tick
+        const int32_t khi = min(max(P.nticks + T - 1 - aa, 0), T);       // one past the last kept tick
+        const double dropped = klo >= khi ? pf[T] : pf[klo] + (pf[T] - pf[khi]);
+        acc += (double)cval * dropped;
+    }
+    return acc;
+}
+
+__device__ __forceinline__ double block_sum_double(double v, double *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < kWG / 64; ++i) t += red[i];
+    return t;
+}
+
+// Sorted variant: one workgroup per active pixel (dynamic work queue); the pixel's segments in ascending id
+// order; per-pair FP32 sums in registers added into a Kahan-compensated FP32 accumulator in LDS.
+template <int RT>
+__global__ __launch_bounds__(kWG) void k_induce_sorted(DevParams P, const SegInfo *__restrict__ si,
+                                                       const float *__restrict__ cells, const float *__restrict__ Rpad,
+                                                       const double *__restrict__ prefix,
+                                                       const int64_t *__restrict__ slot_off,
+                                                       const int32_t *__restrict__ pairs,
+                                                       const int32_t *__restrict__ slot_gp, float *__restrict__ wave,
+                                                       DevHeader *H, double *report) {
+    extern __shared__ float sm[];
+    __shared__ int32_t s_slot;
+    __shared__ double red[kWG / 64];
+    const int NT = P.nticks;
+    float *s_sum = sm, *s_cmp = sm + NT;
+    const int tid = threadIdx.x;
+    const int64_t n_slots = H->n_slots;
+    for (;;) {
+        if (tid == 0) s_slot = (int32_t)atomicAdd(&H->work[0], 1u);
+        __syncthreads();
+        const int64_t slot = s_slot;
+        if (slot >= n_slots) break;
+        for (int n = tid; n < NT; n += kWG) { s_sum[n] = 0.0f; s_cmp[n] = 0.0f; }
+        const int32_t gp = slot_gp[slot];
+        const int32_t e = gp / P.npx, p = gp - e * P.npx;
+        const int32_t ix = p % P.nx, iy = p / P.nx;
+        const int32_t uc = ix * P.nsub + P.nsub / 2, vc = iy * P.nsub + P.nsub / 2;
+        const int64_t pb = slot_off[slot], pe = slot_off[slot + 1];
+        double clip = 0.0;
+        __syncthreads();
+        for (int64_t q = pb; q < pe; ++q) {
+            const int32_t s = __builtin_amdgcn_readfirstlane(pairs[q]);
+            const SegInfo &g = si[s];
+            const int32_t u0 = g.u0, v0 = g.v0, a0 = g.a0, nv = g.nv, nap = g.na_pad, na = g.na;
+            const int32_t ulo = max(u0, uc - P.bx), uhi = min(u0 + g.nu - 1, uc + P.bx - 1);
+            const int32_t vlo = max(v0, vc - P.by), vhi = min(v0 + nv - 1, vc + P.by - 1);
+            if (ulo > uhi || vlo > vhi) continue;
+            const float *cc0 = cells + g.cell_off;
+            const int32_t wlo = a0 - (P.t_r - 1), whi = a0 + na - 1;
+            if (wlo < 0 || whi >= NT)
+                clip += pair_clipped(P, cc0, nv, nap, na, u0, v0, a0, prefix, ulo, uhi, vlo, vhi, uc, vc);
+            const int32_t lo = max(wlo, 0), hi = min(whi, NT - 1);
+            for (int32_t nb0 = lo; nb0 <= hi; nb0 += kWG * RT) {
+                const int32_t nb = nb0 + tid * RT;
+                float acc[RT];
+#pragma unroll
+                for (int r = 0; r < RT; ++r) acc[r] = 0.0f;
+                if (nb <= hi) pair_block<RT>(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, acc);
+#pragma unroll
+                for (int r = 0; r < RT; ++r) {
+                    const int32_t n = nb + r;
+                    if (n <= hi) {                                       // Kahan: s_cmp holds the lost low part
+                        const float y = acc[r] - s_cmp[n];
+                        const float t = s_sum[n] + y;
+                        s_cmp[n] = (t - s_sum[n]) - y;
+                        s_sum[n] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        float *wrow = wave + slot * NT;
+        for (int n = tid; n < NT; n += kWG) wrow[n] = s_sum[n] - s_cmp[n];
+        const double c = block_sum_double(clip, red);
+        if (tid == 0 && c != 0.0) atomicAdd(&report[(int64_t)e * 5 + 3], c);
+        __syncthreads();
+    }
+}
+
+// Atomic variant: one workgroup per segment (dynamic work queue); its pairs in pixel order; FP32 atomics.
+template <int RT>
+__global__ __launch_bounds__(kWG) void k_induce_atomic(DevParams P, const SegInfo *__restrict__ si, int64_t n_seg,
+                                                       const float *__restrict__ cells, const float *__restrict__ Rpad,
+                                                       const double *__restrict__ prefix,
+                                                       const int32_t *__restrict__ pix_slot, float *wave, DevHeader *H,
+                                                       double *report) {
+    __shared__ int32_t s_seg;
+    __shared__ double red[kWG / 64];
+    const int NT = P.nticks;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_seg = (int32_t)atomicAdd(&H->work[1], 1u);
+        __syncthreads();
+        const int64_t s = s_seg;
+        __syncthreads();
+        if (s >= n_seg) break;
+        const SegInfo &g = si[s];
+        if (g.n_pairs == 0) continue;
+        const int32_t u0 = g.u0, v0 = g.v0, a0 = g.a0, nv = g.nv, nap = g.na_pad, na = g.na;
+        const float *cc0 = cells + g.cell_off;
+        const int32_t wlo = a0 - (P.t_r - 1), whi = a0 + na - 1;
+        const int32_t lo = max(wlo, 0), hi = min(whi, NT - 1);
+        double clip = 0.0;
+        for (int32_t iy = g.iy0; iy <= g.iy1; ++iy)
+            for (int32_t ix = g.ix0; ix <= g.ix1; ++ix) {
+                const int32_t uc = ix * P.nsub + P.nsub / 2, vc = iy * P.nsub + P.nsub / 2;
+                const int32_t ulo = max(u0, uc - P.bx), uhi = min(u0 + g.nu - 1, uc + P.bx - 1);
+                const int32_t vlo = max(v0, vc - P.by), vhi = min(v0 + nv - 1, vc + P.by - 1);
+                if (ulo > uhi || vlo > vhi) continue;
+                const int64_t slot = pix_slot[(int64_t)g.event * P.npx + iy * P.nx + ix];
+                float *wrow = wave + slot * NT;
+                if (wlo < 0 || whi >= NT)
+                    clip += pair_clipped(P, cc0, nv, nap, na, u0, v0, a0, prefix, ulo, uhi, vlo, vhi, uc, vc);
+                for (int32_t nb0 = lo; nb0 <= hi; nb0 += kWG * RT) {
+                    const int32_t nb = nb0 + tid * RT;
+                    if (nb > hi) continue;
+                    float acc[RT];
+#pragma unroll
+                    for (int r = 0; r < RT; ++r) acc[r] = 0.0f;
+                    pair_block<RT>(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, acc);
+#pragma unroll
+                    for (int r = 0; r < RT; ++r)
+                        if (nb + r <= hi && acc[r] != 0.0f) atomicAdd(&wrow[nb + r], acc[r]);
+                }
+            }
+        const double c = block_sum_double(clip, red);
+        if (tid == 0 && c != 0.0) atomicAdd(&report[(int64_t)g.event * 5 + 3], c);
+    }
+}
+
+template <int RT>
+static void induce_rt(const DevParams &P, const Work &w, const Table &T, float *wave, int mode, int64_t n_slots,
+                      hipStream_t st) {
+    const int64_t cap = 2048;
+    if (mode == 0) {
+        int64_t g = n_slots < 1 ? 1 : (n_slots > cap ? cap : n_slots);
+        size_t lds = (size_t)2 * P.nticks * sizeof(float);
+        k_induce_sorted<RT><<<(unsigned)g, kWG, lds, st>>>(P, w.si, w.cells, T.Rpad, T.prefix, w.slot_off, w.pairs,
+                                                          w.slot_gp, wave, w.hdr, w.report);
+    } else {
+        int64_t g = w.n_seg < 1 ? 1 : (w.n_seg > cap ? cap : w.n_seg);
+        k_induce_atomic<RT><<<(unsigned)g, kWG, 0, st>>>(P, w.si, w.n_seg, w.cells, T.Rpad, T.prefix, w.pix_slot, wave,
+                                                        w.hdr, w.report);
+    }
+}
+
+void launch_induce(const DevParams &P, const Work &w, const Table &T, float *wave, int mode, int64_t n_slots,
+                   hipStream_t st) {
+    const int32_t win = P.t_r + 32;
+    if (win <= kWG) induce_rt<1>(P, w, T, wave, mode, n_slots, st);
+    else if (win <= 2 * kWG) induce_rt<2>(P, w, T, wave, mode, n_slots, st);
+    else if (win <= 4 * kWG) induce_rt<4>(P, w, T, wave, mode, n_slots, st);
+    else induce_rt<8>(P, w, T, wave, mode, n_slots, st);
+}
+
+// ================================================================================================= electronics
+// One thread per active pixel, sequential in ticks (Sec. 3.4): Q += I[n]; when no sample is pending and
+// n >= ready, a crossing happens if Q + discriminator noise >= threshold; the sample is taken at
+// max(n + hold, last + spacing) with uncorrelated noise added; ADC = clamp(floor(Q_s / q_lsb) + pedestal); the
+// integrator restarts from the reset noise at the next tick.  The discriminator draw is skipped exactly when
+// Q + |g|max * sigma_disc cannot reach the threshold.
+__global__ __launch_bounds__(kWG) void k_electronics(DevParams P, const float *__restrict__ wave,
+                                                     const int32_t *__restrict__ slot_gp,
+                                                     const uint64_t *__restrict__ ev_ids, int32_t n_ev,
+                                                     int64_t n_slots_arg,
+                                                     int32_t *pk_tick, uint16_t *pk_adc, uint8_t *pk_flag,
+                                                     int64_t *pk_cnt, DevHeader *H, double *report) {
+    const int64_t n_slots = n_slots_arg >= 0 ? n_slots_arg : H->n_slots;
+    const int NT = P.nticks;
+    for (int64_t base = (int64_t)blockIdx.x * kWG; base < n_slots; base += (int64_t)gridDim.x * kWG) {
+        const int64_t slot = base + threadIdx.x;
+        const int32_t gp = slot < n_slots ? slot_gp[slot] : -1;
+        const bool valid = gp >= 0 && gp < n_ev * P.npx;            // ids outside the event grids are skipped
+        double rowsum = 0.0;
+        int e = 0;
+        int32_t dropped = 0, over = 0;
+        if (slot < n_slots && !valid) pk_cnt[slot] = 0;
+        if (valid) {
+            e = gp / P.npx;
+            const uint32_t pid = (uint32_t)(gp - e * P.npx);
+            const uint64_t ev = ev_ids[e];
+            const float *w = wave + slot * NT;
+            float Q = 0.0f, Qc = 0.0f, absum = 0.0f;
+            if (P.sig_reset > 0.0f) Q = P.sig_reset * noise_normal(P, pid, kTickInitial, ev, STREAM_RESET);
+            bool pending = false, uncertain = false, done = false;
+            int32_t ns = 0, ready = 0, last = -(1 << 28), cnt = 0;
+            int64_t obase = slot * P.max_packets;
+            for (int32_t n = 0; n < NT; ++n) {
+                const float x = w[n];
+                rowsum += (double)x;
+                if (done) continue;
+                {   // Kahan
+                    const float y = x - Qc;
+                    const float t = Q + y;
+                    Qc = (t - Q) - y;
+                    Q = t;
+                }
+                absum += fabsf(x);
+                const float Qv = Q - Qc;
+                if (!pending && n >= ready) {
+                    float disc = 0.0f;
+                    if (P.sig_disc > 0.0f && Qv + kNormalBound * P.sig_disc >= P.thr)
+                        disc = P.sig_disc * noise_normal(P, pid, (uint32_t)n, ev, STREAM_DISC);
+                    const float m = (Qv + disc) - P.thr;
+                    const float eps = P.eps_abs + P.eps_rel * (absum + fabsf(Qv) + P.thr);
+                    if (fabsf(m) < eps) uncertain = true;
+                    if (m >= 0.0f) {
+                        pending = true;
+                        ns = max(n + P.hold, last + P.spacing);
+                        if (ns >= NT) { ++dropped; done = true; continue; }
+                    }
+                }
+                if (pending && n == ns) {
+                    float qs = Qv;
+                    if (P.sig_unc > 0.0f) qs += P.sig_unc * noise_normal(P, pid, (uint32_t)n, ev, STREAM_SAMPLE);
+                    const float xq = __fdiv_rn(qs, P.q_lsb);
+                    const float fl = floorf(xq);
+                    int32_t code = (int32_t)fmaxf(fminf(fl, 1.0e9f), -1.0e9f) + P.pedestal;
+                    uint8_t flag = uncertain ? 2 : 0;
+                    if (code < 0) { code = 0; flag |= 4; }
+                    if (code > P.adc_max) { code = P.adc_max; flag |= 4; }
+                    const float dist = (xq - fl) * P.q_lsb;
+                    const float eps = P.eps_abs + P.eps_rel * (absum + fabsf(qs) + P.thr);
+                    if (dist < eps || P.q_lsb - dist < eps) flag |= 1;
+                    if (cnt < P.max_packets) {
+                        pk_tick[obase + cnt] = n;
+                        pk_adc[obase + cnt] = (uint16_t)code;
+                        pk_flag[obase + cnt] = flag;
+                        ++cnt;
+                    } else {
+                        ++over;
+                    }
+                    Q = 0.0f;
+                    Qc = 0.0f;
+                    if (P.sig_reset > 0.0f) Q = P.sig_reset * noise_normal(P, pid, (uint32_t)n, ev, STREAM_RESET);
+                    absum = 0.0f;
+                    pending = false;
+                    ready = n + 1;
+                    last = n;
+                }
+            }
+            pk_cnt[slot] = cnt;
+        }
+        add_report(report, e, 2, rowsum, valid);
+        if (dropped) atomicAdd((unsigned long long *)&H->dropped, (unsigned long long)dropped);
+        if (over) atomicAdd((unsigned long long *)&H->over, (unsigned long long)over);
+    }
+}
+
+void launch_electronics(const DevParams &P, const float *wave, const int32_t *slot_gp, const uint64_t *event_ids,
+                        int64_t n_slots, const Work &w, hipStream_t st) {
+    int64_t g = (n_slots + kWG - 1) / kWG;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    k_electronics<<<(unsigned)g, kWG, 0, st>>>(P, wave, slot_gp, event_ids, w.n_ev, n_slots, w.pk_tick, w.pk_adc,
+                                               w.pk_flag, w.pk_off, w.hdr, w.report);
+}
+
+__global__ void k_compact(int32_t max_packets, int64_t n_slots, const int64_t *pk_off, const int32_t *slot_gp,
+                          int32_t npx, const int32_t *pk_tick, const uint16_t *pk_adc, const uint8_t *pk_flag,
+                          int32_t *o_pixel, int32_t *o_tick, uint16_t *o_adc, uint8_t *o_flag, int64_t cap) {
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= n_slots) return;
+    const int64_t off = pk_off[slot], cnt = pk_off[slot + 1] - off;
+    const int32_t pid = slot_gp[slot] % npx;
+    for (int64_t k = 0; k < cnt && off + k < cap; ++k) {
+        const int64_t src = slot * max_packets + k;
+        o_pixel[off + k] = pid;
+        o_tick[off + k] = pk_tick[src];
+        o_adc[off + k] = pk_adc[src];
+        o_flag[off + k] = pk_flag[src];
+    }
+}
+
+__global__ void k_counts(int64_t n_slots, const int64_t *pk_off, const DevHeader *H, int64_t *counts, int64_t cap_pk,
+                         int32_t n_ev, const int64_t *ev_pix_off, int64_t *ev_pkt_off) {
+    const int64_t tot = pk_off[n_slots];
+    if (threadIdx.x == 0 && blockIdx.x == 0 && counts) {
+        counts[0] = n_slots;
+        counts[1] = tot;
+        counts[2] = H->dropped;
+        counts[3] = H->over;
+    }
+    for (int e = threadIdx.x; ev_pkt_off && ev_pix_off && e <= n_ev; e += blockDim.x) ev_pkt_off[e] = pk_off[ev_pix_off[e]];
+    (void)cap_pk;
+}
+
+void launch_compact_packets(const DevParams &P, const Work &w, int64_t n_slots, int32_t *pkt_pixel, int32_t *pkt_tick,
+                            uint16_t *pkt_adc, uint8_t *pkt_flags, int64_t cap_packets, const int64_t *ev_pix_off,
+                            int64_t *ev_pkt_off, int64_t *counts, hipStream_t st) {
+    scan_exclusive<int64_t>(w.pk_off, n_slots + 1, w.scan_tmp, st);
+    if (n_slots > 0)
+        k_compact<<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P.max_packets, n_slots, w.pk_off, w.slot_gp,
+                                                                         P.npx, w.pk_tick, w.pk_adc, w.pk_flag, pkt_pixel,
+                                                                         pkt_tick, pkt_adc, pkt_flags, cap_packets);
+    k_counts<<<1, kWG, 0, st>>>(n_slots, w.pk_off, w.hdr, counts, cap_packets, w.n_ev, ev_pix_off, ev_pkt_off);
+}
+
+// ================================================================================================= Philox test hook
+__global__ void k_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint4 c = make_uint4(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]);
+    uint4 x = philox4x32_10(c, k0, k1);
+    out[4 * i] = x.x; out[4 * i + 1] = x.y; out[4 * i + 2] = x.z; out[4 * i + 3] = x.w;
+}
+
+void launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n, hipStream_t st) {
+    if (n > 0) k_philox<<<(unsigned)((n + kWG - 1) / kWG), kWG, 0, st>>>(ctr, k0, k1, out, n);
+}
+
+}  // namespace ltsim

@@ -1,0 +1,66 @@
+// launch.hpp -- host-side launchers of the gfx950 kernels (internal interface between runtime.hip and kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+
+namespace ltsim {
+
+struct SegArrays {
+    const float *x0, *y0, *z0, *t0, *x1, *y1, *z1, *t1, *energy, *dedx;
+};
+
+// Device buffers of one pipeline invocation (owned by the context's scratch pool).
+struct Work {
+    int64_t n_seg = 0;
+    int32_t n_ev = 0;
+    const int64_t *seg_ev_off = nullptr;     // [n_ev + 1] segment ranges of the events
+    const uint64_t *event_ids = nullptr;     // [n_ev]
+    SegInfo *si = nullptr;                   // [n_seg]
+    int64_t *cell_off = nullptr;             // [n_seg + 1] counts, then exclusive offsets
+    uint64_t *pix_cnt = nullptr;             // [n_ev * npx + 1] packed (pairs | active << 40), then offsets
+    int32_t *cursor = nullptr;               // [n_ev * npx]
+    int32_t *pix_slot = nullptr;             // [n_ev * npx]
+    int32_t *slot_gp = nullptr;              // [cap_slots] global pixel index e * npx + p
+    int64_t *slot_off = nullptr;             // [cap_slots + 1] pair ranges per slot
+    int32_t *pairs_unsorted = nullptr;       // [cap_pairs]
+    int32_t *pairs = nullptr;                // [cap_pairs] segment ids, pixel-major, ascending per pixel
+    float *cells = nullptr;                  // [cap_cells]
+    int32_t *pk_tick = nullptr;              // [cap_slots * max_packets]
+    uint16_t *pk_adc = nullptr;
+    uint8_t *pk_flag = nullptr;
+    int64_t *pk_off = nullptr;               // [cap_slots + 1] counts, then exclusive offsets
+    DevHeader *hdr = nullptr;
+    double *report = nullptr;                // [5 * n_ev]
+    void *scan_tmp = nullptr;                // scan partials
+    int64_t scan_tmp_elems = 0;
+};
+
+struct Table {
+    const float *Rpad = nullptr;             // [bx * by][col_len], zero-padded columns
+    const double *prefix = nullptr;          // [bx * by][t_r + 1] FP64 prefix sums of each column
+};
+
+int64_t scan_tmp_needed(int64_t n);
+void scan_exclusive_i64(int64_t *data, int64_t n, int64_t *total_dst, void *tmp, hipStream_t st);
+void scan_exclusive_u64(uint64_t *data, int64_t n, void *tmp, hipStream_t st);
+
+void launch_quench_drift(const DevParams &P, const SegArrays &S, const Work &w, hipStream_t st);
+void launch_slots(const DevParams &P, const Work &w, int32_t *pixel_id_out, int64_t *ev_pix_off, hipStream_t st);
+void launch_fill_pairs(const DevParams &P, const Work &w, hipStream_t st);
+void launch_sort_pairs(const Work &w, int64_t n_slots_host, hipStream_t st);
+void launch_cells(const DevParams &P, const Work &w, hipStream_t st);
+void launch_induce(const DevParams &P, const Work &w, const Table &T, float *wave, int mode, int64_t n_slots_host,
+                   hipStream_t st);
+void launch_electronics(const DevParams &P, const float *wave, const int32_t *slot_gp, const uint64_t *event_ids,
+                        int64_t n_slots, const Work &w, hipStream_t st);
+void launch_compact_packets(const DevParams &P, const Work &w, int64_t n_slots, int32_t *pkt_pixel, int32_t *pkt_tick,
+                            uint16_t *pkt_adc, uint8_t *pkt_flags, int64_t cap_packets, const int64_t *ev_pix_off,
+                            int64_t *ev_pkt_off, int64_t *counts, hipStream_t st);
+void launch_stage_quench_drift(const DevParams &P, const SegArrays &S, int64_t n, float *out_f, int32_t *out_i,
+                               hipStream_t st);
+void launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n, hipStream_t st);
+
+}  // namespace ltsim

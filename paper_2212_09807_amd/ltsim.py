@@ -1,0 +1,298 @@
+"""Thin Python binding of libltsim (include/ltsim.h): argument marshalling only.
+
+Every step of the simulation runs in the library's gfx950 kernels; this module converts parameter dataclasses to
+the C structs, passes torch device pointers and the current HIP stream, and allocates output tensors of the sizes
+the library reports.  PyTorch provides device memory and streams only.  If the shared library has not been built
+the import of any entry point raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libltsim.so")
+
+LTS_REDUCE_SORTED, LTS_REDUCE_ATOMIC = 0, 1
+STATUS = {0: "LTS_OK", 1: "LTS_ERR_INVALID_ARG", 2: "LTS_ERR_CAPACITY", 3: "LTS_ERR_OOM", 4: "LTS_ERR_DEVICE",
+          5: "LTS_ERR_NOT_READY", 6: "LTS_ERR_CANCELLED", 7: "LTS_ERR_STATE"}
+REPORT_FIELDS = ("q_after_quench", "q_collected", "q_induced", "q_clipped", "q_offgrid")
+
+
+class LtsimError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class lts_physics(C.Structure):
+    _fields_ = [("recomb_model", C.c_int32)] + [(n, C.c_double) for n in (
+        "e_field", "lar_density", "w_ion", "birks_ab", "birks_kb", "box_alpha", "box_beta", "v_drift", "lifetime",
+        "d_long", "d_tran", "z_anode", "sample_step", "n_sigma")]
+
+
+class lts_readout(C.Structure):
+    _fields_ = [("pitch", C.c_double), ("n_x", C.c_int32), ("n_y", C.c_int32), ("x0", C.c_double),
+                ("y0", C.c_double), ("n_sub", C.c_int32), ("tick", C.c_double), ("n_ticks", C.c_int32),
+                ("t_begin", C.c_double)]
+
+
+class lts_electronics(C.Structure):
+    _fields_ = [("threshold", C.c_double), ("hold_ticks", C.c_int32), ("min_spacing", C.c_int32),
+                ("q_lsb", C.c_double), ("pedestal", C.c_int32), ("adc_bits", C.c_int32),
+                ("sigma_reset", C.c_double), ("sigma_disc", C.c_double), ("sigma_unc", C.c_double),
+                ("max_packets", C.c_int32), ("seed", C.c_uint64)]
+
+
+class lts_segments(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("x0", "y0", "z0", "t0", "x1", "y1", "z1", "t1", "energy", "dedx")] + [
+        ("n", C.c_int64)]
+
+
+class lts_outputs(C.Structure):
+    _fields_ = [("pixel_id", C.c_void_p), ("current", C.c_void_p), ("cap_pixels", C.c_int64),
+                ("pkt_pixel", C.c_void_p), ("pkt_tick", C.c_void_p), ("pkt_adc", C.c_void_p),
+                ("pkt_flags", C.c_void_p), ("cap_packets", C.c_int64), ("counts", C.c_void_p),
+                ("report", C.c_void_p), ("event_pixel_offsets", C.c_void_p), ("event_packet_offsets", C.c_void_p)]
+
+
+EXPORTS = ("lts_context_create", "lts_context_destroy", "lts_set_response", "lts_set_reduce_mode", "lts_plan",
+           "lts_simulate", "lts_simulate_batch", "lts_stage_quench_drift", "lts_debug_cells",
+           "lts_stage_electronics", "lts_stage_philox", "lts_status_str", "lts_last_error", "lts_version")
+
+_LIB = None
+
+
+def lib():
+    """Load libltsim.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise LtsimError(4, f"{LIB_PATH} not built: run __graft_entry__.build() or "
+                                "python paper_2212_09807_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.lts_context_create.argtypes = [C.c_int, C.POINTER(lts_physics), C.POINTER(lts_readout),
+                                         C.POINTER(lts_electronics), C.POINTER(P)]
+        L.lts_context_destroy.argtypes = [P]
+        L.lts_context_destroy.restype = None
+        L.lts_set_response.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32]
+        L.lts_set_reduce_mode.argtypes = [P, C.c_int32]
+        L.lts_plan.argtypes = [P, C.POINTER(lts_segments), C.POINTER(C.c_int64), P]
+        L.lts_simulate.argtypes = [P, C.c_uint64, C.POINTER(lts_segments), C.POINTER(lts_outputs), P]
+        L.lts_simulate_batch.argtypes = [P, C.c_int32, P, P, C.POINTER(lts_segments), C.POINTER(lts_outputs), P]
+        L.lts_stage_quench_drift.argtypes = [P, C.POINTER(lts_segments), P, P, P]
+        L.lts_debug_cells.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), P, C.c_int64]
+        L.lts_stage_electronics.argtypes = [P, C.c_uint64, P, P, C.c_int64, C.POINTER(lts_outputs), P]
+        L.lts_stage_philox.argtypes = [P, C.c_uint32, C.c_uint32, P, C.c_int64, P]
+        for f in ("lts_status_str", "lts_last_error", "lts_version"):
+            getattr(L, f).restype = C.c_char_p
+        L.lts_status_str.argtypes = [C.c_int]
+        L.lts_last_error.argtypes = [P]
+        _LIB = L
+    return _LIB
+
+
+def _fill(struct_type, obj):
+    s = struct_type()
+    for name, _ in struct_type._fields_:
+        setattr(s, name, getattr(obj, name))
+    return s
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class DeviceSegments:
+    """Segment columns as torch float32 tensors on the GPU (keeps them alive while the struct points at them)."""
+    cols: list
+    dedx: object
+    n: int
+
+    def struct(self):
+        ptrs = [c.data_ptr() for c in self.cols]
+        return lts_segments(*ptrs, self.dedx.data_ptr() if self.dedx is not None else None, self.n)
+
+
+def to_device(segs, device="cuda") -> DeviceSegments:
+    import torch
+    cols = [torch.from_numpy(np.ascontiguousarray(c, dtype=np.float32)).to(device) for c in segs.columns()]
+    dedx = None if segs.dedx is None else torch.from_numpy(np.ascontiguousarray(segs.dedx, np.float32)).to(device)
+    return DeviceSegments(cols, dedx, segs.n)
+
+
+@dataclass
+class Result:
+    pixel_id: object          # int32 [n_pixels] (torch, device)
+    current: object           # float32 [n_pixels, n_ticks]
+    pkt_pixel: object
+    pkt_tick: object
+    pkt_adc: object           # int16 storage of uint16 codes
+    pkt_flags: object
+    counts: object            # int64 [4]
+    report: object            # float64 [n_events, 5]
+    event_pixel_offsets: object = None
+    event_packet_offsets: object = None
+
+    def host(self):
+        """Copy to numpy (synchronises)."""
+        cnt = self.counts.cpu().numpy()
+        n_pix, n_pk = int(cnt[0]), int(cnt[1])
+        d = {"pixel_id": self.pixel_id[:n_pix].cpu().numpy(), "current": self.current[:n_pix].cpu().numpy(),
+             "pkt_pixel": self.pkt_pixel[:n_pk].cpu().numpy(), "pkt_tick": self.pkt_tick[:n_pk].cpu().numpy(),
+             "pkt_adc": self.pkt_adc[:n_pk].cpu().numpy().view(np.uint16),
+             "pkt_flags": self.pkt_flags[:n_pk].cpu().numpy(), "counts": cnt,
+             "report": self.report.cpu().numpy()}
+        if self.event_pixel_offsets is not None:
+            d["event_pixel_offsets"] = self.event_pixel_offsets.cpu().numpy()
+            d["event_packet_offsets"] = self.event_packet_offsets.cpu().numpy()
+        return d
+
+
+class Context:
+    """One lts_context on a device, with its response table installed."""
+
+    def __init__(self, physics, readout, electronics, table: np.ndarray, device: int = 0,
+                 reduce_mode: int = LTS_REDUCE_SORTED):
+        L = lib()
+        self.physics, self.readout, self.electronics = physics, readout, electronics
+        self._h = C.c_void_p()
+        self._ph, self._ro, self._el = (_fill(lts_physics, physics), _fill(lts_readout, readout),
+                                        _fill(lts_electronics, electronics))
+        st = L.lts_context_create(device, C.byref(self._ph), C.byref(self._ro), C.byref(self._el), C.byref(self._h))
+        if st:
+            raise LtsimError(st, "lts_context_create")
+        self.device = device
+        table = np.ascontiguousarray(table, dtype=np.float32)
+        self._check(L.lts_set_response(self._h, table.ctypes.data_as(C.c_void_p), *table.shape))
+        self.set_reduce_mode(reduce_mode)
+
+    @classmethod
+    def from_workload(cls, w, table=None, **kw):
+        from .workloads import response_table
+        if table is None:
+            table = response_table(w.table, w.readout, w.physics.v_drift)
+        return cls(w.physics, w.readout, w.electronics, table, **kw)
+
+    def _check(self, st):
+        if st:
+            raise LtsimError(st, lib().lts_last_error(self._h).decode())
+
+    def set_reduce_mode(self, mode: int):
+        self._check(lib().lts_set_reduce_mode(self._h, mode))
+
+    def close(self):
+        if self._h:
+            lib().lts_context_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ pipeline
+    def plan(self, segs: DeviceSegments, stream=None):
+        need = (C.c_int64 * 4)()
+        s = segs.struct()
+        self._check(lib().lts_plan(self._h, C.byref(s), need, _stream(stream)))
+        return {"pairs": need[0], "pixels": need[1], "cells": need[2], "packets": need[3]}
+
+    def _alloc(self, n_pixels, n_packets, n_events, batch):
+        import torch
+        dev = torch.device("cuda", self.device)
+        nt = self.readout.n_ticks
+        r = Result(torch.empty(max(n_pixels, 1), dtype=torch.int32, device=dev),
+                   torch.empty((max(n_pixels, 1), nt), dtype=torch.float32, device=dev),
+                   torch.empty(max(n_packets, 1), dtype=torch.int32, device=dev),
+                   torch.empty(max(n_packets, 1), dtype=torch.int32, device=dev),
+                   torch.empty(max(n_packets, 1), dtype=torch.int16, device=dev),
+                   torch.empty(max(n_packets, 1), dtype=torch.uint8, device=dev),
+                   torch.zeros(4, dtype=torch.int64, device=dev),
+                   torch.zeros((n_events, 5), dtype=torch.float64, device=dev))
+        if batch:
+            r.event_pixel_offsets = torch.zeros(n_events + 1, dtype=torch.int64, device=dev)
+            r.event_packet_offsets = torch.zeros(n_events + 1, dtype=torch.int64, device=dev)
+        return r
+
+    @staticmethod
+    def _out_struct(r: Result):
+        return lts_outputs(r.pixel_id.data_ptr(), r.current.data_ptr(), r.pixel_id.numel(), r.pkt_pixel.data_ptr(),
+                           r.pkt_tick.data_ptr(), r.pkt_adc.data_ptr(), r.pkt_flags.data_ptr(), r.pkt_pixel.numel(),
+                           r.counts.data_ptr(), r.report.data_ptr(),
+                           r.event_pixel_offsets.data_ptr() if r.event_pixel_offsets is not None else None,
+                           r.event_packet_offsets.data_ptr() if r.event_packet_offsets is not None else None)
+
+    def simulate(self, segs: DeviceSegments, event_id: int = 0, stream=None, out: Optional[Result] = None) -> Result:
+        if out is None:
+            need = self.plan(segs, stream)
+            out = self._alloc(need["pixels"], need["packets"], 1, False)
+        s = segs.struct()
+        o = self._out_struct(out)
+        self._check(lib().lts_simulate(self._h, event_id, C.byref(s), C.byref(o), _stream(stream)))
+        return out
+
+    def simulate_batch(self, segs: DeviceSegments, seg_offsets: Sequence[int], event_ids: Sequence[int],
+                       stream=None, out: Optional[Result] = None, cap_pixels=None, cap_packets=None) -> Result:
+        n_ev = len(event_ids)
+        offs = np.ascontiguousarray(seg_offsets, dtype=np.int64)
+        ids = np.ascontiguousarray(event_ids, dtype=np.uint64)
+        assert offs.shape == (n_ev + 1,)
+        if out is None:
+            cp = cap_pixels if cap_pixels is not None else n_ev * self.readout.n_x * self.readout.n_y
+            out = self._alloc(cp, cap_packets if cap_packets is not None else cp * self.electronics.max_packets,
+                              n_ev, True)
+        s = segs.struct()
+        o = self._out_struct(out)
+        self._check(lib().lts_simulate_batch(self._h, n_ev, ids.ctypes.data_as(C.c_void_p),
+                                             offs.ctypes.data_as(C.c_void_p), C.byref(s), C.byref(o), _stream(stream)))
+        return out
+
+    # ------------------------------------------------------------------ stages
+    def stage_quench_drift(self, segs: DeviceSegments, stream=None):
+        import torch
+        dev = torch.device("cuda", self.device)
+        f = torch.empty((segs.n, 6), dtype=torch.float32, device=dev)
+        i = torch.empty((segs.n, 2), dtype=torch.int32, device=dev)
+        s = segs.struct()
+        self._check(lib().lts_stage_quench_drift(self._h, C.byref(s), _ptr(f), _ptr(i), _stream(stream)))
+        return f, i
+
+    def debug_cells(self, segment: int):
+        box = (C.c_int64 * 6)()
+        self._check(lib().lts_debug_cells(self._h, segment, box, None, 0))
+        b = tuple(int(x) for x in box)
+        cells = np.zeros(b[1] * b[3] * b[5], np.float32)
+        self._check(lib().lts_debug_cells(self._h, segment, box, cells.ctypes.data_as(C.c_void_p), cells.size))
+        return b, cells.reshape(b[1], b[3], b[5])
+
+    def stage_electronics(self, event_id: int, pixel_ids, current, stream=None) -> Result:
+        n = int(pixel_ids.numel())
+        out = self._alloc(n, n * self.electronics.max_packets, 1, False)
+        o = self._out_struct(out)
+        self._check(lib().lts_stage_electronics(self._h, event_id, _ptr(pixel_ids), _ptr(current), n, C.byref(o),
+                                                _stream(stream)))
+        return out
+
+
+def philox(ctr, k0: int, k1: int, stream=None):
+    """Raw Philox4x32-10 blocks on the GPU: ctr int32 tensor [n, 4] (bit pattern of uint32) -> int32 [n, 4]."""
+    import torch
+    out = torch.empty_like(ctr)
+    st = lib().lts_stage_philox(_ptr(ctr), k0, k1, _ptr(out), ctr.shape[0], _stream(stream))
+    if st:
+        raise LtsimError(st, "lts_stage_philox")
+    return out

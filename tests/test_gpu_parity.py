@@ -1,0 +1,336 @@
+"""HIP path vs the FP64 oracle, through the C ABI (needs an MI355X).
+
+Bars (per output):
+  * currents: per-pixel relative L2 error e_p = ||I_gpu - I_orc||_2 / max(||I_orc||_2, 10 e-) <= 1e-4;
+  * integer / index work (sample-point counts, Philox words, pixel sets, hand-traced packets): bit-exact;
+  * packets: tick and ADC code bit-exact, except where the oracle flags a decision within the FP32 error margin
+    (ADC value near an LSB boundary, or the pixel's timeline after a near-threshold decision);
+  * charge report: FP64 sums within the FP32 accumulation error.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2212_09807_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+TOL_WAVE = 1e-4
+EPS_REL, EPS_ABS = 2e-6, 0.1      # decision margin (electrons) within which FP32 and FP64 may legitimately differ
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a visible MI355X"
+    return t
+
+
+@pytest.fixture(scope="module")
+def lt(torch):
+    from paper_2212_09807_amd import ltsim
+    ltsim.lib()
+    return ltsim
+
+
+def per_pixel_errors(g, o):
+    num = np.sqrt(((g - o) ** 2).sum(axis=1))
+    den = np.maximum(np.sqrt((o ** 2).sum(axis=1)), 10.0)
+    return num / den
+
+
+def run_gpu(lt, w, ev=0, mode=0, table=None):
+    ctx = lt.Context.from_workload(w, table=table, reduce_mode=mode)
+    segs = lt.to_device(w.events[ev])
+    r = ctx.simulate(segs, event_id=w.event_ids[ev])
+    h = r.host()
+    return ctx, h
+
+
+def gpu_packets_by_pixel(h):
+    out = {}
+    for p, t, a, f in zip(h["pkt_pixel"], h["pkt_tick"], h["pkt_adc"], h["pkt_flags"]):
+        out.setdefault(int(p), []).append((int(t), int(a), int(f)))
+    return out
+
+
+def compare_packets(h, pixels, orc_pk, ufrom):
+    """Return (compared, flagged, mismatches) over the oracle's pixels."""
+    gb = gpu_packets_by_pixel(h)
+    compared = flagged = 0
+    bad = []
+    for q, p in enumerate(pixels):
+        ot, oa, of = orc_pk[q]
+        uf = int(ufrom[q])
+        g = gb.get(int(p), [])
+        gt = np.array([x[0] for x in g], np.int64)
+        ga = np.array([x[1] for x in g], np.int64)
+        osel, gsel = ot < uf, gt < uf
+        flagged += int((~osel).sum())
+        if osel.sum() != gsel.sum() or np.any(ot[osel] != gt[gsel]):
+            bad.append((int(p), "ticks", ot[osel].tolist(), gt[gsel].tolist()))
+            continue
+        chk = (of[osel] & 1) == 0
+        flagged += int((~chk).sum())
+        compared += int(chk.sum())
+        if np.any(oa[osel][chk] != ga[gsel][chk]):
+            bad.append((int(p), "adc", oa[osel].tolist(), ga[gsel].tolist()))
+    return compared, flagged, bad
+
+
+def check_event(lt, orc, w, ev=0, mode=0, table=None, full=True):
+    ctx, h = run_gpu(lt, w, ev, mode, table)
+    segs = w.events[ev]
+    r = orc.simulate(w, ev, table=table, eps_rel=EPS_REL, eps_abs=EPS_ABS)
+    opix = r["pixels"]
+    gpix = h["pixel_id"]
+    # every pixel the oracle reaches is active on the GPU; GPU-only pixels carry no current at all
+    assert np.all(np.diff(gpix) > 0)
+    pos = np.searchsorted(gpix, opix)
+    assert np.all(pos < len(gpix)) and np.array_equal(gpix[pos], opix)
+    extra = np.setdiff1d(np.arange(len(gpix)), pos)
+    assert np.all(h["current"][extra] == 0.0)
+    e = per_pixel_errors(h["current"][pos].astype(np.float64), r["wave"])
+    assert e.max() <= TOL_WAVE, (e.max(), opix[np.argmax(e)])
+    # FP64 report
+    rep_g = h["report"][0]
+    rep_o = r["report"]
+    assert rep_g[0] == pytest.approx(rep_o["q_after_quench"], rel=2e-6)
+    assert rep_g[1] == pytest.approx(rep_o["q_collected"], rel=2e-6)
+    scale = rep_o["q_collected"]
+    assert rep_g[2] == pytest.approx(rep_o["q_induced"], abs=1e-5 * scale)
+    assert rep_g[3] == pytest.approx(rep_o["q_clipped"], abs=1e-5 * scale)
+    assert rep_g[4] == pytest.approx(rep_o["q_offgrid"], abs=1e-5 * scale)
+    cmp_, flg, bad = compare_packets(h, opix, r["packets"], r["uncertain_from"])
+    assert not bad, bad[:5]
+    return h, r, e, (cmp_, flg)
+
+
+# ----------------------------------------------------------------------------------------------- Philox / stages
+
+def test_philox_known_answers_and_oracle(lt, orc, torch):
+    rows = [list(map(lambda x: int(x, 16), l.split())) for l in open(os.path.join(GOLD, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    for v in rows:
+        ctr = torch.tensor(np.array(v[:4], np.uint32).view(np.int32)[None], device="cuda")
+        out = lt.philox(ctr, v[4], v[5]).cpu().numpy().view(np.uint32)[0]
+        assert out.tolist() == v[6:]
+    rng = np.random.default_rng(3)
+    ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    k0, k1 = 0x12345678, 0x9ABCDEF0
+    out = lt.philox(torch.tensor(ctr.view(np.int32), device="cuda"), k0, k1).cpu().numpy().view(np.uint32)
+    for i in range(0, 4096, 97):
+        assert out[i].tolist() == orc.philox4x32_10(ctr[i], [k0, k1]).tolist()
+
+
+@pytest.mark.parametrize("cfg,model", [(1, 0), (2, 0), (2, 1)])
+def test_quench_drift_stage(lt, orc, torch, cfg, model):
+    w = W.make_workload(cfg)
+    w.physics.recomb_model = model
+    ctx = lt.Context.from_workload(w)
+    f, i = ctx.stage_quench_drift(lt.to_device(w.events[0]))
+    f, i = f.cpu().numpy().astype(np.float64), i.cpu().numpy()
+    o = orc.quench_drift(w.physics, w.events[0])
+    assert np.array_equal(i[:, 0], o["n_points"])                    # integer decided in FP32 on both sides
+    assert np.array_equal(i[:, 1], o["flags"])
+    for k, name in enumerate(("q_r", "q_a", "t_drift", "sigma_t", "sigma_time", "dedx")):
+        np.testing.assert_allclose(f[:, k], o[name], rtol=2e-6, atol=1e-12, err_msg=name)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_charge_cells(lt, orc, torch, cfg):
+    w = W.make_workload(cfg)
+    if cfg == 2:
+        w.events[0] = w.events[0].subset(np.arange(0, 20000, 500))
+    ctx = lt.Context.from_workload(w)
+    ctx.simulate(lt.to_device(w.events[0]))
+    torch.cuda.synchronize()
+    for s in range(0, w.events[0].n, max(1, w.events[0].n // 25)):
+        (ga0, gna, gu0, gnu, gv0, gnv), gc = ctx.debug_cells(s)
+        (oa0, ona, ou0, onu, ov0, onv), oc = orc.segment_cells(w.physics, w.readout, w.events[0], s)
+        big = np.zeros((max(ga0 + gna, oa0 + ona) - min(ga0, oa0), max(gu0 + gnu, ou0 + onu) - min(gu0, ou0),
+                        max(gv0 + gnv, ov0 + onv) - min(gv0, ov0)))
+        A, U, V = min(ga0, oa0), min(gu0, ou0), min(gv0, ov0)
+        g = big.copy()
+        g[ga0 - A:ga0 - A + gna, gu0 - U:gu0 - U + gnu, gv0 - V:gv0 - V + gnv] = gc
+        big[oa0 - A:oa0 - A + ona, ou0 - U:ou0 - U + onu, ov0 - V:ov0 - V + onv] = oc
+        assert np.abs(g - big).max() <= 2e-6 * big.sum(), s
+        assert g.sum() == pytest.approx(big.sum(), rel=2e-6)
+
+
+# ----------------------------------------------------------------------------------------------- whole events
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_cfg1_event_parity(lt, orc, torch, mode):
+    h, r, e, (cmp_, flg) = check_event(lt, orc, W.make_workload(1), mode=mode)
+    print(f"cfg1 mode={mode}: pixels {len(r['pixels'])} max e_p {e.max():.2e} p99 {np.percentile(e, 99):.2e} "
+          f"packets compared {cmp_} flagged {flg}")
+    assert cmp_ > 50
+
+
+def _ragged_workload(seed=7):
+    """Several tiles' worth of pixels in a non-square grid, a tick count that is not a multiple of 4, segments
+    leaving the grid, arriving before tick 0 and after the window, one zero-length deposit and one segment that
+    crosses the anode plane."""
+    rng = np.random.default_rng(seed)
+    w = W.config(1)
+    w.readout = W.Readout(n_x=23, n_y=17, n_ticks=777)
+    parts = []
+    for _ in range(6):
+        p0 = np.array([rng.uniform(-1.0, 11.0), rng.uniform(-1.0, 8.5), rng.uniform(0.2, 12.0)])
+        d = W.isotropic(rng)
+        n = 30
+        s = np.arange(n + 1) / n * rng.uniform(1.0, 6.0)
+        pts = p0[None] + s[:, None] * d[None]
+        pts[:, 2] = np.abs(pts[:, 2]) + 0.05
+        L = np.linalg.norm(np.diff(pts, axis=0), axis=1)
+        t0 = rng.uniform(-5.0, 30.0)
+        parts.append(W.make_segments(pts[:-1], pts[1:], W.mip_dedx(rng, n) * L, t0=t0, t1=t0))
+    parts.append(W.make_segments([[4.0, 3.0, 2.0]], [[4.0, 3.0, 2.0]], [0.02], t0=[1.0], t1=[1.0], dedx=[3.0]))
+    parts.append(W.make_segments([[5.0, 4.0, -0.05]], [[5.05, 4.02, 0.07]], [0.05], t0=[2.0], t1=[2.0]))
+    segs = W.Segments.concat(parts)
+    segs.dedx = np.where(np.isnan(segs.dedx), np.float32(0.0), segs.dedx).astype(np.float32)
+    w.events, w.event_ids = [segs], [77]
+    return w
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_ragged_multi_tile_parity(lt, orc, torch, mode):
+    h, r, e, _ = check_event(lt, orc, _ragged_workload(), mode=mode)
+    assert r["report"]["q_clipped"] != 0.0 and r["report"]["q_offgrid"] > 0.0
+
+
+def test_cfg2_full_size_sampled_pixels(lt, orc, torch):
+    """The module-scale event at full size, in the launch configuration the benchmark times; the oracle
+    recomputes a sample of pixels one by one."""
+    w = W.make_workload(2)
+    ctx, h = run_gpu(lt, w)
+    gpix, cur = h["pixel_id"], h["current"]
+    tot = np.abs(cur).sum(axis=1)
+    rng = np.random.default_rng(11)
+    pick = np.unique(np.r_[np.argsort(tot)[-4:], rng.choice(len(gpix), 4, replace=False)])
+    o_wave, _ = orc.waveforms(w.physics, w.readout, W.response_table(w.table, w.readout, w.physics.v_drift),
+                              w.events[0], gpix[pick])
+    e = per_pixel_errors(cur[pick].astype(np.float64), o_wave)
+    print("cfg2 sampled e_p:", e)
+    assert e.max() <= TOL_WAVE
+    qd = orc.quench_drift(w.physics, w.events[0])
+    rep = h["report"][0]
+    assert rep[0] == pytest.approx(qd["q_r"].sum(), rel=2e-6)
+    assert rep[1] == pytest.approx(qd["q_a"].sum(), rel=2e-6)
+    # conservation at full size: collected = induced in window + clipped + off-grid
+    assert rep[2] + rep[3] + rep[4] == pytest.approx(rep[1], rel=2e-5)
+    pk, _, uf = orc.electronics(w.electronics, w.readout, w.event_ids[0], gpix[pick], o_wave, EPS_REL, EPS_ABS,
+                                with_uncertain=True)
+    _, _, bad = compare_packets(h, gpix[pick], pk, uf)
+    assert not bad
+
+
+def test_sorted_and_atomic_agree(lt, torch):
+    w = W.make_workload(1)
+    _, a = run_gpu(lt, w, mode=0)
+    _, b = run_gpu(lt, w, mode=1)
+    assert np.array_equal(a["pixel_id"], b["pixel_id"])
+    assert per_pixel_errors(b["current"].astype(np.float64), a["current"].astype(np.float64)).max() < 1e-5
+
+
+# ----------------------------------------------------------------------------------------------- edge cases
+
+def test_empty_event(lt, torch):
+    w = W.make_workload(1)
+    w.events = [w.events[0].subset(np.arange(0))]
+    ctx = lt.Context.from_workload(w)
+    h = ctx.simulate(lt.to_device(w.events[0])).host()
+    assert h["counts"][0] == 0 and h["counts"][1] == 0 and np.all(h["report"] == 0.0)
+
+
+def test_invalid_inputs_and_capacity(lt, torch):
+    w = W.make_workload(1)
+    ctx = lt.Context.from_workload(w)
+    bad = w.events[0].subset(np.arange(5))
+    bad.x0 = bad.x0.copy()
+    bad.x0[2] = np.nan
+    with pytest.raises(lt.LtsimError) as ei:
+        ctx.simulate(lt.to_device(bad))
+    assert ei.value.status == 1
+    zl = W.make_segments([[1.0, 1.0, 1.0]], [[1.0, 1.0, 1.0]], [0.01])
+    with pytest.raises(lt.LtsimError) as ei:
+        ctx.simulate(lt.to_device(zl))
+    assert ei.value.status == 1
+    long = W.make_segments([[1.0, 1.0, 1.0]], [[1.0, 1.0, 20.0]], [40.0])
+    with pytest.raises(lt.LtsimError) as ei:
+        ctx.simulate(lt.to_device(long))
+    assert ei.value.status == 1
+    segs = lt.to_device(w.events[0])
+    need = ctx.plan(segs)
+    small = ctx._alloc(need["pixels"] - 1, need["packets"], 1, False)
+    with pytest.raises(lt.LtsimError) as ei:
+        ctx.simulate(segs, out=small)
+    assert ei.value.status == 2
+    assert int(small.counts[0].item()) == need["pixels"]
+    # the context stays usable after recoverable errors
+    h = ctx.simulate(segs).host()
+    assert h["counts"][0] == need["pixels"]
+
+
+# ----------------------------------------------------------------------------------------------- electronics
+
+def test_electronics_hand_traced(lt, orc, torch):
+    for c in json.load(open(os.path.join(GOLD, "electronics_traces.json")))["cases"]:
+        w = W.config(1)
+        w.readout = W.Readout(n_x=4, n_y=4, n_ticks=len(c["current"]))
+        w.electronics = W.Electronics(threshold=c["threshold"], hold_ticks=c["hold_ticks"],
+                                      min_spacing=c["min_spacing"], q_lsb=c["q_lsb"], pedestal=c["pedestal"],
+                                      adc_bits=c["adc_bits"], sigma_unc=0.0, max_packets=16)
+        ctx = lt.Context.from_workload(w)
+        pix = torch.tensor([5], dtype=torch.int32, device="cuda")
+        cur = torch.tensor(np.array(c["current"], np.float32)[None], device="cuda")
+        h = ctx.stage_electronics(0, pix, cur).host()
+        got = [[int(t), int(a)] for t, a in zip(h["pkt_tick"], h["pkt_adc"])]
+        assert got == c["packets"], c["name"]
+        assert int(h["counts"][2]) == c["dropped"], c["name"]
+
+
+def test_electronics_with_full_noise_vs_oracle(lt, orc, torch):
+    w = W.config(5)
+    w.readout = W.Readout(n_x=64, n_y=64, n_ticks=1500)
+    rng = np.random.default_rng(9)
+    n = 400
+    cur = np.zeros((n, 1500))
+    for q in range(n):
+        for _ in range(rng.integers(1, 5)):
+            t0, amp, wid = rng.integers(0, 1400), rng.uniform(200, 3000), rng.uniform(2, 30)
+            tt = np.arange(1500)
+            cur[q] += amp * np.exp(-0.5 * ((tt - t0) / wid) ** 2)
+    cur32 = cur.astype(np.float32)
+    pix = np.sort(rng.choice(64 * 64, n, replace=False)).astype(np.int32)
+    ctx = lt.Context.from_workload(w)
+    h = ctx.stage_electronics(123, torch.tensor(pix, device="cuda"), torch.tensor(cur32, device="cuda")).host()
+    pk, st, uf = orc.electronics(w.electronics, w.readout, 123, pix, cur32.astype(np.float64), EPS_REL, EPS_ABS,
+                                 with_uncertain=True)
+    cmp_, flg, bad = compare_packets(h, pix, pk, uf)
+    print(f"noise electronics: compared {cmp_} flagged {flg}")
+    assert not bad, bad[:3]
+    assert cmp_ > 500 and flg <= 0.01 * (cmp_ + flg)
+
+
+# ----------------------------------------------------------------------------------------------- batching
+
+def test_batch_equals_single_events(lt, torch):
+    w = W.make_workload(1, n_events=3)
+    w.events[1] = w.events[1].shifted(dt=3.0)
+    ctx = lt.Context.from_workload(w)
+    singles = [ctx.simulate(lt.to_device(s), event_id=i).host() for s, i in zip(w.events, w.event_ids)]
+    allsegs = W.Segments.concat(w.events)
+    offs = np.r_[0, np.cumsum([s.n for s in w.events])]
+    b = ctx.simulate_batch(lt.to_device(allsegs), offs, w.event_ids).host()
+    po, ko = b["event_pixel_offsets"], b["event_packet_offsets"]
+    for e, s in enumerate(singles):
+        assert np.array_equal(b["pixel_id"][po[e]:po[e + 1]], s["pixel_id"])
+        assert np.array_equal(b["current"][po[e]:po[e + 1]], s["current"])          # bit-identical (sorted mode)
+        assert np.array_equal(b["pkt_tick"][ko[e]:ko[e + 1]], s["pkt_tick"])
+        assert np.array_equal(b["pkt_adc"][ko[e]:ko[e + 1]], s["pkt_adc"])
+        np.testing.assert_allclose(b["report"][e], s["report"][0], rtol=1e-12, atol=1e-9)
