@@ -1,0 +1,209 @@
+#!/usr/bin/env python
+"""Throughput of the pixelated-LArTPC charge path on one MI355X.
+
+A step is one pass of the whole path (recombination, drift, rasterisation, charge cells, induction, per-pixel sum,
+electronics, FP64 charge report) over one module-scale event: 20,000 segments from 40 tracks in a 140 x 140-pixel
+tile, 3000 ticks, 45 x 45 x 1950 response table (seeded synthetic input, see paper_2212_09807_amd.workloads).
+Inputs are resident in device memory before the timed region; each step is one lts_simulate call followed by a
+stream synchronisation (plain per-event launches), so the per-step wall times give the event latency.
+
+Printed: one JSON line with segments/s and events/s, per-event latency percentiles, the induction kernel's roofline
+position (its duration measured with HIP events on the launch stream during the timed steps, its multiply-adds
+counted exactly by the library), and the FP64 CPU oracle timed on a bounded sample of the same event.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz; one FP32 FMA (2 flops) per lane per clock without packed-FP32
+# instructions (which this build does not emit).
+PEAK_FP32_FMA_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The oracle as it stands, on the first S segments of the same event (all pixels they reach, full window,
+    electronics); S grows until the run takes about budget_s."""
+    import oracle
+    from paper_2212_09807_amd import workloads as W
+    oracle.build(force=False)
+    table = W.response_table(w.table, w.readout, w.physics.v_drift)
+    full = w.events[0]
+    S, dt = 8, 0.0
+    while True:
+        sub = full.subset(list(range(S)))
+        t0 = time.perf_counter()
+        pix = oracle.active_pixels(w.physics, w.readout, w.table, sub)
+        wave, _ = oracle.waveforms(w.physics, w.readout, table, sub, pix)
+        oracle.electronics(w.electronics, w.readout, w.event_ids[0], pix, wave)
+        dt = time.perf_counter() - t0
+        if dt >= budget_s / 3 or S >= full.n:
+            break
+        S = min(full.n, int(S * max(2.0, budget_s / max(dt, 1e-3) * 0.5)))
+    return {"value": S / dt, "unit": "segments/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {S} of {full.n} segments of the module-scale event, all {len(pix)} pixels they reach, "
+                      f"3000 ticks, induction + electronics, FP64, {dt:.1f} s"}
+
+
+def batched_vs_plain(ltsim, W, n_events, mode):
+    """The first n_events of the batched-spill workload: one lts_simulate_batch call vs one lts_simulate per event,
+    same results; events/s of each (one untimed pass of each first)."""
+    import numpy as np
+    import torch
+    w = W.make_workload(3, n_events=n_events)
+    ctx = ltsim.Context.from_workload(w, reduce_mode=mode)
+    allsegs = W.Segments.concat(w.events)
+    offs = np.r_[0, np.cumsum([e.n for e in w.events])]
+    dsegs = ltsim.to_device(allsegs)
+    singles = [ltsim.to_device(e) for e in w.events]
+    outs = [ctx._alloc(ctx.plan(d)["pixels"], ctx.plan(d)["packets"], 1, False) for d in singles]
+    cap = sum(int(o.pixel_id.numel()) for o in outs)
+    bout = ctx._alloc(cap, cap * w.electronics.max_packets // 4, n_events, True)
+    res = {}
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.simulate_batch(dsegs, offs, w.event_ids, out=bout)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for d, o, i in zip(singles, outs, w.event_ids):
+            ctx.simulate(d, event_id=i, out=o)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        print(f"[bench] batched pass {rep}: batch {tb:.3f} s, plain {tp:.3f} s", file=sys.stderr, flush=True)
+    res = {"events": n_events, "segments": int(allsegs.n), "batched_events_per_s": n_events / tb,
+           "plain_events_per_s": n_events / tp, "batched_segments_per_s": allsegs.n / tb,
+           "plain_segments_per_s": allsegs.n / tp, "gain": tp / tb}
+    return res
+
+
+def served(ltsim, W, rate_hz, n_events, mode, lanes=2):
+    """Poisson arrivals at rate_hz of the batched-spill event mix through the library's request loop."""
+    import numpy as np
+    w = W.make_workload(4, n_events=n_events)
+    arr = W.poisson_arrivals(rate_hz, n_events)
+    ctx = ltsim.Context.from_workload(w, reduce_mode=mode)
+    srv = ltsim.Server(ctx, n_lanes=lanes, max_batch_events=64)
+    try:
+        t0 = time.perf_counter()
+        tickets = []
+        for seg, eid, ta in zip(w.events, w.event_ids, arr):
+            dt = t0 + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(srv.submit(seg, eid))
+        res = [srv.wait(t) for t in tickets]
+        t1 = time.perf_counter()
+        for t in tickets:
+            srv.release(t)
+    finally:
+        srv.stop()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+    nseg = sum(e.n for e in w.events)
+    return {"rate_hz": rate_hz, "events": n_events, "events_per_s": n_events / (t1 - t0),
+            "segments_per_s": nseg / (t1 - t0), "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                                                               "p99": float(np.percentile(lat, 99) * 1e3)},
+            "mean_batch_events": float(np.mean([r["batch_events"] for r in res])), "lanes": lanes}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", choices=("sorted", "atomic"), default="sorted")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--batched", type=int, default=0, help="also compare a batch of N spill events with N plain calls")
+    ap.add_argument("--served", type=float, nargs=2, default=None, metavar=("RATE_HZ", "N"),
+                    help="also serve N spill events arriving as a Poisson process at RATE_HZ")
+    ap.add_argument("--slices", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (events shard across GPUs "
+              f"with no exchange, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2212_09807_amd import ltsim, workloads as W
+
+    w = W.make_workload(2)
+    segs_h = w.events[0]
+    mode = 0 if args.mode == "sorted" else 1
+    ctx = ltsim.Context.from_workload(w, reduce_mode=mode)
+    ctx.set_induce_slices(args.slices)
+    segs = ltsim.to_device(segs_h)
+    need = ctx.plan(segs)
+    out = ctx._alloc(need["pixels"], need["packets"], 1, False)
+    print(f"[bench] event: {segs_h.n} segments, {need['pairs']} pairs, {need['pixels']} active pixels, "
+          f"{need['cells']} cells", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        ctx.simulate(segs, event_id=w.event_ids[0], out=out)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    stats = ctx.work_stats()
+    ctx.set_timing(True)
+    ctx.get_timing()
+    lat = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        ctx.simulate(segs, event_id=w.event_ids[0], out=out)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        print(f"[bench] step {i + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    timing = ctx.get_timing()
+    ctx.set_timing(False)
+
+    ind_ms, ind_calls = timing["induce"]
+    ind_s = ind_ms / 1e3 / max(ind_calls, 1)
+    achieved = 2.0 * stats["fma"] / ind_s / 1e12
+    n_seg = segs_h.n
+    line = {
+        "metric": "segments/s",
+        "value": n_seg * args.steps / elapsed,
+        "unit": "segments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "module-scale event: 20000 segments (30 muon-like + 10 proton-like tracks), "
+                               "140x140 pixels, 3000 ticks, 45x45x1950 response table, plain per-event path",
+                   "segments_per_event": n_seg, "pairs": int(stats["pairs"]), "active_pixels": need["pixels"],
+                   "reduce": args.mode},
+        "events_per_s": args.steps / elapsed,
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
+        "stage_ms": {k: (v[0] / max(v[1], 1)) for k, v in timing.items()},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_FMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_FMA_TFLOPS, "traffic": None,
+                     "kernel": "k_induce_sorted" if args.mode == "sorted" else "k_induce_atomic",
+                     "flops_per_launch": 2.0 * stats["fma"], "launch_ms": ind_s * 1e3},
+    }
+    line["config"]["induce_slices"] = args.slices if args.mode == "sorted" else 1
+    if args.batched:
+        line["batched"] = batched_vs_plain(ltsim, W, args.batched, mode)
+    if args.served:
+        line["served"] = served(ltsim, W, args.served[0], int(args.served[1]), mode)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

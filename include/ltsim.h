@@ -150,6 +150,11 @@ lts_status lts_set_response(lts_context *ctx, const float *R_host, int32_t t_r, 
 
 lts_status lts_set_reduce_mode(lts_context *ctx, int32_t mode);
 
+/* Sorted variant only: split each pixel's induction over `slices` workgroups by the mirror-folded x-bin index of
+ * the table (default 8, one slice per XCD, so each XCD's L2 holds only its part of the table); the slices'
+ * waveforms are added in a fixed order.  1 = one workgroup per pixel. */
+lts_status lts_set_induce_slices(lts_context *ctx, int32_t slices);
+
 /* Sizing pass (synchronous on `stream`): need[4] = (segment-pixel pairs, active pixels, charge cells,
  * packet upper bound = active pixels * max_packets).  Host pointer need. */
 lts_status lts_plan(lts_context *ctx, const lts_segments *segs, int64_t need[4], void *stream);
@@ -184,8 +189,77 @@ lts_status lts_debug_cells(lts_context *ctx, int64_t segment, int64_t box[6], fl
 lts_status lts_stage_electronics(lts_context *ctx, uint64_t event_id, const int32_t *pixel_ids, const float *current,
                                  int64_t n_pix, const lts_outputs *out, void *stream);
 
+/* Algorithmic work of the last lts_simulate / lts_simulate_batch / lts_plan call on this context (synchronous):
+ * out[0] (segment, pixel) pairs; out[1] products c[a,u,v] * R[k,i,j] of eq. (current) that land in the tick
+ * window, summed over pairs (the multiply-adds of the induction); out[2] charge cells in reach summed over pairs;
+ * out[3] charge cells of all segments. */
+lts_status lts_work_stats(lts_context *ctx, double out[4]);
+
 /* Raw Philox4x32-10 blocks: ctr[n*4] (device) with key (k0, k1) -> out[n*4] (device). */
 lts_status lts_stage_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n, void *stream);
+
+/* ---- serving ----------------------------------------------------------------------------------------------
+ * A request loop with continuous batching: submitted events (segments in HOST memory, copied at submit) wait in a
+ * queue; each of n_lanes worker lanes (own HIP stream, own scratch pool and device buffers, the response table of
+ * the parent context) repeatedly takes every waiting event that fits its admission budget (at most
+ * max_batch_events events, max_batch_segments segments and an estimated mem_budget_bytes / n_lanes bytes of
+ * device memory) and runs them as one batch (lts_simulate_batch), so events that arrive while other batches are on
+ * the GPU are admitted as soon as a lane frees up, and the lanes' work overlaps on the device.  Results are copied
+ * back to host memory owned by the server until lts_server_release.  Thread-safe. */
+typedef struct lts_server lts_server;
+
+typedef struct lts_server_cfg {
+    int32_t n_lanes;              /* concurrent batches in flight (>= 1; default 2 if 0) */
+    int32_t max_batch_events;     /* events per batch (default 64 if 0) */
+    int64_t max_batch_segments;   /* segments per batch (default 4,000,000 if 0) */
+    int64_t mem_budget_bytes;     /* device-memory budget for all lanes (default 32 GiB if 0) */
+    int32_t return_currents;      /* copy per-pixel currents back (otherwise only pixel ids, packets, report) */
+} lts_server_cfg;
+
+typedef struct lts_result_view {  /* host memory owned by the server, valid until lts_server_release */
+    uint64_t event_id;
+    int32_t status;               /* lts_status of the event's batch */
+    int64_t n_pixels, n_packets;
+    const int32_t *pixel_id;      /* [n_pixels] */
+    const float *current;         /* [n_pixels * n_ticks] or NULL if return_currents == 0 */
+    const int32_t *pkt_pixel, *pkt_tick;
+    const uint16_t *pkt_adc;
+    const uint8_t *pkt_flags;
+    double report[5];
+    int64_t counts[4];
+    double t_submit, t_start, t_done;   /* seconds on a monotonic clock: submission, batch launch, completion */
+    int32_t batch_events;         /* events in the batch that carried this one */
+} lts_result_view;
+
+/* Start a server for the parameters and response table of ctx (the server creates its own lane contexts; ctx
+ * stays usable and must outlive nothing of the server). */
+lts_status lts_server_start(lts_context *ctx, const lts_server_cfg *cfg, lts_server **out);
+/* Copy an event's host segment table and queue it; *ticket identifies it. */
+lts_status lts_server_submit(lts_server *srv, uint64_t event_id, const lts_segments *host_segs, uint64_t *ticket);
+/* LTS_ERR_NOT_READY until the ticket's batch has finished; then LTS_OK (or the batch's error) and a view. */
+lts_status lts_server_poll(lts_server *srv, uint64_t ticket, lts_result_view *out);
+/* Like poll, but blocks up to timeout_s seconds (< 0: forever). */
+lts_status lts_server_wait(lts_server *srv, uint64_t ticket, lts_result_view *out, double timeout_s);
+/* Free a finished ticket's host results. */
+lts_status lts_server_release(lts_server *srv, uint64_t ticket);
+/* Cancel queued tickets (their poll returns LTS_ERR_CANCELLED), finish in-flight batches, free everything. */
+lts_status lts_server_stop(lts_server *srv);
+
+/* ---- stage timing --------------------------------------------------------------------------------------
+ * When enabled, the library records HIP events on the caller's stream around each stage group of every
+ * pipeline call.  lts_get_timing waits for the recorded events, returns the summed elapsed milliseconds and the
+ * number of timed calls per stage since the previous lts_get_timing, and resets them.  Host arrays of
+ * LTS_N_STAGES entries; calls may be NULL. */
+enum {
+    LTS_STAGE_QUENCH_DRIFT = 0,   /* recombination, drift, charge boxes, pair counts, scans (Sec. 3.1-3.2) */
+    LTS_STAGE_RASTERIZE = 1,      /* active-pixel compaction, pair lists, per-pixel ordering */
+    LTS_STAGE_CELLS = 2,          /* diffused charge cells per segment (Sec. 3.3.2, eq. (rho)) */
+    LTS_STAGE_INDUCE = 3,         /* induced current and per-pixel sum (Sec. 3.3.2 eq. (current), Sec. 3.4) */
+    LTS_STAGE_ELECTRONICS = 4,    /* front end, packets and the FP64 current sum (Sec. 3.4) */
+    LTS_N_STAGES = 5
+};
+lts_status lts_set_timing(lts_context *ctx, int32_t enabled);
+lts_status lts_get_timing(lts_context *ctx, double ms[LTS_N_STAGES], int64_t calls[LTS_N_STAGES]);
 
 const char *lts_status_str(lts_status s);
 const char *lts_last_error(const lts_context *ctx);

@@ -13,6 +13,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # no implicit multiply-add fusion: the error-free transformations (two-sum, product error terms) that keep
+    # coordinates exact relative to the sub-pixel / tick grid must round exactly as written; every intended FMA
+    # in the kernels is an explicit fmaf
+    "-ffp-contract=off",
     "-Wall", "-Wextra", "-Wno-unused-parameter",
     # no packed-FP32 instructions (v_pk_fma_f32 and friends) anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1,6 +1,7 @@
 // device.hpp -- types and device helpers shared by the gfx950 kernels of libltsim.
 //
-// Precision scheme: all bulk arithmetic is FP32.  Coordinates are never used in absolute FP32 form where a
+// Precision scheme: all bulk arithmetic is FP32.  The library is compiled with -ffp-contract=off; multiply-adds
+// that should be fused are written as fmaf.  Coordinates are never used in absolute FP32 form where a
 // rounding of the absolute value would move charge relative to the sub-pixel or tick grid: each segment gets an
 // integer reference bin / tick and an FP32 offset from it, computed once per segment with error-free
 // transformations (two-sum / two-product on FP32 hi/lo pairs), so that offsets are accurate to ~1e-9 cm and

@@ -359,10 +359,12 @@ void launch_slots(const DevParams &P, const Work &w, int32_t *pixel_id_out, int6
         k_event_pixel_offsets<<<(w.n_ev + 1 + kWG - 1) / kWG, kWG, 0, st>>>(w.n_ev, P.npx, w.pix_cnt, ev_pix_off);
 }
 
-__global__ __launch_bounds__(kWG) void k_fill_pairs(DevParams P, const SegInfo *si, int64_t n_seg, const uint64_t *pix_off,
-                                                    int32_t *cursor, int32_t *pairs) {
+// Also stores each segment's scanned charge-cell offset in its record (the scan runs after k_quench_drift).
+__global__ __launch_bounds__(kWG) void k_fill_pairs(DevParams P, SegInfo *si, int64_t n_seg, const int64_t *cell_off,
+                                                    const uint64_t *pix_off, int32_t *cursor, int32_t *pairs) {
     int64_t s = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (s >= n_seg) return;
+    si[s].cell_off = cell_off[s];
     const SegInfo &g = si[s];
     const int64_t base = (int64_t)g.event * P.npx;
     for (int32_t iy = g.iy0; iy <= g.iy1; ++iy)
@@ -375,8 +377,8 @@ __global__ __launch_bounds__(kWG) void k_fill_pairs(DevParams P, const SegInfo *
 
 void launch_fill_pairs(const DevParams &P, const Work &w, hipStream_t st) {
     if (w.n_seg > 0)
-        k_fill_pairs<<<(unsigned)((w.n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.n_seg, w.pix_cnt, w.cursor,
-                                                                          w.pairs_unsorted);
+        k_fill_pairs<<<(unsigned)((w.n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.n_seg, w.cell_off, w.pix_cnt,
+                                                                          w.cursor, w.pairs_unsorted);
 }
 
 // Each pixel's segment list in ascending segment id (ids are unique within a list): rank = number of smaller ids.
@@ -700,6 +702,127 @@ __global__ __launch_bounds__(kWG) void k_induce_atomic(DevParams P, const SegInf
     }
 }
 
+// XCD-sliced sorted variant: workgroup b handles pixel slot slot0 + b / NS and slice x = b % NS of the
+// mirror-folded x-bin index (table bins i in [x*bx/NS, (x+1)*bx/NS)).  Workgroups are dispatched to the 8 XCDs
+// round-robin by id, so each XCD's L2 only ever holds its slice of the field-response table.  The pixel's per-slice
+// waveform (Kahan over its segments in ascending order) goes to part[x][slot - slot0][tick]; k_sum_slices adds the
+// slices in a fixed order.  Deterministic and batch-invariant like the unsliced kernel.
+template <int RT>
+__global__ __launch_bounds__(kWG) void k_induce_slices(DevParams P, int32_t NS, int64_t slot0, int64_t chunk,
+                                                       const SegInfo *__restrict__ si, const float *__restrict__ cells,
+                                                       const float *__restrict__ Rpad, const double *__restrict__ prefix,
+                                                       const int64_t *__restrict__ slot_off,
+                                                       const int32_t *__restrict__ pairs,
+                                                       const int32_t *__restrict__ slot_gp, float *__restrict__ part,
+                                                       const DevHeader *H, double *report) {
+    extern __shared__ float sm[];
+    __shared__ double red[kWG / 64];
+    const int NT = P.nticks;
+    float *s_sum = sm, *s_cmp = sm + NT;
+    const int tid = threadIdx.x;
+    const int64_t local = blockIdx.x / NS;
+    const int32_t x = blockIdx.x - (int32_t)local * NS;
+    const int64_t slot = slot0 + local;
+    if (slot >= H->n_slots) return;
+    const int32_t ilo = x * P.bx / NS, ihi = (x + 1) * P.bx / NS - 1;
+    for (int n = tid; n < NT; n += kWG) { s_sum[n] = 0.0f; s_cmp[n] = 0.0f; }
+    const int32_t gp = slot_gp[slot];
+    const int32_t e = gp / P.npx, p = gp - e * P.npx;
+    const int32_t ix = p % P.nx, iy = p / P.nx;
+    const int32_t uc = ix * P.nsub + P.nsub / 2, vc = iy * P.nsub + P.nsub / 2;
+    const int64_t pb = slot_off[slot], pe = slot_off[slot + 1];
+    double clip = 0.0;
+    __syncthreads();
+    if (ilo <= ihi) {
+        for (int64_t q = pb; q < pe; ++q) {
+            const int32_t s = __builtin_amdgcn_readfirstlane(pairs[q]);
+            const SegInfo &g = si[s];
+            const int32_t u0 = g.u0, v0 = g.v0, a0 = g.a0, nv = g.nv, nap = g.na_pad, na = g.na;
+            const int32_t ue = u0 + g.nu - 1;
+            // fold(u - uc) in [ilo, ihi]: u - uc in [ilo, ihi] or in [-ihi-1, -ilo-1]
+            const int32_t ua0 = max(u0, uc + ilo), ua1 = min(ue, uc + ihi);
+            const int32_t ub0 = max(u0, uc - ihi - 1), ub1 = min(ue, uc - ilo - 1);
+            const int32_t vlo = max(v0, vc - P.by), vhi = min(v0 + nv - 1, vc + P.by - 1);
+            if ((ua0 > ua1 && ub0 > ub1) || vlo > vhi) continue;
+            const float *cc0 = cells + g.cell_off;
+            const int32_t wlo = a0 - (P.t_r - 1), whi = a0 + na - 1;
+            if (wlo < 0 || whi >= NT) {
+                if (ua0 <= ua1) clip += pair_clipped(P, cc0, nv, nap, na, u0, v0, a0, prefix, ua0, ua1, vlo, vhi, uc, vc);
+                if (ub0 <= ub1) clip += pair_clipped(P, cc0, nv, nap, na, u0, v0, a0, prefix, ub0, ub1, vlo, vhi, uc, vc);
+            }
+            const int32_t lo = max(wlo, 0), hi = min(whi, NT - 1);
+            for (int32_t nb0 = lo; nb0 <= hi; nb0 += kWG * RT) {
+                const int32_t nb = nb0 + tid * RT;
+                float acc[RT];
+#pragma unroll
+                for (int r = 0; r < RT; ++r) acc[r] = 0.0f;
+                if (nb <= hi) {
+                    if (ua0 <= ua1) pair_block<RT>(P, cc0, nv, nap, u0, v0, a0, Rpad, ua0, ua1, vlo, vhi, uc, vc, nb, acc);
+                    if (ub0 <= ub1) pair_block<RT>(P, cc0, nv, nap, u0, v0, a0, Rpad, ub0, ub1, vlo, vhi, uc, vc, nb, acc);
+                }
+#pragma unroll
+                for (int r = 0; r < RT; ++r) {
+                    const int32_t n = nb + r;
+                    if (n <= hi) {
+                        const float y = acc[r] - s_cmp[n];
+                        const float t = s_sum[n] + y;
+                        s_cmp[n] = (t - s_sum[n]) - y;
+                        s_sum[n] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    float *prow = part + ((int64_t)x * chunk + local) * NT;
+    for (int n = tid; n < NT; n += kWG) prow[n] = s_sum[n] - s_cmp[n];
+    const double c = block_sum_double(clip, red);
+    if (tid == 0 && c != 0.0) atomicAdd(&report[(int64_t)e * 5 + 3], c);
+}
+
+// current[slot][n] = sum over slices x = 0..NS-1 (in that order, Kahan) of part[x][slot - slot0][n].
+__global__ __launch_bounds__(kWG) void k_sum_slices(int32_t NS, int32_t NT, int64_t slot0, int64_t chunk,
+                                                    const float *__restrict__ part, float *__restrict__ wave,
+                                                    const DevHeader *H) {
+    const int64_t n_slots = H->n_slots;
+    const int64_t nrows = min(chunk, n_slots - slot0);
+    const int64_t total = nrows * NT;
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < total; i += (int64_t)gridDim.x * kWG) {
+        float sum = 0.0f, cmp = 0.0f;
+        for (int32_t x = 0; x < NS; ++x) {
+            const float y = part[(int64_t)x * chunk * NT + i] - cmp;
+            const float t = sum + y;
+            cmp = (t - sum) - y;
+            sum = t;
+        }
+        wave[slot0 * NT + i] = sum - cmp;
+    }
+}
+
+template <int RT>
+static void induce_slices_rt(const DevParams &P, const Work &w, const Table &T, float *wave, int64_t n_slots, int32_t NS,
+                             float *part, int64_t chunk, hipStream_t st) {
+    const size_t lds = (size_t)2 * P.nticks * sizeof(float);
+    for (int64_t s0 = 0; s0 < n_slots; s0 += chunk) {
+        const int64_t rows = n_slots - s0 < chunk ? n_slots - s0 : chunk;
+        k_induce_slices<RT><<<(unsigned)(rows * NS), kWG, lds, st>>>(P, NS, s0, chunk, w.si, w.cells, T.Rpad, T.prefix,
+                                                                   w.slot_off, w.pairs, w.slot_gp, part, w.hdr, w.report);
+        int64_t g = (rows * P.nticks + kWG - 1) / kWG;
+        if (g > 16384) g = 16384;
+        k_sum_slices<<<(unsigned)g, kWG, 0, st>>>(NS, P.nticks, s0, chunk, part, wave, w.hdr);
+    }
+}
+
+void launch_induce_slices(const DevParams &P, const Work &w, const Table &T, float *wave, int64_t n_slots, int32_t NS,
+                          float *part, int64_t chunk, hipStream_t st) {
+    if (n_slots <= 0) return;
+    const int32_t win = P.t_r + 32;
+    if (win <= kWG) induce_slices_rt<1>(P, w, T, wave, n_slots, NS, part, chunk, st);
+    else if (win <= 2 * kWG) induce_slices_rt<2>(P, w, T, wave, n_slots, NS, part, chunk, st);
+    else if (win <= 4 * kWG) induce_slices_rt<4>(P, w, T, wave, n_slots, NS, part, chunk, st);
+    else induce_slices_rt<8>(P, w, T, wave, n_slots, NS, part, chunk, st);
+}
+
 template <int RT>
 static void induce_rt(const DevParams &P, const Work &w, const Table &T, float *wave, int mode, int64_t n_slots,
                       hipStream_t st) {
@@ -866,6 +989,38 @@ void launch_compact_packets(const DevParams &P, const Work &w, int64_t n_slots, 
                                                                          P.npx, w.pk_tick, w.pk_adc, w.pk_flag, pkt_pixel,
                                                                          pkt_tick, pkt_adc, pkt_flags, cap_packets);
     k_counts<<<1, kWG, 0, st>>>(n_slots, w.pk_off, w.hdr, counts, cap_packets, w.n_ev, ev_pix_off, ev_pkt_off);
+}
+
+// ================================================================================================= work statistics
+// Algorithmic work of the induction stage of the last pipeline call: for every (segment, pixel) pair, the number of
+// charge cells in the pixel's table reach and the number of (cell, tick) products that land in the tick window.
+__global__ void k_work_stats(DevParams P, const SegInfo *si, int64_t n_seg, unsigned long long *acc) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_seg) return;
+    const SegInfo g = si[s];
+    if (g.n_pairs == 0) return;
+    // kept table ticks summed over the segment's cell ticks a (independent of the pixel)
+    unsigned long long kept = 0;
+    for (int32_t a = g.a0; a < g.a0 + g.na; ++a) {
+        const int32_t lo = max(a - P.t_r + 1, 0), hi = min(a, P.nticks - 1);
+        if (hi >= lo) kept += (unsigned long long)(hi - lo + 1);
+    }
+    unsigned long long cols = 0;
+    for (int32_t iy = g.iy0; iy <= g.iy1; ++iy)
+        for (int32_t ix = g.ix0; ix <= g.ix1; ++ix) {
+            const int32_t uc = ix * P.nsub + P.nsub / 2, vc = iy * P.nsub + P.nsub / 2;
+            const int32_t nu = min(g.u0 + g.nu - 1, uc + P.bx - 1) - max(g.u0, uc - P.bx) + 1;
+            const int32_t nv = min(g.v0 + g.nv - 1, vc + P.by - 1) - max(g.v0, vc - P.by) + 1;
+            if (nu > 0 && nv > 0) cols += (unsigned long long)nu * nv;
+        }
+    atomicAdd(&acc[0], (unsigned long long)g.n_pairs);
+    atomicAdd(&acc[1], cols * kept);
+    atomicAdd(&acc[2], cols * (unsigned long long)g.na);
+    atomicAdd(&acc[3], (unsigned long long)g.nu * g.nv * g.na);
+}
+
+void launch_work_stats(const DevParams &P, const SegInfo *si, int64_t n_seg, unsigned long long *acc, hipStream_t st) {
+    if (n_seg > 0) k_work_stats<<<(unsigned)((n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, si, n_seg, acc);
 }
 
 // ================================================================================================= Philox test hook

@@ -54,6 +54,8 @@ void launch_sort_pairs(const Work &w, int64_t n_slots_host, hipStream_t st);
 void launch_cells(const DevParams &P, const Work &w, hipStream_t st);
 void launch_induce(const DevParams &P, const Work &w, const Table &T, float *wave, int mode, int64_t n_slots_host,
                    hipStream_t st);
+void launch_induce_slices(const DevParams &P, const Work &w, const Table &T, float *wave, int64_t n_slots, int32_t NS,
+                          float *part, int64_t chunk, hipStream_t st);
 void launch_electronics(const DevParams &P, const float *wave, const int32_t *slot_gp, const uint64_t *event_ids,
                         int64_t n_slots, const Work &w, hipStream_t st);
 void launch_compact_packets(const DevParams &P, const Work &w, int64_t n_slots, int32_t *pkt_pixel, int32_t *pkt_tick,
@@ -61,6 +63,7 @@ void launch_compact_packets(const DevParams &P, const Work &w, int64_t n_slots, 
                             int64_t *ev_pkt_off, int64_t *counts, hipStream_t st);
 void launch_stage_quench_drift(const DevParams &P, const SegArrays &S, int64_t n, float *out_f, int32_t *out_i,
                                hipStream_t st);
+void launch_work_stats(const DevParams &P, const SegInfo *si, int64_t n_seg, unsigned long long *acc, hipStream_t st);
 void launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n, hipStream_t st);
 
 }  // namespace ltsim

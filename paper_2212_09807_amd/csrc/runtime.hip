@@ -3,10 +3,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/ltsim.h"
@@ -30,14 +37,24 @@ struct lts_context {
     lts_readout ro{};
     lts_electronics el{};
     int32_t reduce_mode = LTS_REDUCE_SORTED;
+    int32_t induce_slices = 8;       // sorted variant: table slices (one per XCD); 1 = unsliced kernel
+    DevBuf part;                     // per-slice partial waveforms of the sliced sorted variant
     DevParams P{};
     bool has_table = false;
     DevBuf Rpad, prefix;
+    std::vector<float> table_host;   // kept to build server lanes
+    int32_t t_r = 0, b_x = 0, b_y = 0;
     // scratch pool
     DevBuf si, cell_off, pix_cnt, cursor, pix_slot, slot_gp, slot_off, pairs_u, pairs, cells, pk_tick, pk_adc,
         pk_flag, pk_off, hdr, scan_tmp, ev_off, ev_ids, report_tmp, counts_tmp;
     DevHeader *hdr_host = nullptr;   // pinned
     int64_t last_n_seg = -1;
+    // optional stage timing: HIP events recorded on the caller's stream around each stage group
+    bool timing = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending_ev;
+    std::vector<hipEvent_t> free_ev;
+    double stage_ms[LTS_N_STAGES] = {0};
+    int64_t stage_calls[LTS_N_STAGES] = {0};
     std::string err;
     lts_status sticky = LTS_OK;
 };
@@ -176,6 +193,38 @@ lts_status validate_and_derive(lts_context *c) {
 template <typename T>
 T *as(DevBuf &b) { return (T *)b.p; }
 
+hipEvent_t take_event(lts_context *c) {
+    if (!c->free_ev.empty()) {
+        hipEvent_t e = c->free_ev.back();
+        c->free_ev.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Brackets a stage group with events on the stream when timing is enabled.
+struct StageTimer {
+    lts_context *c;
+    hipStream_t st;
+    int stage;
+    hipEvent_t a = nullptr;
+    StageTimer(lts_context *c_, hipStream_t st_, int stage_) : c(c_), st(st_), stage(stage_) {
+        if (c->timing && (a = take_event(c))) (void)hipEventRecord(a, st);
+    }
+    ~StageTimer() {
+        if (!a) return;
+        hipEvent_t b = take_event(c);
+        if (!b) { c->free_ev.push_back(a); return; }
+        (void)hipEventRecord(b, st);
+        c->pending_ev.push_back({stage, {a, b}});
+    }
+};
+
 hipStream_t to_stream(void *s) { return (hipStream_t)s; }
 
 lts_status check_segments(lts_context *c, const lts_segments *s) {
@@ -233,7 +282,10 @@ lts_status run_sizing(lts_context *c, int32_t n_ev, const uint64_t *event_ids, c
     w.report = report;
     w.scan_tmp = c->scan_tmp.p;
     SegArrays S = seg_arrays(segs);
-    launch_quench_drift(c->P, S, w, st);
+    {
+        StageTimer t(c, st, LTS_STAGE_QUENCH_DRIFT);
+        launch_quench_drift(c->P, S, w, st);
+    }
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipMemcpyAsync(c->hdr_host, c->hdr.p, sizeof(DevHeader), hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
@@ -288,20 +340,36 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
     w.scan_tmp = c->scan_tmp.p;
     HIP_TRY(c, hipMemsetAsync(w.pk_off, 0, sizeof(int64_t) * (size_t)(n_slots + 1), st));
     const DevParams &P = c->P;
-    launch_slots(P, w, out->pixel_id, out->event_pixel_offsets, st);
-    launch_fill_pairs(P, w, st);
-    if (c->reduce_mode == LTS_REDUCE_SORTED) launch_sort_pairs(w, n_slots, st);
-    launch_cells(P, w, st);
+    {
+        StageTimer t(c, st, LTS_STAGE_RASTERIZE);
+        launch_slots(P, w, out->pixel_id, out->event_pixel_offsets, st);
+        launch_fill_pairs(P, w, st);
+        if (c->reduce_mode == LTS_REDUCE_SORTED) launch_sort_pairs(w, n_slots, st);
+    }
+    {
+        StageTimer t(c, st, LTS_STAGE_CELLS);
+        launch_cells(P, w, st);
+    }
     Table T{as<float>(c->Rpad), as<double>(c->prefix)};
     if (c->reduce_mode == LTS_REDUCE_ATOMIC)
         HIP_TRY(c, hipMemsetAsync(out->current, 0, sizeof(float) * (size_t)n_slots * P.nticks, st));
-    if (c->reduce_mode == LTS_REDUCE_ATOMIC) {
-        // the atomic variant walks segments, not pairs: reuse the pixel-major pair arrays only for slots
+    if (c->reduce_mode == LTS_REDUCE_SORTED && c->induce_slices > 1 && n_slots > 0) {
+        // slices of at most 1 GiB of partial waveforms at a time
+        const int64_t row_bytes = (int64_t)c->induce_slices * P.nticks * (int64_t)sizeof(float);
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_slots, (1ll << 30) / row_bytes));
+        if ((r = ensure(c, c->part, (size_t)(row_bytes * chunk)))) return r;
+        StageTimer t(c, st, LTS_STAGE_INDUCE);
+        launch_induce_slices(P, w, T, out->current, n_slots, c->induce_slices, as<float>(c->part), chunk, st);
+    } else {
+        StageTimer t(c, st, LTS_STAGE_INDUCE);
+        launch_induce(P, w, T, out->current, c->reduce_mode, n_slots, st);
     }
-    launch_induce(P, w, T, out->current, c->reduce_mode, n_slots, st);
-    launch_electronics(P, out->current, w.slot_gp, w.event_ids, n_slots, w, st);
-    launch_compact_packets(P, w, n_slots, out->pkt_pixel, out->pkt_tick, out->pkt_adc, out->pkt_flags, out->cap_packets,
-                           out->event_pixel_offsets, out->event_packet_offsets, out->counts, st);
+    {
+        StageTimer t(c, st, LTS_STAGE_ELECTRONICS);
+        launch_electronics(P, out->current, w.slot_gp, w.event_ids, n_slots, w, st);
+        launch_compact_packets(P, w, n_slots, out->pkt_pixel, out->pkt_tick, out->pkt_adc, out->pkt_flags,
+                               out->cap_packets, out->event_pixel_offsets, out->event_packet_offsets, out->counts, st);
+    }
     HIP_TRY(c, hipGetLastError());
     if (out->cap_packets < n_slots * mp) {
         int64_t cnt[4];
@@ -365,12 +433,52 @@ lts_status lts_context_create(int device, const lts_physics *physics, const lts_
 void lts_context_destroy(lts_context *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    DevBuf *bufs[] = {&c->Rpad, &c->prefix, &c->si, &c->cell_off, &c->pix_cnt, &c->cursor, &c->pix_slot, &c->slot_gp,
+    for (auto &pe : c->pending_ev) {
+        (void)hipEventDestroy(pe.second.first);
+        (void)hipEventDestroy(pe.second.second);
+    }
+    for (hipEvent_t e : c->free_ev) (void)hipEventDestroy(e);
+    DevBuf *bufs[] = {&c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off, &c->pix_cnt, &c->cursor, &c->pix_slot, &c->slot_gp,
                       &c->slot_off, &c->pairs_u, &c->pairs, &c->cells, &c->pk_tick, &c->pk_adc, &c->pk_flag,
                       &c->pk_off, &c->hdr, &c->scan_tmp, &c->ev_off, &c->ev_ids, &c->report_tmp, &c->counts_tmp};
     for (DevBuf *b : bufs) free_buf(*b);
     if (c->hdr_host) (void)hipHostFree(c->hdr_host);
     delete c;
+}
+
+lts_status lts_set_timing(lts_context *c, int32_t enabled) {
+    if (!c) return LTS_ERR_INVALID_ARG;
+    c->timing = enabled != 0;
+    return LTS_OK;
+}
+
+lts_status lts_get_timing(lts_context *c, double ms[LTS_N_STAGES], int64_t calls[LTS_N_STAGES]) {
+    if (!c || !ms) return LTS_ERR_INVALID_ARG;
+    HIP_TRY(c, hipSetDevice(c->device));
+    for (auto &pe : c->pending_ev) {
+        float t = 0.0f;
+        HIP_TRY(c, hipEventSynchronize(pe.second.second));
+        HIP_TRY(c, hipEventElapsedTime(&t, pe.second.first, pe.second.second));
+        c->stage_ms[pe.first] += t;
+        c->stage_calls[pe.first] += 1;
+        c->free_ev.push_back(pe.second.first);
+        c->free_ev.push_back(pe.second.second);
+    }
+    c->pending_ev.clear();
+    for (int i = 0; i < LTS_N_STAGES; ++i) {
+        ms[i] = c->stage_ms[i];
+        if (calls) calls[i] = c->stage_calls[i];
+        c->stage_ms[i] = 0.0;
+        c->stage_calls[i] = 0;
+    }
+    return LTS_OK;
+}
+
+lts_status lts_set_induce_slices(lts_context *c, int32_t slices) {
+    if (!c) return LTS_ERR_INVALID_ARG;
+    if (slices < 1 || slices > 64) return fail(c, LTS_ERR_INVALID_ARG, "slices must be in [1, 64]");
+    c->induce_slices = slices;
+    return LTS_OK;
 }
 
 lts_status lts_set_reduce_mode(lts_context *c, int32_t mode) {
@@ -407,6 +515,10 @@ lts_status lts_set_response(lts_context *c, const float *R, int32_t t_r, int32_t
     if ((r = ensure(c, c->prefix, sizeof(double) * pre.size()))) return r;
     HIP_TRY(c, hipMemcpy(c->Rpad.p, pad.data(), sizeof(float) * pad.size(), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->prefix.p, pre.data(), sizeof(double) * pre.size(), hipMemcpyHostToDevice));
+    c->table_host.assign(R, R + (size_t)t_r * b_x * b_y);
+    c->t_r = t_r;
+    c->b_x = b_x;
+    c->b_y = b_y;
     c->P.t_r = t_r;
     c->P.bx = b_x;
     c->P.by = b_y;
@@ -520,10 +632,401 @@ lts_status lts_stage_electronics(lts_context *c, uint64_t event_id, const int32_
     return LTS_OK;
 }
 
+lts_status lts_work_stats(lts_context *c, double out[4]) {
+    if (!c || !out) return LTS_ERR_INVALID_ARG;
+    if (c->last_n_seg < 0) return fail(c, LTS_ERR_STATE, "no pipeline call yet");
+    HIP_TRY(c, hipSetDevice(c->device));
+    lts_status r;
+    if ((r = ensure(c, c->counts_tmp, 4 * sizeof(unsigned long long)))) return r;
+    HIP_TRY(c, hipDeviceSynchronize());
+    HIP_TRY(c, hipMemset(c->counts_tmp.p, 0, 4 * sizeof(unsigned long long)));
+    launch_work_stats(c->P, as<SegInfo>(c->si), c->last_n_seg, as<unsigned long long>(c->counts_tmp), nullptr);
+    HIP_TRY(c, hipGetLastError());
+    unsigned long long h[4];
+    HIP_TRY(c, hipMemcpy(h, c->counts_tmp.p, sizeof(h), hipMemcpyDeviceToHost));
+    for (int i = 0; i < 4; ++i) out[i] = (double)h[i];
+    return LTS_OK;
+}
+
 lts_status lts_stage_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n, void *stream) {
     if (!ctr || !out || n < 0) return LTS_ERR_INVALID_ARG;
     launch_philox(ctr, k0, k1, out, n, to_stream(stream));
     return hipGetLastError() == hipSuccess ? LTS_OK : LTS_ERR_DEVICE;
+}
+
+}  // extern "C"
+
+// ================================================================================================= server
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    uint64_t ticket = 0, event_id = 0;
+    int64_t n = 0;
+    std::vector<float> cols;        // 10 columns of n floats (dedx column filled with NaN when absent)
+    double t_submit = 0.0;
+};
+
+struct Finished {
+    lts_result_view v{};
+    std::vector<int32_t> pixel_id, pkt_pixel, pkt_tick;
+    std::vector<float> current;
+    std::vector<uint16_t> pkt_adc;
+    std::vector<uint8_t> pkt_flags;
+};
+
+struct PinnedBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+bool ensure_pinned(PinnedBuf &b, size_t bytes) {
+    if (b.bytes >= bytes) return true;
+    if (b.p) (void)hipHostFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    size_t want = std::max(bytes, b.bytes * 3 / 2);
+    if (hipHostMalloc(&b.p, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    b.bytes = want;
+    return true;
+}
+
+}  // namespace
+
+struct lts_server;
+
+struct Lane {
+    lts_server *srv = nullptr;
+    lts_context *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    std::thread th;
+    DevBuf seg, pix, cur, pkp, pkt, pka, pkf, counts, report, evpix, evpkt;
+    int64_t cap_pixels = 0, cap_packets = 0;
+    PinnedBuf stage, hcounts, hevpix, hevpkt, hreport;
+};
+
+struct lts_server {
+    lts_server_cfg cfg{};
+    int device = 0;
+    int32_t n_ticks = 0;
+    std::vector<std::unique_ptr<Lane>> lanes;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> queue;
+    std::unordered_map<uint64_t, Finished *> done;
+    std::unordered_map<uint64_t, int> state;   // 0 queued, 1 running, 2 finished, 3 cancelled
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+    double bytes_per_segment = 65536.0;        // admission estimate, refined from finished batches
+};
+
+namespace {
+
+void lane_run_batch(Lane *L, std::vector<Request *> &batch) {
+    lts_server *S = L->srv;
+    lts_context *c = L->ctx;
+    const int32_t ne = (int32_t)batch.size();
+    const double t_start = now_s();
+    int64_t nseg = 0;
+    for (Request *r : batch) nseg += r->n;
+    std::vector<int64_t> offs(ne + 1, 0);
+    std::vector<uint64_t> ids(ne);
+    for (int32_t e = 0; e < ne; ++e) {
+        offs[e + 1] = offs[e] + batch[e]->n;
+        ids[e] = batch[e]->event_id;
+    }
+    lts_status st = LTS_OK;
+    const size_t colb = sizeof(float) * (size_t)std::max<int64_t>(nseg, 1);
+    if (!ensure_pinned(L->stage, 10 * colb)) st = LTS_ERR_OOM;
+    if (st == LTS_OK) st = ensure(c, L->seg, 10 * colb);
+    if (st == LTS_OK) {
+        float *h = (float *)L->stage.p;
+        for (int k = 0; k < 10; ++k)
+            for (int32_t e = 0; e < ne; ++e)
+                if (batch[e]->n)
+                    std::memcpy(h + (size_t)k * nseg + offs[e], batch[e]->cols.data() + (size_t)k * batch[e]->n,
+                                sizeof(float) * (size_t)batch[e]->n);
+        if (hipMemcpyAsync(L->seg.p, L->stage.p, 10 * colb, hipMemcpyHostToDevice, L->stream) != hipSuccess)
+            st = LTS_ERR_DEVICE;
+    }
+    float *d = (float *)L->seg.p;
+    lts_segments segs{d, d + nseg, d + 2 * nseg, d + 3 * nseg, d + 4 * nseg, d + 5 * nseg, d + 6 * nseg, d + 7 * nseg,
+                      d + 8 * nseg, d + 9 * nseg, nseg};
+    lts_outputs o{};
+    for (int attempt = 0; st == LTS_OK && attempt < 3; ++attempt) {
+        const int64_t mp = c->P.max_packets;
+        if ((st = ensure(c, L->pix, sizeof(int32_t) * (size_t)std::max<int64_t>(L->cap_pixels, 1)))) break;
+        if ((st = ensure(c, L->cur, sizeof(float) * (size_t)std::max<int64_t>(L->cap_pixels, 1) * S->n_ticks))) break;
+        L->cap_packets = std::max<int64_t>(L->cap_packets, L->cap_pixels * mp / 8 + 1024);
+        if ((st = ensure(c, L->pkp, sizeof(int32_t) * (size_t)L->cap_packets))) break;
+        if ((st = ensure(c, L->pkt, sizeof(int32_t) * (size_t)L->cap_packets))) break;
+        if ((st = ensure(c, L->pka, sizeof(uint16_t) * (size_t)L->cap_packets))) break;
+        if ((st = ensure(c, L->pkf, sizeof(uint8_t) * (size_t)L->cap_packets))) break;
+        if ((st = ensure(c, L->counts, sizeof(int64_t) * 4))) break;
+        if ((st = ensure(c, L->report, sizeof(double) * 5 * (size_t)ne))) break;
+        if ((st = ensure(c, L->evpix, sizeof(int64_t) * (size_t)(ne + 1)))) break;
+        if ((st = ensure(c, L->evpkt, sizeof(int64_t) * (size_t)(ne + 1)))) break;
+        o = lts_outputs{(int32_t *)L->pix.p, (float *)L->cur.p, L->cap_pixels, (int32_t *)L->pkp.p, (int32_t *)L->pkt.p,
+                        (uint16_t *)L->pka.p, (uint8_t *)L->pkf.p, L->cap_packets, (int64_t *)L->counts.p,
+                        (double *)L->report.p, (int64_t *)L->evpix.p, (int64_t *)L->evpkt.p};
+        st = run_pipeline(c, ne, ids.data(), offs.data(), &segs, &o, L->stream);
+        if (st != LTS_ERR_CAPACITY) break;
+        int64_t need[4] = {0, 0, 0, 0};
+        if (hipMemcpy(need, L->counts.p, sizeof(need), hipMemcpyDeviceToHost) != hipSuccess) { st = LTS_ERR_DEVICE; break; }
+        L->cap_pixels = std::max(L->cap_pixels, need[0] + need[0] / 4 + 64);
+        L->cap_packets = std::max(L->cap_packets, need[1] + need[1] / 4 + 64);
+        st = LTS_OK;
+    }
+    // results back to host
+    std::vector<Finished *> fin(ne, nullptr);
+    int64_t cnt[4] = {0, 0, 0, 0};
+    std::vector<int64_t> evpix(ne + 1, 0), evpkt(ne + 1, 0);
+    std::vector<double> rep(5 * (size_t)ne, 0.0);
+    if (st == LTS_OK) {
+        if (hipMemcpyAsync(cnt, L->counts.p, sizeof(cnt), hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
+            hipMemcpyAsync(evpix.data(), L->evpix.p, sizeof(int64_t) * (ne + 1), hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
+            hipMemcpyAsync(evpkt.data(), L->evpkt.p, sizeof(int64_t) * (ne + 1), hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
+            hipMemcpyAsync(rep.data(), L->report.p, sizeof(double) * 5 * ne, hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
+            hipStreamSynchronize(L->stream) != hipSuccess)
+            st = LTS_ERR_DEVICE;
+    }
+    for (int32_t e = 0; e < ne; ++e) {
+        Finished *f = new Finished();
+        fin[e] = f;
+        f->v.event_id = batch[e]->event_id;
+        f->v.t_submit = batch[e]->t_submit;
+        f->v.t_start = t_start;
+        f->v.batch_events = ne;
+        if (st == LTS_OK) {
+            const int64_t p0 = evpix[e], p1 = evpix[e + 1], k0 = evpkt[e], k1 = evpkt[e + 1];
+            f->pixel_id.resize(p1 - p0);
+            f->pkt_pixel.resize(k1 - k0);
+            f->pkt_tick.resize(k1 - k0);
+            f->pkt_adc.resize(k1 - k0);
+            f->pkt_flags.resize(k1 - k0);
+            bool ok = hipMemcpy(f->pixel_id.data(), (int32_t *)L->pix.p + p0, sizeof(int32_t) * (p1 - p0), hipMemcpyDeviceToHost) == hipSuccess &&
+                      hipMemcpy(f->pkt_pixel.data(), (int32_t *)L->pkp.p + k0, sizeof(int32_t) * (k1 - k0), hipMemcpyDeviceToHost) == hipSuccess &&
+                      hipMemcpy(f->pkt_tick.data(), (int32_t *)L->pkt.p + k0, sizeof(int32_t) * (k1 - k0), hipMemcpyDeviceToHost) == hipSuccess &&
+                      hipMemcpy(f->pkt_adc.data(), (uint16_t *)L->pka.p + k0, sizeof(uint16_t) * (k1 - k0), hipMemcpyDeviceToHost) == hipSuccess &&
+                      hipMemcpy(f->pkt_flags.data(), (uint8_t *)L->pkf.p + k0, sizeof(uint8_t) * (k1 - k0), hipMemcpyDeviceToHost) == hipSuccess;
+            if (ok && S->cfg.return_currents) {
+                f->current.resize((size_t)(p1 - p0) * S->n_ticks);
+                ok = hipMemcpy(f->current.data(), (float *)L->cur.p + (size_t)p0 * S->n_ticks,
+                               sizeof(float) * f->current.size(), hipMemcpyDeviceToHost) == hipSuccess;
+            }
+            if (!ok) st = LTS_ERR_DEVICE;
+            f->v.n_pixels = p1 - p0;
+            f->v.n_packets = k1 - k0;
+            for (int k = 0; k < 5; ++k) f->v.report[k] = rep[5 * (size_t)e + k];
+            f->v.counts[0] = p1 - p0;
+            f->v.counts[1] = k1 - k0;
+            f->v.counts[2] = cnt[2];
+            f->v.counts[3] = cnt[3];
+        }
+        f->v.status = st;
+        f->v.pixel_id = f->pixel_id.data();
+        f->v.current = S->cfg.return_currents ? f->current.data() : nullptr;
+        f->v.pkt_pixel = f->pkt_pixel.data();
+        f->v.pkt_tick = f->pkt_tick.data();
+        f->v.pkt_adc = f->pkt_adc.data();
+        f->v.pkt_flags = f->pkt_flags.data();
+    }
+    // refine the admission estimate from the scratch actually used
+    const double used = (double)c->si.bytes + c->cells.bytes + c->pairs.bytes + c->pairs_u.bytes + L->cur.bytes +
+                        L->seg.bytes;
+    const double t_done = now_s();
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (nseg > 0) S->bytes_per_segment = std::max(0.5 * S->bytes_per_segment + 0.5 * used / nseg, 256.0);
+    for (int32_t e = 0; e < ne; ++e) {
+        fin[e]->v.t_done = t_done;
+        const uint64_t t = batch[e]->ticket;
+        auto it = S->state.find(t);
+        if (it != S->state.end()) {
+            S->done[t] = fin[e];
+            it->second = 2;
+        } else {
+            delete fin[e];
+        }
+        delete batch[e];
+    }
+    S->cv_done.notify_all();
+}
+
+void lane_loop(Lane *L) {
+    lts_server *S = L->srv;
+    (void)hipSetDevice(S->device);
+    const double budget = (double)S->cfg.mem_budget_bytes / (double)S->cfg.n_lanes;
+    for (;;) {
+        std::vector<Request *> batch;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_work.wait(lk, [&] { return S->stopping || !S->queue.empty(); });
+            if (S->stopping) return;
+            int64_t segs = 0;
+            while (!S->queue.empty() && (int32_t)batch.size() < S->cfg.max_batch_events) {
+                Request *r = S->queue.front();
+                const double est = (double)(segs + r->n) * S->bytes_per_segment;
+                if (!batch.empty() && (segs + r->n > S->cfg.max_batch_segments || est > budget)) break;
+                S->queue.pop_front();
+                S->state[r->ticket] = 1;
+                batch.push_back(r);
+                segs += r->n;
+            }
+        }
+        lane_run_batch(L, batch);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+lts_status lts_server_start(lts_context *ctx, const lts_server_cfg *cfg, lts_server **out) {
+    if (!ctx || !out) return LTS_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!ctx->has_table) return fail(ctx, LTS_ERR_STATE, "no response table: call lts_set_response first");
+    lts_server *S = new (std::nothrow) lts_server();
+    if (!S) return LTS_ERR_OOM;
+    if (cfg) S->cfg = *cfg;
+    if (S->cfg.n_lanes <= 0) S->cfg.n_lanes = 2;
+    if (S->cfg.max_batch_events <= 0) S->cfg.max_batch_events = 64;
+    if (S->cfg.max_batch_segments <= 0) S->cfg.max_batch_segments = 4000000;
+    if (S->cfg.mem_budget_bytes <= 0) S->cfg.mem_budget_bytes = 32ll << 30;
+    S->device = ctx->device;
+    S->n_ticks = ctx->ro.n_ticks;
+    for (int i = 0; i < S->cfg.n_lanes; ++i) {
+        std::unique_ptr<Lane> L(new Lane());
+        L->srv = S;
+        lts_status r = lts_context_create(ctx->device, &ctx->ph, &ctx->ro, &ctx->el, &L->ctx);
+        if (r == LTS_OK) r = lts_set_response(L->ctx, ctx->table_host.data(), ctx->t_r, ctx->b_x, ctx->b_y);
+        if (r == LTS_OK) r = lts_set_reduce_mode(L->ctx, ctx->reduce_mode);
+        if (r == LTS_OK) r = lts_set_induce_slices(L->ctx, ctx->induce_slices);
+        if (r == LTS_OK && hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess) r = LTS_ERR_DEVICE;
+        if (r != LTS_OK) {
+            if (L->ctx) lts_context_destroy(L->ctx);
+            S->stopping = true;
+            for (auto &l : S->lanes) {
+                lts_context_destroy(l->ctx);
+                (void)hipStreamDestroy(l->stream);
+            }
+            delete S;
+            return fail(ctx, r, "server lane creation failed");
+        }
+        S->lanes.push_back(std::move(L));
+    }
+    for (auto &L : S->lanes) L->th = std::thread(lane_loop, L.get());
+    *out = S;
+    return LTS_OK;
+}
+
+lts_status lts_server_submit(lts_server *S, uint64_t event_id, const lts_segments *h, uint64_t *ticket) {
+    if (!S || !h || !ticket || h->n < 0) return LTS_ERR_INVALID_ARG;
+    if (h->n > 0 && !(h->x0 && h->y0 && h->z0 && h->t0 && h->x1 && h->y1 && h->z1 && h->t1 && h->energy))
+        return LTS_ERR_INVALID_ARG;
+    Request *r = new (std::nothrow) Request();
+    if (!r) return LTS_ERR_OOM;
+    r->event_id = event_id;
+    r->n = h->n;
+    r->t_submit = now_s();
+    r->cols.resize(10 * (size_t)h->n);
+    const float *src[10] = {h->x0, h->y0, h->z0, h->t0, h->x1, h->y1, h->z1, h->t1, h->energy, h->dedx};
+    for (int k = 0; k < 10; ++k) {
+        float *dst = r->cols.data() + (size_t)k * h->n;
+        if (src[k]) std::memcpy(dst, src[k], sizeof(float) * (size_t)h->n);
+        else std::fill(dst, dst + h->n, NAN);
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stopping) {
+        delete r;
+        return LTS_ERR_STATE;
+    }
+    r->ticket = S->next_ticket++;
+    S->state[r->ticket] = 0;
+    S->queue.push_back(r);
+    *ticket = r->ticket;
+    S->cv_work.notify_one();
+    return LTS_OK;
+}
+
+static lts_status server_view(lts_server *S, uint64_t t, lts_result_view *out) {
+    auto it = S->state.find(t);
+    if (it == S->state.end()) return LTS_ERR_INVALID_ARG;
+    if (it->second == 3) return LTS_ERR_CANCELLED;
+    if (it->second != 2) return LTS_ERR_NOT_READY;
+    Finished *f = S->done[t];
+    if (out) *out = f->v;
+    return (lts_status)f->v.status;
+}
+
+lts_status lts_server_poll(lts_server *S, uint64_t t, lts_result_view *out) {
+    if (!S) return LTS_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    return server_view(S, t, out);
+}
+
+lts_status lts_server_wait(lts_server *S, uint64_t t, lts_result_view *out, double timeout_s) {
+    if (!S) return LTS_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto ready = [&] {
+        auto it = S->state.find(t);
+        return it == S->state.end() || it->second >= 2;
+    };
+    if (timeout_s < 0) S->cv_done.wait(lk, ready);
+    else S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready);
+    return server_view(S, t, out);
+}
+
+lts_status lts_server_release(lts_server *S, uint64_t t) {
+    if (!S) return LTS_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->state.find(t);
+    if (it == S->state.end()) return LTS_ERR_INVALID_ARG;
+    if (it->second < 2) return LTS_ERR_NOT_READY;
+    auto d = S->done.find(t);
+    if (d != S->done.end()) {
+        delete d->second;
+        S->done.erase(d);
+    }
+    S->state.erase(it);
+    return LTS_OK;
+}
+
+lts_status lts_server_stop(lts_server *S) {
+    if (!S) return LTS_ERR_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stopping = true;
+        for (Request *r : S->queue) {
+            S->state[r->ticket] = 3;
+            delete r;
+        }
+        S->queue.clear();
+        S->cv_work.notify_all();
+        S->cv_done.notify_all();
+    }
+    for (auto &L : S->lanes)
+        if (L->th.joinable()) L->th.join();
+    for (auto &L : S->lanes) {
+        (void)hipSetDevice(S->device);
+        (void)hipStreamSynchronize(L->stream);
+        DevBuf *bufs[] = {&L->seg, &L->pix, &L->cur, &L->pkp, &L->pkt, &L->pka, &L->pkf, &L->counts, &L->report,
+                          &L->evpix, &L->evpkt};
+        for (DevBuf *b : bufs) free_buf(*b);
+        PinnedBuf *pins[] = {&L->stage, &L->hcounts, &L->hevpix, &L->hevpkt, &L->hreport};
+        for (PinnedBuf *p : pins)
+            if (p->p) (void)hipHostFree(p->p);
+        (void)hipStreamDestroy(L->stream);
+        lts_context_destroy(L->ctx);
+    }
+    for (auto &kv : S->done) delete kv.second;
+    delete S;
+    return LTS_OK;
 }
 
 }  // extern "C"

@@ -60,8 +60,24 @@ class lts_outputs(C.Structure):
                 ("report", C.c_void_p), ("event_pixel_offsets", C.c_void_p), ("event_packet_offsets", C.c_void_p)]
 
 
-EXPORTS = ("lts_context_create", "lts_context_destroy", "lts_set_response", "lts_set_reduce_mode", "lts_plan",
-           "lts_simulate", "lts_simulate_batch", "lts_stage_quench_drift", "lts_debug_cells",
+class lts_server_cfg(C.Structure):
+    _fields_ = [("n_lanes", C.c_int32), ("max_batch_events", C.c_int32), ("max_batch_segments", C.c_int64),
+                ("mem_budget_bytes", C.c_int64), ("return_currents", C.c_int32)]
+
+
+class lts_result_view(C.Structure):
+    _fields_ = [("event_id", C.c_uint64), ("status", C.c_int32), ("n_pixels", C.c_int64), ("n_packets", C.c_int64),
+                ("pixel_id", C.c_void_p), ("current", C.c_void_p), ("pkt_pixel", C.c_void_p),
+                ("pkt_tick", C.c_void_p), ("pkt_adc", C.c_void_p), ("pkt_flags", C.c_void_p),
+                ("report", C.c_double * 5), ("counts", C.c_int64 * 4), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double), ("batch_events", C.c_int32)]
+
+
+STAGES = ("quench_drift", "rasterize", "cells", "induce", "electronics")
+
+EXPORTS = ("lts_server_start", "lts_server_submit", "lts_server_poll", "lts_server_wait", "lts_server_release",
+           "lts_server_stop", "lts_set_timing", "lts_get_timing", "lts_work_stats", "lts_context_create", "lts_context_destroy",
+           "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_plan", "lts_simulate", "lts_simulate_batch", "lts_stage_quench_drift", "lts_debug_cells",
            "lts_stage_electronics", "lts_stage_philox", "lts_status_str", "lts_last_error", "lts_version")
 
 _LIB = None
@@ -82,6 +98,7 @@ def lib():
         L.lts_context_destroy.restype = None
         L.lts_set_response.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32]
         L.lts_set_reduce_mode.argtypes = [P, C.c_int32]
+        L.lts_set_induce_slices.argtypes = [P, C.c_int32]
         L.lts_plan.argtypes = [P, C.POINTER(lts_segments), C.POINTER(C.c_int64), P]
         L.lts_simulate.argtypes = [P, C.c_uint64, C.POINTER(lts_segments), C.POINTER(lts_outputs), P]
         L.lts_simulate_batch.argtypes = [P, C.c_int32, P, P, C.POINTER(lts_segments), C.POINTER(lts_outputs), P]
@@ -89,6 +106,15 @@ def lib():
         L.lts_debug_cells.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), P, C.c_int64]
         L.lts_stage_electronics.argtypes = [P, C.c_uint64, P, P, C.c_int64, C.POINTER(lts_outputs), P]
         L.lts_stage_philox.argtypes = [P, C.c_uint32, C.c_uint32, P, C.c_int64, P]
+        L.lts_work_stats.argtypes = [P, C.POINTER(C.c_double)]
+        L.lts_server_start.argtypes = [P, C.POINTER(lts_server_cfg), C.POINTER(P)]
+        L.lts_server_submit.argtypes = [P, C.c_uint64, C.POINTER(lts_segments), C.POINTER(C.c_uint64)]
+        L.lts_server_poll.argtypes = [P, C.c_uint64, C.POINTER(lts_result_view)]
+        L.lts_server_wait.argtypes = [P, C.c_uint64, C.POINTER(lts_result_view), C.c_double]
+        L.lts_server_release.argtypes = [P, C.c_uint64]
+        L.lts_server_stop.argtypes = [P]
+        L.lts_set_timing.argtypes = [P, C.c_int32]
+        L.lts_get_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         for f in ("lts_status_str", "lts_last_error", "lts_version"):
             getattr(L, f).restype = C.c_char_p
         L.lts_status_str.argtypes = [C.c_int]
@@ -189,6 +215,25 @@ class Context:
     def _check(self, st):
         if st:
             raise LtsimError(st, lib().lts_last_error(self._h).decode())
+
+    def set_timing(self, enabled: bool):
+        self._check(lib().lts_set_timing(self._h, int(bool(enabled))))
+
+    def get_timing(self):
+        """{stage: (total ms, calls)} since the previous call (waits for the recorded events)."""
+        ms = (C.c_double * len(STAGES))()
+        calls = (C.c_int64 * len(STAGES))()
+        self._check(lib().lts_get_timing(self._h, ms, calls))
+        return {k: (ms[i], calls[i]) for i, k in enumerate(STAGES)}
+
+    def work_stats(self):
+        """Algorithmic work of the last call: pairs, induction multiply-adds, cells in reach, cells."""
+        out = (C.c_double * 4)()
+        self._check(lib().lts_work_stats(self._h, out))
+        return {"pairs": out[0], "fma": out[1], "cells_in_reach": out[2], "cells": out[3]}
+
+    def set_induce_slices(self, slices: int):
+        self._check(lib().lts_set_induce_slices(self._h, slices))
 
     def set_reduce_mode(self, mode: int):
         self._check(lib().lts_set_reduce_mode(self._h, mode))
@@ -296,3 +341,73 @@ def philox(ctr, k0: int, k1: int, stream=None):
     if st:
         raise LtsimError(st, "lts_stage_philox")
     return out
+
+
+def _arr(ptr, n, dtype):
+    if n == 0 or not ptr:
+        return np.zeros(0, dtype)
+    return np.frombuffer(C.string_at(ptr, n * np.dtype(dtype).itemsize), dtype=dtype).copy()
+
+
+class Server:
+    """Continuous-batching request loop of the library (lts_server_*): submit host events, poll / wait results."""
+
+    def __init__(self, ctx: Context, n_lanes=2, max_batch_events=64, max_batch_segments=4_000_000,
+                 mem_budget_bytes=32 << 30, return_currents=False):
+        self.ctx = ctx
+        self._h = C.c_void_p()
+        cfg = lts_server_cfg(n_lanes, max_batch_events, max_batch_segments, mem_budget_bytes, int(return_currents))
+        ctx._check(lib().lts_server_start(ctx._h, C.byref(cfg), C.byref(self._h)))
+        self.n_ticks = ctx.readout.n_ticks
+
+    def submit(self, segs, event_id: int) -> int:
+        cols = [np.ascontiguousarray(c, dtype=np.float32) for c in segs.columns()]
+        dedx = None if segs.dedx is None else np.ascontiguousarray(segs.dedx, dtype=np.float32)
+        st = lts_segments(*[c.ctypes.data for c in cols], dedx.ctypes.data if dedx is not None else None, segs.n)
+        t = C.c_uint64()
+        rc = lib().lts_server_submit(self._h, event_id, C.byref(st), C.byref(t))
+        if rc:
+            raise LtsimError(rc, "lts_server_submit")
+        return t.value
+
+    def _result(self, v):
+        d = {"event_id": v.event_id, "status": v.status, "pixel_id": _arr(v.pixel_id, v.n_pixels, np.int32),
+             "pkt_pixel": _arr(v.pkt_pixel, v.n_packets, np.int32), "pkt_tick": _arr(v.pkt_tick, v.n_packets, np.int32),
+             "pkt_adc": _arr(v.pkt_adc, v.n_packets, np.uint16), "pkt_flags": _arr(v.pkt_flags, v.n_packets, np.uint8),
+             "report": np.array(v.report[:]), "counts": np.array(v.counts[:]), "t_submit": v.t_submit,
+             "t_start": v.t_start, "t_done": v.t_done, "batch_events": v.batch_events}
+        if v.current:
+            d["current"] = _arr(v.current, v.n_pixels * self.n_ticks, np.float32).reshape(v.n_pixels, self.n_ticks)
+        return d
+
+    def poll(self, ticket: int):
+        v = lts_result_view()
+        rc = lib().lts_server_poll(self._h, ticket, C.byref(v))
+        if rc == 5:
+            return None
+        if rc:
+            raise LtsimError(rc, "lts_server_poll")
+        return self._result(v)
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        v = lts_result_view()
+        rc = lib().lts_server_wait(self._h, ticket, C.byref(v), timeout)
+        if rc:
+            raise LtsimError(rc, "lts_server_wait")
+        return self._result(v)
+
+    def release(self, ticket: int):
+        rc = lib().lts_server_release(self._h, ticket)
+        if rc:
+            raise LtsimError(rc, "lts_server_release")
+
+    def stop(self):
+        if self._h:
+            lib().lts_server_stop(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

@@ -42,8 +42,9 @@ def per_pixel_errors(g, o):
     return num / den
 
 
-def run_gpu(lt, w, ev=0, mode=0, table=None):
+def run_gpu(lt, w, ev=0, mode=0, table=None, slices=8):
     ctx = lt.Context.from_workload(w, table=table, reduce_mode=mode)
+    ctx.set_induce_slices(slices)
     segs = lt.to_device(w.events[ev])
     r = ctx.simulate(segs, event_id=w.event_ids[ev])
     h = r.host()
@@ -81,8 +82,8 @@ def compare_packets(h, pixels, orc_pk, ufrom):
     return compared, flagged, bad
 
 
-def check_event(lt, orc, w, ev=0, mode=0, table=None, full=True):
-    ctx, h = run_gpu(lt, w, ev, mode, table)
+def check_event(lt, orc, w, ev=0, mode=0, table=None, slices=8):
+    ctx, h = run_gpu(lt, w, ev, mode, table, slices)
     segs = w.events[ev]
     r = orc.simulate(w, ev, table=table, eps_rel=EPS_REL, eps_abs=EPS_ABS)
     opix = r["pixels"]
@@ -163,10 +164,10 @@ def test_charge_cells(lt, orc, torch, cfg):
 
 # ----------------------------------------------------------------------------------------------- whole events
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_cfg1_event_parity(lt, orc, torch, mode):
-    h, r, e, (cmp_, flg) = check_event(lt, orc, W.make_workload(1), mode=mode)
-    print(f"cfg1 mode={mode}: pixels {len(r['pixels'])} max e_p {e.max():.2e} p99 {np.percentile(e, 99):.2e} "
+@pytest.mark.parametrize("mode,slices", [(0, 8), (0, 1), (1, 1)])
+def test_cfg1_event_parity(lt, orc, torch, mode, slices):
+    h, r, e, (cmp_, flg) = check_event(lt, orc, W.make_workload(1), mode=mode, slices=slices)
+    print(f"cfg1 mode={mode} slices={slices}: pixels {len(r['pixels'])} max e_p {e.max():.2e} p99 {np.percentile(e, 99):.2e} "
           f"packets compared {cmp_} flagged {flg}")
     assert cmp_ > 50
 
@@ -197,9 +198,9 @@ def _ragged_workload(seed=7):
     return w
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_ragged_multi_tile_parity(lt, orc, torch, mode):
-    h, r, e, _ = check_event(lt, orc, _ragged_workload(), mode=mode)
+@pytest.mark.parametrize("mode,slices", [(0, 8), (0, 3), (1, 1)])
+def test_ragged_multi_tile_parity(lt, orc, torch, mode, slices):
+    h, r, e, _ = check_event(lt, orc, _ragged_workload(), mode=mode, slices=slices)
     assert r["report"]["q_clipped"] != 0.0 and r["report"]["q_offgrid"] > 0.0
 
 
@@ -233,8 +234,13 @@ def test_sorted_and_atomic_agree(lt, torch):
     w = W.make_workload(1)
     _, a = run_gpu(lt, w, mode=0)
     _, b = run_gpu(lt, w, mode=1)
-    assert np.array_equal(a["pixel_id"], b["pixel_id"])
+    _, c = run_gpu(lt, w, mode=0, slices=1)
+    assert np.array_equal(a["pixel_id"], b["pixel_id"]) and np.array_equal(a["pixel_id"], c["pixel_id"])
     assert per_pixel_errors(b["current"].astype(np.float64), a["current"].astype(np.float64)).max() < 1e-5
+    assert per_pixel_errors(c["current"].astype(np.float64), a["current"].astype(np.float64)).max() < 1e-5
+    # the sorted reduction is deterministic: a second run is bit-identical
+    _, a2 = run_gpu(lt, w, mode=0)
+    assert np.array_equal(a["current"], a2["current"])
 
 
 # ----------------------------------------------------------------------------------------------- edge cases
@@ -334,3 +340,29 @@ def test_batch_equals_single_events(lt, torch):
         assert np.array_equal(b["pkt_tick"][ko[e]:ko[e + 1]], s["pkt_tick"])
         assert np.array_equal(b["pkt_adc"][ko[e]:ko[e + 1]], s["pkt_adc"])
         np.testing.assert_allclose(b["report"][e], s["report"][0], rtol=1e-12, atol=1e-9)
+
+
+# ----------------------------------------------------------------------------------------------- serving
+
+def test_served_results_equal_alone(lt, torch):
+    """Events served in a mix (continuous batching over two lanes) give the same result as each event alone."""
+    w = W.make_workload(1, n_events=6)
+    for e in range(6):
+        w.events[e] = w.events[e].shifted(dt=0.5 * e)
+    ctx = lt.Context.from_workload(w)
+    alone = [ctx.simulate(lt.to_device(s), event_id=i).host() for s, i in zip(w.events, w.event_ids)]
+    srv = lt.Server(ctx, n_lanes=2, max_batch_events=4, return_currents=True)
+    try:
+        tickets = [srv.submit(s, i) for s, i in zip(w.events, w.event_ids)]
+        got = [srv.wait(t, 60.0) for t in tickets]
+        for t in tickets:
+            srv.release(t)
+    finally:
+        srv.stop()
+    assert max(g["batch_events"] for g in got) > 1          # some events really were batched together
+    for a, g in zip(alone, got):
+        assert g["status"] == 0
+        assert np.array_equal(a["pixel_id"], g["pixel_id"])
+        assert np.array_equal(a["current"], g["current"])            # deterministic sorted reduction
+        assert np.array_equal(a["pkt_tick"], g["pkt_tick"]) and np.array_equal(a["pkt_adc"], g["pkt_adc"])
+        np.testing.assert_allclose(a["report"][0], g["report"], rtol=1e-12, atol=1e-9)
