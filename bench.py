@@ -124,7 +124,7 @@ def main():
     ap.add_argument("--batched", type=int, default=0, help="also compare a batch of N spill events with N plain calls")
     ap.add_argument("--served", type=float, nargs=2, default=None, metavar=("RATE_HZ", "N"),
                     help="also serve N spill events arriving as a Poisson process at RATE_HZ")
-    ap.add_argument("--slices", type=int, default=8)
+    ap.add_argument("--slices", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (events shard across GPUs "

@@ -151,8 +151,8 @@ lts_status lts_set_response(lts_context *ctx, const float *R_host, int32_t t_r, 
 lts_status lts_set_reduce_mode(lts_context *ctx, int32_t mode);
 
 /* Sorted variant only: split each pixel's induction over `slices` workgroups by the mirror-folded x-bin index of
- * the table (default 8, one slice per XCD, so each XCD's L2 holds only its part of the table); the slices'
- * waveforms are added in a fixed order.  1 = one workgroup per pixel. */
+ * the table (e.g. 8, one slice per XCD, so each XCD's L2 holds only its part of the table); the slices'
+ * waveforms are added in a fixed order.  1 (default) = one workgroup per pixel. */
 lts_status lts_set_induce_slices(lts_context *ctx, int32_t slices);
 
 /* Sizing pass (synchronous on `stream`): need[4] = (segment-pixel pairs, active pixels, charge cells,

@@ -37,7 +37,7 @@ struct lts_context {
     lts_readout ro{};
     lts_electronics el{};
     int32_t reduce_mode = LTS_REDUCE_SORTED;
-    int32_t induce_slices = 8;       // sorted variant: table slices (one per XCD); 1 = unsliced kernel
+    int32_t induce_slices = 1;       // sorted variant: table slices (one per XCD); 1 = unsliced kernel
     DevBuf part;                     // per-slice partial waveforms of the sliced sorted variant
     DevParams P{};
     bool has_table = false;

@@ -42,7 +42,7 @@ def per_pixel_errors(g, o):
     return num / den
 
 
-def run_gpu(lt, w, ev=0, mode=0, table=None, slices=8):
+def run_gpu(lt, w, ev=0, mode=0, table=None, slices=1):
     ctx = lt.Context.from_workload(w, table=table, reduce_mode=mode)
     ctx.set_induce_slices(slices)
     segs = lt.to_device(w.events[ev])
@@ -82,7 +82,7 @@ def compare_packets(h, pixels, orc_pk, ufrom):
     return compared, flagged, bad
 
 
-def check_event(lt, orc, w, ev=0, mode=0, table=None, slices=8):
+def check_event(lt, orc, w, ev=0, mode=0, table=None, slices=1):
     ctx, h = run_gpu(lt, w, ev, mode, table, slices)
     segs = w.events[ev]
     r = orc.simulate(w, ev, table=table, eps_rel=EPS_REL, eps_abs=EPS_ABS)

@@ -37,3 +37,22 @@ def test_table_shapes():
         w = W.config(k)
         t = W.response_table(w.table, w.readout, w.physics.v_drift)
         assert t.shape == shape and t.dtype == np.float32 and t.flags.c_contiguous
+
+
+def test_large_spill_tiles_and_halo():
+    rng = np.random.default_rng(5)
+    tiles, ids = W.large_spill(rng, n_segments=20000)
+    assert len(tiles) == W.TILES_X * W.TILES_Y == len(ids)
+    total = sum(t.n for t in tiles)
+    assert total >= 20000                      # halo segments are replicated to neighbouring tiles
+    for t in tiles:
+        if t.n:
+            mx = 0.5 * (t.x0.astype(float) + t.x1)
+            assert mx.min() >= -2.4 - 1e-3 and mx.max() <= W.MODULE_W + 2.4 + 1e-3
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess, sys, os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True)
+    assert r.returncode == 2 and "one GPU" in r.stderr
