@@ -118,7 +118,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", choices=("sorted", "atomic"), default="sorted")
+    ap.add_argument("--mode", choices=("sorted", "atomic", "summed"), default="sorted")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--batched", type=int, default=0, help="also compare a batch of N spill events with N plain calls")
@@ -137,7 +137,7 @@ def main():
 
     w = W.make_workload(2)
     segs_h = w.events[0]
-    mode = 0 if args.mode == "sorted" else 1
+    mode = {"sorted": 0, "atomic": 1, "summed": 2}[args.mode]
     ctx = ltsim.Context.from_workload(w, reduce_mode=mode)
     ctx.set_induce_slices(args.slices)
     segs = ltsim.to_device(segs_h)
@@ -192,7 +192,7 @@ def main():
         "stage_ms": {k: (v[0] / max(v[1], 1)) for k, v in timing.items()},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_FMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_FMA_TFLOPS, "traffic": None,
-                     "kernel": "k_induce_sorted" if args.mode == "sorted" else "k_induce_atomic",
+                     "kernel": "k_induce_atomic" if args.mode == "atomic" else "k_induce_sorted",
                      "flops_per_launch": 2.0 * stats["fma"], "launch_ms": ind_s * 1e3},
     }
     line["config"]["induce_slices"] = args.slices if args.mode == "sorted" else 1

@@ -131,8 +131,12 @@ typedef struct lts_context lts_context;
 /* Reduction variant for the per-pixel sum over segments (Sec. 3.4):
  *   LTS_REDUCE_SORTED: pairs sorted pixel-major, one workgroup per pixel, Kahan-compensated FP32 accumulation in a
  *                      fixed segment order (deterministic, batch-invariant; default);
- *   LTS_REDUCE_ATOMIC: segment-major, per-pair currents added with FP32 atomics (order-dependent rounding). */
-enum { LTS_REDUCE_SORTED = 0, LTS_REDUCE_ATOMIC = 1 };
+ *   LTS_REDUCE_ATOMIC: segment-major, per-pair currents added with FP32 atomics (order-dependent rounding);
+ *   LTS_REDUCE_SUMMED: sum-then-convolve: eq. (current) is linear in the charge, so each sub-pixel column's charge
+ *                      is first summed over all segments (fixed order, Kahan) and each pixel then convolves the summed
+ *                      columns in its reach once; the same result without per-pair currents, with fewer
+ *                      multiply-adds where clouds of neighbouring segments overlap (deterministic). */
+enum { LTS_REDUCE_SORTED = 0, LTS_REDUCE_ATOMIC = 1, LTS_REDUCE_SUMMED = 2 };
 
 /* Create a context on HIP device `device` with copies of the parameter sets.  Validates them
  * (LTS_ERR_INVALID_ARG: non-positive v_drift / lifetime / pitch / tick / sample_step, negative diffusion,
@@ -154,6 +158,10 @@ lts_status lts_set_reduce_mode(lts_context *ctx, int32_t mode);
  * the table (e.g. 8, one slice per XCD, so each XCD's L2 holds only its part of the table); the slices'
  * waveforms are added in a fixed order.  1 (default) = one workgroup per pixel. */
 lts_status lts_set_induce_slices(lts_context *ctx, int32_t slices);
+
+/* Induction tick tile: each of the 256 threads of a workgroup computes `rt` consecutive ticks of a pair's window
+ * (1, 2, 4 or 8; 0 = the smallest that covers the table length plus a typical charge extent). */
+lts_status lts_set_ticks_per_thread(lts_context *ctx, int32_t rt);
 
 /* Sizing pass (synchronous on `stream`): need[4] = (segment-pixel pairs, active pixels, charge cells,
  * packet upper bound = active pixels * max_packets).  Host pointer need. */
@@ -191,8 +199,9 @@ lts_status lts_stage_electronics(lts_context *ctx, uint64_t event_id, const int3
 
 /* Algorithmic work of the last lts_simulate / lts_simulate_batch / lts_plan call on this context (synchronous):
  * out[0] (segment, pixel) pairs; out[1] products c[a,u,v] * R[k,i,j] of eq. (current) that land in the tick
- * window, summed over pairs (the multiply-adds of the induction); out[2] charge cells in reach summed over pairs;
- * out[3] charge cells of all segments. */
+ * window, summed over pairs (the multiply-adds of the induction; in LTS_REDUCE_SUMMED the products of summed
+ * column charges, summed over pixels); out[2] charge cells in reach summed over pairs (summed columns' ticks in
+ * reach summed over pixels in LTS_REDUCE_SUMMED); out[3] charge cells of all segments. */
 lts_status lts_work_stats(lts_context *ctx, double out[4]);
 
 /* Raw Philox4x32-10 blocks: ctr[n*4] (device) with key (k0, k1) -> out[n*4] (device). */

@@ -1,0 +1,96 @@
+"""Project autotuner for the work split of the induction stage.
+
+Candidates are the library's work-split knobs: the reduction variant (sorted with Kahan / atomic), the number of
+table slices per pixel in the sorted variant (one per XCD or fewer) and the tick tile per thread.  Each candidate
+runs the whole path on the given events (device-resident), timed with the library's stage events; the fastest
+candidate whose currents agree with the deterministic sorted reference to 1e-5 (per-pixel relative L2) wins.
+Results are cached in a JSON file keyed by the workload shape.
+"""
+from __future__ import annotations
+
+import json
+import os
+from dataclasses import asdict, dataclass
+from typing import Dict, Iterable, List, Optional
+
+import numpy as np
+
+from . import ltsim
+
+
+@dataclass(frozen=True)
+class Choice:
+    reduce_mode: int = ltsim.LTS_REDUCE_SORTED
+    slices: int = 1
+    ticks_per_thread: int = 0
+
+    def apply(self, ctx: "ltsim.Context"):
+        ctx.set_reduce_mode(self.reduce_mode)
+        ctx.set_induce_slices(self.slices)
+        ctx.set_ticks_per_thread(self.ticks_per_thread)
+
+
+DEFAULT_CANDIDATES = tuple(
+    [Choice(ltsim.LTS_REDUCE_SORTED, s, rt) for s in (1, 2, 4, 8) for rt in (0, 4)] +
+    [Choice(ltsim.LTS_REDUCE_ATOMIC, 1, rt) for rt in (0, 4)])
+
+
+def shape_key(w, n_segments: int) -> str:
+    ro, tb = w.readout, w.table
+    return f"{ro.n_x}x{ro.n_y}x{ro.n_ticks}_t{tb.t_r}x{tb.b_x}x{tb.b_y}_seg{int(np.log2(max(n_segments, 1)))}"
+
+
+def _run(ctx, dsegs, event_ids, reps):
+    import torch
+    ctx.get_timing()
+    ctx.set_timing(True)
+    outs = []
+    for _ in range(reps):
+        outs = [ctx.simulate(d, event_id=i) for d, i in zip(dsegs, event_ids)]
+    torch.cuda.synchronize()
+    t = ctx.get_timing()
+    ctx.set_timing(False)
+    total = sum(v[0] for v in t.values()) / reps
+    return total, [o.host() for o in outs]
+
+
+def autotune(w, events: Optional[List] = None, candidates: Iterable[Choice] = DEFAULT_CANDIDATES, reps: int = 2,
+             cache: Optional[str] = None, verbose: bool = False) -> Dict:
+    """Time every candidate on `events` (workload events by default) and return the best with all timings."""
+    events = events if events is not None else w.events
+    key = shape_key(w, sum(e.n for e in events) // max(len(events), 1))
+    if cache and os.path.exists(cache):
+        db = json.load(open(cache))
+        if key in db:
+            return db[key]
+    ctx = ltsim.Context.from_workload(w)
+    dsegs = [ltsim.to_device(e) for e in events]
+    ids = list(w.event_ids[: len(events)]) if w.event_ids else list(range(len(events)))
+    Choice().apply(ctx)
+    _run(ctx, dsegs, ids, 1)                                   # warm-up: allocations, table upload
+    _, ref = _run(ctx, dsegs, ids, 1)
+    results = []
+    for c in candidates:
+        c.apply(ctx)
+        _run(ctx, dsegs, ids, 1)
+        ms, out = _run(ctx, dsegs, ids, reps)
+        err = 0.0
+        for a, b in zip(ref, out):
+            if not np.array_equal(a["pixel_id"], b["pixel_id"]):
+                err = np.inf
+                break
+            g, o = b["current"].astype(np.float64), a["current"].astype(np.float64)
+            e = np.sqrt(((g - o) ** 2).sum(1)) / np.maximum(np.sqrt((o ** 2).sum(1)), 10.0)
+            err = max(err, float(e.max()) if e.size else 0.0)
+        results.append({"choice": asdict(c), "ms": ms, "max_rel_l2_vs_sorted": err})
+        if verbose:
+            print(f"[autotune] {asdict(c)}: {ms:.2f} ms, err {err:.1e}", flush=True)
+    ok = [r for r in results if r["max_rel_l2_vs_sorted"] <= 1e-5]
+    best = min(ok, key=lambda r: r["ms"])
+    res = {"key": key, "best": best, "all": results}
+    if cache:
+        db = json.load(open(cache)) if os.path.exists(cache) else {}
+        db[key] = res
+        json.dump(db, open(cache, "w"), indent=1)
+    ctx.close()
+    return res

@@ -19,6 +19,7 @@ constexpr int kBoxMax = 256;         // maximum charge-box extent in sub-pixel b
 constexpr int kAC = 8;               // cell ticks per register block in the induction inner loop
 constexpr int kRTMax = 8;            // ticks per thread in the induction inner loop (max)
 constexpr int kPad = kNaMax + kRTMax + kAC + 8;   // zero padding on each side of every table column
+static_assert(kPad >= kNaMax + 16, "the induction prefetch reads up to 16 values below a cell-tick block");
 constexpr int kMaxTicks = 16384;
 constexpr float kNormalBound = 6.7638f;  // |Box-Muller normal| <= sqrt(-2 ln 2^-33) = 6.76372 for u >= 2^-33
 
@@ -66,6 +67,7 @@ static_assert(sizeof(SegInfo) == 176, "SegInfo layout");
 struct DevHeader {
     int64_t n_pairs, n_slots, n_cells, n_packets;
     int64_t dropped, over;
+    int64_t n_colseg;                       // sum over segments of nu * nv (bound for the summed induction)
     uint32_t work[4];                       // dynamic work counters of persistent kernels
     int32_t status;                         // ST_* bits
     int32_t _pad[3];

@@ -271,6 +271,7 @@ __global__ __launch_bounds__(kWG) void k_quench_drift(DevParams P, SegArrays S, 
         si[s] = g;
         const bool skip = g.flags & (SEG_INVALID | SEG_TOO_LONG);
         cell_cnt[s] = skip ? 0 : (int64_t)g.nu * g.nv * g.na_pad;
+        if (!skip) atomicAdd((unsigned long long *)&H->n_colseg, (unsigned long long)g.nu * g.nv);
         if (g.flags & SEG_INVALID) atomicOr(&H->status, ST_INVALID);
         if (g.flags & SEG_TOO_LONG) atomicOr(&H->status, ST_TOO_LONG);
         uint64_t *pc = pix_cnt + (int64_t)e * P.npx;
@@ -546,6 +547,73 @@ __device__ __forceinline__ void pair_block(const DevParams &P, const float *__re
     }
 }
 
+// Value of lane - 1 of the wavefront (DPP wave_shr:1); lane 0 has no source lane and keeps `lane0`.
+__device__ __forceinline__ float shift_up_or(float v, float lane0) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, lane0),
+                                                                  __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ const float *uniform_ptr(const float *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const float *)(((uint64_t)hi << 32) | lo);
+}
+
+// The same product for RT = 8 with the table window shared across lanes: lane t covers ticks nb .. nb+7, so its
+// window R[K0-ac-7 .. K0-ac+7] is its own 8 values R[K0-ac .. K0-ac+7] plus 7 values owned by lane t-1; and the
+// next cell-tick block (ac + 8) needs exactly lane t-1's current 8 values.  Each lane therefore loads 8 values
+// once per column (coalesced) and afterwards receives them from the lane below; lane 0 of each wavefront loads
+// its 8 values from memory.  All 64 lanes must execute this (inactive lanes pass active = false and are given a
+// safe in-bounds base; their results are discarded, and lanes above an inactive lane are inactive too).
+__device__ __forceinline__ void pair_block_shfl(const DevParams &P, const float *__restrict__ cc0, int32_t nv, int32_t nap,
+                                                int32_t u0, int32_t v0, int32_t a0, const float *__restrict__ Rpad,
+                                                int32_t ulo, int32_t uhi, int32_t vlo, int32_t vhi, int32_t uc,
+                                                int32_t vc, int32_t nb, bool active, float (&acc)[8]) {
+    const int32_t K0 = active ? nb - a0 + P.t_r - 1 + kPad : kPad;
+    for (int32_t u = ulo; u <= uhi; ++u) {
+        const int32_t i = fold(u - uc);
+        const float *ccu = cc0 + (int64_t)(u - u0) * nv * nap;
+        for (int32_t v = vlo; v <= vhi; ++v) {
+            const int32_t j = fold(v - vc);
+            const float *col = Rpad + (int64_t)(i * P.by + j) * P.col_len + K0;
+            const float *cc = ccu + (int64_t)(v - v0) * nap;
+            // lane 0's pointer is wave-uniform: its next 8 values come through the scalar cache, one block ahead
+            const float *col0 = uniform_ptr(col);
+            float own[8], pre[8], cn[kAC];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) own[k] = col[k];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) pre[k] = col0[k - 8];
+#pragma unroll
+            for (int q = 0; q < kAC; ++q) cn[q] = cc[q];
+            for (int32_t ac = 0; ac < nap; ac += kAC) {
+                float nxt[8], cv[kAC];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) nxt[k] = shift_up_or(own[k], pre[k]);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) pre[k] = col0[k - ac - 16];          // in bounds: kPad >= kNaMax + 16
+#pragma unroll
+                for (int q = 0; q < kAC; ++q) cv[q] = cn[q];
+                if (ac + kAC < nap) {
+#pragma unroll
+                    for (int q = 0; q < kAC; ++q) cn[q] = cc[ac + kAC + q];
+                }
+                // w[m] = R[K0 - ac - 7 + m]: m < 7 from nxt[m + 1], m >= 7 from own[m - 7]
+#pragma unroll
+                for (int q = 0; q < kAC; ++q)
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) {
+                        const int m = r - q + kAC - 1;
+                        acc[r] = fmaf(cv[q], m < 7 ? nxt[m + 1] : own[m - 7], acc[r]);
+                    }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) own[k] = nxt[k];
+            }
+        }
+    }
+}
+
 // Signed induction of a pair's cells that falls outside the tick window [0, n_ticks), from FP64 prefix sums of
 // the table columns.  Threads of the workgroup split the cells; returns this thread's part.
 __device__ double pair_clipped(const DevParams &P, const float *cc0, int32_t nv, int32_t nap, int32_t na, int32_t u0,
@@ -629,7 +697,10 @@ __global__ __launch_bounds__(kWG) void k_induce_sorted(DevParams P, const SegInf
                 float acc[RT];
 #pragma unroll
                 for (int r = 0; r < RT; ++r) acc[r] = 0.0f;
-                if (nb <= hi) pair_block<RT>(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, acc);
+                if constexpr (RT == 8)
+                    pair_block_shfl(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, nb <= hi, acc);
+                else if (nb <= hi)
+                    pair_block<RT>(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, acc);
 #pragma unroll
                 for (int r = 0; r < RT; ++r) {
                     const int32_t n = nb + r;
@@ -813,14 +884,23 @@ static void induce_slices_rt(const DevParams &P, const Work &w, const Table &T, 
     }
 }
 
-void launch_induce_slices(const DevParams &P, const Work &w, const Table &T, float *wave, int64_t n_slots, int32_t NS,
-                          float *part, int64_t chunk, hipStream_t st) {
-    if (n_slots <= 0) return;
+// Ticks per thread of the induction: the smallest of 1, 2, 4, 8 whose 256-thread tile covers a pair's window
+// (table length + a typical charge-box extent), unless forced.
+static int32_t pick_rt(const DevParams &P, int32_t forced) {
+    if (forced == 1 || forced == 2 || forced == 4 || forced == 8) return forced;
     const int32_t win = P.t_r + 32;
-    if (win <= kWG) induce_slices_rt<1>(P, w, T, wave, n_slots, NS, part, chunk, st);
-    else if (win <= 2 * kWG) induce_slices_rt<2>(P, w, T, wave, n_slots, NS, part, chunk, st);
-    else if (win <= 4 * kWG) induce_slices_rt<4>(P, w, T, wave, n_slots, NS, part, chunk, st);
-    else induce_slices_rt<8>(P, w, T, wave, n_slots, NS, part, chunk, st);
+    return win <= kWG ? 1 : win <= 2 * kWG ? 2 : win <= 4 * kWG ? 4 : 8;
+}
+
+void launch_induce_slices(const DevParams &P, const Work &w, const Table &T, float *wave, int64_t n_slots, int32_t NS,
+                          float *part, int64_t chunk, int32_t rt, hipStream_t st) {
+    if (n_slots <= 0) return;
+    switch (pick_rt(P, rt)) {
+        case 1: induce_slices_rt<1>(P, w, T, wave, n_slots, NS, part, chunk, st); break;
+        case 2: induce_slices_rt<2>(P, w, T, wave, n_slots, NS, part, chunk, st); break;
+        case 4: induce_slices_rt<4>(P, w, T, wave, n_slots, NS, part, chunk, st); break;
+        default: induce_slices_rt<8>(P, w, T, wave, n_slots, NS, part, chunk, st); break;
+    }
 }
 
 template <int RT>
@@ -839,13 +919,181 @@ static void induce_rt(const DevParams &P, const Work &w, const Table &T, float *
     }
 }
 
-void launch_induce(const DevParams &P, const Work &w, const Table &T, float *wave, int mode, int64_t n_slots,
+void launch_induce(const DevParams &P, const Work &w, const Table &T, float *wave, int mode, int64_t n_slots, int32_t rt,
                    hipStream_t st) {
-    const int32_t win = P.t_r + 32;
-    if (win <= kWG) induce_rt<1>(P, w, T, wave, mode, n_slots, st);
-    else if (win <= 2 * kWG) induce_rt<2>(P, w, T, wave, mode, n_slots, st);
-    else if (win <= 4 * kWG) induce_rt<4>(P, w, T, wave, mode, n_slots, st);
-    else induce_rt<8>(P, w, T, wave, mode, n_slots, st);
+    switch (pick_rt(P, rt)) {
+        case 1: induce_rt<1>(P, w, T, wave, mode, n_slots, st); break;
+        case 2: induce_rt<2>(P, w, T, wave, mode, n_slots, st); break;
+        case 4: induce_rt<4>(P, w, T, wave, mode, n_slots, st); break;
+        default: induce_rt<8>(P, w, T, wave, mode, n_slots, st); break;
+    }
+}
+
+// ================================================================================================= summed induction
+// Sum-then-convolve: by linearity of eq. (current), the current on pixel p is the time convolution of each absolute
+// sub-pixel column's charge, summed over all segments, with that column's folded table column.  The columns are
+// summed once per event (fixed segment order, Kahan) and cut into pieces of at most kPieceTicks ticks; each piece is
+// a 1 x 1 x L charge box, and every active pixel's list of pieces in its reach replaces its pair list, so the
+// sorted induction kernel runs unchanged on the summed data.
+
+__global__ void k_sum_init(int32_t *lo, int32_t *hi, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) { lo[i] = INT32_MAX; hi[i] = INT32_MIN; }
+}
+
+// per segment: every column of its charge box that some pixel can reach gets the box's tick range and a count
+__global__ void k_sum_ranges(DevParams P, const SegInfo *si, int64_t n_seg, SumWork sw) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_seg) return;
+    const SegInfo &g = si[s];
+    if (g.flags & (SEG_INVALID | SEG_TOO_LONG)) return;
+    const int32_t u_a = max(g.u0, sw.UL), u_b = min(g.u0 + g.nu - 1, sw.UL + sw.CU - 1);
+    const int32_t v_a = max(g.v0, sw.VL), v_b = min(g.v0 + g.nv - 1, sw.VL + sw.CV - 1);
+    const int64_t base = (int64_t)g.event * sw.CU * sw.CV;
+    for (int32_t u = u_a; u <= u_b; ++u)
+        for (int32_t v = v_a; v <= v_b; ++v) {
+            const int64_t c = base + (int64_t)(u - sw.UL) * sw.CV + (v - sw.VL);
+            atomicMin(&sw.col_lo[c], g.a0);
+            atomicMax(&sw.col_hi[c], g.a0 + g.na - 1);
+            atomicAdd((unsigned long long *)&sw.col_seg_off[c], 1ull);
+        }
+}
+
+void launch_sum_ranges(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st) {
+    k_sum_init<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(sw.col_lo, sw.col_hi, sw.n_cols);
+    if (w.n_seg > 0) k_sum_ranges<<<(unsigned)((w.n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.n_seg, sw);
+}
+
+__global__ void k_sum_fill(DevParams P, const SegInfo *si, int64_t n_seg, SumWork sw) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_seg) return;
+    const SegInfo &g = si[s];
+    if (g.flags & (SEG_INVALID | SEG_TOO_LONG)) return;
+    const int32_t u_a = max(g.u0, sw.UL), u_b = min(g.u0 + g.nu - 1, sw.UL + sw.CU - 1);
+    const int32_t v_a = max(g.v0, sw.VL), v_b = min(g.v0 + g.nv - 1, sw.VL + sw.CV - 1);
+    const int64_t base = (int64_t)g.event * sw.CU * sw.CV;
+    for (int32_t u = u_a; u <= u_b; ++u)
+        for (int32_t v = v_a; v <= v_b; ++v) {
+            const int64_t c = base + (int64_t)(u - sw.UL) * sw.CV + (v - sw.VL);
+            sw.col_seg[sw.col_seg_off[c] + atomicAdd(&sw.col_cursor[c], 1)] = (int32_t)s;
+        }
+}
+
+// per column: sort its segment list (ascending id, insertion sort: lists are short), count its pieces and the
+// padded summed-charge length.
+__global__ void k_sum_columns(SumWork sw) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= sw.n_cols) return;
+    const int64_t b = sw.col_seg_off[c], e = sw.col_seg_off[c + 1];
+    for (int64_t i = b + 1; i < e; ++i) {
+        const int32_t x = sw.col_seg[i];
+        int64_t j = i - 1;
+        while (j >= b && sw.col_seg[j] > x) { sw.col_seg[j + 1] = sw.col_seg[j]; --j; }
+        sw.col_seg[j + 1] = x;
+    }
+    const int32_t lo = sw.col_lo[c], hi = sw.col_hi[c];
+    int64_t np = 0, ns = 0;
+    if (e > b && hi >= lo) {
+        const int32_t L = hi - lo + 1;
+        np = (L + kPieceTicks - 1) / kPieceTicks;
+        const int32_t last = L - (int32_t)(np - 1) * kPieceTicks;
+        ns = (np - 1) * kPieceTicks + (last + kAC - 1) / kAC * kAC;
+    }
+    sw.piece_off[c] = np;
+    sw.s_off[c] = ns;
+}
+
+void launch_sum_fill(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st) {
+    if (w.n_seg > 0) k_sum_fill<<<(unsigned)((w.n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.n_seg, sw);
+    k_sum_columns<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(sw);
+}
+
+// per column: piece records, and the summed charge of each tick (segments in ascending id, Kahan)
+__global__ void k_sum_pieces(DevParams P, const SegInfo *si, const float *cells, SumWork sw) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= sw.n_cols) return;
+    const int64_t np = sw.piece_off[c + 1] - sw.piece_off[c];
+    if (np == 0) return;
+    const int32_t e = (int32_t)(c / ((int64_t)sw.CU * sw.CV));
+    const int64_t r = c - (int64_t)e * sw.CU * sw.CV;
+    const int32_t u = sw.UL + (int32_t)(r / sw.CV), v = sw.VL + (int32_t)(r % sw.CV);
+    const int32_t lo = sw.col_lo[c], L = sw.col_hi[c] - lo + 1;
+    const int64_t sb = sw.col_seg_off[c], se = sw.col_seg_off[c + 1];
+    float *S = sw.S + sw.s_off[c];
+    const int32_t Lpad = (int32_t)(sw.s_off[c + 1] - sw.s_off[c]);
+    for (int32_t a = 0; a < Lpad; ++a) {
+        float sum = 0.0f, cmp = 0.0f;
+        if (a < L) {
+            const int32_t aa = lo + a;
+            for (int64_t q = sb; q < se; ++q) {
+                const SegInfo &g = si[sw.col_seg[q]];
+                if (aa < g.a0 || aa >= g.a0 + g.na) continue;
+                const float x = cells[g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad + (aa - g.a0)];
+                const float y = x - cmp;
+                const float t = sum + y;
+                cmp = (t - sum) - y;
+                sum = t;
+            }
+        }
+        S[a] = sum - cmp;
+    }
+    for (int64_t k = 0; k < np; ++k) {
+        SegInfo g = {};
+        g.u0 = u; g.nu = 1; g.v0 = v; g.nv = 1;
+        g.a0 = lo + (int32_t)k * kPieceTicks;
+        g.na = min(kPieceTicks, L - (int32_t)k * kPieceTicks);
+        g.na_pad = (g.na + kAC - 1) / kAC * kAC;
+        g.cell_off = sw.s_off[c] + k * kPieceTicks;
+        g.event = e;
+        g.n_pairs = 1;
+        sw.piece[sw.piece_off[c] + k] = g;
+    }
+}
+
+void launch_sum_pieces(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st) {
+    k_sum_pieces<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.cells, sw);
+}
+
+// per active pixel: number of column pieces in its table reach, then their ids in column order
+template <bool FILL>
+__global__ void k_sum_lists(DevParams P, int64_t n_slots, const int32_t *slot_gp, SumWork sw) {
+    int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= n_slots) return;
+    const int32_t gp = slot_gp[slot];
+    const int32_t e = gp / P.npx, p = gp - e * P.npx;
+    const int32_t ix = p % P.nx, iy = p / P.nx;
+    const int32_t cu0 = ix * P.nsub + P.nsub / 2 - P.bx - sw.UL, cv0 = iy * P.nsub + P.nsub / 2 - P.by - sw.VL;
+    const int64_t base = (int64_t)e * sw.CU * sw.CV;
+    int64_t cnt = 0, pos = FILL ? sw.list_off[slot] : 0;
+    for (int32_t du = 0; du < 2 * P.bx; ++du) {
+        const int64_t row = base + (int64_t)(cu0 + du) * sw.CV + cv0;
+        for (int32_t dv = 0; dv < 2 * P.by; ++dv) {
+            const int64_t pb = sw.piece_off[row + dv], pe = sw.piece_off[row + dv + 1];
+            if (FILL)
+                for (int64_t k = pb; k < pe; ++k) sw.list[pos++] = (int32_t)k;
+            cnt += pe - pb;
+        }
+    }
+    if (!FILL) sw.list_off[slot] = cnt;
+}
+
+void launch_sum_lists_count(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, hipStream_t st) {
+    if (n_slots > 0)
+        k_sum_lists<false><<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
+}
+void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, hipStream_t st) {
+    if (n_slots > 0)
+        k_sum_lists<true><<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
+}
+
+void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, const Table &T, float *wave,
+                          int64_t n_slots, int32_t rt, hipStream_t st) {
+    Work ws = w;
+    ws.si = sw.piece;
+    ws.cells = sw.S;
+    ws.slot_off = sw.list_off;
+    ws.pairs = sw.list;
+    launch_induce(P, ws, T, wave, 0, n_slots, rt, st);
 }
 
 // ================================================================================================= electronics
@@ -1021,6 +1269,31 @@ __global__ void k_work_stats(DevParams P, const SegInfo *si, int64_t n_seg, unsi
 
 void launch_work_stats(const DevParams &P, const SegInfo *si, int64_t n_seg, unsigned long long *acc, hipStream_t st) {
     if (n_seg > 0) k_work_stats<<<(unsigned)((n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, si, n_seg, acc);
+}
+
+// Summed induction: per active pixel, the (column-piece tick, table tick) products that land in the window.
+__global__ void k_work_stats_summed(DevParams P, int64_t n_slots, const int64_t *list_off, const int32_t *list,
+                                    const SegInfo *piece, unsigned long long *acc) {
+    int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= n_slots) return;
+    unsigned long long f = 0, cells = 0;
+    for (int64_t q = list_off[slot]; q < list_off[slot + 1]; ++q) {
+        const SegInfo &g = piece[list[q]];
+        for (int32_t a = g.a0; a < g.a0 + g.na; ++a) {
+            const int32_t lo = max(a - P.t_r + 1, 0), hi = min(a, P.nticks - 1);
+            if (hi >= lo) f += (unsigned long long)(hi - lo + 1);
+        }
+        cells += (unsigned long long)g.na;
+    }
+    atomicAdd(&acc[0], (unsigned long long)(list_off[slot + 1] - list_off[slot]));
+    atomicAdd(&acc[1], f);
+    atomicAdd(&acc[2], cells);
+}
+
+void launch_work_stats_summed(const DevParams &P, int64_t n_slots, const int64_t *list_off, const int32_t *list,
+                              const SegInfo *piece, unsigned long long *acc, hipStream_t st) {
+    if (n_slots > 0)
+        k_work_stats_summed<<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, list_off, list, piece, acc);
 }
 
 // ================================================================================================= Philox test hook

@@ -43,6 +43,32 @@ struct Table {
     const double *prefix = nullptr;          // [bx * by][t_r + 1] FP64 prefix sums of each column
 };
 
+// Device buffers of the summed (sum-then-convolve) induction: per event an absolute grid of sub-pixel columns
+// u in [UL, UL + CU) x v in [VL, VL + CV), UL = nsub/2 - bx (the columns some in-grid pixel can reach).
+struct SumWork {
+    int32_t CU = 0, CV = 0, UL = 0, VL = 0;
+    int64_t n_cols = 0;                      // n_ev * CU * CV
+    int32_t *col_lo = nullptr, *col_hi = nullptr;   // [n_cols] tick range of the column's charge
+    int64_t *col_seg_off = nullptr;          // [n_cols + 1] segments per column, then offsets
+    int32_t *col_cursor = nullptr;           // [n_cols]
+    int32_t *col_seg = nullptr;              // [n_col_seg] segment ids per column (ascending after sorting)
+    int64_t *piece_off = nullptr;            // [n_cols + 1] pieces per column, then offsets
+    int64_t *s_off = nullptr;                // [n_cols + 1] summed-cell floats per column, then offsets
+    SegInfo *piece = nullptr;                // [n_pieces] one 1 x 1 x L box per column piece
+    float *S = nullptr;                      // [n_s] summed charge per column piece (padded to kAC)
+    int64_t *list_off = nullptr;             // [n_slots + 1] pieces in reach per active pixel, then offsets
+    int32_t *list = nullptr;                 // [n_list] piece ids per active pixel, in column order
+};
+constexpr int32_t kPieceTicks = 248;         // ticks per column piece (a multiple of kAC, <= kNaMax)
+
+void launch_sum_ranges(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st);   // + counts
+void launch_sum_fill(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st);     // lists, pieces
+void launch_sum_pieces(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st);   // piece records, S
+void launch_sum_lists_count(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, hipStream_t st);
+void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, hipStream_t st);
+void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, const Table &T, float *wave,
+                          int64_t n_slots, int32_t rt, hipStream_t st);
+
 int64_t scan_tmp_needed(int64_t n);
 void scan_exclusive_i64(int64_t *data, int64_t n, int64_t *total_dst, void *tmp, hipStream_t st);
 void scan_exclusive_u64(uint64_t *data, int64_t n, void *tmp, hipStream_t st);
@@ -53,9 +79,9 @@ void launch_fill_pairs(const DevParams &P, const Work &w, hipStream_t st);
 void launch_sort_pairs(const Work &w, int64_t n_slots_host, hipStream_t st);
 void launch_cells(const DevParams &P, const Work &w, hipStream_t st);
 void launch_induce(const DevParams &P, const Work &w, const Table &T, float *wave, int mode, int64_t n_slots_host,
-                   hipStream_t st);
+                   int32_t rt, hipStream_t st);
 void launch_induce_slices(const DevParams &P, const Work &w, const Table &T, float *wave, int64_t n_slots, int32_t NS,
-                          float *part, int64_t chunk, hipStream_t st);
+                          float *part, int64_t chunk, int32_t rt, hipStream_t st);
 void launch_electronics(const DevParams &P, const float *wave, const int32_t *slot_gp, const uint64_t *event_ids,
                         int64_t n_slots, const Work &w, hipStream_t st);
 void launch_compact_packets(const DevParams &P, const Work &w, int64_t n_slots, int32_t *pkt_pixel, int32_t *pkt_tick,
@@ -64,6 +90,8 @@ void launch_compact_packets(const DevParams &P, const Work &w, int64_t n_slots, 
 void launch_stage_quench_drift(const DevParams &P, const SegArrays &S, int64_t n, float *out_f, int32_t *out_i,
                                hipStream_t st);
 void launch_work_stats(const DevParams &P, const SegInfo *si, int64_t n_seg, unsigned long long *acc, hipStream_t st);
+void launch_work_stats_summed(const DevParams &P, int64_t n_slots, const int64_t *list_off, const int32_t *list,
+                              const SegInfo *piece, unsigned long long *acc, hipStream_t st);
 void launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n, hipStream_t st);
 
 }  // namespace ltsim

@@ -38,7 +38,9 @@ struct lts_context {
     lts_electronics el{};
     int32_t reduce_mode = LTS_REDUCE_SORTED;
     int32_t induce_slices = 1;       // sorted variant: table slices (one per XCD); 1 = unsliced kernel
+    int32_t ticks_per_thread = 0;    // induction tick tile per thread (0 = chosen from the table length)
     DevBuf part;                     // per-slice partial waveforms of the sliced sorted variant
+    DevBuf col_lo, col_hi, col_seg_off, col_cursor, col_seg, piece_off, s_off, piece, S, list_off, list;
     DevParams P{};
     bool has_table = false;
     DevBuf Rpad, prefix;
@@ -49,6 +51,8 @@ struct lts_context {
         pk_flag, pk_off, hdr, scan_tmp, ev_off, ev_ids, report_tmp, counts_tmp;
     DevHeader *hdr_host = nullptr;   // pinned
     int64_t last_n_seg = -1;
+    int64_t last_n_slots = 0;
+    int32_t last_mode = -1;
     // optional stage timing: HIP events recorded on the caller's stream around each stage group
     bool timing = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending_ev;
@@ -298,6 +302,72 @@ lts_status run_sizing(lts_context *c, int32_t n_ev, const uint64_t *event_ids, c
     return LTS_OK;
 }
 
+// Sum-then-convolve induction (exact by linearity): columns summed over segments, then the sorted induction kernel
+// over per-pixel lists of column pieces.
+lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t n_slots, float *wave, hipStream_t st) {
+    const DevParams &P = c->P;
+    lts_status r;
+    SumWork sw;
+    const int32_t half = P.nsub / 2;
+    sw.UL = half - P.bx;
+    sw.VL = half - P.by;
+    sw.CU = (P.nx - 1) * P.nsub + 2 * P.bx;
+    sw.CV = (P.ny - 1) * P.nsub + 2 * P.by;
+    sw.n_cols = (int64_t)w.n_ev * sw.CU * sw.CV;
+    const int64_t nc1 = sw.n_cols + 1;
+    const int64_t n_colseg = std::max<int64_t>(h.n_colseg, 1);
+    const int64_t max_pieces = n_colseg + h.n_cells / kPieceTicks + 1;
+    const int64_t max_s = h.n_cells + (int64_t)kAC * n_colseg + kAC;
+    if ((r = ensure(c, c->col_lo, sizeof(int32_t) * (size_t)sw.n_cols))) return r;
+    if ((r = ensure(c, c->col_hi, sizeof(int32_t) * (size_t)sw.n_cols))) return r;
+    if ((r = ensure(c, c->col_seg_off, sizeof(int64_t) * (size_t)nc1))) return r;
+    if ((r = ensure(c, c->col_cursor, sizeof(int32_t) * (size_t)sw.n_cols))) return r;
+    if ((r = ensure(c, c->col_seg, sizeof(int32_t) * (size_t)n_colseg))) return r;
+    if ((r = ensure(c, c->piece_off, sizeof(int64_t) * (size_t)nc1))) return r;
+    if ((r = ensure(c, c->s_off, sizeof(int64_t) * (size_t)nc1))) return r;
+    if ((r = ensure(c, c->piece, sizeof(SegInfo) * (size_t)max_pieces))) return r;
+    if ((r = ensure(c, c->S, sizeof(float) * (size_t)max_s))) return r;
+    if ((r = ensure(c, c->list_off, sizeof(int64_t) * (size_t)(n_slots + 1)))) return r;
+    if ((r = ensure(c, c->scan_tmp, sizeof(int64_t) * (size_t)scan_tmp_needed(std::max(nc1, n_slots + 1))))) return r;
+    sw.col_lo = as<int32_t>(c->col_lo);
+    sw.col_hi = as<int32_t>(c->col_hi);
+    sw.col_seg_off = as<int64_t>(c->col_seg_off);
+    sw.col_cursor = as<int32_t>(c->col_cursor);
+    sw.col_seg = as<int32_t>(c->col_seg);
+    sw.piece_off = as<int64_t>(c->piece_off);
+    sw.s_off = as<int64_t>(c->s_off);
+    sw.piece = as<SegInfo>(c->piece);
+    sw.S = as<float>(c->S);
+    sw.list_off = as<int64_t>(c->list_off);
+    void *tmp = c->scan_tmp.p;
+    HIP_TRY(c, hipMemsetAsync(sw.col_seg_off, 0, sizeof(int64_t) * (size_t)nc1, st));
+    HIP_TRY(c, hipMemsetAsync(sw.col_cursor, 0, sizeof(int32_t) * (size_t)sw.n_cols, st));
+    HIP_TRY(c, hipMemsetAsync(sw.piece_off + sw.n_cols, 0, sizeof(int64_t), st));
+    HIP_TRY(c, hipMemsetAsync(sw.s_off + sw.n_cols, 0, sizeof(int64_t), st));
+    HIP_TRY(c, hipMemsetAsync(sw.list_off + n_slots, 0, sizeof(int64_t), st));
+    launch_sum_ranges(P, w, sw, st);
+    scan_exclusive_i64(sw.col_seg_off, nc1, nullptr, tmp, st);
+    launch_sum_fill(P, w, sw, st);
+    scan_exclusive_i64(sw.piece_off, nc1, nullptr, tmp, st);
+    scan_exclusive_i64(sw.s_off, nc1, nullptr, tmp, st);
+    launch_sum_pieces(P, w, sw, st);
+    launch_sum_lists_count(P, w, sw, n_slots, st);
+    scan_exclusive_i64(sw.list_off, n_slots + 1, nullptr, tmp, st);
+    int64_t tot[3] = {0, 0, 0};
+    HIP_TRY(c, hipMemcpyAsync(&tot[0], sw.list_off + n_slots, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(&tot[1], sw.piece_off + sw.n_cols, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(&tot[2], sw.s_off + sw.n_cols, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (tot[1] > max_pieces || tot[2] > max_s)
+        return fail(c, LTS_ERR_DEVICE, "summed induction: column pieces exceed their bound");
+    if ((r = ensure(c, c->list, sizeof(int32_t) * (size_t)std::max<int64_t>(tot[0], 1)))) return r;
+    sw.list = as<int32_t>(c->list);
+    launch_sum_lists_fill(P, w, sw, n_slots, st);
+    Table T{as<float>(c->Rpad), as<double>(c->prefix)};
+    launch_induce_summed(P, w, sw, T, wave, n_slots, c->ticks_per_thread, st);
+    return LTS_OK;
+}
+
 lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids, const int64_t *seg_offsets,
                         const lts_segments *segs, const lts_outputs *out, hipStream_t st) {
     if (c->sticky) return fail(c, c->sticky, "context is in a failed state: " + c->err);
@@ -312,6 +382,8 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
     DevHeader h;
     if ((r = run_sizing(c, n_ev, event_ids, seg_offsets, segs, out->report, st, w, h))) return r;
     const int64_t n_slots = h.n_slots, n_pairs = h.n_pairs, n_cells = h.n_cells;
+    c->last_n_slots = n_slots;
+    c->last_mode = c->reduce_mode;
     const int64_t mp = c->P.max_packets;
     if (n_slots > out->cap_pixels) {
         int64_t need[4] = {n_slots, n_slots * mp, 0, 0};
@@ -353,16 +425,20 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
     Table T{as<float>(c->Rpad), as<double>(c->prefix)};
     if (c->reduce_mode == LTS_REDUCE_ATOMIC)
         HIP_TRY(c, hipMemsetAsync(out->current, 0, sizeof(float) * (size_t)n_slots * P.nticks, st));
-    if (c->reduce_mode == LTS_REDUCE_SORTED && c->induce_slices > 1 && n_slots > 0) {
+    if (c->reduce_mode == LTS_REDUCE_SUMMED) {
+        StageTimer t(c, st, LTS_STAGE_INDUCE);
+        if ((r = run_summed(c, w, h, n_slots, out->current, st))) return r;
+    } else if (c->reduce_mode == LTS_REDUCE_SORTED && c->induce_slices > 1 && n_slots > 0) {
         // slices of at most 1 GiB of partial waveforms at a time
         const int64_t row_bytes = (int64_t)c->induce_slices * P.nticks * (int64_t)sizeof(float);
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_slots, (1ll << 30) / row_bytes));
         if ((r = ensure(c, c->part, (size_t)(row_bytes * chunk)))) return r;
         StageTimer t(c, st, LTS_STAGE_INDUCE);
-        launch_induce_slices(P, w, T, out->current, n_slots, c->induce_slices, as<float>(c->part), chunk, st);
+        launch_induce_slices(P, w, T, out->current, n_slots, c->induce_slices, as<float>(c->part), chunk,
+                             c->ticks_per_thread, st);
     } else {
         StageTimer t(c, st, LTS_STAGE_INDUCE);
-        launch_induce(P, w, T, out->current, c->reduce_mode, n_slots, st);
+        launch_induce(P, w, T, out->current, c->reduce_mode, n_slots, c->ticks_per_thread, st);
     }
     {
         StageTimer t(c, st, LTS_STAGE_ELECTRONICS);
@@ -438,7 +514,8 @@ void lts_context_destroy(lts_context *c) {
         (void)hipEventDestroy(pe.second.second);
     }
     for (hipEvent_t e : c->free_ev) (void)hipEventDestroy(e);
-    DevBuf *bufs[] = {&c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off, &c->pix_cnt, &c->cursor, &c->pix_slot, &c->slot_gp,
+    DevBuf *bufs[] = {&c->col_lo, &c->col_hi, &c->col_seg_off, &c->col_cursor, &c->col_seg, &c->piece_off, &c->s_off,
+                      &c->piece, &c->S, &c->list_off, &c->list, &c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off, &c->pix_cnt, &c->cursor, &c->pix_slot, &c->slot_gp,
                       &c->slot_off, &c->pairs_u, &c->pairs, &c->cells, &c->pk_tick, &c->pk_adc, &c->pk_flag,
                       &c->pk_off, &c->hdr, &c->scan_tmp, &c->ev_off, &c->ev_ids, &c->report_tmp, &c->counts_tmp};
     for (DevBuf *b : bufs) free_buf(*b);
@@ -481,9 +558,18 @@ lts_status lts_set_induce_slices(lts_context *c, int32_t slices) {
     return LTS_OK;
 }
 
+lts_status lts_set_ticks_per_thread(lts_context *c, int32_t rt) {
+    if (!c) return LTS_ERR_INVALID_ARG;
+    if (rt != 0 && rt != 1 && rt != 2 && rt != 4 && rt != 8)
+        return fail(c, LTS_ERR_INVALID_ARG, "ticks per thread must be 0 (auto), 1, 2, 4 or 8");
+    c->ticks_per_thread = rt;
+    return LTS_OK;
+}
+
 lts_status lts_set_reduce_mode(lts_context *c, int32_t mode) {
     if (!c) return LTS_ERR_INVALID_ARG;
-    if (mode != LTS_REDUCE_SORTED && mode != LTS_REDUCE_ATOMIC) return fail(c, LTS_ERR_INVALID_ARG, "unknown reduce mode");
+    if (mode != LTS_REDUCE_SORTED && mode != LTS_REDUCE_ATOMIC && mode != LTS_REDUCE_SUMMED)
+        return fail(c, LTS_ERR_INVALID_ARG, "unknown reduce mode");
     c->reduce_mode = mode;
     return LTS_OK;
 }
@@ -640,6 +726,23 @@ lts_status lts_work_stats(lts_context *c, double out[4]) {
     if ((r = ensure(c, c->counts_tmp, 4 * sizeof(unsigned long long)))) return r;
     HIP_TRY(c, hipDeviceSynchronize());
     HIP_TRY(c, hipMemset(c->counts_tmp.p, 0, 4 * sizeof(unsigned long long)));
+    if (c->last_mode == LTS_REDUCE_SUMMED) {
+        launch_work_stats_summed(c->P, c->last_n_slots, as<int64_t>(c->list_off), as<int32_t>(c->list),
+                                 as<SegInfo>(c->piece), as<unsigned long long>(c->counts_tmp), nullptr);
+        HIP_TRY(c, hipGetLastError());
+        unsigned long long hs[4];
+        HIP_TRY(c, hipMemcpy(hs, c->counts_tmp.p, sizeof(hs), hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemset(c->counts_tmp.p, 0, 4 * sizeof(unsigned long long)));
+        launch_work_stats(c->P, as<SegInfo>(c->si), c->last_n_seg, as<unsigned long long>(c->counts_tmp), nullptr);
+        HIP_TRY(c, hipGetLastError());
+        unsigned long long hp[4];
+        HIP_TRY(c, hipMemcpy(hp, c->counts_tmp.p, sizeof(hp), hipMemcpyDeviceToHost));
+        out[0] = (double)hp[0];
+        out[1] = (double)hs[1];
+        out[2] = (double)hs[2];
+        out[3] = (double)hp[3];
+        return LTS_OK;
+    }
     launch_work_stats(c->P, as<SegInfo>(c->si), c->last_n_seg, as<unsigned long long>(c->counts_tmp), nullptr);
     HIP_TRY(c, hipGetLastError());
     unsigned long long h[4];
@@ -907,6 +1010,7 @@ lts_status lts_server_start(lts_context *ctx, const lts_server_cfg *cfg, lts_ser
         if (r == LTS_OK) r = lts_set_response(L->ctx, ctx->table_host.data(), ctx->t_r, ctx->b_x, ctx->b_y);
         if (r == LTS_OK) r = lts_set_reduce_mode(L->ctx, ctx->reduce_mode);
         if (r == LTS_OK) r = lts_set_induce_slices(L->ctx, ctx->induce_slices);
+        if (r == LTS_OK) r = lts_set_ticks_per_thread(L->ctx, ctx->ticks_per_thread);
         if (r == LTS_OK && hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess) r = LTS_ERR_DEVICE;
         if (r != LTS_OK) {
             if (L->ctx) lts_context_destroy(L->ctx);

@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libltsim.so")
 
-LTS_REDUCE_SORTED, LTS_REDUCE_ATOMIC = 0, 1
+LTS_REDUCE_SORTED, LTS_REDUCE_ATOMIC, LTS_REDUCE_SUMMED = 0, 1, 2
 STATUS = {0: "LTS_OK", 1: "LTS_ERR_INVALID_ARG", 2: "LTS_ERR_CAPACITY", 3: "LTS_ERR_OOM", 4: "LTS_ERR_DEVICE",
           5: "LTS_ERR_NOT_READY", 6: "LTS_ERR_CANCELLED", 7: "LTS_ERR_STATE"}
 REPORT_FIELDS = ("q_after_quench", "q_collected", "q_induced", "q_clipped", "q_offgrid")
@@ -77,7 +77,8 @@ STAGES = ("quench_drift", "rasterize", "cells", "induce", "electronics")
 
 EXPORTS = ("lts_server_start", "lts_server_submit", "lts_server_poll", "lts_server_wait", "lts_server_release",
            "lts_server_stop", "lts_set_timing", "lts_get_timing", "lts_work_stats", "lts_context_create", "lts_context_destroy",
-           "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_plan", "lts_simulate", "lts_simulate_batch", "lts_stage_quench_drift", "lts_debug_cells",
+           "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_set_ticks_per_thread",
+           "lts_plan", "lts_simulate", "lts_simulate_batch", "lts_stage_quench_drift", "lts_debug_cells",
            "lts_stage_electronics", "lts_stage_philox", "lts_status_str", "lts_last_error", "lts_version")
 
 _LIB = None
@@ -99,6 +100,7 @@ def lib():
         L.lts_set_response.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32]
         L.lts_set_reduce_mode.argtypes = [P, C.c_int32]
         L.lts_set_induce_slices.argtypes = [P, C.c_int32]
+        L.lts_set_ticks_per_thread.argtypes = [P, C.c_int32]
         L.lts_plan.argtypes = [P, C.POINTER(lts_segments), C.POINTER(C.c_int64), P]
         L.lts_simulate.argtypes = [P, C.c_uint64, C.POINTER(lts_segments), C.POINTER(lts_outputs), P]
         L.lts_simulate_batch.argtypes = [P, C.c_int32, P, P, C.POINTER(lts_segments), C.POINTER(lts_outputs), P]
@@ -234,6 +236,9 @@ class Context:
 
     def set_induce_slices(self, slices: int):
         self._check(lib().lts_set_induce_slices(self._h, slices))
+
+    def set_ticks_per_thread(self, rt: int):
+        self._check(lib().lts_set_ticks_per_thread(self._h, rt))
 
     def set_reduce_mode(self, mode: int):
         self._check(lib().lts_set_reduce_mode(self._h, mode))

@@ -164,7 +164,7 @@ def test_charge_cells(lt, orc, torch, cfg):
 
 # ----------------------------------------------------------------------------------------------- whole events
 
-@pytest.mark.parametrize("mode,slices", [(0, 8), (0, 1), (1, 1)])
+@pytest.mark.parametrize("mode,slices", [(0, 8), (0, 1), (1, 1), (2, 1)])
 def test_cfg1_event_parity(lt, orc, torch, mode, slices):
     h, r, e, (cmp_, flg) = check_event(lt, orc, W.make_workload(1), mode=mode, slices=slices)
     print(f"cfg1 mode={mode} slices={slices}: pixels {len(r['pixels'])} max e_p {e.max():.2e} p99 {np.percentile(e, 99):.2e} "
@@ -198,17 +198,18 @@ def _ragged_workload(seed=7):
     return w
 
 
-@pytest.mark.parametrize("mode,slices", [(0, 8), (0, 3), (1, 1)])
+@pytest.mark.parametrize("mode,slices", [(0, 8), (0, 3), (1, 1), (2, 1)])
 def test_ragged_multi_tile_parity(lt, orc, torch, mode, slices):
     h, r, e, _ = check_event(lt, orc, _ragged_workload(), mode=mode, slices=slices)
     assert r["report"]["q_clipped"] != 0.0 and r["report"]["q_offgrid"] > 0.0
 
 
-def test_cfg2_full_size_sampled_pixels(lt, orc, torch):
-    """The module-scale event at full size, in the launch configuration the benchmark times; the oracle
+@pytest.mark.parametrize("mode", [0, 2])
+def test_cfg2_full_size_sampled_pixels(lt, orc, torch, mode):
+    """The module-scale event at full size, in the launch configurations the benchmark times; the oracle
     recomputes a sample of pixels one by one."""
     w = W.make_workload(2)
-    ctx, h = run_gpu(lt, w)
+    ctx, h = run_gpu(lt, w, mode=mode)
     gpix, cur = h["pixel_id"], h["current"]
     tot = np.abs(cur).sum(axis=1)
     rng = np.random.default_rng(11)
@@ -325,10 +326,11 @@ def test_electronics_with_full_noise_vs_oracle(lt, orc, torch):
 
 # ----------------------------------------------------------------------------------------------- batching
 
-def test_batch_equals_single_events(lt, torch):
+@pytest.mark.parametrize("mode", [0, 2])
+def test_batch_equals_single_events(lt, torch, mode):
     w = W.make_workload(1, n_events=3)
     w.events[1] = w.events[1].shifted(dt=3.0)
-    ctx = lt.Context.from_workload(w)
+    ctx = lt.Context.from_workload(w, reduce_mode=mode)
     singles = [ctx.simulate(lt.to_device(s), event_id=i).host() for s, i in zip(w.events, w.event_ids)]
     allsegs = W.Segments.concat(w.events)
     offs = np.r_[0, np.cumsum([s.n for s in w.events])]
@@ -366,3 +368,16 @@ def test_served_results_equal_alone(lt, torch):
         assert np.array_equal(a["current"], g["current"])            # deterministic sorted reduction
         assert np.array_equal(a["pkt_tick"], g["pkt_tick"]) and np.array_equal(a["pkt_adc"], g["pkt_adc"])
         np.testing.assert_allclose(a["report"][0], g["report"], rtol=1e-12, atol=1e-9)
+
+
+# ----------------------------------------------------------------------------------------------- autotuner
+
+def test_autotune_picks_an_accurate_candidate(lt, torch, tmp_path):
+    from paper_2212_09807_amd import autotune as AT
+    w = W.make_workload(1)
+    cands = [AT.Choice(0, 1, 0), AT.Choice(0, 2, 0), AT.Choice(1, 1, 0), AT.Choice(0, 1, 2)]
+    res = AT.autotune(w, candidates=cands, reps=1, cache=str(tmp_path / "tune.json"))
+    assert res["best"]["max_rel_l2_vs_sorted"] <= 1e-5
+    assert len(res["all"]) == 4 and all(r["ms"] > 0 for r in res["all"])
+    again = AT.autotune(w, candidates=cands, cache=str(tmp_path / "tune.json"))     # served from the cache
+    assert again["best"] == res["best"]
