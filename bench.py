@@ -113,6 +113,32 @@ def served(ltsim, W, rate_hz, n_events, mode, lanes=2):
             "mean_batch_events": float(np.mean([r["batch_events"] for r in res])), "lanes": lanes}
 
 
+def time_mode(ltsim, w, segs, mode, steps):
+    """Whole path in another reduce mode on the same device-resident event: segments/s and its induction roofline."""
+    import torch
+    ctx = ltsim.Context.from_workload(w, reduce_mode=mode)
+    need = ctx.plan(segs)
+    out = ctx._alloc(need["pixels"], need["packets"], 1, False)
+    ctx.simulate(segs, event_id=w.event_ids[0], out=out)
+    torch.cuda.synchronize()
+    stats = ctx.work_stats()
+    ctx.set_timing(True)
+    ctx.get_timing()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.simulate(segs, event_id=w.event_ids[0], out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tm = ctx.get_timing()
+    ind_ms = tm["induce"][0] / max(tm["induce"][1], 1)
+    ach = 2.0 * stats["fma"] / (ind_ms / 1e3) / 1e12
+    return {"value": segs.n * steps / el, "unit": "segments/s", "ms_per_step": el / steps * 1e3,
+            "stage_ms": {k: v[0] / max(v[1], 1) for k, v in tm.items()},
+            "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_FMA_TFLOPS, "unit": "TFLOP/s",
+                         "frac": ach / PEAK_FP32_FMA_TFLOPS, "traffic": None, "flops_per_launch": 2.0 * stats["fma"],
+                         "launch_ms": ind_ms}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,11 +147,15 @@ def main():
     ap.add_argument("--mode", choices=("sorted", "atomic", "summed"), default="sorted")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--batched", type=int, default=0, help="also compare a batch of N spill events with N plain calls")
-    ap.add_argument("--served", type=float, nargs=2, default=None, metavar=("RATE_HZ", "N"),
+    ap.add_argument("--batched", type=int, default=8, help="also compare a batch of N spill events with N plain calls")
+    ap.add_argument("--served", type=float, nargs=2, default=(2.0, 16), metavar=("RATE_HZ", "N"),
                     help="also serve N spill events arriving as a Poisson process at RATE_HZ")
     ap.add_argument("--slices", type=int, default=1)
+    ap.add_argument("--also", default="summed", help="comma-separated other reduce modes to time on the same event")
+    ap.add_argument("--quick", action="store_true", help="only the headline path (no other modes, batch or serving)")
     args = ap.parse_args()
+    if args.quick:
+        args.also, args.batched, args.served = "", 0, None
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (events shard across GPUs "
               f"with no exchange, see DESIGN.md)", file=sys.stderr)
@@ -196,6 +226,9 @@ def main():
                      "flops_per_launch": 2.0 * stats["fma"], "launch_ms": ind_s * 1e3},
     }
     line["config"]["induce_slices"] = args.slices if args.mode == "sorted" else 1
+    for other in [m for m in args.also.split(",") if m and m != args.mode]:
+        line.setdefault("modes", {})[other] = time_mode(ltsim, w, segs, {"sorted": 0, "atomic": 1, "summed": 2}[other],
+                                                        args.steps)
     if args.batched:
         line["batched"] = batched_vs_plain(ltsim, W, args.batched, mode)
     if args.served:

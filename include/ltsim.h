@@ -83,6 +83,8 @@ typedef struct lts_electronics {
     double sigma_unc;          /* electrons: per-sample uncorrelated noise */
     int32_t max_packets;       /* per pixel (further samples are counted as overflow) */
     uint64_t seed;             /* Philox4x32-10 key (low word, high word) */
+    int32_t reset_period;      /* periodic reset every reset_period ticks (0 = off): at ticks k * reset_period, k >= 1,
+                                  before that tick's charge, a pixel with no pending sample restarts from reset noise */
 } lts_electronics;
 
 /* Segment table, structure of arrays, FP32, device pointers; n rows.  dedx may be NULL; it is read only
@@ -153,6 +155,11 @@ void lts_context_destroy(lts_context *ctx);
 lts_status lts_set_response(lts_context *ctx, const float *R_host, int32_t t_r, int32_t b_x, int32_t b_y);
 
 lts_status lts_set_reduce_mode(lts_context *ctx, int32_t mode);
+
+/* Disabled channels (Sec. 6: part of the pixels of a tile can be switched off): host mask of n_x * n_y bytes
+ * indexed by tile-local pixel id, non-zero = disabled.  Disabled pixels keep their currents but produce no packets.
+ * mask = NULL (or n = 0) enables every pixel.  Copied; applies to every later event on the context. */
+lts_status lts_set_channel_mask(lts_context *ctx, const uint8_t *mask, int64_t n);
 
 /* Sorted variant only: split each pixel's induction over `slices` workgroups by the mirror-folded x-bin index of
  * the table (e.g. 8, one slice per XCD, so each XCD's L2 holds only its part of the table); the slices'

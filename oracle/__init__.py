@@ -51,7 +51,7 @@ class _Electronics(C.Structure):
     _fields_ = [("threshold", C.c_double), ("hold_ticks", C.c_int32), ("min_spacing", C.c_int32),
                 ("q_lsb", C.c_double), ("pedestal", C.c_int32), ("adc_bits", C.c_int32),
                 ("sigma_reset", C.c_double), ("sigma_disc", C.c_double), ("sigma_unc", C.c_double),
-                ("max_packets", C.c_int32), ("seed", C.c_uint64)]
+                ("max_packets", C.c_int32), ("seed", C.c_uint64), ("reset_period", C.c_int32)]
 
 
 _FP = C.POINTER(C.c_float)

@@ -64,6 +64,7 @@ typedef struct {
     double sigma_reset, sigma_disc, sigma_unc;
     int32_t max_packets;
     uint64_t seed;
+    int32_t reset_period;
 } orc_electronics_params;
 
 typedef struct {
@@ -543,6 +544,14 @@ int orc_electronics(const orc_electronics_params *el, const orc_readout_params *
         int32_t cnt = 0;
         int32_t ufrom = INT32_MAX;
         for (int64_t n = 0; n < nt; ++n) {
+            /* periodic reset (Sec. 3.4): at every multiple of the period, a pixel without a pending sample
+             * discards its integrated charge before this tick's charge arrives */
+            if (el->reset_period > 0 && n > 0 && n % el->reset_period == 0 && !pending) {
+                Q = 0.0;
+                if (el->sigma_reset > 0.0)
+                    Q = el->sigma_reset * orc_noise_normal(el->seed, pid, (uint32_t)n, event_id, ORC_STREAM_RESET);
+                absum = 0.0;
+            }
             Q += w[n];
             absum += fabs(w[n]);
             if (!pending && n >= ready) {

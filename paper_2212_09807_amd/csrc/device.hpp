@@ -42,7 +42,7 @@ struct DevParams {
     int32_t t_r, bx, by, col_len;           // col_len = kPad + t_r + kPad
     // electronics (Sec. 3.4)
     float thr, q_lsb, sig_reset, sig_disc, sig_unc;
-    int32_t hold, spacing, pedestal, adc_max, max_packets;
+    int32_t hold, spacing, pedestal, adc_max, max_packets, reset_period;
     uint32_t key0, key1;
     float eps_rel, eps_abs;
 };

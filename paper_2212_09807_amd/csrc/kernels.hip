@@ -1105,7 +1105,7 @@ void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, 
 __global__ __launch_bounds__(kWG) void k_electronics(DevParams P, const float *__restrict__ wave,
                                                      const int32_t *__restrict__ slot_gp,
                                                      const uint64_t *__restrict__ ev_ids, int32_t n_ev,
-                                                     int64_t n_slots_arg,
+                                                     const uint8_t *__restrict__ disabled, int64_t n_slots_arg,
                                                      int32_t *pk_tick, uint16_t *pk_adc, uint8_t *pk_flag,
                                                      int64_t *pk_cnt, DevHeader *H, double *report) {
     const int64_t n_slots = n_slots_arg >= 0 ? n_slots_arg : H->n_slots;
@@ -1121,6 +1121,7 @@ __global__ __launch_bounds__(kWG) void k_electronics(DevParams P, const float *_
         if (valid) {
             e = gp / P.npx;
             const uint32_t pid = (uint32_t)(gp - e * P.npx);
+            const bool off = disabled && disabled[pid];               // disabled channel: no packets
             const uint64_t ev = ev_ids[e];
             const float *w = wave + slot * NT;
             float Q = 0.0f, Qc = 0.0f, absum = 0.0f;
@@ -1128,10 +1129,17 @@ __global__ __launch_bounds__(kWG) void k_electronics(DevParams P, const float *_
             bool pending = false, uncertain = false, done = false;
             int32_t ns = 0, ready = 0, last = -(1 << 28), cnt = 0;
             int64_t obase = slot * P.max_packets;
+            if (off) done = true;
             for (int32_t n = 0; n < NT; ++n) {
                 const float x = w[n];
                 rowsum += (double)x;
                 if (done) continue;
+                if (P.reset_period > 0 && n > 0 && n % P.reset_period == 0 && !pending) {   // periodic reset
+                    Q = 0.0f;
+                    Qc = 0.0f;
+                    if (P.sig_reset > 0.0f) Q = P.sig_reset * noise_normal(P, pid, (uint32_t)n, ev, STREAM_RESET);
+                    absum = 0.0f;
+                }
                 {   // Kahan
                     const float y = x - Qc;
                     const float t = Q + y;
@@ -1195,8 +1203,8 @@ void launch_electronics(const DevParams &P, const float *wave, const int32_t *sl
     int64_t g = (n_slots + kWG - 1) / kWG;
     if (g < 1) g = 1;
     if (g > 4096) g = 4096;
-    k_electronics<<<(unsigned)g, kWG, 0, st>>>(P, wave, slot_gp, event_ids, w.n_ev, n_slots, w.pk_tick, w.pk_adc,
-                                               w.pk_flag, w.pk_off, w.hdr, w.report);
+    k_electronics<<<(unsigned)g, kWG, 0, st>>>(P, wave, slot_gp, event_ids, w.n_ev, w.disabled, n_slots, w.pk_tick,
+                                               w.pk_adc, w.pk_flag, w.pk_off, w.hdr, w.report);
 }
 
 __global__ void k_compact(int32_t max_packets, int64_t n_slots, const int64_t *pk_off, const int32_t *slot_gp,

@@ -34,6 +34,7 @@ struct Work {
     int64_t *pk_off = nullptr;               // [cap_slots + 1] counts, then exclusive offsets
     DevHeader *hdr = nullptr;
     double *report = nullptr;                // [5 * n_ev]
+    const uint8_t *disabled = nullptr;       // [npx] disabled-channel mask or null
     void *scan_tmp = nullptr;                // scan partials
     int64_t scan_tmp_elems = 0;
 };

@@ -40,6 +40,8 @@ struct lts_context {
     int32_t induce_slices = 1;       // sorted variant: table slices (one per XCD); 1 = unsliced kernel
     int32_t ticks_per_thread = 0;    // induction tick tile per thread (0 = chosen from the table length)
     DevBuf part;                     // per-slice partial waveforms of the sliced sorted variant
+    DevBuf mask;                     // disabled-channel mask (npx bytes) when set
+    bool has_mask = false;
     DevBuf col_lo, col_hi, col_seg_off, col_cursor, col_seg, piece_off, s_off, piece, S, list_off, list;
     DevParams P{};
     bool has_table = false;
@@ -149,6 +151,7 @@ lts_status validate_and_derive(lts_context *c) {
     if (el.max_packets < 1 || el.max_packets > 65536) return fail(c, LTS_ERR_INVALID_ARG, "max_packets must be in [1, 65536]");
     if (!(el.q_lsb > 0)) return fail(c, LTS_ERR_INVALID_ARG, "q_lsb must be > 0");
     if (el.hold_ticks < 0 || el.min_spacing < 0) return fail(c, LTS_ERR_INVALID_ARG, "hold / spacing must be >= 0");
+    if (el.reset_period < 0) return fail(c, LTS_ERR_INVALID_ARG, "reset_period must be >= 0");
     if (!(el.sigma_reset >= 0 && el.sigma_disc >= 0 && el.sigma_unc >= 0))
         return fail(c, LTS_ERR_INVALID_ARG, "noise sigmas must be >= 0");
     DevParams &P = c->P;
@@ -187,6 +190,7 @@ lts_status validate_and_derive(lts_context *c) {
     P.pedestal = el.pedestal;
     P.adc_max = (1 << el.adc_bits) - 1;
     P.max_packets = el.max_packets;
+    P.reset_period = el.reset_period;
     P.key0 = (uint32_t)(el.seed & 0xffffffffu);
     P.key1 = (uint32_t)(el.seed >> 32);
     P.eps_rel = 2e-6f;
@@ -285,6 +289,7 @@ lts_status run_sizing(lts_context *c, int32_t n_ev, const uint64_t *event_ids, c
     w.hdr = as<DevHeader>(c->hdr);
     w.report = report;
     w.scan_tmp = c->scan_tmp.p;
+    w.disabled = c->has_mask ? as<uint8_t>(c->mask) : nullptr;
     SegArrays S = seg_arrays(segs);
     {
         StageTimer t(c, st, LTS_STAGE_QUENCH_DRIFT);
@@ -514,7 +519,7 @@ void lts_context_destroy(lts_context *c) {
         (void)hipEventDestroy(pe.second.second);
     }
     for (hipEvent_t e : c->free_ev) (void)hipEventDestroy(e);
-    DevBuf *bufs[] = {&c->col_lo, &c->col_hi, &c->col_seg_off, &c->col_cursor, &c->col_seg, &c->piece_off, &c->s_off,
+    DevBuf *bufs[] = {&c->mask, &c->col_lo, &c->col_hi, &c->col_seg_off, &c->col_cursor, &c->col_seg, &c->piece_off, &c->s_off,
                       &c->piece, &c->S, &c->list_off, &c->list, &c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off, &c->pix_cnt, &c->cursor, &c->pix_slot, &c->slot_gp,
                       &c->slot_off, &c->pairs_u, &c->pairs, &c->cells, &c->pk_tick, &c->pk_adc, &c->pk_flag,
                       &c->pk_off, &c->hdr, &c->scan_tmp, &c->ev_off, &c->ev_ids, &c->report_tmp, &c->counts_tmp};
@@ -563,6 +568,21 @@ lts_status lts_set_ticks_per_thread(lts_context *c, int32_t rt) {
     if (rt != 0 && rt != 1 && rt != 2 && rt != 4 && rt != 8)
         return fail(c, LTS_ERR_INVALID_ARG, "ticks per thread must be 0 (auto), 1, 2, 4 or 8");
     c->ticks_per_thread = rt;
+    return LTS_OK;
+}
+
+lts_status lts_set_channel_mask(lts_context *c, const uint8_t *mask, int64_t n) {
+    if (!c) return LTS_ERR_INVALID_ARG;
+    if (!mask || n == 0) {
+        c->has_mask = false;
+        return LTS_OK;
+    }
+    if (n != (int64_t)c->P.npx) return fail(c, LTS_ERR_INVALID_ARG, "channel mask must have n_x * n_y entries");
+    HIP_TRY(c, hipSetDevice(c->device));
+    lts_status r;
+    if ((r = ensure(c, c->mask, (size_t)n))) return r;
+    HIP_TRY(c, hipMemcpy(c->mask.p, mask, (size_t)n, hipMemcpyHostToDevice));
+    c->has_mask = true;
     return LTS_OK;
 }
 
@@ -711,6 +731,7 @@ lts_status lts_stage_electronics(lts_context *c, uint64_t event_id, const int32_
     w.report = rep;
     w.scan_tmp = c->scan_tmp.p;
     w.slot_gp = const_cast<int32_t *>(pixel_ids);
+    w.disabled = c->has_mask ? as<uint8_t>(c->mask) : nullptr;
     launch_electronics(c->P, current, pixel_ids, as<uint64_t>(c->ev_ids), n_pix, w, st);
     launch_compact_packets(c->P, w, n_pix, out->pkt_pixel, out->pkt_tick, out->pkt_adc, out->pkt_flags, out->cap_packets,
                            nullptr, nullptr, out->counts, st);

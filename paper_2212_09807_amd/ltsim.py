@@ -45,7 +45,7 @@ class lts_electronics(C.Structure):
     _fields_ = [("threshold", C.c_double), ("hold_ticks", C.c_int32), ("min_spacing", C.c_int32),
                 ("q_lsb", C.c_double), ("pedestal", C.c_int32), ("adc_bits", C.c_int32),
                 ("sigma_reset", C.c_double), ("sigma_disc", C.c_double), ("sigma_unc", C.c_double),
-                ("max_packets", C.c_int32), ("seed", C.c_uint64)]
+                ("max_packets", C.c_int32), ("seed", C.c_uint64), ("reset_period", C.c_int32)]
 
 
 class lts_segments(C.Structure):
@@ -77,7 +77,7 @@ STAGES = ("quench_drift", "rasterize", "cells", "induce", "electronics")
 
 EXPORTS = ("lts_server_start", "lts_server_submit", "lts_server_poll", "lts_server_wait", "lts_server_release",
            "lts_server_stop", "lts_set_timing", "lts_get_timing", "lts_work_stats", "lts_context_create", "lts_context_destroy",
-           "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_set_ticks_per_thread",
+           "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_set_ticks_per_thread", "lts_set_channel_mask",
            "lts_plan", "lts_simulate", "lts_simulate_batch", "lts_stage_quench_drift", "lts_debug_cells",
            "lts_stage_electronics", "lts_stage_philox", "lts_status_str", "lts_last_error", "lts_version")
 
@@ -101,6 +101,7 @@ def lib():
         L.lts_set_reduce_mode.argtypes = [P, C.c_int32]
         L.lts_set_induce_slices.argtypes = [P, C.c_int32]
         L.lts_set_ticks_per_thread.argtypes = [P, C.c_int32]
+        L.lts_set_channel_mask.argtypes = [P, P, C.c_int64]
         L.lts_plan.argtypes = [P, C.POINTER(lts_segments), C.POINTER(C.c_int64), P]
         L.lts_simulate.argtypes = [P, C.c_uint64, C.POINTER(lts_segments), C.POINTER(lts_outputs), P]
         L.lts_simulate_batch.argtypes = [P, C.c_int32, P, P, C.POINTER(lts_segments), C.POINTER(lts_outputs), P]
@@ -236,6 +237,14 @@ class Context:
 
     def set_induce_slices(self, slices: int):
         self._check(lib().lts_set_induce_slices(self._h, slices))
+
+    def set_channel_mask(self, disabled=None):
+        """Disable pixels (bool / uint8 array of n_x * n_y, True = disabled); None enables all."""
+        if disabled is None:
+            self._check(lib().lts_set_channel_mask(self._h, None, 0))
+            return
+        m = np.ascontiguousarray(disabled, dtype=np.uint8)
+        self._check(lib().lts_set_channel_mask(self._h, m.ctypes.data_as(C.c_void_p), m.size))
 
     def set_ticks_per_thread(self, rt: int):
         self._check(lib().lts_set_ticks_per_thread(self._h, rt))

@@ -89,6 +89,7 @@ class Electronics:
     sigma_unc: float = 500.0        # electrons (paper: 500)
     max_packets: int = 128          # per pixel
     seed: int = 0x2212098070000001
+    reset_period: int = 0           # periodic reset every N ticks (0 = off)
 
 
 @dataclass

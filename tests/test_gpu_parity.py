@@ -291,7 +291,8 @@ def test_electronics_hand_traced(lt, orc, torch):
         w.readout = W.Readout(n_x=4, n_y=4, n_ticks=len(c["current"]))
         w.electronics = W.Electronics(threshold=c["threshold"], hold_ticks=c["hold_ticks"],
                                       min_spacing=c["min_spacing"], q_lsb=c["q_lsb"], pedestal=c["pedestal"],
-                                      adc_bits=c["adc_bits"], sigma_unc=0.0, max_packets=16)
+                                      adc_bits=c["adc_bits"], sigma_unc=0.0, max_packets=16,
+                                      reset_period=c.get("reset_period", 0))
         ctx = lt.Context.from_workload(w)
         pix = torch.tensor([5], dtype=torch.int32, device="cuda")
         cur = torch.tensor(np.array(c["current"], np.float32)[None], device="cuda")
@@ -301,8 +302,10 @@ def test_electronics_hand_traced(lt, orc, torch):
         assert int(h["counts"][2]) == c["dropped"], c["name"]
 
 
-def test_electronics_with_full_noise_vs_oracle(lt, orc, torch):
+@pytest.mark.parametrize("period", [0, 37])
+def test_electronics_with_full_noise_vs_oracle(lt, orc, torch, period):
     w = W.config(5)
+    w.electronics.reset_period = period
     w.readout = W.Readout(n_x=64, n_y=64, n_ticks=1500)
     rng = np.random.default_rng(9)
     n = 400
@@ -381,3 +384,23 @@ def test_autotune_picks_an_accurate_candidate(lt, torch, tmp_path):
     assert len(res["all"]) == 4 and all(r["ms"] > 0 for r in res["all"])
     again = AT.autotune(w, candidates=cands, cache=str(tmp_path / "tune.json"))     # served from the cache
     assert again["best"] == res["best"]
+
+
+def test_disabled_channels_produce_no_packets(lt, torch):
+    w = W.make_workload(1)
+    ctx = lt.Context.from_workload(w)
+    segs = lt.to_device(w.events[0])
+    full = ctx.simulate(segs, event_id=w.event_ids[0]).host()
+    rng = np.random.default_rng(8)
+    mask = rng.random(w.readout.n_x * w.readout.n_y) < 0.078           # Module-0 disabled fraction (Sec. 6)
+    ctx.set_channel_mask(mask)
+    part = ctx.simulate(segs, event_id=w.event_ids[0]).host()
+    assert np.array_equal(full["current"], part["current"])           # currents are still computed
+    keep = ~mask[full["pkt_pixel"]]
+    assert not mask[part["pkt_pixel"]].any()
+    assert np.array_equal(full["pkt_pixel"][keep], part["pkt_pixel"])
+    assert np.array_equal(full["pkt_tick"][keep], part["pkt_tick"])
+    assert np.array_equal(full["pkt_adc"][keep], part["pkt_adc"])
+    ctx.set_channel_mask(None)
+    again = ctx.simulate(segs, event_id=w.event_ids[0]).host()
+    assert np.array_equal(again["pkt_tick"], full["pkt_tick"])

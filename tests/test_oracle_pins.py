@@ -343,7 +343,7 @@ def test_brute_force_cross_check(orc, seed):
 def _el(case, **kw):
     return W.Electronics(threshold=case["threshold"], hold_ticks=case["hold_ticks"], min_spacing=case["min_spacing"],
                          q_lsb=case["q_lsb"], pedestal=case["pedestal"], adc_bits=case["adc_bits"], sigma_reset=0.0,
-                         sigma_disc=0.0, sigma_unc=0.0, max_packets=16, **kw)
+                         sigma_disc=0.0, sigma_unc=0.0, max_packets=16, reset_period=case.get("reset_period", 0), **kw)
 
 
 def test_hand_traced_electronics(orc):
