@@ -158,7 +158,7 @@ def main():
         args.also, args.batched, args.served = "", 0, None
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (events shard across GPUs "
-              f"with no exchange, see DESIGN.md)", file=sys.stderr)
+              f"with no exchange, so a multi-GPU run is one such process per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

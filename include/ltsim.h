@@ -57,6 +57,12 @@ typedef struct lts_physics {
     double z_anode;            /* cm */
     double sample_step;        /* cm; N = max(1, ceil(L / sample_step)) points per segment, eq. (rho) */
     double n_sigma;            /* diffusion truncation in sigmas (>= 1) */
+    int32_t mc_draws;          /* diffusion estimator of eq. (rho): 0 = expectation over the Gaussian perturbations
+                                  (deterministic); M in [1, 65535] = the paper's Monte Carlo form, M perturbations per
+                                  sample point drawn from Philox4x32-10 (key = electronics seed, counter = (segment
+                                  index within the event, point * M + draw, event id low word, (event id high word << 4)
+                                  | 3 + try)), each normal truncated to n_sigma by re-drawing; every moved copy puts
+                                  Q_a / (N M) into the cell that holds it */
 } lts_physics;
 
 /* Pixel plane and time sampling. */

@@ -38,7 +38,11 @@ def build(force: bool = True) -> str:
 class _Physics(C.Structure):
     _fields_ = [("recomb_model", C.c_int32)] + [(n, C.c_double) for n in (
         "e_field", "lar_density", "w_ion", "birks_ab", "birks_kb", "box_alpha", "box_beta", "v_drift", "lifetime",
-        "d_long", "d_tran", "z_anode", "sample_step", "n_sigma")]
+        "d_long", "d_tran", "z_anode", "sample_step", "n_sigma")] + [("mc_draws", C.c_int32)]
+
+
+class _MCKey(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("event_id", C.c_uint64)]
 
 
 class _Readout(C.Structure):
@@ -97,13 +101,13 @@ def lib():
         L.orc_bin_masses.argtypes = [C.c_double] * 5 + [C.c_int64, C.c_int64, C.POINTER(C.c_double)]
         L.orc_bin_masses.restype = None
         L.orc_segment_cells.argtypes = [C.POINTER(_Physics), C.POINTER(_Readout), C.POINTER(_Segments), C.c_int64,
-                                        C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+                                        C.POINTER(_MCKey), C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.orc_active_pixels.argtypes = [C.POINTER(_Physics), C.POINTER(_Readout), C.c_int32, C.c_int32, C.c_int32,
                                         C.POINTER(_Segments), C.POINTER(C.c_int32), C.c_int64]
         L.orc_active_pixels.restype = C.c_int64
         L.orc_waveforms.argtypes = [C.POINTER(_Physics), C.POINTER(_Readout), _FP, C.c_int32, C.c_int32, C.c_int32,
                                     C.POINTER(_Segments), C.POINTER(C.c_int32), C.c_int64, C.POINTER(C.c_double),
-                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(_MCKey)]
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         L.orc_philox4x32_10.restype = None
         L.orc_noise_normal.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32]
@@ -113,6 +117,9 @@ def lib():
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         L.orc_num_threads.restype = C.c_int
+        L.orc_mc_clear_near_edges.restype = None
+        L.orc_mc_near_edges.argtypes = [C.POINTER(C.c_int32), C.c_int64]
+        L.orc_mc_near_edges.restype = C.c_int64
         _LIB = L
     return _LIB
 
@@ -147,16 +154,22 @@ def bin_masses(mean, sigma, n_sigma, origin, width, k0, nk):
     return out
 
 
-def segment_cells(physics, readout, segs, i):
-    """(box, cells): box = (a0, na, u0, nu, v0, nv); cells[a, u, v] in FP64."""
+def _key(mc_key):
+    return None if mc_key is None else C.byref(_MCKey(int(mc_key[0]), int(mc_key[1])))
+
+
+def segment_cells(physics, readout, segs, i, mc_key=None):
+    """(box, cells): box = (a0, na, u0, nu, v0, nv); cells[a, u, v] in FP64.  mc_key = (seed, event_id) selects the
+    Monte Carlo draws when physics.mc_draws > 0."""
     h = _SegHolder(segs)
     box = np.zeros(6, np.int64)
     P, R = _fill(_Physics, physics), _fill(_Readout, readout)
-    rc = lib().orc_segment_cells(C.byref(P), C.byref(R), C.byref(h.s), i, _ptr(box, C.c_int64), None)
+    rc = lib().orc_segment_cells(C.byref(P), C.byref(R), C.byref(h.s), i, _key(mc_key), _ptr(box, C.c_int64), None)
     if rc:
         raise ValueError(f"orc_segment_cells rc={rc}")
     cells = np.zeros(int(box[1] * box[3] * box[5]))
-    rc = lib().orc_segment_cells(C.byref(P), C.byref(R), C.byref(h.s), i, _ptr(box, C.c_int64), _ptr(cells))
+    rc = lib().orc_segment_cells(C.byref(P), C.byref(R), C.byref(h.s), i, _key(mc_key), _ptr(box, C.c_int64),
+                                 _ptr(cells))
     if rc:
         raise ValueError(f"orc_segment_cells rc={rc}")
     return tuple(int(b) for b in box), cells.reshape(int(box[1]), int(box[3]), int(box[5]))
@@ -173,9 +186,9 @@ def active_pixels(physics, readout, table_shape, segs):
     return out[:n]
 
 
-def waveforms(physics, readout, table, segs, pixels, with_sums=False):
+def waveforms(physics, readout, table, segs, pixels, with_sums=False, mc_key=None):
     """FP64 waveforms [len(pixels), n_ticks], per-pixel clipped charge, and (if with_sums) the segment sums
-    (sum Q_R, sum Q_a, off-grid charge)."""
+    (sum Q_R, sum Q_a, off-grid charge).  mc_key = (seed, event_id) is required when physics.mc_draws > 0."""
     table = np.ascontiguousarray(table, dtype=np.float32)
     T, bx, by = table.shape
     pixels = np.ascontiguousarray(pixels, dtype=np.int32)
@@ -185,10 +198,24 @@ def waveforms(physics, readout, table, segs, pixels, with_sums=False):
     sums = np.zeros(3)
     rc = lib().orc_waveforms(C.byref(_fill(_Physics, physics)), C.byref(_fill(_Readout, readout)),
                              table.ctypes.data_as(_FP), T, bx, by, C.byref(h.s), _ptr(pixels, C.c_int32),
-                             len(pixels), _ptr(wave), _ptr(clipped), _ptr(sums) if with_sums else None)
+                             len(pixels), _ptr(wave), _ptr(clipped), _ptr(sums) if with_sums else None,
+                             _key(mc_key))
     if rc:
         raise ValueError(f"orc_waveforms rc={rc}")
     return (wave, clipped, sums) if with_sums else (wave, clipped)
+
+
+def mc_clear_near_edges():
+    lib().orc_mc_clear_near_edges()
+
+
+def mc_near_edges():
+    """(u, v) bins of the Monte Carlo draws recorded since the last clear that landed within 1e-5 of a bin or tick
+    edge (an FP32 evaluation may put them in the neighbouring cell)."""
+    n = int(lib().orc_mc_near_edges(None, 0))
+    out = np.zeros((max(n, 1), 2), np.int32)
+    n2 = int(lib().orc_mc_near_edges(_ptr(out, C.c_int32), n))
+    return out[:min(n, n2, 65536)]
 
 
 def philox4x32_10(ctr, key):
@@ -236,8 +263,11 @@ def simulate(workload, event_index=0, pixels=None, table=None, eps_rel=0.0, eps_
     full = pixels is None
     if full:
         pixels = active_pixels(workload.physics, workload.readout, workload.table, segs)
-    wave, clipped, sums = waveforms(workload.physics, workload.readout, table, segs, pixels, with_sums=full)
-    res = {"pixels": np.asarray(pixels, np.int32), "wave": wave, "clipped": clipped}
+    key = (workload.electronics.seed, workload.event_ids[event_index])
+    mc_clear_near_edges()
+    wave, clipped, sums = waveforms(workload.physics, workload.readout, table, segs, pixels, with_sums=full,
+                                    mc_key=key)
+    res = {"pixels": np.asarray(pixels, np.int32), "wave": wave, "clipped": clipped, "mc_near_edges": mc_near_edges()}
     if full:
         res["report"] = {"q_after_quench": sums[0], "q_collected": sums[1], "q_induced": float(wave.sum()),
                          "q_clipped": float(clipped.sum()), "q_offgrid": sums[2]}

@@ -13,6 +13,8 @@
  *      replaced by their M -> infinity expectation ("D-exact"): the probability that the perturbed point
  *      falls in each sub-pixel bin (x, y) and each tick (arrival time), a product of truncated-Gaussian
  *      bin masses (truncated at n_sigma and renormalised).
+ *      With mc_draws = M > 0 the paper's own estimator is used instead: each point is moved M times by Philox-keyed
+ *      Gaussian draws (truncated at n_sigma) and each moved copy puts Q_a / (N M) into the cell containing it.
  *   4. Induced current, Sec. 3.3.2, eq. (current): each charge cell (tick a, bin u, v) adds
  *      q * R[k, i, j] to pixel p at tick a - (T_R - 1) + k, where (i, j) is the bin's mirror-folded offset
  *      from the pixel centre (the table is quadrant-symmetric, Sec. 3.3.1) and the table is arrival-aligned.
@@ -21,7 +23,7 @@
  *      with reset / discriminator / uncorrelated Gaussian noise drawn from a counter-based Philox4x32-10
  *      generator (Salmon et al., SC'11) through Box-Muller.
  *
- * Readings of points the paper leaves open are listed in the design doc; the ones that change arithmetic here:
+ * Readings of points the paper leaves open that change arithmetic here:
  *   - the number of points N is an integer decided by floating point, so it is decided in FP32 exactly as
  *     the device decides it (sqrt / divide / ceil in IEEE single, no contraction);
  *   - arrival time of a point = its interpolated time + |z - z_anode| / v_d;
@@ -44,7 +46,14 @@ typedef struct {
     int32_t recomb_model;
     double e_field, lar_density, w_ion, birks_ab, birks_kb, box_alpha, box_beta;
     double v_drift, lifetime, d_long, d_tran, z_anode, sample_step, n_sigma;
+    int32_t mc_draws;       /* 0: expectation over the perturbations (D-exact); M > 0: M random draws per point */
 } orc_physics_params;
+
+/* Key of the Monte Carlo perturbations (used only when mc_draws > 0). */
+typedef struct {
+    uint64_t seed;          /* Philox key */
+    uint64_t event_id;
+} orc_mc_key;
 
 typedef struct {
     double pitch;
@@ -260,6 +269,125 @@ static int segment_cells(const orc_physics_params *ph, const orc_readout_params 
     return 0;
 }
 
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Four standard normals from one Philox block: Box-Muller on words (0, 1) gives g[0] (cosine branch) and g[1]
+ * (sine branch), on words (2, 3) g[2] and g[3]; each word x maps to u = (x + 1/2) 2^-32 in (0, 1). */
+static void philox_normals(const uint32_t ctr[4], const uint32_t key[2], double g[4])
+{
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    const double two_m32 = 2.3283064365386963e-10, two_pi = 6.283185307179586477;
+    for (int h = 0; h < 2; ++h) {
+        double u0 = ((double)x[2 * h] + 0.5) * two_m32;
+        double u1 = ((double)x[2 * h + 1] + 0.5) * two_m32;
+        double r = sqrt(-2.0 * log(u0));
+        g[2 * h] = r * cos(two_pi * u1);
+        g[2 * h + 1] = r * sin(two_pi * u1);
+    }
+}
+
+#define ORC_MC_TRIES 9
+
+/* Perturbation of draw (mu, m) of segment seg: normals (g_x, g_y, g_t) from the cosine and sine branches of words
+ * (0, 1) and the cosine branch of words (2, 3).  Each is a standard normal truncated to |g| <= nsig: a component
+ * outside is replaced by the same component of the next try (try r uses stream 3 + r; a component with no accepted
+ * value after nine tries, probability below 1e-50 at nsig >= 1, is set to 0).  Counter of try r:
+ * (seg, mu * M + m, event id low word, (event id high word << 4) | (3 + r)). */
+static void mc_perturbation(const orc_mc_key *k, double nsig, uint32_t seg, uint32_t draw, double g[3])
+{
+    const uint32_t key[2] = {(uint32_t)k->seed, (uint32_t)(k->seed >> 32)};
+    int have[3] = {0, 0, 0};
+    g[0] = g[1] = g[2] = 0.0;
+    for (uint32_t r = 0; r < ORC_MC_TRIES && !(have[0] && have[1] && have[2]); ++r) {
+        const uint32_t ctr[4] = {seg, draw, (uint32_t)k->event_id,
+                                 (uint32_t)((k->event_id >> 32) << 4) | ((3u + r) & 15u)};
+        double gg[4];
+        philox_normals(ctr, key, gg);
+        for (int a = 0; a < 3; ++a)
+            if (!have[a] && fabs(gg[a]) <= nsig) { g[a] = gg[a]; have[a] = 1; }
+    }
+}
+
+/* Draws that land within a small margin of a sub-pixel or tick edge (1e-5 of the bin) are those whose cell an FP32
+ * evaluation of the same position may legitimately decide differently; their (u, v) bins are recorded so a
+ * comparison can flag the pixels in their reach.  The record is cleared by orc_mc_clear_near_edges. */
+#define ORC_NEAR_CAP 65536
+static int64_t g_near_n = 0;
+static int32_t g_near_uv[2 * ORC_NEAR_CAP];
+
+static int near_edge(double y, double origin, double width)
+{
+    double f = (y - origin) / width;
+    double d = f - floor(f);
+    return d < 1e-5 || d > 1.0 - 1e-5;
+}
+
+void orc_mc_clear_near_edges(void) { g_near_n = 0; }
+
+/* Number of near-edge draws recorded since the last clear; copies up to cap (u, v) pairs to uv. */
+int64_t orc_mc_near_edges(int32_t *uv, int64_t cap)
+{
+    int64_t n = g_near_n < ORC_NEAR_CAP ? g_near_n : ORC_NEAR_CAP;
+    for (int64_t k = 0; k < n && k < cap; ++k) { uv[2 * k] = g_near_uv[2 * k]; uv[2 * k + 1] = g_near_uv[2 * k + 1]; }
+    return g_near_n;
+}
+
+/* The paper's estimator of the charge density (eq. (rho)): every point is moved M times by a random 3-D Gaussian
+ * perturbation (transverse sigma_T in x and y, longitudinal sigma_L / v_d in arrival time) and each moved copy
+ * carries q / M into the cell (tick, sub-pixel bin) that contains it.  Cells are integer hit counts times q / M. */
+static int segment_cells_mc(const orc_physics_params *ph, const orc_readout_params *ro, const orc_segments *sg,
+                            int64_t i, const orc_seginfo *si, const orc_mc_key *key, orc_cells *cb)
+{
+    segment_box(ph, ro, sg, i, si, cb);
+    size_t ncell = (size_t)(cb->na * cb->nu * cb->nv);
+    int64_t *hits = (int64_t *)calloc(ncell ? ncell : 1, sizeof(int64_t));
+    cb->c = (double *)calloc(ncell ? ncell : 1, sizeof(double));
+    if (!hits || !cb->c) return -1;
+    const double b = ro->pitch / ro->n_sub;
+    const int32_t M = ph->mc_draws;
+    for (int32_t mu = 0; mu < si->n_points; ++mu) {
+        double x, y, t;
+        point_at(ph, sg, i, si->n_points, mu, &x, &y, &t);
+        for (int32_t m = 0; m < M; ++m) {
+            double g[3];
+            mc_perturbation(key, ph->n_sigma, (uint32_t)i, (uint32_t)((int64_t)mu * M + m), g);
+            int64_t u = (int64_t)floor((x + si->sigma_t * g[0] - ro->x0) / b);
+            int64_t v = (int64_t)floor((y + si->sigma_t * g[1] - ro->y0) / b);
+            int64_t a = (int64_t)floor((t + si->sigma_time * g[2] - ro->t_begin) / ro->tick);
+            if (near_edge(x + si->sigma_t * g[0], ro->x0, b) || near_edge(y + si->sigma_t * g[1], ro->y0, b) ||
+                near_edge(t + si->sigma_time * g[2], ro->t_begin, ro->tick)) {
+#pragma omp critical(orc_near)
+                {
+                    if (g_near_n < ORC_NEAR_CAP) {
+                        g_near_uv[2 * g_near_n] = (int32_t)u;
+                        g_near_uv[2 * g_near_n + 1] = (int32_t)v;
+                    }
+                    ++g_near_n;
+                }
+            }
+            if (u < cb->u0 || u >= cb->u0 + cb->nu || v < cb->v0 || v >= cb->v0 + cb->nv || a < cb->a0 ||
+                a >= cb->a0 + cb->na) {
+                free(hits);
+                return -4;                        /* cannot happen: the box holds the truncated cloud */
+            }
+            hits[((a - cb->a0) * cb->nu + (u - cb->u0)) * cb->nv + (v - cb->v0)] += 1;
+        }
+    }
+    const double w = si->q_a / si->n_points / M;
+    for (size_t c = 0; c < ncell; ++c) cb->c[c] = (double)hits[c] * w;
+    free(hits);
+    return 0;
+}
+
+/* cells of one segment by the estimator the parameters select */
+static int cells_of(const orc_physics_params *ph, const orc_readout_params *ro, const orc_segments *sg, int64_t i,
+                    const orc_seginfo *si, const orc_mc_key *key, orc_cells *cb)
+{
+    if (ph->mc_draws > 0) return key ? segment_cells_mc(ph, ro, sg, i, si, key, cb) : -3;
+    return segment_cells(ph, ro, sg, i, si, cb);
+}
+
 /* mirror fold of a bin offset k from the pixel centre: k >= 0 -> k, k < 0 -> -k-1 */
 static inline int64_t fold(int64_t k) { return k >= 0 ? k : -k - 1; }
 
@@ -293,10 +421,11 @@ void orc_bin_masses(double mean, double sigma, double nsig, double origin, doubl
     }
 }
 
-/* Charge cells of one segment.  box[6] = a0, na, u0, nu, v0, nv.  If cells == NULL only the box is
- * returned; otherwise cells must hold na*nu*nv doubles (layout [a][u][v]). */
+/* Charge cells of one segment (index i of the event's segments).  box[6] = a0, na, u0, nu, v0, nv.  If cells == NULL
+ * only the box is returned; otherwise cells must hold na*nu*nv doubles (layout [a][u][v]).  key: Monte Carlo key,
+ * required when ph->mc_draws > 0 (else -3). */
 int orc_segment_cells(const orc_physics_params *ph, const orc_readout_params *ro, const orc_segments *sg, int64_t i,
-                      int64_t *box, double *cells)
+                      const orc_mc_key *key, int64_t *box, double *cells)
 {
     orc_seginfo si;
     segment_physics(ph, sg, i, &si);
@@ -305,7 +434,8 @@ int orc_segment_cells(const orc_physics_params *ph, const orc_readout_params *ro
     if (!cells) {
         segment_box(ph, ro, sg, i, &si, &cb);
     } else {
-        if (segment_cells(ph, ro, sg, i, &si, &cb)) return -1;
+        int rc = cells_of(ph, ro, sg, i, &si, key, &cb);
+        if (rc) return rc;
         memcpy(cells, cb.c, sizeof(double) * (size_t)(cb.na * cb.nu * cb.nv));
         free(cb.c);
     }
@@ -368,11 +498,12 @@ int64_t orc_active_pixels(const orc_physics_params *ph, const orc_readout_params
  *   wave:  n_pix * n_ticks doubles (output).
  *   clipped: per listed pixel, the summed contribution that fell outside [0, n_ticks) (output, may be NULL).
  *   seg_sums (may be NULL): 3 doubles: sum Q_R, sum Q_a, off-grid charge (cells outside the pixel grid).
- * Returns 0, or -2 if a segment is invalid, -1 on allocation failure.
+ *   key: Monte Carlo key (event id, seed), required when ph->mc_draws > 0.
+ * Returns 0, or -2 if a segment is invalid, -1 on allocation failure or a missing key.
  */
 int orc_waveforms(const orc_physics_params *ph, const orc_readout_params *ro, const float *table, int32_t t_r, int32_t bx,
                   int32_t by, const orc_segments *sg, const int32_t *pixels, int64_t n_pix, double *wave,
-                  double *clipped, double *seg_sums)
+                  double *clipped, double *seg_sums, const orc_mc_key *key)
 {
     int64_t nseg = sg->n;
     int64_t nt = ro->n_ticks;
@@ -412,7 +543,7 @@ int orc_waveforms(const orc_physics_params *ph, const orc_readout_params *ro, co
     }
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
     for (int64_t s = 0; s < nseg; ++s)
-        if (need[s] && segment_cells(ph, ro, sg, s, &si[s], &cb[s])) err = 1;
+        if (need[s] && cells_of(ph, ro, sg, s, &si[s], key, &cb[s])) err = 1;
     if (err) return -1;
 
     if (seg_sums) {

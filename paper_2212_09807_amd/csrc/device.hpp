@@ -35,6 +35,7 @@ struct DevParams {
     float birks_ab, birks_kb_eps, box_alpha, box_beta_eps, inv_w_ion;
     float inv_vd_hi, inv_vd_lo, inv_lifetime, two_dl, two_dt, za_hi, za_lo;
     float step, nsig, inv_norm;             // inv_norm = 1 / P(|g| <= n_sigma)
+    int32_t mc_draws;                       // 0: expectation over the diffusion draws; M > 0: M draws per point
     // grid
     float b_hi, b_lo, x0_hi, x0_lo, y0_hi, y0_lo, tick_hi, tick_lo, tb_hi, tb_lo;
     int32_t nx, ny, nsub, nticks, npx;
@@ -144,6 +145,42 @@ __device__ __forceinline__ float noise_normal(const DevParams &P, uint32_t pixel
     float u0 = fmaf((float)x.x, 0x1p-32f, 0x1p-33f);
     float u1 = fmaf((float)x.y, 0x1p-32f, 0x1p-33f);
     return sqrtf(-2.0f * logf(u0)) * cospif(2.0f * u1);
+}
+
+// Diffusion perturbation of draw `draw` (= point * M + m) of segment `seg` of an event (Monte Carlo form of
+// eq. (rho)): the cosine and sine Box-Muller branches of words (0, 1) give the x and y normals, the cosine branch of
+// words (2, 3) the arrival-time normal.  Each normal is truncated to |g| <= n_sigma: a component outside is replaced
+// by the same component of the next try (try r uses stream 3 + r, nine tries; none accepted leaves 0).
+constexpr int kMcTries = 9;
+__device__ __forceinline__ void mc_normals(const DevParams &P, uint32_t seg, uint32_t draw, uint64_t event, float &gx,
+                                           float &gy, float &gt) {
+    gx = gy = gt = 0.0f;
+    bool hx = false, hy = false, ht = false;
+    for (uint32_t r = 0; r < (uint32_t)kMcTries && !(hx && hy && ht); ++r) {
+        const uint4 c = make_uint4(seg, draw, (uint32_t)event, (uint32_t)((event >> 32) << 4) | ((STREAM_MC + r) & 15u));
+        const uint4 x = philox4x32_10(c, P.key0, P.key1);
+        const float r0 = sqrtf(-2.0f * logf(fmaf((float)x.x, 0x1p-32f, 0x1p-33f)));
+        const float a0 = 2.0f * fmaf((float)x.y, 0x1p-32f, 0x1p-33f);
+        const float r1 = sqrtf(-2.0f * logf(fmaf((float)x.z, 0x1p-32f, 0x1p-33f)));
+        const float a1 = 2.0f * fmaf((float)x.w, 0x1p-32f, 0x1p-33f);
+        const float cx = r0 * cospif(a0), cy = r0 * sinpif(a0), ct = r1 * cospif(a1);
+        if (!hx && fabsf(cx) <= P.nsig) { gx = cx; hx = true; }
+        if (!hy && fabsf(cy) <= P.nsig) { gy = cy; hy = true; }
+        if (!ht && fabsf(ct) <= P.nsig) { gt = ct; ht = true; }
+    }
+}
+
+// Index of the bin of local coordinate y on a grid of edges k * (wh + wl) (the same edge expression as the bin
+// masses use), from a first guess by division.
+__device__ __forceinline__ int32_t local_bin(float y, float wh, float wl) {
+    float kf = floorf(__fdiv_rn(y, wh));
+    if (__fadd_rn(fmaf(kf, wh, -y), __fmul_rn(kf, wl)) > 0.0f) {
+        kf -= 1.0f;
+    } else {
+        const float k1 = kf + 1.0f;
+        if (__fadd_rn(fmaf(k1, wh, -y), __fmul_rn(k1, wl)) <= 0.0f) kf = k1;
+    }
+    return (int32_t)kf;
 }
 
 // ------------------------------------------------------------------------------------------------ Gaussian

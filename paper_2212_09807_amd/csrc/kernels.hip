@@ -444,7 +444,43 @@ __device__ void axis_masses(float l, float sigma, int32_t k0, int32_t nk, float 
 
 constexpr int kCellLds = 12288;   // floats (48 KB)
 
-__global__ __launch_bounds__(kWG) void k_cells(DevParams P, const SegInfo *si, int64_t n_seg, float *cells, double *report) {
+// Monte Carlo cells of one segment (the paper's estimator of eq. (rho) with M = P.mc_draws perturbations per point):
+// every moved copy of a sample point adds one hit to the cell that contains it (integer counts, in LDS when the box
+// fits, else in the cell buffer itself), then cell = hits * q / M.  Counts make the result independent of the order
+// in which the workgroup's threads land their hits.
+__device__ void mc_cells(const DevParams &P, const SegInfo &g, uint32_t seg, uint64_t event, float *out,
+                         uint32_t *lds, int64_t ncell) {
+    const int tid = threadIdx.x;
+    const bool in_lds = ncell <= kCellLds;
+    uint32_t *hist = in_lds ? lds : (uint32_t *)out;
+    for (int64_t c = tid; c < ncell; c += kWG) hist[c] = 0u;
+    __threadfence();
+    __syncthreads();
+    const uint32_t M = (uint32_t)P.mc_draws;
+    const int64_t nd = (int64_t)g.n_points * M;
+    for (int64_t d = tid; d < nd; d += kWG) {
+        float lx, ly, lt, gx, gy, gt;
+        point_local(g, P, (int32_t)(d / M), lx, ly, lt);
+        mc_normals(P, seg, (uint32_t)d, event, gx, gy, gt);
+        // the truncated cloud lies inside the box; the clamps only guard the memory
+        const int32_t u = min(max(g.u_ref + local_bin(fmaf(g.sigma_t, gx, lx), P.b_hi, P.b_lo) - g.u0, 0), g.nu - 1);
+        const int32_t v = min(max(g.v_ref + local_bin(fmaf(g.sigma_t, gy, ly), P.b_hi, P.b_lo) - g.v0, 0), g.nv - 1);
+        const int32_t a =
+            min(max(g.a_ref + local_bin(fmaf(g.sigma_time, gt, lt), P.tick_hi, P.tick_lo) - g.a0, 0), g.na - 1);
+        atomicAdd(&hist[((int64_t)u * g.nv + v) * g.na_pad + a], 1u);
+    }
+    __threadfence();
+    __syncthreads();
+    const float w = __fdiv_rn(g.q_pt, (float)M);
+    for (int64_t c = tid; c < ncell; c += kWG) {
+        const uint32_t h = in_lds ? hist[c] : __hip_atomic_load(&hist[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        out[c] = (float)h * w;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kWG) void k_cells(DevParams P, const SegInfo *si, int64_t n_seg, float *cells,
+                                               const int64_t *seg_ev_off, const uint64_t *event_ids, double *report) {
     __shared__ float sm[kCellLds];
     __shared__ double red[kWG / 64];
     const int tid = threadIdx.x;
@@ -457,7 +493,9 @@ __global__ __launch_bounds__(kWG) void k_cells(DevParams P, const SegInfo *si, i
         float *fx = sm, *fy = sm + pc * nu, *ft = fy + pc * nv;
         const int64_t ncell = (int64_t)nu * nv * nap;
         float *out = cells + g.cell_off;
-        for (int32_t mu0 = 0; mu0 < N; mu0 += pc) {
+        if (P.mc_draws > 0)
+            mc_cells(P, g, (uint32_t)(s - seg_ev_off[g.event]), event_ids[g.event], out, (uint32_t *)sm, ncell);
+        for (int32_t mu0 = 0; mu0 < (P.mc_draws > 0 ? 0 : N); mu0 += pc) {
             const int32_t np = min(pc, N - mu0);
             for (int r = tid; r < np * 3; r += kWG) {
                 const int32_t m = r / 3, ax = r - 3 * (r / 3);
@@ -510,7 +548,7 @@ __global__ __launch_bounds__(kWG) void k_cells(DevParams P, const SegInfo *si, i
 void launch_cells(const DevParams &P, const Work &w, hipStream_t st) {
     if (w.n_seg <= 0) return;
     int64_t g = w.n_seg > 8192 ? 8192 : w.n_seg;
-    k_cells<<<(unsigned)g, kWG, 0, st>>>(P, w.si, w.n_seg, w.cells, w.report);
+    k_cells<<<(unsigned)g, kWG, 0, st>>>(P, w.si, w.n_seg, w.cells, w.seg_ev_off, w.event_ids, w.report);
 }
 
 // ================================================================================================= induction

@@ -7,6 +7,7 @@ Bars (per output):
     (ADC value near an LSB boundary, or the pixel's timeline after a near-threshold decision);
   * charge report: FP64 sums within the FP32 accumulation error.
 """
+import dataclasses
 import json
 import os
 
@@ -58,14 +59,33 @@ def gpu_packets_by_pixel(h):
     return out
 
 
-def compare_packets(h, pixels, orc_pk, ufrom):
-    """Return (compared, flagged, mismatches) over the oracle's pixels."""
+def near_edge_pixels(w, uv):
+    """Pixels whose table reach holds a bin where a Monte Carlo draw landed within FP32 reach of a bin edge."""
+    ro, tb = w.readout, w.table
+    out = set()
+    for u, v in uv:
+        for ix in range(max(0, (u - tb.b_x) // ro.n_sub - 1), min(ro.n_x, (u + tb.b_x) // ro.n_sub + 2)):
+            for iy in range(max(0, (v - tb.b_y) // ro.n_sub - 1), min(ro.n_y, (v + tb.b_y) // ro.n_sub + 2)):
+                uc, vc = ix * ro.n_sub + ro.n_sub // 2, iy * ro.n_sub + ro.n_sub // 2
+                if -tb.b_x <= u - uc < tb.b_x and -tb.b_y <= v - vc < tb.b_y:
+                    out.add(iy * ro.n_x + ix)
+    return out
+
+
+def compare_packets(h, pixels, orc_pk, ufrom, uncertain_pixels=()):
+    """Return (compared, flagged, mismatches) over the oracle's pixels.  A pixel in `uncertain_pixels` whose
+    packets differ counts as flagged (its current may legitimately differ by a draw landing across a bin edge)."""
     gb = gpu_packets_by_pixel(h)
     compared = flagged = 0
     bad = []
     for q, p in enumerate(pixels):
         ot, oa, of = orc_pk[q]
         uf = int(ufrom[q])
+        if int(p) in uncertain_pixels:
+            g = gb.get(int(p), [])
+            if [(int(t), int(a)) for t, a in zip(ot, oa)] != [(x[0], x[1]) for x in g]:
+                flagged += len(ot)
+                continue
         g = gb.get(int(p), [])
         gt = np.array([x[0] for x in g], np.int64)
         ga = np.array([x[1] for x in g], np.int64)
@@ -105,7 +125,8 @@ def check_event(lt, orc, w, ev=0, mode=0, table=None, slices=1):
     assert rep_g[2] == pytest.approx(rep_o["q_induced"], abs=1e-5 * scale)
     assert rep_g[3] == pytest.approx(rep_o["q_clipped"], abs=1e-5 * scale)
     assert rep_g[4] == pytest.approx(rep_o["q_offgrid"], abs=1e-5 * scale)
-    cmp_, flg, bad = compare_packets(h, opix, r["packets"], r["uncertain_from"])
+    unc = near_edge_pixels(w, r["mc_near_edges"]) if w.physics.mc_draws > 0 else ()
+    cmp_, flg, bad = compare_packets(h, opix, r["packets"], r["uncertain_from"], unc)
     assert not bad, bad[:5]
     return h, r, e, (cmp_, flg)
 
@@ -404,3 +425,38 @@ def test_disabled_channels_produce_no_packets(lt, torch):
     ctx.set_channel_mask(None)
     again = ctx.simulate(segs, event_id=w.event_ids[0]).host()
     assert np.array_equal(again["pkt_tick"], full["pkt_tick"])
+
+
+# ----------------------------------------------------------------------------------------------- Monte Carlo diffusion
+
+@pytest.mark.parametrize("cfg,M,mode", [(1, 1, 0), (1, 16, 0), (1, 16, 2), (1, 64, 1)])
+def test_mc_diffusion_parity(lt, orc, torch, cfg, M, mode):
+    """The paper's estimator (M Philox-keyed perturbations per point): the device draws the same normals as the
+    oracle, so currents meet the same bar; packets are exact except on pixels in reach of a draw that landed within
+    FP32 reach of a bin edge (recorded by the oracle)."""
+    w = W.make_workload(cfg)
+    w.physics = dataclasses.replace(w.physics, mc_draws=M)
+    h, r, e, (cmp_, flg) = check_event(lt, orc, w, 0, mode)
+    print(f"[mc] cfg{cfg} M={M} mode={mode}: pixels {len(r['pixels'])}, max e_p {e.max():.2e}, packets compared "
+          f"{cmp_}, flagged {flg}, near-edge draws {len(r['mc_near_edges'])}")
+    # the expectation differs from one Monte Carlo realisation by far more than the bar
+    w0 = dataclasses.replace(w.physics, mc_draws=0)
+    w.physics = w0
+    r0 = orc.simulate(w, 0, pixels=r["pixels"], with_packets=False)
+    assert per_pixel_errors(h["current"][np.searchsorted(h["pixel_id"], r["pixels"])].astype(np.float64),
+                            r0["wave"]).max() > 10 * TOL_WAVE
+
+
+def test_mc_diffusion_batch_invariant(lt, torch):
+    """Draws are keyed by (event id, segment index in the event): a batch gives each event's single-call result."""
+    w = W.make_workload(3, n_events=3)
+    w.events = [e.subset(np.arange(0, min(e.n, 3000))) for e in w.events]
+    w.physics = dataclasses.replace(w.physics, mc_draws=8)
+    ctx = lt.Context.from_workload(w)
+    singles = [ctx.simulate(lt.to_device(e), event_id=i).host() for e, i in zip(w.events, w.event_ids)]
+    offs = np.r_[0, np.cumsum([e.n for e in w.events])]
+    b = ctx.simulate_batch(lt.to_device(W.Segments.concat(w.events)), offs, w.event_ids).host()
+    po = b["event_pixel_offsets"]
+    for e, s in enumerate(singles):
+        assert np.array_equal(b["pixel_id"][po[e]:po[e + 1]], s["pixel_id"])
+        assert np.array_equal(b["current"][po[e]:po[e + 1]], s["current"])

@@ -1,0 +1,137 @@
+"""Pins of the oracle's Monte Carlo diffusion estimator (Sec. 3.3.2, eq. (rho) with M random perturbations per
+sample point) against the mathematics, on the CPU.
+
+The estimator's expectation is the D-exact charge density, its total is the segment's charge exactly, it reduces
+to the D-exact cells when there is no diffusion, and its per-axis draws follow the truncated normal (rejection
+re-draws included).  A wrong axis, sign, bin edge, truncation or charge weight fails one of these.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2212_09807_amd import workloads as W
+
+SEED, EVENT = 0x2212098070000000 + 1, 7
+
+
+def _ro():
+    return W.Readout(n_x=12, n_y=12, n_ticks=400)
+
+
+def _segment(r0, r1, dedx=2.1, t=0.0):
+    r0, r1 = np.asarray(r0, float), np.asarray(r1, float)
+    L = float(np.linalg.norm(r1 - r0))
+    return W.make_segments([r0], [r1], [dedx * L if L > 0 else dedx * 0.01], t0=[t], t1=[t], dedx=[dedx])
+
+
+def test_mc_mean_is_dexact_and_charge_is_conserved(orc):
+    """Cell by cell, MC cells differ from the D-exact cells by sampling noise only: with the variance bound
+    var <= (q / M) * c_D the z-scores stay below 6 and their mean square is about one; the MC total is Q_a."""
+    ro = _ro()
+    M = 400
+    ph = W.Physics(d_tran=4e-5, d_long=2e-5, mc_draws=M)             # wide clouds: many cells
+    segs = _segment([2.10, 2.30, 10.0], [2.16, 2.26, 10.05])
+    box_d, c_d = orc.segment_cells(dataclasses.replace(ph, mc_draws=0), ro, segs, 0)
+    box_m, c_m = orc.segment_cells(ph, ro, segs, 0, mc_key=(SEED, EVENT))
+    assert box_d == box_m
+    qd = orc.quench_drift(ph, segs)
+    q_a, n = qd["q_a"][0], int(qd["n_points"][0])
+    assert c_m.sum() == pytest.approx(q_a, rel=1e-12)
+    assert c_d.sum() == pytest.approx(q_a, rel=1e-9)
+    w = q_a / n / M
+    # every MC cell is an integer number of hits of weight q / M
+    hits = c_m / w
+    assert np.allclose(hits, np.round(hits), atol=1e-6)
+    assert int(np.round(hits).sum()) == n * M
+    m = c_d > 20 * w                                                 # cells expecting >= 20 hits
+    z = (c_m[m] - c_d[m]) / np.sqrt(w * c_d[m])
+    assert m.sum() > 200
+    assert np.abs(z).max() < 6.0
+    assert 0.6 < float(np.mean(z ** 2)) < 1.15
+    # the sparse cells together: their hit total is Poisson-like around its expectation
+    lo_exp, lo_obs = c_d[~m].sum() / w, hits[~m].sum()
+    assert abs(lo_obs - lo_exp) < 6 * np.sqrt(lo_exp) + 1
+    # no hits where the D-exact density is zero (outside the truncated cloud)
+    assert np.all(c_m[c_d == 0.0] == 0.0)
+
+
+def test_mc_without_diffusion_is_dexact(orc):
+    """sigma = 0: every copy of a point stays in the point's own cell, so MC and D-exact agree exactly."""
+    ro = _ro()
+    ph = W.Physics(d_tran=0.0, d_long=0.0, mc_draws=7)
+    segs = _segment([1.01, 2.02, 3.0], [1.33, 2.11, 3.4], t=0.55)
+    _, c_d = orc.segment_cells(dataclasses.replace(ph, mc_draws=0), ro, segs, 0)
+    _, c_m = orc.segment_cells(ph, ro, segs, 0, mc_key=(SEED, EVENT))
+    np.testing.assert_allclose(c_m, c_d, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("n_sigma", [1.5, 5.0])
+def test_mc_marginals_follow_the_truncated_normal(orc, n_sigma):
+    """A point deposit (one sample point) with many draws: the x, y and arrival-time marginals of the hits are the
+    truncated-normal bin masses (chi-square), including at a tight truncation where a draw is re-drawn 13 % of
+    the time; x and y come from different normals (their hit correlation vanishes)."""
+    ro = _ro()
+    M = 20000
+    ph = W.Physics(d_tran=4e-5, d_long=2e-5, mc_draws=M, n_sigma=n_sigma)
+    segs = _segment([2.2, 2.4, 12.0], [2.2, 2.4, 12.0], t=0.3)
+    (a0, na, u0, nu, v0, nv), c = orc.segment_cells(ph, ro, segs, 0, mc_key=(SEED, EVENT))
+    qd = orc.quench_drift(ph, segs)
+    hits = np.round(c / (qd["q_a"][0] / M)).astype(np.int64)
+    assert hits.sum() == M
+    b = ro.pitch / ro.n_sub
+    xf, yf = float(np.float32(2.2)), float(np.float32(2.4))
+    tarr = float(np.float32(0.3)) + float(np.float32(12.0)) / ph.v_drift
+    sig_t, sig_time = qd["sigma_t"][0], qd["sigma_time"][0]
+    for axis, (k0, nk, mean, sig, width, origin) in enumerate(
+            [(a0, na, tarr, sig_time, ro.tick, ro.t_begin), (u0, nu, xf, sig_t, b, ro.x0), (v0, nv, yf, sig_t, b, ro.y0)]):
+        obs = hits.sum(axis=tuple(i for i in range(3) if i != axis))
+        edges = origin + (k0 + np.arange(nk + 1)) * width
+        cdf = stats.truncnorm.cdf(edges, -n_sigma, n_sigma, loc=mean, scale=sig)
+        exp = M * np.diff(cdf)
+        keep = exp > 5
+        chi2 = float(((obs[keep] - exp[keep]) ** 2 / exp[keep]).sum())
+        dof = int(keep.sum()) - 1
+        assert stats.chi2.sf(chi2, dof) > 1e-4, (axis, chi2, dof)
+        assert obs[~keep].sum() <= max(30, 5 * exp[~keep].sum())
+    hu, hv = hits.sum(axis=(0, 2)), hits.sum(axis=(0, 1))
+    uu, vv = np.meshgrid(np.arange(nu), np.arange(nv), indexing="ij")
+    huv = hits.sum(axis=0)
+    cov = (huv * uu * vv).sum() / M - (hu * np.arange(nu)).sum() / M * (hv * np.arange(nv)).sum() / M
+    sd = np.sqrt(((hu * np.arange(nu) ** 2).sum() / M - ((hu * np.arange(nu)).sum() / M) ** 2) *
+                 ((hv * np.arange(nv) ** 2).sum() / M - ((hv * np.arange(nv)).sum() / M) ** 2))
+    assert abs(cov / sd) < 5.0 / np.sqrt(M)
+
+
+def test_mc_draws_depend_on_counter_fields(orc):
+    """Different event ids, keys or segment positions give different draws; the same ones give the same."""
+    ro = _ro()
+    ph = W.Physics(d_tran=4e-5, d_long=2e-5, mc_draws=50)
+    s = _segment([2.10, 2.30, 10.0], [2.16, 2.26, 10.05])
+    _, a = orc.segment_cells(ph, ro, s, 0, mc_key=(SEED, EVENT))
+    _, b = orc.segment_cells(ph, ro, s, 0, mc_key=(SEED, EVENT))
+    _, c = orc.segment_cells(ph, ro, s, 0, mc_key=(SEED, EVENT + 1))
+    _, d = orc.segment_cells(ph, ro, s, 0, mc_key=(SEED + 1, EVENT))
+    two = W.Segments.concat([s, s])
+    _, e = orc.segment_cells(ph, ro, two, 1, mc_key=(SEED, EVENT))
+    assert np.array_equal(a, b)
+    for other in (c, d, e):
+        assert not np.array_equal(a, other)
+        assert other.sum() == pytest.approx(a.sum(), rel=1e-12)
+
+
+def test_mc_requires_a_key(orc):
+    ph = W.Physics(mc_draws=3)
+    with pytest.raises(ValueError):
+        orc.segment_cells(ph, _ro(), _segment([1, 1, 1], [1.1, 1, 1]), 0)
+
+
+def test_mc_event_conserves_charge(orc):
+    """Whole cfg1 event with M = 8 draws per point: induced + clipped + off-grid charge equals the collected
+    charge (collecting table columns sum to one, the others to zero), as for the expectation."""
+    w = W.make_workload(1)
+    w.physics = dataclasses.replace(w.physics, mc_draws=8)
+    r = orc.simulate(w, with_packets=False)
+    rep = r["report"]
+    assert rep["q_induced"] + rep["q_clipped"] + rep["q_offgrid"] == pytest.approx(rep["q_collected"], rel=1e-7)
