@@ -27,6 +27,30 @@ PEAK_FP32_FMA_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 
+def kernel_source_digest():
+    """SHA-256 over the device sources (kernels.hip, device.hpp): identifies the kernel build a profile was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2212_09807_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel):
+    """Memory traffic per launch of `kernel` (bytes read + written beyond L2, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+    counters scaled by a plain copy's readings), taken from the committed profile summaries; None unless a summary
+    was recorded on the current kernel sources."""
+    import glob
+    digest = kernel_source_digest()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(f):
+            if line.startswith("traffic-record:"):
+                kv = dict(t.split("=", 1) for t in line.split()[1:])
+                if kv.get("kernel") == kernel and kv.get("source") == digest:
+                    return float(kv["read_bytes"]) + float(kv["write_bytes"])
+    return None
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The oracle as it stands, on the first S segments of the same event (all pixels they reach, full window,
     electronics); S grows until the run takes about budget_s."""
@@ -113,10 +137,16 @@ def served(ltsim, W, rate_hz, n_events, mode, lanes=2):
             "mean_batch_events": float(np.mean([r["batch_events"] for r in res])), "lanes": lanes}
 
 
-def time_mode(ltsim, w, segs, mode, steps):
-    """Whole path in another reduce mode on the same device-resident event: segments/s and its induction roofline."""
+MODES = {"sorted": (0, 0), "atomic": (1, 0), "summed": (2, 0), "sorted-shift": (0, 1)}   # (reduce, lane exchange)
+
+
+def time_mode(ltsim, w, segs, name, steps):
+    """Whole path in another variant (reduce mode, and for the per-pair kernels whether lanes exchange table
+    windows) on the same device-resident event: segments/s and its induction roofline."""
     import torch
+    mode, shift = MODES[name]
     ctx = ltsim.Context.from_workload(w, reduce_mode=mode)
+    ctx.set_lane_exchange(shift)
     need = ctx.plan(segs)
     out = ctx._alloc(need["pixels"], need["packets"], 1, False)
     ctx.simulate(segs, event_id=w.event_ids[0], out=out)
@@ -151,11 +181,15 @@ def main():
     ap.add_argument("--served", type=float, nargs=2, default=(2.0, 16), metavar=("RATE_HZ", "N"),
                     help="also serve N spill events arriving as a Poisson process at RATE_HZ")
     ap.add_argument("--slices", type=int, default=1)
-    ap.add_argument("--also", default="summed", help="comma-separated other reduce modes to time on the same event")
-    ap.add_argument("--quick", action="store_true", help="only the headline path (no other modes, batch or serving)")
+    ap.add_argument("--also", default=None,
+                    help="comma-separated other reduce modes to time on the same event (default: summed; none with --quick)")
+    ap.add_argument("--quick", action="store_true", help="only the headline path (no batch or serving, and no other "
+                                                         "modes unless --also names them)")
     args = ap.parse_args()
     if args.quick:
-        args.also, args.batched, args.served = "", 0, None
+        args.batched, args.served = 0, None
+    if args.also is None:
+        args.also = "" if args.quick else "summed"
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (events shard across GPUs "
               f"with no exchange, so a multi-GPU run is one such process per GPU)", file=sys.stderr)
@@ -221,14 +255,16 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
         "stage_ms": {k: (v[0] / max(v[1], 1)) for k, v in timing.items()},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_FMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_FMA_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_FMA_TFLOPS,
+                     "traffic": profiled_traffic("k_induce_atomic" if args.mode == "atomic" else "k_induce_sorted"),
+                     "traffic_unit": "bytes per launch beyond L2 (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "kernel_source": kernel_source_digest(),
                      "kernel": "k_induce_atomic" if args.mode == "atomic" else "k_induce_sorted",
                      "flops_per_launch": 2.0 * stats["fma"], "launch_ms": ind_s * 1e3},
     }
     line["config"]["induce_slices"] = args.slices if args.mode == "sorted" else 1
     for other in [m for m in args.also.split(",") if m and m != args.mode]:
-        line.setdefault("modes", {})[other] = time_mode(ltsim, w, segs, {"sorted": 0, "atomic": 1, "summed": 2}[other],
-                                                        args.steps)
+        line.setdefault("modes", {})[other] = time_mode(ltsim, w, segs, other, args.steps)
     if args.batched:
         line["batched"] = batched_vs_plain(ltsim, W, args.batched, mode)
     if args.served:

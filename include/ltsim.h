@@ -176,6 +176,12 @@ lts_status lts_set_induce_slices(lts_context *ctx, int32_t slices);
  * (1, 2, 4 or 8; 0 = the smallest that covers the table length plus a typical charge extent). */
 lts_status lts_set_ticks_per_thread(lts_context *ctx, int32_t rt);
 
+/* Per-pair induction with 8-tick tiles: 1 = lanes share each table window by shifting it one lane per cell-tick
+ * block (one coalesced load per column and lane); 0 (default, faster on gfx950) = every lane loads its own 15-value
+ * window per block.
+ * Both give the same sums in the same order.  A tuning option (Sec. 3.3.2 sets no kernel design). */
+lts_status lts_set_lane_exchange(lts_context *ctx, int32_t on);
+
 /* Sizing pass (synchronous on `stream`): need[4] = (segment-pixel pairs, active pixels, charge cells,
  * packet upper bound = active pixels * max_packets).  Host pointer need. */
 lts_status lts_plan(lts_context *ctx, const lts_segments *segs, int64_t need[4], void *stream);

@@ -265,8 +265,8 @@ def simulate(workload, event_index=0, pixels=None, table=None, eps_rel=0.0, eps_
         pixels = active_pixels(workload.physics, workload.readout, workload.table, segs)
     key = (workload.electronics.seed, workload.event_ids[event_index])
     mc_clear_near_edges()
-    wave, clipped, sums = waveforms(workload.physics, workload.readout, table, segs, pixels, with_sums=full,
-                                    mc_key=key)
+    out = waveforms(workload.physics, workload.readout, table, segs, pixels, with_sums=full, mc_key=key)
+    wave, clipped, sums = out if full else (out[0], out[1], None)
     res = {"pixels": np.asarray(pixels, np.int32), "wave": wave, "clipped": clipped, "mc_near_edges": mc_near_edges()}
     if full:
         res["report"] = {"q_after_quench": sums[0], "q_collected": sums[1], "q_induced": float(wave.sum()),

@@ -1,7 +1,8 @@
 """Project autotuner for the work split of the induction stage.
 
 Candidates are the library's work-split knobs: the reduction variant (sorted with Kahan / atomic), the number of
-table slices per pixel in the sorted variant (one per XCD or fewer) and the tick tile per thread.  Each candidate
+table slices per pixel in the sorted variant (one per XCD or fewer), the tick tile per thread and whether lanes
+exchange table windows.  Each candidate
 runs the whole path on the given events (device-resident), timed with the library's stage events; the fastest
 candidate whose currents agree with the deterministic sorted reference to 1e-5 (per-pixel relative L2) wins.
 Results are cached in a JSON file keyed by the workload shape.
@@ -23,15 +24,19 @@ class Choice:
     reduce_mode: int = ltsim.LTS_REDUCE_SORTED
     slices: int = 1
     ticks_per_thread: int = 0
+    lane_exchange: int = 0
 
     def apply(self, ctx: "ltsim.Context"):
         ctx.set_reduce_mode(self.reduce_mode)
         ctx.set_induce_slices(self.slices)
         ctx.set_ticks_per_thread(self.ticks_per_thread)
+        ctx.set_lane_exchange(self.lane_exchange)
 
 
 DEFAULT_CANDIDATES = tuple(
-    [Choice(ltsim.LTS_REDUCE_SORTED, s, rt) for s in (1, 2, 4, 8) for rt in (0, 4)] +
+    [Choice(ltsim.LTS_REDUCE_SORTED, 1, 0, x) for x in (1, 0)] +
+    [Choice(ltsim.LTS_REDUCE_SORTED, s, rt) for s in (2, 4, 8) for rt in (0, 4)] +
+    [Choice(ltsim.LTS_REDUCE_SORTED, 1, 4)] +
     [Choice(ltsim.LTS_REDUCE_ATOMIC, 1, rt) for rt in (0, 4)])
 
 

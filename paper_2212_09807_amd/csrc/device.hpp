@@ -18,9 +18,16 @@ constexpr int kNaMax = 256;          // maximum charge-box extent in ticks per s
 constexpr int kBoxMax = 256;         // maximum charge-box extent in sub-pixel bins per axis
 constexpr int kAC = 8;               // cell ticks per register block in the induction inner loop
 constexpr int kRTMax = 8;            // ticks per thread in the induction inner loop (max)
-constexpr int kPad = kNaMax + kRTMax + kAC + 8;   // zero padding on each side of every table column
-static_assert(kPad >= kNaMax + 16, "the induction prefetch reads up to 16 values below a cell-tick block");
+constexpr int kTileTicks = 512;      // ticks of one wavefront work unit of the summed induction (64 lanes x 8)
+constexpr int kPieceMax = 248;       // maximum ticks of a summed charge column piece
+// Zero padding on each side of every table column.  The per-pair induction reads at most kNaMax + 16 values below
+// and kNaMax + 8 above the table span; the summed induction's tiles overhang a column's tick window by up to
+// kTileTicks - 1 ticks, so it reads at most kTileTicks + kPieceMax + 16 below and kTileTicks + kPieceMax above.
+constexpr int kPad = 792;
+static_assert(kPad >= kNaMax + 16, "per-pair induction reads");
+static_assert(kPad >= kTileTicks + kPieceMax + 16, "summed induction reads");
 constexpr int kMaxTicks = 16384;
+constexpr int kCellSlack = 2 * kAC;  // floats allocated past the last cell: the induction loop loads one block ahead
 constexpr float kNormalBound = 6.7638f;  // |Box-Muller normal| <= sqrt(-2 ln 2^-33) = 6.76372 for u >= 2^-33
 
 enum : int32_t { SEG_BOX_CLAMP = 1, SEG_INVALID = 2, SEG_TOO_LONG = 4, SEG_STRADDLE = 8 };

@@ -591,65 +591,135 @@ __device__ __forceinline__ float shift_up_or(float v, float lane0) {
                                                                   __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
 }
 
-__device__ __forceinline__ const float *uniform_ptr(const float *p) {
+// A global-memory pointer whose value is taken from the first active lane (wave-uniform by construction).  The
+// global address space is kept explicit so loads through it stay global loads (a generic pointer would become a
+// flat load, whose completion order forces a full wait on every outstanding load).
+typedef const float __attribute__((address_space(1))) *gfloat_ptr;
+__device__ __forceinline__ gfloat_ptr uniform_ptr(const float *p) {
     const uint64_t v = (uint64_t)p;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return (const float *)(((uint64_t)hi << 32) | lo);
+    return (gfloat_ptr)(((uint64_t)hi << 32) | lo);
+}
+// The same for data that no kernel of the launch writes (charge cells during induction): loads through the
+// constant address space become scalar loads into SGPRs, read by the whole wavefront at once.
+typedef const float __attribute__((address_space(4))) *cfloat_ptr;
+__device__ __forceinline__ cfloat_ptr uniform_cptr(const float *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (cfloat_ptr)(((uint64_t)hi << 32) | lo);
 }
 
-// The same product for RT = 8 with the table window shared across lanes: lane t covers ticks nb .. nb+7, so its
-// window R[K0-ac-7 .. K0-ac+7] is its own 8 values R[K0-ac .. K0-ac+7] plus 7 values owned by lane t-1; and the
-// next cell-tick block (ac + 8) needs exactly lane t-1's current 8 values.  Each lane therefore loads 8 values
-// once per column (coalesced) and afterwards receives them from the lane below; lane 0 of each wavefront loads
-// its 8 values from memory.  All 64 lanes must execute this (inactive lanes pass active = false and are given a
-// safe in-bounds base; their results are discarded, and lanes above an inactive lane are inactive too).
-__device__ __forceinline__ void pair_block_shfl(const DevParams &P, const float *__restrict__ cc0, int32_t nv, int32_t nap,
+// The same product for RT = 8 with the table window shared across lanes.  Lane t covers ticks nb .. nb+7; for
+// cell-tick block j (ticks a0 + 8j .. +7) its window is R[K0-8j-7 .. K0-8j+7]: its own block b_j = R[K0-8j .. +7]
+// and seven values of b_{j+1} = R[K0-8j-8 .. -1].  b_{j+1} is b_j of the lane below (DPP wave_shr:1); lane 0 has no
+// lane below and takes the 8 values from memory (one address for the whole wavefront).  Per column, each lane
+// loads b_0 once (coalesced) and every later block arrives by one lane shift.
+//   The blocks live in a ring of four register slots: the lane-0 values of b_{j+3} are loaded into the slot of the
+// dead block b_{j-1} three blocks ahead, and the shift writes b_{j+1} over its slot (the shifted-out lane keeps the
+// loaded value), so no block is ever copied.  The next column's b_0 and its first two lane-0 blocks are loaded while
+// the current column runs.  All 64 lanes must execute this (inactive lanes pass active = false and are given a safe
+// in-bounds base; their results are discarded, and lanes above an inactive lane are inactive too).
+template <int S>
+__device__ __forceinline__ void ring_block(float (&B)[4][8], const float (&cv)[kAC], float (&acc)[8]) {
+    constexpr int N = (S + 1) & 3;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) B[N][k] = shift_up_or(B[S][k], B[N][k]);
+    // w[m] = R[K0 - 8j - 7 + m]: m < 7 from b_{j+1}[m + 1], m >= 7 from b_j[m - 7]
+#pragma unroll
+    for (int q = 0; q < kAC; ++q)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int m = r - q + kAC - 1;
+            acc[r] = fmaf(cv[q], m < 7 ? B[N][m + 1] : B[S][m - 7], acc[r]);
+        }
+}
+
+// Streams a sequence of (table column, cell column) pairs through the ring.  `col` is this lane's pointer to
+// R[K0 .. K0+7] of the first table column, `cc` the first cell column (nblk blocks of kAC ticks).  adv(col, cc, nblk)
+// moves to the next column (false at the end); it is called while the current column runs, so the next column's
+// first blocks are in flight before they are needed.  done() runs after each column's last block.
+template <class Adv, class Done>
+__device__ __forceinline__ void column_stream(const float *col, const float *cc, int32_t nblk, Adv adv, Done done,
+                                              float (&acc)[8]) {
+    // Lane 0 alone loads the values shifted in at the bottom of the wavefront (an exec-masked load moves 32 bytes,
+    // where a load at one address from every lane would move 64 copies through the texture path).
+    const bool lane0 = lane_id() == 0;
+    gfloat_ptr col0 = uniform_ptr(col);
+    float F[8], P1[8] = {}, P2[8] = {};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) F[k] = col[k];
+    if (lane0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) { P1[k] = col0[k - 8]; P2[k] = col0[k - 16]; }
+    }
+    for (;;) {
+        float B[4][8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) { B[0][k] = F[k]; B[1][k] = P1[k]; B[2][k] = P2[k]; B[3][k] = 0.0f; }
+        gfloat_ptr c0 = col0;
+        cfloat_ptr ccu = uniform_cptr(cc);
+        const int32_t nb_cur = nblk;
+        const float *ncol = col;
+        const bool more = adv(ncol, cc, nblk);
+        if (more) {                                     // next column, one column ahead
+            col0 = uniform_ptr(ncol);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) F[k] = ncol[k];
+            if (lane0) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) { P1[k] = col0[k - 8]; P2[k] = col0[k - 16]; }
+            }
+        }
+        float cvb[2][kAC];                              // cell values of the current and the next block
+#pragma unroll
+        for (int q = 0; q < kAC; ++q) cvb[0][q] = ccu[q];
+        // lane-0 loads reach at most nap + 16 values below K0 (in bounds: every caller keeps K0 >= nap + 16); the
+        // cell values of the block after a column's last lie in the next column or in the buffer's kCellSlack tail
+        for (int32_t j = 0; j < nb_cur; j += 4) {
+#define LTS_RING_STEP(S)                                                                        \
+    {                                                                                           \
+        _Pragma("unroll") for (int q = 0; q < kAC; ++q) cvb[(S + 1) & 1][q] = ccu[kAC * (j + S + 1) + q]; \
+        if (lane0) {                                                                            \
+            _Pragma("unroll") for (int k = 0; k < 8; ++k) B[(S + 3) & 3][k] = c0[k - 8 * (j + S + 3)]; \
+        }                                                                                       \
+        __builtin_amdgcn_sched_barrier(0);          /* keep the prefetches ahead of this block's math */ \
+        ring_block<S>(B, cvb[S & 1], acc);                                                      \
+    }
+            LTS_RING_STEP(0)
+            if (j + 1 >= nb_cur) break;
+            LTS_RING_STEP(1)
+            if (j + 2 >= nb_cur) break;
+            LTS_RING_STEP(2)
+            if (j + 3 >= nb_cur) break;
+            LTS_RING_STEP(3)
+#undef LTS_RING_STEP
+        }
+        done();
+        if (!more) break;
+    }
+}
+
+// One (segment, pixel) pair: the columns (u, v) of its charge box inside the pixel's reach, in row order.
+__device__ __forceinline__ void pair_block_ring(const DevParams &P, const float *__restrict__ cc0, int32_t nv, int32_t nap,
                                                 int32_t u0, int32_t v0, int32_t a0, const float *__restrict__ Rpad,
                                                 int32_t ulo, int32_t uhi, int32_t vlo, int32_t vhi, int32_t uc,
                                                 int32_t vc, int32_t nb, bool active, float (&acc)[8]) {
     const int32_t K0 = active ? nb - a0 + P.t_r - 1 + kPad : kPad;
-    for (int32_t u = ulo; u <= uhi; ++u) {
-        const int32_t i = fold(u - uc);
-        const float *ccu = cc0 + (int64_t)(u - u0) * nv * nap;
-        for (int32_t v = vlo; v <= vhi; ++v) {
-            const int32_t j = fold(v - vc);
-            const float *col = Rpad + (int64_t)(i * P.by + j) * P.col_len + K0;
-            const float *cc = ccu + (int64_t)(v - v0) * nap;
-            // lane 0's pointer is wave-uniform: its next 8 values come through the scalar cache, one block ahead
-            const float *col0 = uniform_ptr(col);
-            float own[8], pre[8], cn[kAC];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) own[k] = col[k];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) pre[k] = col0[k - 8];
-#pragma unroll
-            for (int q = 0; q < kAC; ++q) cn[q] = cc[q];
-            for (int32_t ac = 0; ac < nap; ac += kAC) {
-                float nxt[8], cv[kAC];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) nxt[k] = shift_up_or(own[k], pre[k]);
-#pragma unroll
-                for (int k = 0; k < 8; ++k) pre[k] = col0[k - ac - 16];          // in bounds: kPad >= kNaMax + 16
-#pragma unroll
-                for (int q = 0; q < kAC; ++q) cv[q] = cn[q];
-                if (ac + kAC < nap) {
-#pragma unroll
-                    for (int q = 0; q < kAC; ++q) cn[q] = cc[ac + kAC + q];
-                }
-                // w[m] = R[K0 - ac - 7 + m]: m < 7 from nxt[m + 1], m >= 7 from own[m - 7]
-#pragma unroll
-                for (int q = 0; q < kAC; ++q)
-#pragma unroll
-                    for (int r = 0; r < 8; ++r) {
-                        const int m = r - q + kAC - 1;
-                        acc[r] = fmaf(cv[q], m < 7 ? nxt[m + 1] : own[m - 7], acc[r]);
-                    }
-#pragma unroll
-                for (int k = 0; k < 8; ++k) own[k] = nxt[k];
-            }
-        }
-    }
+    int32_t u = ulo, v = vlo;
+    auto colp = [&](int32_t uu, int32_t vv) {
+        return Rpad + (int64_t)(fold(uu - uc) * P.by + fold(vv - vc)) * P.col_len + K0;
+    };
+    auto cellp = [&](int32_t uu, int32_t vv) { return cc0 + ((int64_t)(uu - u0) * nv + (vv - v0)) * nap; };
+    auto adv = [&](const float *&col, const float *&cc, int32_t &nblk) {
+        if (++v > vhi) { v = vlo; ++u; }
+        if (u > uhi) return false;
+        col = colp(u, v);
+        cc = cellp(u, v);
+        return true;
+    };
+    column_stream(colp(u, v), cellp(u, v), nap / kAC, adv, [] {}, acc);
 }
 
 // Signed induction of a pair's cells that falls outside the tick window [0, n_ticks), from FP64 prefix sums of
@@ -690,7 +760,7 @@ __device__ __forceinline__ double block_sum_double(double v, double *red) {
 
 // Sorted variant: one workgroup per active pixel (dynamic work queue); the pixel's segments in ascending id
 // order; per-pair FP32 sums in registers added into a Kahan-compensated FP32 accumulator in LDS.
-template <int RT>
+template <int RT, bool SHIFT>
 __global__ __launch_bounds__(kWG) void k_induce_sorted(DevParams P, const SegInfo *__restrict__ si,
                                                        const float *__restrict__ cells, const float *__restrict__ Rpad,
                                                        const double *__restrict__ prefix,
@@ -735,8 +805,8 @@ __global__ __launch_bounds__(kWG) void k_induce_sorted(DevParams P, const SegInf
                 float acc[RT];
 #pragma unroll
                 for (int r = 0; r < RT; ++r) acc[r] = 0.0f;
-                if constexpr (RT == 8)
-                    pair_block_shfl(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, nb <= hi, acc);
+                if constexpr (RT == 8 && SHIFT)
+                    pair_block_ring(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, nb <= hi, acc);
                 else if (nb <= hi)
                     pair_block<RT>(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, acc);
 #pragma unroll
@@ -941,14 +1011,14 @@ void launch_induce_slices(const DevParams &P, const Work &w, const Table &T, flo
     }
 }
 
-template <int RT>
+template <int RT, bool SHIFT>
 static void induce_rt(const DevParams &P, const Work &w, const Table &T, float *wave, int mode, int64_t n_slots,
                       hipStream_t st) {
     const int64_t cap = 2048;
     if (mode == 0) {
         int64_t g = n_slots < 1 ? 1 : (n_slots > cap ? cap : n_slots);
         size_t lds = (size_t)2 * P.nticks * sizeof(float);
-        k_induce_sorted<RT><<<(unsigned)g, kWG, lds, st>>>(P, w.si, w.cells, T.Rpad, T.prefix, w.slot_off, w.pairs,
+        k_induce_sorted<RT, SHIFT><<<(unsigned)g, kWG, lds, st>>>(P, w.si, w.cells, T.Rpad, T.prefix, w.slot_off, w.pairs,
                                                           w.slot_gp, wave, w.hdr, w.report);
     } else {
         int64_t g = w.n_seg < 1 ? 1 : (w.n_seg > cap ? cap : w.n_seg);
@@ -958,12 +1028,15 @@ static void induce_rt(const DevParams &P, const Work &w, const Table &T, float *
 }
 
 void launch_induce(const DevParams &P, const Work &w, const Table &T, float *wave, int mode, int64_t n_slots, int32_t rt,
-                   hipStream_t st) {
+                   bool shift, hipStream_t st) {
     switch (pick_rt(P, rt)) {
-        case 1: induce_rt<1>(P, w, T, wave, mode, n_slots, st); break;
-        case 2: induce_rt<2>(P, w, T, wave, mode, n_slots, st); break;
-        case 4: induce_rt<4>(P, w, T, wave, mode, n_slots, st); break;
-        default: induce_rt<8>(P, w, T, wave, mode, n_slots, st); break;
+        case 1: induce_rt<1, false>(P, w, T, wave, mode, n_slots, st); break;
+        case 2: induce_rt<2, false>(P, w, T, wave, mode, n_slots, st); break;
+        case 4: induce_rt<4, false>(P, w, T, wave, mode, n_slots, st); break;
+        default:
+            if (shift) induce_rt<8, true>(P, w, T, wave, mode, n_slots, st);
+            else induce_rt<8, false>(P, w, T, wave, mode, n_slots, st);
+            break;
     }
 }
 
@@ -1124,14 +1197,115 @@ void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw,
         k_sum_lists<true><<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
 }
 
+// Summed induction, one wavefront per work unit (active pixel, tile of kTileTicks ticks): lane t owns ticks
+// t0 + 8t .. +7 of the tile, and the wavefront streams every column piece of the pixel's list whose tick window
+// [a0 - T_R + 1, a0 + na - 1] meets the tile through the register ring.  Lanes whose ticks lie outside a piece's
+// window read the table's zero padding, so they add exact zeros.  Each piece's product is added to the lane's
+// running sums with Kahan compensation (pieces in list order: deterministic and batch-invariant).  Wavefronts take
+// units from a counter and never synchronise with each other; the first tile of a pixel also accounts the charge
+// that its pieces induce outside the window.
+__global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInfo *__restrict__ piece,
+                                                       const float *__restrict__ S, const float *__restrict__ Rpad,
+                                                       const double *__restrict__ prefix,
+                                                       const int64_t *__restrict__ list_off,
+                                                       const int32_t *__restrict__ list,
+                                                       const int32_t *__restrict__ slot_gp, float *__restrict__ wave,
+                                                       DevHeader *H, double *report) {
+    const int lane = threadIdx.x & 63;
+    const int32_t NT = P.nticks, TR = P.t_r;
+    const int32_t n_tiles = (NT + kTileTicks - 1) / kTileTicks;
+    const int64_t n_units = H->n_slots * n_tiles;
+    for (;;) {
+        uint32_t got = 0;
+        if (lane == 0) got = atomicAdd(&H->work[2], 1u);
+        const int64_t unit = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
+        if (unit >= n_units) break;
+        const int64_t slot = unit / n_tiles;
+        const int32_t t0 = (int32_t)(unit - slot * n_tiles) * kTileTicks, t1 = t0 + kTileTicks - 1;
+        const int32_t gp = slot_gp[slot];
+        const int32_t e = gp / P.npx, p = gp - e * P.npx;
+        const int32_t uc = (p % P.nx) * P.nsub + P.nsub / 2, vc = (p / P.nx) * P.nsub + P.nsub / 2;
+        const int32_t nb = t0 + 8 * lane;
+        const int64_t pb = list_off[slot], pe = list_off[slot + 1];
+        float acc[8], sum[8], cmp[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) { acc[r] = 0.0f; sum[r] = 0.0f; cmp[r] = 0.0f; }
+        auto meets = [&](int64_t k) {
+            const SegInfo &g = piece[list[k]];
+            return g.a0 + g.na - 1 >= t0 && g.a0 - (TR - 1) <= t1;
+        };
+        auto colof = [&](int64_t k, const float *&col, const float *&cc, int32_t &nblk) {
+            const SegInfo &g = piece[list[k]];
+            col = Rpad + (int64_t)(fold(g.u0 - uc) * P.by + fold(g.v0 - vc)) * P.col_len + (nb - g.a0 + TR - 1 + kPad);
+            cc = S + g.cell_off;
+            nblk = g.na_pad / kAC;
+        };
+        int64_t q = pb;
+        while (q < pe && !meets(q)) ++q;
+        if (q < pe) {
+            const float *col, *cc;
+            int32_t nblk;
+            colof(q, col, cc, nblk);
+            auto adv = [&](const float *&ncol, const float *&ncc, int32_t &nn) {
+                do { ++q; } while (q < pe && !meets(q));
+                if (q >= pe) return false;
+                colof(q, ncol, ncc, nn);
+                return true;
+            };
+            auto done = [&] {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const float y = acc[r] - cmp[r];
+                    const float t = sum[r] + y;
+                    cmp[r] = (t - sum[r]) - y;
+                    sum[r] = t;
+                    acc[r] = 0.0f;
+                }
+            };
+            column_stream(col, cc, nblk, adv, done, acc);
+        }
+        float *wrow = wave + slot * NT;
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            if (nb + r < NT) wrow[nb + r] = sum[r] - cmp[r];
+        if (t0 == 0) {                                  // charge induced outside [0, NT) by the pixel's pieces
+            double clip = 0.0;
+            for (int64_t k = pb + lane; k < pe; k += 64) {
+                const SegInfo &g = piece[list[k]];
+                const int32_t wlo = g.a0 - (TR - 1), whi = g.a0 + g.na - 1;
+                if (wlo >= 0 && whi < NT) continue;
+                const double *pf = prefix + (int64_t)(fold(g.u0 - uc) * P.by + fold(g.v0 - vc)) * (TR + 1);
+                const float *cv = S + g.cell_off;
+                for (int32_t a = 0; a < g.na; ++a) {
+                    const int32_t aa = g.a0 + a;
+                    const int32_t klo = min(max(TR - 1 - aa, 0), TR), khi = min(max(NT + TR - 1 - aa, 0), TR);
+                    const double dropped = klo >= khi ? pf[TR] : pf[klo] + (pf[TR] - pf[khi]);
+                    clip += (double)cv[a] * dropped;
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) clip += __shfl_xor(clip, o);
+            if (lane == 0 && clip != 0.0) atomicAdd(&report[(int64_t)e * 5 + 3], clip);
+        }
+    }
+}
+
 void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, const Table &T, float *wave,
                           int64_t n_slots, int32_t rt, hipStream_t st) {
-    Work ws = w;
-    ws.si = sw.piece;
-    ws.cells = sw.S;
-    ws.slot_off = sw.list_off;
-    ws.pairs = sw.list;
-    launch_induce(P, ws, T, wave, 0, n_slots, rt, st);
+    if (rt != 0 && rt != 8) {                           // the per-pair kernel on the summed pieces (tuning option)
+        Work ws = w;
+        ws.si = sw.piece;
+        ws.cells = sw.S;
+        ws.slot_off = sw.list_off;
+        ws.pairs = sw.list;
+        launch_induce(P, ws, T, wave, 0, n_slots, rt, false, st);
+        return;
+    }
+    if (n_slots <= 0) return;
+    const int64_t units = n_slots * ((P.nticks + kTileTicks - 1) / kTileTicks);
+    const int64_t g = std::min<int64_t>((units + kWG / 64 - 1) / (kWG / 64), 256 * 8);
+    k_induce_summed<<<(unsigned)g, kWG, 0, st>>>(P, sw.piece, sw.S, T.Rpad, T.prefix, sw.list_off, sw.list, w.slot_gp,
+                                                 wave, w.hdr, w.report);
 }
 
 // ================================================================================================= electronics

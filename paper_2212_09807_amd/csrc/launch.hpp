@@ -60,7 +60,8 @@ struct SumWork {
     int64_t *list_off = nullptr;             // [n_slots + 1] pieces in reach per active pixel, then offsets
     int32_t *list = nullptr;                 // [n_list] piece ids per active pixel, in column order
 };
-constexpr int32_t kPieceTicks = 248;         // ticks per column piece (a multiple of kAC, <= kNaMax)
+constexpr int32_t kPieceTicks = kPieceMax;   // ticks per column piece (a multiple of kAC, <= kNaMax)
+static_assert(kPieceTicks % kAC == 0 && kPieceTicks <= kNaMax, "piece length");
 
 void launch_sum_ranges(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st);   // + counts
 void launch_sum_fill(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st);     // lists, pieces
@@ -80,7 +81,7 @@ void launch_fill_pairs(const DevParams &P, const Work &w, hipStream_t st);
 void launch_sort_pairs(const Work &w, int64_t n_slots_host, hipStream_t st);
 void launch_cells(const DevParams &P, const Work &w, hipStream_t st);
 void launch_induce(const DevParams &P, const Work &w, const Table &T, float *wave, int mode, int64_t n_slots_host,
-                   int32_t rt, hipStream_t st);
+                   int32_t rt, bool shift, hipStream_t st);
 void launch_induce_slices(const DevParams &P, const Work &w, const Table &T, float *wave, int64_t n_slots, int32_t NS,
                           float *part, int64_t chunk, int32_t rt, hipStream_t st);
 void launch_electronics(const DevParams &P, const float *wave, const int32_t *slot_gp, const uint64_t *event_ids,

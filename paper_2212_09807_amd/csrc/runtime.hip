@@ -39,6 +39,7 @@ struct lts_context {
     int32_t reduce_mode = LTS_REDUCE_SORTED;
     int32_t induce_slices = 1;       // sorted variant: table slices (one per XCD); 1 = unsliced kernel
     int32_t ticks_per_thread = 0;    // induction tick tile per thread (0 = chosen from the table length)
+    int32_t lane_exchange = 0;       // 8-tick tiles share table windows across lanes (1) or load their own (0)
     DevBuf part;                     // per-slice partial waveforms of the sliced sorted variant
     DevBuf mask;                     // disabled-channel mask (npx bytes) when set
     bool has_mask = false;
@@ -333,7 +334,7 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     if ((r = ensure(c, c->piece_off, sizeof(int64_t) * (size_t)nc1))) return r;
     if ((r = ensure(c, c->s_off, sizeof(int64_t) * (size_t)nc1))) return r;
     if ((r = ensure(c, c->piece, sizeof(SegInfo) * (size_t)max_pieces))) return r;
-    if ((r = ensure(c, c->S, sizeof(float) * (size_t)max_s))) return r;
+    if ((r = ensure(c, c->S, sizeof(float) * (size_t)(max_s + kCellSlack)))) return r;
     if ((r = ensure(c, c->list_off, sizeof(int64_t) * (size_t)(n_slots + 1)))) return r;
     if ((r = ensure(c, c->scan_tmp, sizeof(int64_t) * (size_t)scan_tmp_needed(std::max(nc1, n_slots + 1))))) return r;
     sw.col_lo = as<int32_t>(c->col_lo);
@@ -401,7 +402,7 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
     if ((r = ensure(c, c->slot_off, sizeof(int64_t) * (size_t)(n_slots + 1)))) return r;
     if ((r = ensure(c, c->pairs_u, sizeof(int32_t) * (size_t)std::max<int64_t>(n_pairs, 1)))) return r;
     if ((r = ensure(c, c->pairs, sizeof(int32_t) * (size_t)std::max<int64_t>(n_pairs, 1)))) return r;
-    if ((r = ensure(c, c->cells, sizeof(float) * (size_t)std::max<int64_t>(n_cells, 1)))) return r;
+    if ((r = ensure(c, c->cells, sizeof(float) * (size_t)(n_cells + kCellSlack)))) return r;
     if ((r = ensure(c, c->pk_tick, sizeof(int32_t) * (size_t)(n_slots * mp)))) return r;
     if ((r = ensure(c, c->pk_adc, sizeof(uint16_t) * (size_t)(n_slots * mp)))) return r;
     if ((r = ensure(c, c->pk_flag, sizeof(uint8_t) * (size_t)(n_slots * mp)))) return r;
@@ -445,7 +446,7 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
                              c->ticks_per_thread, st);
     } else {
         StageTimer t(c, st, LTS_STAGE_INDUCE);
-        launch_induce(P, w, T, out->current, c->reduce_mode, n_slots, c->ticks_per_thread, st);
+        launch_induce(P, w, T, out->current, c->reduce_mode, n_slots, c->ticks_per_thread, c->lane_exchange != 0, st);
     }
     {
         StageTimer t(c, st, LTS_STAGE_ELECTRONICS);
@@ -570,6 +571,13 @@ lts_status lts_set_ticks_per_thread(lts_context *c, int32_t rt) {
     if (rt != 0 && rt != 1 && rt != 2 && rt != 4 && rt != 8)
         return fail(c, LTS_ERR_INVALID_ARG, "ticks per thread must be 0 (auto), 1, 2, 4 or 8");
     c->ticks_per_thread = rt;
+    return LTS_OK;
+}
+
+lts_status lts_set_lane_exchange(lts_context *c, int32_t on) {
+    if (!c) return LTS_ERR_INVALID_ARG;
+    if (on != 0 && on != 1) return fail(c, LTS_ERR_INVALID_ARG, "lane exchange must be 0 or 1");
+    c->lane_exchange = on;
     return LTS_OK;
 }
 
@@ -1034,6 +1042,7 @@ lts_status lts_server_start(lts_context *ctx, const lts_server_cfg *cfg, lts_ser
         if (r == LTS_OK) r = lts_set_reduce_mode(L->ctx, ctx->reduce_mode);
         if (r == LTS_OK) r = lts_set_induce_slices(L->ctx, ctx->induce_slices);
         if (r == LTS_OK) r = lts_set_ticks_per_thread(L->ctx, ctx->ticks_per_thread);
+        if (r == LTS_OK) r = lts_set_lane_exchange(L->ctx, ctx->lane_exchange);
         if (r == LTS_OK && hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess) r = LTS_ERR_DEVICE;
         if (r != LTS_OK) {
             if (L->ctx) lts_context_destroy(L->ctx);

@@ -427,6 +427,20 @@ def test_disabled_channels_produce_no_packets(lt, torch):
     assert np.array_equal(again["pkt_tick"], full["pkt_tick"])
 
 
+def test_lane_exchange_is_bit_identical(lt, torch):
+    """Sharing table windows across lanes only changes where the values come from: same products, same order."""
+    w = W.make_workload(3, n_events=1)
+    ctx = lt.Context.from_workload(w)
+    d = lt.to_device(w.events[0])
+    ctx.set_lane_exchange(True)
+    a = ctx.simulate(d, event_id=w.event_ids[0]).host()
+    ctx.set_lane_exchange(False)
+    b = ctx.simulate(d, event_id=w.event_ids[0]).host()
+    assert np.array_equal(a["pixel_id"], b["pixel_id"])
+    assert np.array_equal(a["current"], b["current"])
+    assert np.array_equal(a["pkt_tick"], b["pkt_tick"]) and np.array_equal(a["pkt_adc"], b["pkt_adc"])
+
+
 # ----------------------------------------------------------------------------------------------- Monte Carlo diffusion
 
 @pytest.mark.parametrize("cfg,M,mode", [(1, 1, 0), (1, 16, 0), (1, 16, 2), (1, 64, 1)])
