@@ -24,6 +24,7 @@ constexpr int kPieceMax = 248;       // maximum ticks of a summed charge column 
 // and kNaMax + 8 above the table span; the summed induction's tiles overhang a column's tick window by up to
 // kTileTicks - 1 ticks, so it reads at most kTileTicks + kPieceMax + 16 below and kTileTicks + kPieceMax above.
 constexpr int kPad = 792;
+static_assert(kPad % 8 == 0, "table columns keep 32-byte alignment");
 static_assert(kPad >= kNaMax + 16, "per-pair induction reads");
 static_assert(kPad >= kTileTicks + kPieceMax + 16, "summed induction reads");
 constexpr int kMaxTicks = 16384;
@@ -47,7 +48,7 @@ struct DevParams {
     float b_hi, b_lo, x0_hi, x0_lo, y0_hi, y0_lo, tick_hi, tick_lo, tb_hi, tb_lo;
     int32_t nx, ny, nsub, nticks, npx;
     // field-response table
-    int32_t t_r, bx, by, col_len;           // col_len = kPad + t_r + kPad
+    int32_t t_r, bx, by, col_len;           // col_len = kPad + t_r rounded up to 8 + kPad
     // electronics (Sec. 3.4)
     float thr, q_lsb, sig_reset, sig_disc, sig_unc;
     int32_t hold, spacing, pedestal, adc_max, max_packets, reset_period;

@@ -611,21 +611,23 @@ __device__ __forceinline__ cfloat_ptr uniform_cptr(const float *p) {
     return (cfloat_ptr)(((uint64_t)hi << 32) | lo);
 }
 
-// The same product for RT = 8 with the table window shared across lanes.  Lane t covers ticks nb .. nb+7; for
-// cell-tick block j (ticks a0 + 8j .. +7) its window is R[K0-8j-7 .. K0-8j+7]: its own block b_j = R[K0-8j .. +7]
-// and seven values of b_{j+1} = R[K0-8j-8 .. -1].  b_{j+1} is b_j of the lane below (DPP wave_shr:1); lane 0 has no
-// lane below and takes the 8 values from memory (one address for the whole wavefront).  Per column, each lane
-// loads b_0 once (coalesced) and every later block arrives by one lane shift.
-//   The blocks live in a ring of four register slots: the lane-0 values of b_{j+3} are loaded into the slot of the
-// dead block b_{j-1} three blocks ahead, and the shift writes b_{j+1} over its slot (the shifted-out lane keeps the
-// loaded value), so no block is ever copied.  The next column's b_0 and its first two lane-0 blocks are loaded while
-// the current column runs.  All 64 lanes must execute this (inactive lanes pass active = false and are given a safe
-// in-bounds base; their results are discarded, and lanes above an inactive lane are inactive too).
-template <int S>
+// The same product for RT = 8, streaming each table column through a ring of four 8-value register blocks.  Lane t
+// covers ticks nb .. nb+7; for cell-tick block j (ticks a0 + 8j .. +7) its window is R[K0-8j-7 .. K0-8j+7], i.e.
+// its block b_j = R[K0-8j .. +7] and seven values of b_{j+1} = R[K0-8j-8 .. -1], so every block serves two
+// consecutive cell-tick blocks and is fetched once.  Block b_{j+3} is fetched into the slot of the dead block
+// b_{j-1}, three blocks ahead; the next column's first three blocks are fetched while the current column runs.
+//   Two ways to fetch b_{j+1}:
+//   * SHIFT = false: every lane loads its own 8 values (two 16-byte loads when ALIGNED, i.e. K0 % 8 == 0);
+//   * SHIFT = true: b_{j+1} is b_j of the lane below (DPP wave_shr:1); only lane 0 loads (its values come from
+//     below the wavefront's span).  All 64 lanes must then execute the loop (inactive lanes get a safe in-bounds
+//     base; their results are discarded, and lanes above an inactive lane are inactive too).
+template <int S, bool SHIFT>
 __device__ __forceinline__ void ring_block(float (&B)[4][8], const float (&cv)[kAC], float (&acc)[8]) {
     constexpr int N = (S + 1) & 3;
+    if constexpr (SHIFT) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) B[N][k] = shift_up_or(B[S][k], B[N][k]);
+        for (int k = 0; k < 8; ++k) B[N][k] = shift_up_or(B[S][k], B[N][k]);
+    }
     // w[m] = R[K0 - 8j - 7 + m]: m < 7 from b_{j+1}[m + 1], m >= 7 from b_j[m - 7]
 #pragma unroll
     for (int q = 0; q < kAC; ++q)
@@ -636,38 +638,54 @@ __device__ __forceinline__ void ring_block(float (&B)[4][8], const float (&cv)[k
         }
 }
 
+template <bool ALIGNED>
+__device__ __forceinline__ void load8(const float *p, float (&d)[8]) {
+    if constexpr (ALIGNED) {
+        const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 4);
+        d[0] = a.x; d[1] = a.y; d[2] = a.z; d[3] = a.w; d[4] = b.x; d[5] = b.y; d[6] = b.z; d[7] = b.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) d[k] = p[k];
+    }
+}
+
 // Streams a sequence of (table column, cell column) pairs through the ring.  `col` is this lane's pointer to
 // R[K0 .. K0+7] of the first table column, `cc` the first cell column (nblk blocks of kAC ticks).  adv(col, cc, nblk)
 // moves to the next column (false at the end); it is called while the current column runs, so the next column's
-// first blocks are in flight before they are needed.  done() runs after each column's last block.
-template <class Adv, class Done>
+// first blocks are in flight before they are needed.  done() runs after each column's last block.  Loads reach at
+// most 8 * nblk + 16 values below K0 (every caller keeps them inside the column's zero padding); the cell values of
+// the block after a column's last lie in the next column or in the buffer's kCellSlack tail.
+template <bool SHIFT, bool ALIGNED, class Adv, class Done>
 __device__ __forceinline__ void column_stream(const float *col, const float *cc, int32_t nblk, Adv adv, Done done,
                                               float (&acc)[8]) {
-    // Lane 0 alone loads the values shifted in at the bottom of the wavefront (an exec-masked load moves 32 bytes,
-    // where a load at one address from every lane would move 64 copies through the texture path).
     const bool lane0 = lane_id() == 0;
     gfloat_ptr col0 = uniform_ptr(col);
     float F[8], P1[8] = {}, P2[8] = {};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) F[k] = col[k];
-    if (lane0) {
+    load8<ALIGNED>(col, F);
+    if (!SHIFT) {
+        load8<ALIGNED>(col - 8, P1);
+        load8<ALIGNED>(col - 16, P2);
+    } else if (lane0) {                                 // lane 0 alone loads what is shifted in at the bottom
 #pragma unroll
         for (int k = 0; k < 8; ++k) { P1[k] = col0[k - 8]; P2[k] = col0[k - 16]; }
     }
+    const float *cl = col;
     for (;;) {
         float B[4][8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) { B[0][k] = F[k]; B[1][k] = P1[k]; B[2][k] = P2[k]; B[3][k] = 0.0f; }
         gfloat_ptr c0 = col0;
+        const float *cur = cl;
         cfloat_ptr ccu = uniform_cptr(cc);
         const int32_t nb_cur = nblk;
-        const float *ncol = col;
-        const bool more = adv(ncol, cc, nblk);
+        const bool more = adv(cl, cc, nblk);
         if (more) {                                     // next column, one column ahead
-            col0 = uniform_ptr(ncol);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) F[k] = ncol[k];
-            if (lane0) {
+            col0 = uniform_ptr(cl);
+            load8<ALIGNED>(cl, F);
+            if (!SHIFT) {
+                load8<ALIGNED>(cl - 8, P1);
+                load8<ALIGNED>(cl - 16, P2);
+            } else if (lane0) {
 #pragma unroll
                 for (int k = 0; k < 8; ++k) { P1[k] = col0[k - 8]; P2[k] = col0[k - 16]; }
             }
@@ -675,17 +693,17 @@ __device__ __forceinline__ void column_stream(const float *col, const float *cc,
         float cvb[2][kAC];                              // cell values of the current and the next block
 #pragma unroll
         for (int q = 0; q < kAC; ++q) cvb[0][q] = ccu[q];
-        // lane-0 loads reach at most nap + 16 values below K0 (in bounds: every caller keeps K0 >= nap + 16); the
-        // cell values of the block after a column's last lie in the next column or in the buffer's kCellSlack tail
         for (int32_t j = 0; j < nb_cur; j += 4) {
 #define LTS_RING_STEP(S)                                                                        \
     {                                                                                           \
         _Pragma("unroll") for (int q = 0; q < kAC; ++q) cvb[(S + 1) & 1][q] = ccu[kAC * (j + S + 1) + q]; \
-        if (lane0) {                                                                            \
+        if constexpr (!SHIFT) {                                                                 \
+            load8<ALIGNED>(cur - 8 * (j + S + 3), B[(S + 3) & 3]);                              \
+        } else if (lane0) {                                                                     \
             _Pragma("unroll") for (int k = 0; k < 8; ++k) B[(S + 3) & 3][k] = c0[k - 8 * (j + S + 3)]; \
         }                                                                                       \
         __builtin_amdgcn_sched_barrier(0);          /* keep the prefetches ahead of this block's math */ \
-        ring_block<S>(B, cvb[S & 1], acc);                                                      \
+        ring_block<S, SHIFT>(B, cvb[S & 1], acc);                                               \
     }
             LTS_RING_STEP(0)
             if (j + 1 >= nb_cur) break;
@@ -701,7 +719,40 @@ __device__ __forceinline__ void column_stream(const float *col, const float *cc,
     }
 }
 
-// One (segment, pixel) pair: the columns (u, v) of its charge box inside the pixel's reach, in row order.
+// Products of one table column with one cell column for RT = 8, two 8-value blocks in ping-pong: block j of cell
+// ticks needs b_j = R[K0-8j .. +7] and b_{j+1} = R[K0-8j-8 .. -1]; the buffer holding b_j is refilled with b_{j+2}
+// after block j, so each block loads only its 8 new values (no copies, no cross-lane traffic).
+template <bool ALIGNED>
+__device__ __forceinline__ void column_pingpong(const float *col, cfloat_ptr cc, int32_t nblk, float (&acc)[8]) {
+    float X[8], Y[8], cv[kAC];
+    load8<ALIGNED>(col, X);
+    for (int32_t j = 0; j < nblk; j += 2) {
+        load8<ALIGNED>(col - 8 * (j + 1), Y);
+#pragma unroll
+        for (int q = 0; q < kAC; ++q) cv[q] = cc[kAC * j + q];
+#pragma unroll
+        for (int q = 0; q < kAC; ++q)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int m = r - q + kAC - 1;
+                acc[r] = fmaf(cv[q], m < 7 ? Y[m + 1] : X[m - 7], acc[r]);
+            }
+        if (j + 1 >= nblk) break;
+        load8<ALIGNED>(col - 8 * (j + 2), X);
+#pragma unroll
+        for (int q = 0; q < kAC; ++q) cv[q] = cc[kAC * (j + 1) + q];
+#pragma unroll
+        for (int q = 0; q < kAC; ++q)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int m = r - q + kAC - 1;
+                acc[r] = fmaf(cv[q], m < 7 ? X[m + 1] : Y[m - 7], acc[r]);
+            }
+    }
+}
+
+// One (segment, pixel) pair through the lane-exchange ring: the columns (u, v) of its charge box inside the pixel's
+// reach, in row order.
 __device__ __forceinline__ void pair_block_ring(const DevParams &P, const float *__restrict__ cc0, int32_t nv, int32_t nap,
                                                 int32_t u0, int32_t v0, int32_t a0, const float *__restrict__ Rpad,
                                                 int32_t ulo, int32_t uhi, int32_t vlo, int32_t vhi, int32_t uc,
@@ -719,7 +770,7 @@ __device__ __forceinline__ void pair_block_ring(const DevParams &P, const float 
         cc = cellp(u, v);
         return true;
     };
-    column_stream(colp(u, v), cellp(u, v), nap / kAC, adv, [] {}, acc);
+    column_stream<true, false>(colp(u, v), cellp(u, v), nap / kAC, adv, [] {}, acc);
 }
 
 // Signed induction of a pair's cells that falls outside the tick window [0, n_ticks), from FP64 prefix sums of
@@ -1091,8 +1142,9 @@ __global__ void k_sum_fill(DevParams P, const SegInfo *si, int64_t n_seg, SumWor
 }
 
 // per column: sort its segment list (ascending id, insertion sort: lists are short), count its pieces and the
-// padded summed-charge length.
-__global__ void k_sum_columns(SumWork sw) {
+// padded summed-charge length.  The column's first tick is moved down (zero charge in front) to the residue
+// (T_R - 1 + kPad) mod 8, which makes every lane's table offset in the summed induction a multiple of 8.
+__global__ void k_sum_columns(int32_t align_res, SumWork sw) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= sw.n_cols) return;
     const int64_t b = sw.col_seg_off[c], e = sw.col_seg_off[c + 1];
@@ -1102,9 +1154,12 @@ __global__ void k_sum_columns(SumWork sw) {
         while (j >= b && sw.col_seg[j] > x) { sw.col_seg[j + 1] = sw.col_seg[j]; --j; }
         sw.col_seg[j + 1] = x;
     }
-    const int32_t lo = sw.col_lo[c], hi = sw.col_hi[c];
+    const int32_t hi = sw.col_hi[c];
+    int32_t lo = sw.col_lo[c];
     int64_t np = 0, ns = 0;
     if (e > b && hi >= lo) {
+        lo -= ((lo - align_res) % 8 + 8) % 8;
+        sw.col_lo[c] = lo;
         const int32_t L = hi - lo + 1;
         np = (L + kPieceTicks - 1) / kPieceTicks;
         const int32_t last = L - (int32_t)(np - 1) * kPieceTicks;
@@ -1116,7 +1171,7 @@ __global__ void k_sum_columns(SumWork sw) {
 
 void launch_sum_fill(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st) {
     if (w.n_seg > 0) k_sum_fill<<<(unsigned)((w.n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.n_seg, sw);
-    k_sum_columns<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(sw);
+    k_sum_columns<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(((P.t_r - 1 + kPad) % 8 + 8) % 8, sw);
 }
 
 // per column: piece records, and the summed charge of each tick (segments in ascending id, Kahan)
@@ -1199,11 +1254,13 @@ void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw,
 
 // Summed induction, one wavefront per work unit (active pixel, tile of kTileTicks ticks): lane t owns ticks
 // t0 + 8t .. +7 of the tile, and the wavefront streams every column piece of the pixel's list whose tick window
-// [a0 - T_R + 1, a0 + na - 1] meets the tile through the register ring.  Lanes whose ticks lie outside a piece's
+// [a0 - T_R + 1, a0 + na - 1] meets the tile through registers (pieces start at the aligning residue, so every
+// lane's table offset is a multiple of 8).  Lanes whose ticks lie outside a piece's
 // window read the table's zero padding, so they add exact zeros.  Each piece's product is added to the lane's
 // running sums with Kahan compensation (pieces in list order: deterministic and batch-invariant).  Wavefronts take
 // units from a counter and never synchronise with each other; the first tile of a pixel also accounts the charge
 // that its pieces induce outside the window.
+template <bool SHIFT>
 __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInfo *__restrict__ piece,
                                                        const float *__restrict__ S, const float *__restrict__ Rpad,
                                                        const double *__restrict__ prefix,
@@ -1242,7 +1299,23 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
         };
         int64_t q = pb;
         while (q < pe && !meets(q)) ++q;
-        if (q < pe) {
+        if constexpr (!SHIFT) {                         // aligned ping-pong per piece, Kahan after each piece
+            for (; q < pe; ++q) {
+                if (!meets(q)) continue;
+                const float *col, *cc;
+                int32_t nblk;
+                colof(q, col, cc, nblk);
+                column_pingpong<true>(col, uniform_cptr(cc), nblk, acc);
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const float y = acc[r] - cmp[r];
+                    const float t = sum[r] + y;
+                    cmp[r] = (t - sum[r]) - y;
+                    sum[r] = t;
+                    acc[r] = 0.0f;
+                }
+            }
+        } else if (q < pe) {
             const float *col, *cc;
             int32_t nblk;
             colof(q, col, cc, nblk);
@@ -1262,7 +1335,7 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
                     acc[r] = 0.0f;
                 }
             };
-            column_stream(col, cc, nblk, adv, done, acc);
+            column_stream<SHIFT, false>(col, cc, nblk, adv, done, acc);
         }
         float *wrow = wave + slot * NT;
 #pragma unroll
@@ -1291,7 +1364,7 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
 }
 
 void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, const Table &T, float *wave,
-                          int64_t n_slots, int32_t rt, hipStream_t st) {
+                          int64_t n_slots, int32_t rt, bool shift, hipStream_t st) {
     if (rt != 0 && rt != 8) {                           // the per-pair kernel on the summed pieces (tuning option)
         Work ws = w;
         ws.si = sw.piece;
@@ -1304,8 +1377,12 @@ void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, 
     if (n_slots <= 0) return;
     const int64_t units = n_slots * ((P.nticks + kTileTicks - 1) / kTileTicks);
     const int64_t g = std::min<int64_t>((units + kWG / 64 - 1) / (kWG / 64), 256 * 8);
-    k_induce_summed<<<(unsigned)g, kWG, 0, st>>>(P, sw.piece, sw.S, T.Rpad, T.prefix, sw.list_off, sw.list, w.slot_gp,
-                                                 wave, w.hdr, w.report);
+    if (shift)
+        k_induce_summed<true><<<(unsigned)g, kWG, 0, st>>>(P, sw.piece, sw.S, T.Rpad, T.prefix, sw.list_off, sw.list,
+                                                           w.slot_gp, wave, w.hdr, w.report);
+    else
+        k_induce_summed<false><<<(unsigned)g, kWG, 0, st>>>(P, sw.piece, sw.S, T.Rpad, T.prefix, sw.list_off, sw.list,
+                                                            w.slot_gp, wave, w.hdr, w.report);
 }
 
 // ================================================================================================= electronics

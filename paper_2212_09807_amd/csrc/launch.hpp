@@ -69,7 +69,7 @@ void launch_sum_pieces(const DevParams &P, const Work &w, const SumWork &sw, hip
 void launch_sum_lists_count(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, hipStream_t st);
 void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, hipStream_t st);
 void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, const Table &T, float *wave,
-                          int64_t n_slots, int32_t rt, hipStream_t st);
+                          int64_t n_slots, int32_t rt, bool shift, hipStream_t st);
 
 int64_t scan_tmp_needed(int64_t n);
 void scan_exclusive_i64(int64_t *data, int64_t n, int64_t *total_dst, void *tmp, hipStream_t st);

@@ -324,8 +324,10 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     sw.n_cols = (int64_t)w.n_ev * sw.CU * sw.CV;
     const int64_t nc1 = sw.n_cols + 1;
     const int64_t n_colseg = std::max<int64_t>(h.n_colseg, 1);
-    const int64_t max_pieces = n_colseg + h.n_cells / kPieceTicks + 1;
-    const int64_t max_s = h.n_cells + (int64_t)kAC * n_colseg + kAC;
+    // a column with charge spans at most the sum of its segments' tick extents, plus up to 7 ticks of alignment in
+    // front and 7 of padding at the end; every column with charge has at least one segment (n_colseg >= columns)
+    const int64_t max_pieces = 2 * n_colseg + h.n_cells / kPieceTicks + 1;
+    const int64_t max_s = h.n_cells + 2 * (int64_t)kAC * n_colseg + kAC;
     if ((r = ensure(c, c->col_lo, sizeof(int32_t) * (size_t)sw.n_cols))) return r;
     if ((r = ensure(c, c->col_hi, sizeof(int32_t) * (size_t)sw.n_cols))) return r;
     if ((r = ensure(c, c->col_seg_off, sizeof(int64_t) * (size_t)nc1))) return r;
@@ -372,7 +374,7 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     sw.list = as<int32_t>(c->list);
     launch_sum_lists_fill(P, w, sw, n_slots, st);
     Table T{as<float>(c->Rpad), as<double>(c->prefix)};
-    launch_induce_summed(P, w, sw, T, wave, n_slots, c->ticks_per_thread, st);
+    launch_induce_summed(P, w, sw, T, wave, n_slots, c->ticks_per_thread, c->lane_exchange != 0, st);
     return LTS_OK;
 }
 
@@ -609,7 +611,7 @@ lts_status lts_set_response(lts_context *c, const float *R, int32_t t_r, int32_t
     if (!R || t_r < 1 || t_r > 8192 || b_x < 1 || b_x > 256 || b_y < 1 || b_y > 256)
         return fail(c, LTS_ERR_INVALID_ARG, "response table shape must be 1..8192 x 1..256 x 1..256");
     const size_t ncol = (size_t)b_x * b_y;
-    const int32_t col_len = kPad + t_r + kPad;
+    const int32_t col_len = kPad + (t_r + 7) / 8 * 8 + kPad;      // a multiple of 8: columns start 32-byte aligned
     std::vector<float> pad(ncol * (size_t)col_len, 0.0f);
     std::vector<double> pre(ncol * (size_t)(t_r + 1), 0.0);
     for (int32_t i = 0; i < b_x; ++i)
