@@ -137,16 +137,19 @@ def served(ltsim, W, rate_hz, n_events, mode, lanes=2):
             "mean_batch_events": float(np.mean([r["batch_events"] for r in res])), "lanes": lanes}
 
 
-MODES = {"sorted": (0, 0), "atomic": (1, 0), "summed": (2, 0), "sorted-shift": (0, 1)}   # (reduce, lane exchange)
+# name: (reduce mode, lane exchange, ticks per thread)
+MODES = {"sorted": (0, 0, 0), "atomic": (1, 0, 0), "summed": (2, 0, 0), "sorted-shift": (0, 1, 0),
+         "sorted-noprefetch": (0, 0, 8)}
 
 
 def time_mode(ltsim, w, segs, name, steps):
     """Whole path in another variant (reduce mode, and for the per-pair kernels whether lanes exchange table
     windows) on the same device-resident event: segments/s and its induction roofline."""
     import torch
-    mode, shift = MODES[name]
+    mode, shift, rt = MODES[name]
     ctx = ltsim.Context.from_workload(w, reduce_mode=mode)
     ctx.set_lane_exchange(shift)
+    ctx.set_ticks_per_thread(rt)
     need = ctx.plan(segs)
     out = ctx._alloc(need["pixels"], need["packets"], 1, False)
     ctx.simulate(segs, event_id=w.event_ids[0], out=out)

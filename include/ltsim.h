@@ -173,7 +173,9 @@ lts_status lts_set_channel_mask(lts_context *ctx, const uint8_t *mask, int64_t n
 lts_status lts_set_induce_slices(lts_context *ctx, int32_t slices);
 
 /* Induction tick tile: each of the 256 threads of a workgroup computes `rt` consecutive ticks of a pair's window
- * (1, 2, 4 or 8; 0 = the smallest that covers the table length plus a typical charge extent). */
+ * (1, 2, 4 or 8; 0 = the smallest that covers the table length plus a typical charge extent, and for 8 ticks the
+ * loop that loads the next cell-tick block's window while computing the current one; an explicit 8 selects the
+ * loop without that prefetch).  All choices give the same sums in the same order. */
 lts_status lts_set_ticks_per_thread(lts_context *ctx, int32_t rt);
 
 /* Per-pair induction with 8-tick tiles: 1 = lanes share each table window by shifting it one lane per cell-tick

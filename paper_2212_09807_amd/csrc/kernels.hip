@@ -552,6 +552,26 @@ void launch_cells(const DevParams &P, const Work &w, hipStream_t st) {
 }
 
 // ================================================================================================= induction
+// A global-memory pointer whose value is taken from the first active lane (wave-uniform by construction).  The
+// global address space is kept explicit so loads through it stay global loads (a generic pointer would become a
+// flat load, whose completion order forces a full wait on every outstanding load).
+typedef const float __attribute__((address_space(1))) *gfloat_ptr;
+__device__ __forceinline__ gfloat_ptr uniform_ptr(const float *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (gfloat_ptr)(((uint64_t)hi << 32) | lo);
+}
+// The same for data that no kernel of the launch writes (charge cells during induction): loads through the
+// constant address space become scalar loads into SGPRs, read by the whole wavefront at once.
+typedef const float __attribute__((address_space(4))) *cfloat_ptr;
+__device__ __forceinline__ cfloat_ptr uniform_cptr(const float *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (cfloat_ptr)(((uint64_t)hi << 32) | lo);
+}
+
 // Current of one (segment, pixel) pair on RT consecutive ticks nb .. nb+RT-1 (eq. (current)):
 //   I[n] = sum over cells (a, u, v) in the pixel's reach of c[a,u,v] * R[n - a + T_R - 1, fold(u - uc), fold(v - vc)].
 // The table column is zero-padded by kPad on both sides, so no bounds test is needed in the inner loop; the cell
@@ -585,31 +605,62 @@ __device__ __forceinline__ void pair_block(const DevParams &P, const float *__re
     }
 }
 
+// pair_block<8> with the loads of the next cell-tick block (its 15-value table window and 8 cell values) issued
+// before the products of the current one, across column boundaries: the pair's blocks are walked as one sequence
+// (column-major, all columns of a pair have the same number of blocks) with two register buffers in turn.
+struct BlockCursor {
+    int32_t u, v, j;
+};
+
+__device__ __forceinline__ void pair_block_pf(const DevParams &P, const float *__restrict__ cc0, int32_t nv, int32_t nap,
+                                              int32_t u0, int32_t v0, int32_t a0, const float *__restrict__ Rpad,
+                                              int32_t ulo, int32_t uhi, int32_t vlo, int32_t vhi, int32_t uc,
+                                              int32_t vc, int32_t nb, float (&acc)[8]) {
+    const int32_t K0 = nb - a0 + P.t_r - 1 + kPad;
+    const int32_t nblk = nap / kAC;
+    const int64_t total = (int64_t)(uhi - ulo + 1) * (vhi - vlo + 1) * nblk;
+    BlockCursor f{ulo, vlo, 0};                         // next block to fetch
+    int64_t nf = 0;                                     // blocks fetched so far
+    // Loads are issued unconditionally (past the last block the last block is fetched again), so the number of
+    // loads in flight is the same on every path and the waits only cover the block about to be used.
+    auto fetch = [&](float (&w)[8 + kAC - 1], float (&cv)[kAC]) {
+        const float *col = Rpad + (int64_t)(fold(f.u - uc) * P.by + fold(f.v - vc)) * P.col_len + K0 - (kAC - 1) -
+                           kAC * f.j;
+        cfloat_ptr cc = uniform_cptr(cc0 + ((int64_t)(f.u - u0) * nv + (f.v - v0)) * nap + kAC * f.j);
+#pragma unroll
+        for (int m = 0; m < 8 + kAC - 1; ++m) w[m] = col[m];
+#pragma unroll
+        for (int q = 0; q < kAC; ++q) cv[q] = cc[q];
+        if (++nf < total && ++f.j == nblk) {
+            f.j = 0;
+            if (++f.v > vhi) { f.v = vlo; ++f.u; }
+        }
+    };
+    auto block = [&](const float (&w)[8 + kAC - 1], const float (&cv)[kAC]) {
+#pragma unroll
+        for (int q = 0; q < kAC; ++q)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) acc[r] = fmaf(cv[q], w[r - q + kAC - 1], acc[r]);
+    };
+    float wa[8 + kAC - 1], ca[kAC], wb[8 + kAC - 1], cb[kAC];
+    fetch(wa, ca);
+    for (int64_t b = 0; b < total; b += 2) {
+        fetch(wb, cb);
+        __builtin_amdgcn_sched_barrier(0);
+        block(wa, ca);
+        if (b + 1 >= total) break;
+        fetch(wa, ca);
+        __builtin_amdgcn_sched_barrier(0);
+        block(wb, cb);
+    }
+}
+
 // Value of lane - 1 of the wavefront (DPP wave_shr:1); lane 0 has no source lane and keeps `lane0`.
 __device__ __forceinline__ float shift_up_or(float v, float lane0) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, lane0),
                                                                   __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
 }
 
-// A global-memory pointer whose value is taken from the first active lane (wave-uniform by construction).  The
-// global address space is kept explicit so loads through it stay global loads (a generic pointer would become a
-// flat load, whose completion order forces a full wait on every outstanding load).
-typedef const float __attribute__((address_space(1))) *gfloat_ptr;
-__device__ __forceinline__ gfloat_ptr uniform_ptr(const float *p) {
-    const uint64_t v = (uint64_t)p;
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return (gfloat_ptr)(((uint64_t)hi << 32) | lo);
-}
-// The same for data that no kernel of the launch writes (charge cells during induction): loads through the
-// constant address space become scalar loads into SGPRs, read by the whole wavefront at once.
-typedef const float __attribute__((address_space(4))) *cfloat_ptr;
-__device__ __forceinline__ cfloat_ptr uniform_cptr(const float *p) {
-    const uint64_t v = (uint64_t)p;
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return (cfloat_ptr)(((uint64_t)hi << 32) | lo);
-}
 
 // The same product for RT = 8, streaming each table column through a ring of four 8-value register blocks.  Lane t
 // covers ticks nb .. nb+7; for cell-tick block j (ticks a0 + 8j .. +7) its window is R[K0-8j-7 .. K0-8j+7], i.e.
@@ -811,7 +862,7 @@ __device__ __forceinline__ double block_sum_double(double v, double *red) {
 
 // Sorted variant: one workgroup per active pixel (dynamic work queue); the pixel's segments in ascending id
 // order; per-pair FP32 sums in registers added into a Kahan-compensated FP32 accumulator in LDS.
-template <int RT, bool SHIFT>
+template <int RT, bool SHIFT, bool PREFETCH = false>
 __global__ __launch_bounds__(kWG) void k_induce_sorted(DevParams P, const SegInfo *__restrict__ si,
                                                        const float *__restrict__ cells, const float *__restrict__ Rpad,
                                                        const double *__restrict__ prefix,
@@ -858,7 +909,10 @@ __global__ __launch_bounds__(kWG) void k_induce_sorted(DevParams P, const SegInf
                 for (int r = 0; r < RT; ++r) acc[r] = 0.0f;
                 if constexpr (RT == 8 && SHIFT)
                     pair_block_ring(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, nb <= hi, acc);
-                else if (nb <= hi)
+                else if constexpr (RT == 8 && PREFETCH) {
+                    if (nb <= hi)
+                        pair_block_pf(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, acc);
+                } else if (nb <= hi)
                     pair_block<RT>(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, acc);
 #pragma unroll
                 for (int r = 0; r < RT; ++r) {
@@ -1062,14 +1116,14 @@ void launch_induce_slices(const DevParams &P, const Work &w, const Table &T, flo
     }
 }
 
-template <int RT, bool SHIFT>
+template <int RT, bool SHIFT, bool PREFETCH = false>
 static void induce_rt(const DevParams &P, const Work &w, const Table &T, float *wave, int mode, int64_t n_slots,
                       hipStream_t st) {
     const int64_t cap = 2048;
     if (mode == 0) {
         int64_t g = n_slots < 1 ? 1 : (n_slots > cap ? cap : n_slots);
         size_t lds = (size_t)2 * P.nticks * sizeof(float);
-        k_induce_sorted<RT, SHIFT><<<(unsigned)g, kWG, lds, st>>>(P, w.si, w.cells, T.Rpad, T.prefix, w.slot_off, w.pairs,
+        k_induce_sorted<RT, SHIFT, PREFETCH><<<(unsigned)g, kWG, lds, st>>>(P, w.si, w.cells, T.Rpad, T.prefix, w.slot_off, w.pairs,
                                                           w.slot_gp, wave, w.hdr, w.report);
     } else {
         int64_t g = w.n_seg < 1 ? 1 : (w.n_seg > cap ? cap : w.n_seg);
@@ -1086,6 +1140,7 @@ void launch_induce(const DevParams &P, const Work &w, const Table &T, float *wav
         case 4: induce_rt<4, false>(P, w, T, wave, mode, n_slots, st); break;
         default:
             if (shift) induce_rt<8, true>(P, w, T, wave, mode, n_slots, st);
+            else if (rt == 0) induce_rt<8, false, true>(P, w, T, wave, mode, n_slots, st);   // auto: prefetched
             else induce_rt<8, false>(P, w, T, wave, mode, n_slots, st);
             break;
     }
