@@ -43,9 +43,11 @@ def per_pixel_errors(g, o):
     return num / den
 
 
-def run_gpu(lt, w, ev=0, mode=0, table=None, slices=1):
+def run_gpu(lt, w, ev=0, mode=0, table=None, slices=1, rt=0, shift=False):
     ctx = lt.Context.from_workload(w, table=table, reduce_mode=mode)
     ctx.set_induce_slices(slices)
+    ctx.set_ticks_per_thread(rt)
+    ctx.set_lane_exchange(shift)
     segs = lt.to_device(w.events[ev])
     r = ctx.simulate(segs, event_id=w.event_ids[ev])
     h = r.host()
@@ -102,8 +104,8 @@ def compare_packets(h, pixels, orc_pk, ufrom, uncertain_pixels=()):
     return compared, flagged, bad
 
 
-def check_event(lt, orc, w, ev=0, mode=0, table=None, slices=1):
-    ctx, h = run_gpu(lt, w, ev, mode, table, slices)
+def check_event(lt, orc, w, ev=0, mode=0, table=None, slices=1, rt=0, shift=False):
+    ctx, h = run_gpu(lt, w, ev, mode, table, slices, rt, shift)
     segs = w.events[ev]
     r = orc.simulate(w, ev, table=table, eps_rel=EPS_REL, eps_abs=EPS_ABS)
     opix = r["pixels"]
@@ -223,6 +225,41 @@ def _ragged_workload(seed=7):
 def test_ragged_multi_tile_parity(lt, orc, torch, mode, slices):
     h, r, e, _ = check_event(lt, orc, _ragged_workload(), mode=mode, slices=slices)
     assert r["report"]["q_clipped"] != 0.0 and r["report"]["q_offgrid"] > 0.0
+
+
+def _max_window_workload():
+    """The largest tick window the library accepts (8000 ticks) with a table longer than one 2048-tick pass of the
+    per-pair kernel (T_R = 2300), steep segments whose charge boxes span ~200 ticks, a vertical track whose summed
+    column series needs several pieces, a late track and one crossing the end of the window."""
+    rng = np.random.default_rng(5)
+    w = W.config(1)
+    w.readout = W.Readout(n_x=12, n_y=10, n_ticks=8000)
+    w.table = W.TableShape(2300, 10, 10)
+    parts = []
+    zs = np.linspace(2.0, 20.0, 7)                      # vertical track: 6 segments of 3 cm at one (x, y)
+    a = np.stack([np.full(6, 2.13), np.full(6, 2.21), zs[:-1]], 1)
+    b = np.stack([np.full(6, 2.13), np.full(6, 2.21), zs[1:]], 1)
+    parts.append(W.make_segments(a, b, 2.1 * 3.0 * np.ones(6), t0=np.zeros(6), t1=np.zeros(6)))
+    for t0, z0 in ((600.0, 4.0), (780.0, 6.0)):         # inclined tracks, late and at the window's end
+        p0 = np.array([rng.uniform(0.5, 4.5), rng.uniform(0.5, 3.5), z0])
+        d = np.array([0.5, 0.3, 0.8]) / np.linalg.norm([0.5, 0.3, 0.8])
+        n = 12
+        pts = p0[None] + (np.arange(n + 1) / n * 3.0)[:, None] * d[None]
+        L = np.linalg.norm(np.diff(pts, axis=0), axis=1)
+        parts.append(W.make_segments(pts[:-1], pts[1:], W.mip_dedx(rng, n) * L, t0=np.full(n, t0),
+                                     t1=np.full(n, t0)))
+    segs = W.Segments.concat(parts)
+    w.events, w.event_ids = [segs], [123]
+    return w
+
+
+@pytest.mark.parametrize("mode,rt,shift", [(0, 0, False), (0, 8, False), (0, 0, True), (1, 0, False), (2, 0, False)])
+def test_max_window_long_table_parity(lt, orc, torch, mode, rt, shift):
+    w = _max_window_workload()
+    h, r, e, (cmp_, flg) = check_event(lt, orc, w, mode=mode, rt=rt, shift=shift)
+    print(f"max window mode={mode} rt={rt} shift={shift}: pixels {len(r['pixels'])}, max e_p {e.max():.2e}, "
+          f"packets compared {cmp_}")
+    assert r["report"]["q_clipped"] != 0.0 and cmp_ > 0
 
 
 @pytest.mark.parametrize("mode", [0, 2])
