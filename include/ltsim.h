@@ -63,6 +63,9 @@ typedef struct lts_physics {
                                   index within the event, point * M + draw, event id low word, (event id high word << 4)
                                   | 3 + try)), each normal truncated to n_sigma by re-drawing; every moved copy puts
                                   Q_a / (N M) into the cell that holds it */
+    int32_t per_point;         /* 0 = lifetime (eq. (lifetime)) and diffusion widths at the segment midpoint (default);
+                                  1 = at every sample point's own drift time: charge Q_R / N * exp(-t_mu / tau), widths
+                                  sqrt(2 D t_mu); then Q_a is the sum of the points' charges.  Not with mc_draws > 0 */
 } lts_physics;
 
 /* Pixel plane and time sampling. */

@@ -15,6 +15,8 @@
  *      bin masses (truncated at n_sigma and renormalised).
  *      With mc_draws = M > 0 the paper's own estimator is used instead: each point is moved M times by Philox-keyed
  *      Gaussian draws (truncated at n_sigma) and each moved copy puts Q_a / (N M) into the cell containing it.
+ *      With per_point = 1 lifetime and diffusion are evaluated at every sample point's own drift time instead of
+ *      the segment midpoint's (charge Q_R / N * exp(-t_mu / tau), widths sqrt(2 D t_mu)).
  *   4. Induced current, Sec. 3.3.2, eq. (current): each charge cell (tick a, bin u, v) adds
  *      q * R[k, i, j] to pixel p at tick a - (T_R - 1) + k, where (i, j) is the bin's mirror-folded offset
  *      from the pixel centre (the table is quadrant-symmetric, Sec. 3.3.1) and the table is arrival-aligned.
@@ -47,6 +49,7 @@ typedef struct {
     double e_field, lar_density, w_ion, birks_ab, birks_kb, box_alpha, box_beta;
     double v_drift, lifetime, d_long, d_tran, z_anode, sample_step, n_sigma;
     int32_t mc_draws;       /* 0: expectation over the perturbations (D-exact); M > 0: M random draws per point */
+    int32_t per_point;      /* 0: lifetime and diffusion at the segment midpoint; 1: at every sample point */
 } orc_physics_params;
 
 /* Key of the Monte Carlo perturbations (used only when mc_draws > 0). */
@@ -145,6 +148,15 @@ static void segment_physics(const orc_physics_params *ph, const orc_segments *sg
     o->sigma_time = sqrt(2.0 * ph->d_long * o->t_drift) / ph->v_drift;   /* longitudinal, in us */
     o->n_points = point_count_fp32(sg->x1[i] - sg->x0[i], sg->y1[i] - sg->y0[i], sg->z1[i] - sg->z0[i],
                                    (float)ph->sample_step);
+    if (ph->per_point) {                                   /* collected charge = sum over the points' charges */
+        double qa = 0.0;
+        for (int32_t mu = 0; mu < o->n_points; ++mu) {
+            double s = ((double)mu + 0.5) / (double)o->n_points;
+            double pz = sg->z0[i] + s * ((double)sg->z1[i] - sg->z0[i]);
+            qa += o->q_r / o->n_points * exp(-fabs(pz - ph->z_anode) / ph->v_drift / ph->lifetime);
+        }
+        o->q_a = qa;
+    }
 }
 
 /* ------------------------------------------------------------------------------------------------
@@ -197,6 +209,25 @@ static void point_at(const orc_physics_params *ph, const orc_segments *sg, int64
     *tarr = pt + fabs(pz - ph->z_anode) / ph->v_drift;
 }
 
+/* Drift of sample point mu: its charge (lifetime applied at the point's own drift time) and its cloud widths.
+ * With per_point == 0 every point takes the segment midpoint's values. */
+static void point_drift(const orc_physics_params *ph, const orc_segments *sg, int64_t i, const orc_seginfo *si,
+                        int32_t mu, double *q, double *sig_t, double *sig_time)
+{
+    if (!ph->per_point) {
+        *q = si->q_a / si->n_points;
+        *sig_t = si->sigma_t;
+        *sig_time = si->sigma_time;
+        return;
+    }
+    double s = ((double)mu + 0.5) / (double)si->n_points;
+    double pz = sg->z0[i] + s * ((double)sg->z1[i] - sg->z0[i]);
+    double td = fabs(pz - ph->z_anode) / ph->v_drift;                  /* eq. (drift) at the point */
+    *q = si->q_r / si->n_points * exp(-td / ph->lifetime);             /* eq. (lifetime) at the point */
+    *sig_t = sqrt(2.0 * ph->d_tran * td);
+    *sig_time = sqrt(2.0 * ph->d_long * td) / ph->v_drift;
+}
+
 typedef struct {
     int64_t a0, na, u0, nu, v0, nv;   /* box: ticks [a0, a0+na), bins [u0, u0+nu) x [v0, v0+nv) */
     double *c;                        /* c[((a-a0)*nu + (u-u0))*nv + (v-v0)] */
@@ -208,16 +239,17 @@ static void segment_box(const orc_physics_params *ph, const orc_readout_params *
     double b = ro->pitch / ro->n_sub;
     int64_t ulo = INT64_MAX, uhi = INT64_MIN, vlo = INT64_MAX, vhi = INT64_MIN, alo = INT64_MAX, ahi = INT64_MIN;
     for (int32_t mu = 0; mu < si->n_points; ++mu) {
-        double x, y, t;
+        double x, y, t, q, st, stime;
         int64_t lo, hi;
         point_at(ph, sg, i, si->n_points, mu, &x, &y, &t);
-        support(x, si->sigma_t, ph->n_sigma, ro->x0, b, &lo, &hi);
+        point_drift(ph, sg, i, si, mu, &q, &st, &stime);
+        support(x, st, ph->n_sigma, ro->x0, b, &lo, &hi);
         if (lo < ulo) ulo = lo;
         if (hi > uhi) uhi = hi;
-        support(y, si->sigma_t, ph->n_sigma, ro->y0, b, &lo, &hi);
+        support(y, st, ph->n_sigma, ro->y0, b, &lo, &hi);
         if (lo < vlo) vlo = lo;
         if (hi > vhi) vhi = hi;
-        support(t, si->sigma_time, ph->n_sigma, ro->t_begin, ro->tick, &lo, &hi);
+        support(t, stime, ph->n_sigma, ro->t_begin, ro->tick, &lo, &hi);
         if (lo < alo) alo = lo;
         if (hi > ahi) ahi = hi;
     }
@@ -236,24 +268,24 @@ static int segment_cells(const orc_physics_params *ph, const orc_readout_params 
     cb->c = (double *)calloc(ncell ? ncell : 1, sizeof(double));
     if (!cb->c) return -1;
     double b = ro->pitch / ro->n_sub;
-    double q = si->q_a / si->n_points;
     double *fx = (double *)malloc(sizeof(double) * (size_t)(cb->nu + cb->nv + cb->na));
     if (!fx) return -1;
     double *fy = fx + cb->nu, *ft = fy + cb->nv;
     for (int32_t mu = 0; mu < si->n_points; ++mu) {
-        double x, y, t;
+        double x, y, t, q, st, stime;
         point_at(ph, sg, i, si->n_points, mu, &x, &y, &t);
+        point_drift(ph, sg, i, si, mu, &q, &st, &stime);
         for (int64_t u = 0; u < cb->nu; ++u) {
             double lo = ro->x0 + (double)(cb->u0 + u) * b;
-            fx[u] = tn_mass(x, si->sigma_t, ph->n_sigma, lo, lo + b);
+            fx[u] = tn_mass(x, st, ph->n_sigma, lo, lo + b);
         }
         for (int64_t v = 0; v < cb->nv; ++v) {
             double lo = ro->y0 + (double)(cb->v0 + v) * b;
-            fy[v] = tn_mass(y, si->sigma_t, ph->n_sigma, lo, lo + b);
+            fy[v] = tn_mass(y, st, ph->n_sigma, lo, lo + b);
         }
         for (int64_t a = 0; a < cb->na; ++a) {
             double lo = ro->t_begin + (double)(cb->a0 + a) * ro->tick;
-            ft[a] = tn_mass(t, si->sigma_time, ph->n_sigma, lo, lo + ro->tick);
+            ft[a] = tn_mass(t, stime, ph->n_sigma, lo, lo + ro->tick);
         }
         for (int64_t a = 0; a < cb->na; ++a) {
             if (ft[a] == 0.0) continue;
@@ -384,6 +416,7 @@ static int segment_cells_mc(const orc_physics_params *ph, const orc_readout_para
 static int cells_of(const orc_physics_params *ph, const orc_readout_params *ro, const orc_segments *sg, int64_t i,
                     const orc_seginfo *si, const orc_mc_key *key, orc_cells *cb)
 {
+    if (ph->mc_draws > 0 && ph->per_point) return -5;     /* the Monte Carlo form uses the midpoint drift */
     if (ph->mc_draws > 0) return key ? segment_cells_mc(ph, ro, sg, i, si, key, cb) : -3;
     return segment_cells(ph, ro, sg, i, si, cb);
 }

@@ -44,6 +44,7 @@ struct DevParams {
     float inv_vd_hi, inv_vd_lo, inv_lifetime, two_dl, two_dt, za_hi, za_lo;
     float step, nsig, inv_norm;             // inv_norm = 1 / P(|g| <= n_sigma)
     int32_t mc_draws;                       // 0: expectation over the diffusion draws; M > 0: M draws per point
+    int32_t per_point;                      // lifetime and diffusion at each sample point (1) or the midpoint (0)
     // grid
     float b_hi, b_lo, x0_hi, x0_lo, y0_hi, y0_lo, tick_hi, tick_lo, tb_hi, tb_lo;
     int32_t nx, ny, nsub, nticks, npx;
@@ -153,6 +154,17 @@ __device__ __forceinline__ float noise_normal(const DevParams &P, uint32_t pixel
     float u0 = fmaf((float)x.x, 0x1p-32f, 0x1p-33f);
     float u1 = fmaf((float)x.y, 0x1p-32f, 0x1p-33f);
     return sqrtf(-2.0f * logf(u0)) * cospif(2.0f * u1);
+}
+
+// Drift of sample point mu at its own drift time (per-point mode): charge Q_R / N * exp(-t / tau) and the
+// transverse / arrival-time widths sqrt(2 D t).
+__device__ __forceinline__ void point_drift(const SegInfo &g, const DevParams &P, int32_t mu, float &q, float &sT,
+                                            float &sL) {
+    const float s = __fdiv_rn((float)mu + 0.5f, (float)g.n_points);
+    const float td = fabsf(fmaf(s, g.dz, g.zz0)) * P.inv_vd_hi;
+    q = (g.q_r / (float)g.n_points) * expf(-td * P.inv_lifetime);
+    sT = sqrtf(P.two_dt * td);
+    sL = sqrtf(P.two_dl * td) * P.inv_vd_hi;
 }
 
 // Diffusion perturbation of draw `draw` (= point * M + m) of segment `seg` of an event (Monte Carlo form of

@@ -194,6 +194,7 @@ __device__ __forceinline__ void segment_setup(const DevParams &P, const SegArray
     g.q_r = qr; g.q_a = qa; g.q_pt = qa / (float)N; g.t_drift = td;
     g.sigma_t = sT; g.sigma_time = sL; g.dedx = dedx;
     g.n_points = N;
+    float qa_seg = qa;
     // local frame: reference bin / tick of the start point and exact offsets
     ref_offset(x0, 0.0f, P.x0_hi, P.x0_lo, P.b_hi, P.b_lo, g.u_ref, g.ox);
     ref_offset(y0, 0.0f, P.y0_hi, P.y0_lo, P.b_hi, P.b_lo, g.v_ref, g.oy);
@@ -213,7 +214,25 @@ __device__ __forceinline__ void segment_setup(const DevParams &P, const SegArray
     g.dta = fmaf(sg * dz, P.inv_vd_hi, dt);
     if (straddle) flags |= SEG_STRADDLE;
     g.flags = flags;
-    o.q_r = qr; o.q_a = qa; o.t_drift = td; o.sigma_t = sT; o.sigma_time = sL; o.dedx = dedx;
+    if (P.per_point && !(flags & (SEG_INVALID | SEG_TOO_LONG))) {
+        // collected charge = sum of the points' charges; the box uses the widths of the point farthest from the
+        // anode (the widest cloud), a superset of the points' own supports
+        float sum = 0.0f, cmp = 0.0f;
+        for (int32_t mu = 0; mu < N; ++mu) {
+            float q, a, b;
+            point_drift(g, P, mu, q, a, b);
+            const float y = q - cmp, t = sum + y;
+            cmp = (t - sum) - y;
+            sum = t;
+        }
+        qa_seg = sum;
+        g.q_a = sum;
+        g.q_pt = sum / (float)N;
+        const float tdm = fmaxf(fabsf(zz0), fabsf(zz1)) * P.inv_vd_hi;
+        g.sigma_t = sqrtf(P.two_dt * tdm);
+        g.sigma_time = sqrtf(P.two_dl * tdm) * P.inv_vd_hi;
+    }
+    o.q_r = qr; o.q_a = qa_seg; o.t_drift = td; o.sigma_t = sT; o.sigma_time = sL; o.dedx = dedx;
     o.n_points = N; o.flags = flags;
 }
 
@@ -501,12 +520,16 @@ __global__ __launch_bounds__(kWG) void k_cells(DevParams P, const SegInfo *si, i
                 const int32_t m = r / 3, ax = r - 3 * (r / 3);
                 float lx, ly, lt;
                 point_local(g, P, mu0 + m, lx, ly, lt);
+                float q = 1.0f, sT = g.sigma_t, sL = g.sigma_time;
+                if (P.per_point) point_drift(g, P, mu0 + m, q, sT, sL);
                 if (ax == 0) {
-                    axis_masses(lx, g.sigma_t, g.u0 - g.u_ref, nu, P.b_hi, P.b_lo, P, fx + m * nu);
+                    axis_masses(lx, sT, g.u0 - g.u_ref, nu, P.b_hi, P.b_lo, P, fx + m * nu);
                 } else if (ax == 1) {
-                    axis_masses(ly, g.sigma_t, g.v0 - g.v_ref, nv, P.b_hi, P.b_lo, P, fy + m * nv);
-                } else {
-                    axis_masses(lt, g.sigma_time, g.a0 - g.a_ref, na, P.tick_hi, P.tick_lo, P, ft + m * nap);
+                    axis_masses(ly, sT, g.v0 - g.v_ref, nv, P.b_hi, P.b_lo, P, fy + m * nv);
+                } else {                                // per point: its charge rides on the time masses
+                    axis_masses(lt, sL, g.a0 - g.a_ref, na, P.tick_hi, P.tick_lo, P, ft + m * nap);
+                    if (P.per_point)
+                        for (int32_t a = 0; a < na; ++a) ft[m * nap + a] *= q;
                     for (int32_t a = na; a < nap; ++a) ft[m * nap + a] = 0.0f;
                 }
             }
@@ -517,7 +540,7 @@ __global__ __launch_bounds__(kWG) void k_cells(DevParams P, const SegInfo *si, i
                 const int32_t v = uv % nv, u = uv / nv;
                 float acc = 0.0f;
                 for (int32_t m = 0; m < np; ++m) acc = fmaf(ft[m * nap + a] * fx[m * nu + u], fy[m * nv + v], acc);
-                acc *= g.q_pt;
+                if (!P.per_point) acc *= g.q_pt;
                 if (mu0 == 0) out[c] = acc; else out[c] += acc;
             }
             __syncthreads();

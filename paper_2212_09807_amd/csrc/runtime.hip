@@ -143,6 +143,9 @@ lts_status validate_and_derive(lts_context *c) {
     if (!(ph.sample_step > 0)) return fail(c, LTS_ERR_INVALID_ARG, "sample_step must be > 0");
     if (!(ph.n_sigma >= 1 && ph.n_sigma <= 10)) return fail(c, LTS_ERR_INVALID_ARG, "n_sigma must be in [1, 10]");
     if (ph.mc_draws < 0 || ph.mc_draws > 65535) return fail(c, LTS_ERR_INVALID_ARG, "mc_draws must be in [0, 65535]");
+    if (ph.per_point != 0 && ph.per_point != 1) return fail(c, LTS_ERR_INVALID_ARG, "per_point must be 0 or 1");
+    if (ph.per_point && ph.mc_draws > 0)
+        return fail(c, LTS_ERR_INVALID_ARG, "per-point drift is not combined with Monte Carlo diffusion");
     if (!(ro.pitch > 0 && ro.tick > 0)) return fail(c, LTS_ERR_INVALID_ARG, "pitch and tick must be > 0");
     if (ro.n_sub < 2 || (ro.n_sub & 1) || ro.n_sub > 64) return fail(c, LTS_ERR_INVALID_ARG, "n_sub must be even in [2, 64]");
     if (ro.n_x < 1 || ro.n_y < 1 || (int64_t)ro.n_x * ro.n_y > (1 << 22))
@@ -173,6 +176,7 @@ lts_status validate_and_derive(lts_context *c) {
     P.nsig = (float)ph.n_sigma;
     P.inv_norm = (float)(1.0 / std::erf(ph.n_sigma / std::sqrt(2.0)));
     P.mc_draws = ph.mc_draws;
+    P.per_point = ph.per_point;
     split(ro.pitch / ro.n_sub, P.b_hi, P.b_lo);
     split(ro.x0, P.x0_hi, P.x0_lo);
     split(ro.y0, P.y0_hi, P.y0_lo);

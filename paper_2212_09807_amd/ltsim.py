@@ -32,7 +32,7 @@ class LtsimError(RuntimeError):
 class lts_physics(C.Structure):
     _fields_ = [("recomb_model", C.c_int32)] + [(n, C.c_double) for n in (
         "e_field", "lar_density", "w_ion", "birks_ab", "birks_kb", "box_alpha", "box_beta", "v_drift", "lifetime",
-        "d_long", "d_tran", "z_anode", "sample_step", "n_sigma")] + [("mc_draws", C.c_int32)]
+        "d_long", "d_tran", "z_anode", "sample_step", "n_sigma")] + [("mc_draws", C.c_int32), ("per_point", C.c_int32)]
 
 
 class lts_readout(C.Structure):

@@ -60,6 +60,7 @@ class Physics:
     sample_step: float = 0.001      # cm: 10 um sampling interval along the segment (Sec. 3.3.2)
     n_sigma: float = 5.0            # diffusion truncation, in sigmas (not printed; shared reading)
     mc_draws: int = 0               # 0: expectation over the diffusion draws; M > 0: M random draws per point
+    per_point: int = 0              # 0: lifetime and diffusion at the segment midpoint; 1: at every sample point
 
 
 @dataclass

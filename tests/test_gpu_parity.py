@@ -339,6 +339,12 @@ def test_invalid_inputs_and_capacity(lt, torch):
     # the context stays usable after recoverable errors
     h = ctx.simulate(segs).host()
     assert h["counts"][0] == need["pixels"]
+    # parameter combinations the library does not offer are refused at context creation
+    for bad_ph in (dataclasses.replace(w.physics, per_point=1, mc_draws=4), dataclasses.replace(w.physics, per_point=2),
+                   dataclasses.replace(w.physics, mc_draws=-1)):
+        with pytest.raises(lt.LtsimError) as ei:
+            lt.Context(bad_ph, w.readout, w.electronics, W.response_table(w.table, w.readout, w.physics.v_drift))
+        assert ei.value.status == 1
 
 
 # ----------------------------------------------------------------------------------------------- electronics
@@ -476,6 +482,18 @@ def test_lane_exchange_is_bit_identical(lt, torch):
     assert np.array_equal(a["pixel_id"], b["pixel_id"])
     assert np.array_equal(a["current"], b["current"])
     assert np.array_equal(a["pkt_tick"], b["pkt_tick"]) and np.array_equal(a["pkt_adc"], b["pkt_adc"])
+
+
+# ----------------------------------------------------------------------------------------------- per-point drift
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_per_point_drift_parity(lt, orc, torch, mode):
+    """Lifetime and diffusion at every sample point (with a short lifetime, so the gradient along a segment is
+    visible), per-pair and summed induction."""
+    w = W.make_workload(1)
+    w.physics = dataclasses.replace(w.physics, per_point=1, lifetime=500.0)
+    h, r, e, (cmp_, flg) = check_event(lt, orc, w, mode=mode)
+    print(f"per-point mode={mode}: pixels {len(r['pixels'])}, max e_p {e.max():.2e}, packets compared {cmp_}")
 
 
 # ----------------------------------------------------------------------------------------------- Monte Carlo diffusion

@@ -135,3 +135,62 @@ def test_mc_event_conserves_charge(orc):
     r = orc.simulate(w, with_packets=False)
     rep = r["report"]
     assert rep["q_induced"] + rep["q_clipped"] + rep["q_offgrid"] == pytest.approx(rep["q_collected"], rel=1e-7)
+
+
+# ----------------------------------------------------------------------------- per-point lifetime and diffusion
+
+def test_per_point_drift_is_the_sum_of_point_deposits(orc):
+    """Evaluating lifetime and diffusion at every sample point must give exactly what N separate zero-length
+    deposits at those points give with the midpoint evaluation (each a one-point segment whose midpoint is the
+    point), summed: charge, position, arrival time and widths all follow the point."""
+    ro = _ro()
+    ph = W.Physics(per_point=1, lifetime=400.0)                      # short lifetime: a visible gradient
+    r0, r1 = np.array([2.05, 2.33, 4.0]), np.array([2.25, 2.41, 11.0])
+    segs = _segment(r0, r1, dedx=2.3, t=0.4)
+    qd = orc.quench_drift(ph, segs)
+    n = int(qd["n_points"][0])
+    (a0, na, u0, nu, v0, nv), c_pp = orc.segment_cells(ph, ro, segs, 0)
+    s = (np.arange(n) + 0.5) / n
+    p0 = np.asarray(segs.columns()[0:3]).ravel().astype(np.float64)
+    p1 = np.asarray(segs.columns()[4:7]).ravel().astype(np.float64)
+    pts = p0[None] + s[:, None] * (p1 - p0)[None]
+    E = float(segs.energy[0]) / n
+    pieces = W.make_segments(pts, pts, np.full(n, E), t0=np.full(n, 0.4), t1=np.full(n, 0.4),
+                             dedx=np.full(n, float(qd["dedx"][0])))
+    mid = dataclasses.replace(ph, per_point=0)
+    total = np.zeros_like(c_pp)
+    for k in range(n):
+        (b0, bn, bu, bnu, bv, bnv), ck = orc.segment_cells(mid, ro, pieces, k)
+        assert a0 <= b0 and b0 + bn <= a0 + na and u0 <= bu and bu + bnu <= u0 + nu and v0 <= bv and bv + bnv <= v0 + nv
+        total[b0 - a0:b0 - a0 + bn, bu - u0:bu - u0 + bnu, bv - v0:bv - v0 + bnv] += ck
+    # the deposits sit at FP32-rounded point positions (~1e-7 cm) and carry FP32 energies E/N (6e-8 relative):
+    # agreement to that level
+    assert np.abs(c_pp - total).max() <= 2e-5 * c_pp.max()
+    assert c_pp.sum() == pytest.approx(total.sum(), rel=1e-7)
+
+
+def test_per_point_lifetime_matches_the_line_integral(orc):
+    """The per-point collected charge is the midpoint rule of Q_R/L * integral exp(-t(z)/tau) dz, whose exact value
+    for a straight segment is Q_R * v tau / dz * (exp(-z0/(v tau)) - exp(-z1/(v tau)))."""
+    ph = W.Physics(per_point=1, lifetime=300.0, d_tran=0.0, d_long=0.0)
+    segs = _segment([1.0, 1.0, 3.0], [1.0, 1.0, 23.0])
+    qd = orc.quench_drift(ph, segs)
+    n = int(qd["n_points"][0])
+    vt = ph.v_drift * ph.lifetime
+    z0, z1 = float(np.float32(3.0)), float(np.float32(23.0))
+    exact = qd["q_r"][0] * vt / (z1 - z0) * (np.exp(-z0 / vt) - np.exp(-z1 / vt))
+    # midpoint rule error <= (z1 - z0)^2 / (24 n^2) * max |f''| relative to the mean of f
+    bound = ((z1 - z0) / n) ** 2 / 24.0 / vt ** 2 * np.exp(-z0 / vt) / np.exp(-z1 / vt)
+    assert qd["q_a"][0] == pytest.approx(exact, rel=bound + 1e-12)
+    mid = orc.quench_drift(dataclasses.replace(ph, per_point=0), segs)
+    assert abs(mid["q_a"][0] - exact) > 1e3 * abs(qd["q_a"][0] - exact)     # the midpoint value is visibly off
+
+
+def test_per_point_event_conserves_charge_and_rejects_mc(orc):
+    w = W.make_workload(1)
+    w.physics = dataclasses.replace(w.physics, per_point=1)
+    r = orc.simulate(w, with_packets=False)
+    rep = r["report"]
+    assert rep["q_induced"] + rep["q_clipped"] + rep["q_offgrid"] == pytest.approx(rep["q_collected"], rel=1e-7)
+    with pytest.raises(ValueError):
+        orc.segment_cells(dataclasses.replace(w.physics, mc_draws=4), w.readout, w.events[0], 0, mc_key=(SEED, 1))
