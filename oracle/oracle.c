@@ -784,3 +784,104 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ================================================================================================
+ * Light simulation, Sec. 4 (on given photocurrents; the visibility table is an input of the caller).
+ * ================================================================================================ */
+typedef struct {
+    double tick;            /* ns per light tick */
+    double tau_p, tau_s;    /* ns: prompt and slow scintillation decay times */
+    double f_prompt;        /* fraction of the light in the prompt component */
+    double trunc;           /* the scintillation kernel is truncated after trunc * tau_s */
+    double gain;            /* ADC counts per photoelectron */
+    double normal_above;    /* expected p.e. per tick above which the normal approximation replaces Poisson */
+    int32_t n_det, n_ticks;
+    uint64_t seed;
+} orc_light_params;
+
+#define ORC_STREAM_LIGHT_PE 12u
+#define ORC_STREAM_LIGHT_NOISE 13u
+
+/* Number of taps of the truncated scintillation kernel: lags 0 .. trunc * tau_s / tick. */
+int32_t orc_light_taps(const orc_light_params *lp)
+{
+    return (int32_t)floor(lp->trunc * lp->tau_s / lp->tick) + 1;
+}
+
+/* Expected photoelectrons per tick after scintillation (Sec. 4.2, the truncated direct convolution):
+ * mu[d][t] = sum_{k=0}^{K-1} ipe[d][t-k] * f_scint(k * tick) * tick, with the two-component time profile
+ * f_scint(t) = f_p / tau_p exp(-t / tau_p) + (1 - f_p) / tau_s exp(-t / tau_s) sampled at the lag. */
+void orc_light_scint(const orc_light_params *lp, const float *ipe, double *mu)
+{
+    const int32_t K = orc_light_taps(lp), T = lp->n_ticks;
+    double *w = (double *)malloc(sizeof(double) * (size_t)K);
+    for (int32_t k = 0; k < K; ++k) {
+        double t = k * lp->tick;
+        w[k] = lp->tick * (lp->f_prompt / lp->tau_p * exp(-t / lp->tau_p) +
+                           (1.0 - lp->f_prompt) / lp->tau_s * exp(-t / lp->tau_s));
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < (int64_t)lp->n_det * T; ++e) {
+        const int64_t d = e / T;
+        const int32_t t = (int32_t)(e % T);
+        const float *x = ipe + d * T;
+        double acc = 0.0;
+        for (int32_t k = 0; k < K && k <= t; ++k) acc += (double)x[t - k] * w[k];
+        mu[e] = acc;
+    }
+    free(w);
+}
+
+/* Photoelectron counting statistics (Sec. 4.2): per (detector, tick) a Poisson draw of mean mu by inverse transform
+ * sampling (sequential search of the cumulative distribution from 0), or, above normal_above, mu + sqrt(mu) * g
+ * with g standard normal.  One Philox4x32-10 block per element: counter (detector, tick, event id low word, (event id
+ * high word << 4) | 12); u = (x0 + 1/2) 2^-32 for the search, Box-Muller on words (0, 1) for g.
+ * near[e] = 1 when u lies within 1e-12 of a cumulative value the search compared it with (a decision that a different
+ * rounding of mu or exp could change). */
+void orc_light_fluct(const orc_light_params *lp, uint64_t event_id, const double *mu, double *n, int32_t *near)
+{
+    const uint32_t key[2] = {(uint32_t)lp->seed, (uint32_t)(lp->seed >> 32)};
+    const int32_t T = lp->n_ticks;
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < (int64_t)lp->n_det * T; ++e) {
+        const uint32_t ctr[4] = {(uint32_t)(e / T), (uint32_t)(e % T), (uint32_t)event_id,
+                                 (uint32_t)((event_id >> 32) << 4) | ORC_STREAM_LIGHT_PE};
+        uint32_t x[4];
+        orc_philox4x32_10(ctr, key, x);
+        const double two_m32 = 2.3283064365386963e-10;
+        const double u = ((double)x[0] + 0.5) * two_m32;
+        const double m = mu[e];
+        int32_t flag = 0;
+        if (m > lp->normal_above) {
+            const double u1 = ((double)x[1] + 0.5) * two_m32;
+            n[e] = m + sqrt(m) * sqrt(-2.0 * log(u)) * cos(6.283185307179586477 * u1);
+        } else {
+            double p = exp(-m), F = p;
+            int32_t k = 0;
+            if (fabs(u - F) < 1e-12) flag = 1;
+            while (u > F && k < 1000) {
+                ++k;
+                p *= m / k;
+                F += p;
+                if (fabs(u - F) < 1e-12) flag = 1;
+            }
+            n[e] = (double)k;
+        }
+        if (near) near[e] = flag;
+    }
+}
+
+/* Noise phases (Sec. 4.3: random-phase sinusoids): phi[d][f - 1] = 2 pi u for f = 1 .. n_freq, u from word 0 of the
+ * Philox block with counter (detector, f, event id low word, (event id high word << 4) | 13). */
+void orc_light_noise_phases(const orc_light_params *lp, uint64_t event_id, int32_t n_freq, double *phi)
+{
+    const uint32_t key[2] = {(uint32_t)lp->seed, (uint32_t)(lp->seed >> 32)};
+    for (int32_t d = 0; d < lp->n_det; ++d)
+        for (int32_t f = 1; f <= n_freq; ++f) {
+            const uint32_t ctr[4] = {(uint32_t)d, (uint32_t)f, (uint32_t)event_id,
+                                     (uint32_t)((event_id >> 32) << 4) | ORC_STREAM_LIGHT_NOISE};
+            uint32_t x[4];
+            orc_philox4x32_10(ctr, key, x);
+            phi[(int64_t)d * n_freq + f - 1] = 6.283185307179586477 * (((double)x[0] + 0.5) * 2.3283064365386963e-10);
+        }
+}

@@ -473,3 +473,92 @@ def large_spill(rng, n_segments=2_000_000, halo_cm=2.4):
             tiles.append(segs.subset(idx).shifted(dx=-xl, dy=-yl))
             ids.append(ty * TILES_X + tx)
     return tiles, ids
+
+
+# ------------------------------------------------------------------------------------------------ light (Sec. 4)
+
+W_PH_MEV = 19.5e-6                  # MeV per scintillation photon at zero field (not printed; standard LAr value)
+
+
+@dataclass
+class Light:
+    """Light readout and scintillation (Sec. 4).  Field order is the C layout of the library's light parameters."""
+    tick: float = 1.0               # ns per light tick
+    tau_p: float = 7.0              # ns, prompt scintillation decay time (Sec. 4.2: ~7 ns)
+    tau_s: float = 1600.0           # ns, slow decay time (Sec. 4.2: ~1600 ns)
+    f_prompt: float = 0.3           # prompt light fraction (Sec. 4.2: ~0.3)
+    trunc: float = 5.0              # the scintillation kernel is truncated after 5 tau_s (Sec. 4.2)
+    gain: float = 8.0               # ADC counts per p.e. (synthetic detector)
+    normal_above: float = 30.0      # p.e.: normal approximation above this mean (Sec. 4.2)
+    n_det: int = 64                 # light detectors
+    n_ticks: int = 16384            # 16.4 us window
+    group: int = 8                  # detectors summed for triggering (Sec. 4.3)
+    trig_threshold: float = 150.0   # ADC counts on the group sum
+    trig_deadtime: int = 2048       # ticks between triggers of a group
+    max_trig: int = 16              # triggers kept per group
+    seed: int = 0x2212098070000000 + 6
+
+
+def light_response(n_resp: int = 512, tau_r: float = 20.0, tick: float = 1.0) -> np.ndarray:
+    """Unit-normalised impulse response of a synthetic light readout (a CR-RC shape, time constant tau_r ns),
+    sampled at the light tick."""
+    t = (np.arange(n_resp) + 0.5) * tick / tau_r
+    r = t * np.exp(-t)
+    return (r / r.sum()).astype(np.float32)
+
+
+def light_noise_amplitudes(n_freq: int = 2048, sigma: float = 4.0, f_corner: float = 256.0) -> np.ndarray:
+    """Amplitudes of the random-phase noise sinusoids (Sec. 4.3) for frequencies f = 1 .. n_freq (in units of one
+    cycle per window): a spectrum falling as 1 / (1 + (f / f_corner)^2), scaled to an RMS of sigma ADC counts."""
+    f = np.arange(1, n_freq + 1, dtype=np.float64)
+    s = 1.0 / (1.0 + (f / f_corner) ** 2)
+    return (np.sqrt(2.0 * s / s.sum()) * sigma).astype(np.float32)
+
+
+def photocurrents(events: List[Segments], t_offsets_ns, light: Light, physics: Physics, module=(62.08, 62.08, 50.0),
+                  efficiency: float = 0.005) -> np.ndarray:
+    """Synthetic photocurrents I_pe[detector, tick] (p.e. emitted per tick) standing in for the visibility look-up
+    table of Sec. 4.1: photons per segment from the same recombination as the charge, dN/dx = (1/W_ph - R/W_ion)
+    dE/dx; detectors are 10 x 10 cm pads on the two x = const walls of the module (4 x 8 per wall in y, z); the
+    visibility of a segment midpoint is efficiency x the pad's solid-angle fraction (A cos(theta) / (4 pi d^2));
+    light arrives at t0 + t_offset + d / (c / 1.38)."""
+    nd, T = light.n_det, light.n_ticks
+    per_wall = nd // 2
+    ny, nz = 4, per_wall // 4
+    X, Y, Z = module
+    yc = (np.arange(ny) + 0.5) * Y / ny
+    zc = (np.arange(nz) + 0.5) * Z / nz
+    det = np.array([(wx, y, z) for wx in (0.0, X) for y in yc for z in zc])[:nd]
+    ipe = np.zeros((nd, T), np.float64)
+    c_lar = 29.9792458 / 1.38                                   # cm/ns
+    eps = physics.e_field * physics.lar_density
+    for segs, t_off in zip(events, t_offsets_ns):
+        r0 = np.stack([segs.x0, segs.y0, segs.z0], 1).astype(np.float64)
+        r1 = np.stack([segs.x1, segs.y1, segs.z1], 1).astype(np.float64)
+        mid = 0.5 * (r0 + r1)
+        L = np.linalg.norm(r1 - r0, axis=1)
+        dedx = np.where(L > 0, segs.energy / np.maximum(L, 1e-12), np.nan_to_num(segs.dedx if segs.dedx is not None
+                                                                                   else np.zeros(segs.n)))
+        R = physics.birks_ab / (1.0 + physics.birks_kb / eps * dedx)
+        n_gamma = (1.0 / W_PH_MEV - R / physics.w_ion) * dedx * L
+        t0 = 0.5 * (segs.t0 + segs.t1).astype(np.float64) * 1e3 + t_off   # us -> ns
+        for i, p in enumerate(det):
+            dv = mid - p[None]
+            d2 = (dv ** 2).sum(1)
+            cos = np.abs(dv[:, 0]) / np.sqrt(d2)
+            vis = efficiency * 100.0 * cos / (4.0 * np.pi * d2)
+            tick = np.floor((t0 + np.sqrt(d2) / c_lar) / light.tick).astype(np.int64)
+            ok = (tick >= 0) & (tick < T)
+            np.add.at(ipe[i], tick[ok], (vis * n_gamma)[ok])
+    return ipe.astype(np.float32)
+
+
+def light_workload(n_events: int = 4, light: Optional[Light] = None):
+    """A beam-spill light event: n_events module-scale interactions (spill-sized, as cfg3) at seeded times within
+    the first 10 us of the window.  Returns (light parameters, photocurrents, response kernel, noise amplitudes)."""
+    light = light or Light()
+    w = make_workload(3, n_events=n_events)
+    rng = _rng(6, 0)
+    t_off = np.sort(rng.uniform(200.0, 10000.0, size=n_events))
+    ipe = photocurrents(w.events, t_off, light, w.physics)
+    return light, ipe, light_response(tick=light.tick), light_noise_amplitudes()
