@@ -294,6 +294,50 @@ enum {
 lts_status lts_set_timing(lts_context *ctx, int32_t enabled);
 lts_status lts_get_timing(lts_context *ctx, double ms[LTS_N_STAGES], int64_t calls[LTS_N_STAGES]);
 
+/* ---- light path (Sec. 4) --------------------------------------------------------------------------------
+ * On given photocurrents (expected photoelectrons emitted per light tick per detector, the output of the visibility
+ * look-up of Sec. 4.1, which is the caller's): scintillation time profile, photoelectron statistics, electronics
+ * response with noise, and group triggers.  An lts_light object holds the response kernel, the noise spectrum and
+ * its device buffers (sized at creation); it is not thread-safe. */
+typedef struct lts_light_params {
+    double tick;               /* ns per light tick */
+    double tau_p, tau_s;       /* ns: prompt and slow scintillation decay times (Sec. 4.2) */
+    double f_prompt;           /* prompt fraction f_p of the two-exponential profile (Sec. 4.2) */
+    double trunc;              /* the scintillation kernel is truncated after trunc * tau_s (5 in Sec. 4.2) */
+    double gain;               /* G: ADC counts per photoelectron (Sec. 4.3) */
+    double normal_above;       /* mean p.e. per tick above which a normal draw replaces Poisson (30 in Sec. 4.2) */
+    int32_t n_det, n_ticks;    /* detectors; ticks of the window (<= 1 << 20) */
+    int32_t group;             /* consecutive detectors summed for triggering (divides n_det) */
+    double trig_threshold;     /* ADC counts on a group's summed waveform */
+    int32_t trig_deadtime;     /* ticks after a trigger before the group can trigger again (>= 1) */
+    int32_t max_trig;          /* triggers kept per group */
+    uint64_t seed;             /* Philox key of the photoelectron draws and the noise phases */
+} lts_light_params;
+typedef struct lts_light lts_light;
+
+/* Create a light simulator on `device`.  resp: unit-normalised impulse response sampled at the light tick (n_resp
+ * values, host, copied); noise_amp: amplitudes A_f of the noise sinusoids f = 1 .. n_freq cycles per window (host,
+ * copied; n_freq < n_ticks / 2).  INVALID_ARG for inconsistent parameters, OOM / DEVICE on allocation failures. */
+lts_status lts_light_create(int device, const lts_light_params *p, const float *resp, int32_t n_resp,
+                            const float *noise_amp, int32_t n_freq, lts_light **out);
+void lts_light_destroy(lts_light *L);
+
+/* One event, stream-ordered on `stream` (a hipStream_t; NULL = default), all pointers device memory:
+ *   ipe   [n_det][n_ticks] FP32 photocurrent (expected p.e. emitted per tick), read only;
+ *   mu    [n_det][n_ticks] FP64 expected p.e. per tick after the truncated scintillation convolution (Sec. 4.2:
+ *         mu[t] = sum_{k=0}^{trunc tau_s / tick} ipe[t-k] f_scint(k tick) tick) or NULL;
+ *   pe    [n_det][n_ticks] FP64 photoelectrons per tick: Poisson by inverse transform sampling (mean <= normal_above)
+ *         or mu + sqrt(mu) g, Philox counter (detector, tick, event low word, event high word << 4 | 12), or NULL;
+ *   V     [n_det][n_ticks] FP32 waveform: G sum_k pe[t-k] resp[k] + sum_f A_f cos(2 pi f t / n_ticks + phi_f),
+ *         phi_f = 2 pi u, u from Philox counter (detector, f, event low word, event high word << 4 | 13);
+ *   trig  [n_det / group][max_trig] INT32 trigger ticks (-1 after the last), trig_count [n_det / group] INT32:
+ *         per group, scanning in time, each tick where the group's summed V reaches trig_threshold, then none for
+ *         trig_deadtime ticks (Sec. 4.3); may be NULL together.
+ * The event id keys the draws, so results do not depend on call order. */
+lts_status lts_light_simulate(lts_light *L, uint64_t event_id, const float *ipe, double *mu, double *pe, float *V,
+                              int32_t *trig, int32_t *trig_count, void *stream);
+const char *lts_light_last_error(const lts_light *L);
+
 const char *lts_status_str(lts_status s);
 const char *lts_last_error(const lts_context *ctx);
 const char *lts_version(void);

@@ -99,26 +99,32 @@ def response(light, n, resp) -> np.ndarray:
     return np.stack([light.gain * np.convolve(n[d], r)[:T] for d in range(light.n_det)])
 
 
-def triggers(light, V):
+def triggers(light, V, eps_abs=1e-3, eps_rel=1e-5, with_uncertain=False):
     """Step 4: per group of `group` consecutive detectors, ticks where the summed waveform reaches the threshold,
-    scanning in time and skipping `trig_deadtime` ticks after each trigger; at most `max_trig` per group."""
-    out = []
+    scanning in time and skipping `trig_deadtime` ticks after each trigger; at most `max_trig` per group.  With
+    with_uncertain, also per group the first tick whose decision compared a sum within eps_abs + eps_rel * |sum| of
+    the threshold (an FP32 evaluation of the sum may decide it the other way; n_ticks if none)."""
+    out, unc = [], []
     for g in range(light.n_det // light.group):
         s = V[g * light.group:(g + 1) * light.group].sum(axis=0)
-        trig, t = [], 0
+        trig, t, u = [], 0, light.n_ticks
         while t < light.n_ticks and len(trig) < light.max_trig:
+            if u == light.n_ticks and abs(s[t] - light.trig_threshold) < eps_abs + eps_rel * abs(s[t]):
+                u = t
             if s[t] >= light.trig_threshold:
                 trig.append(t)
                 t += light.trig_deadtime
             else:
                 t += 1
         out.append(np.array(trig, np.int64))
-    return out
+        unc.append(u)
+    return (out, np.array(unc, np.int64)) if with_uncertain else out
 
 
 def simulate(light, event_id, ipe, resp, amp):
     """The whole light path for one event."""
     mu = scint(light, ipe)
     n, near = fluct(light, event_id, mu)
-    V = response(light, n, resp) + noise(light, event_id, amp)
-    return {"mu": mu, "n": n, "near": near, "V": V, "triggers": triggers(light, V)}
+    V = response(light, n, resp) + (noise(light, event_id, amp) if len(amp) else 0.0)
+    trig, unc = triggers(light, V, with_uncertain=True)
+    return {"mu": mu, "n": n, "near": near, "V": V, "triggers": trig, "trigger_uncertain_from": unc}

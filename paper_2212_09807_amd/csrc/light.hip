@@ -1,0 +1,344 @@
+// light.hip -- light path of the simulation (Sec. 4.2, 4.3) on given photocurrents, for gfx950, with its C ABI.
+//
+//   mu[d][t] = sum_{k=0}^{K-1} ipe[d][t-k] * w[k],  w[k] = tick * f_scint(k * tick)      (FP64, truncated direct)
+//   pe[d][t] = Poisson(mu) by inverse transform sampling, or mu + sqrt(mu) g above normal_above   (FP64)
+//   V[d][t]  = G * sum_{k<R} pe[d][t-k] * r[k] + sum_{f=1}^{F} A_f cos(2 pi f t / T + phi_{d,f})   (FP32)
+//   triggers per detector group on the summed V (threshold, dead time)
+//
+// The scintillation sum runs in FP64 because the photoelectron counts are integers decided by comparing a uniform
+// variate with cumulative Poisson probabilities of mu: an FP32 mean (a sum of ~8000 products) would move those
+// boundaries by ~1e-6 and flip counts, while FP64 leaves them where an FP64 evaluation puts them (the FP64 vector
+// rate of gfx950 equals its non-packed FP32 rate).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "../../include/ltsim.h"
+
+namespace ltsim {
+namespace {
+
+constexpr int kLWG = 256;            // threads per workgroup
+constexpr int kLRT = 8;              // ticks per thread in the convolutions
+constexpr int kLTile = kLWG * kLRT;  // ticks per workgroup tile
+constexpr uint32_t kStreamLightPe = 12u, kStreamLightNoise = 13u;
+
+typedef const double __attribute__((address_space(4))) *cdouble_ptr;
+typedef const float __attribute__((address_space(4))) *cfloat4_ptr;
+
+// mu for 8 consecutive ticks per thread; xp is the photocurrent row with Kp = 8 nkb + 8 zeros in front (index
+// Kp + t), w the kernel padded with zeros to nkb * 8 taps.  Window of block kb: xp[Kp + t0 - 8kb - 7 .. Kp + t0 -
+// 8kb + 7]; past the row end it reads the next row's zeros (the buffer has 8 floats of slack after the last row),
+// which only reach ticks >= T that are not stored.
+__global__ __launch_bounds__(kLWG) void k_light_scint(const float *__restrict__ xp, int32_t Kp, int32_t T,
+                                                      const double *__restrict__ w, int32_t nkb, double *__restrict__ mu) {
+    const int32_t d = blockIdx.y;
+    const int32_t t0 = blockIdx.x * kLTile + threadIdx.x * kLRT;
+    if (t0 >= T) return;
+    const float *x = xp + (int64_t)d * (Kp + T) + Kp + t0 - 7;
+    cdouble_ptr wc = (cdouble_ptr)w;
+    double acc[kLRT];
+#pragma unroll
+    for (int r = 0; r < kLRT; ++r) acc[r] = 0.0;
+    for (int32_t kb = 0; kb < nkb; ++kb) {
+        double win[kLRT + 7];
+#pragma unroll
+        for (int m = 0; m < kLRT + 7; ++m) win[m] = (double)x[m - 8 * kb];
+        double wk[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) wk[q] = wc[8 * kb + q];
+        // acc[r] += w[8kb + q] * x[t0 + r - 8kb - q] = wk[q] * win[r - q + 7]
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int r = 0; r < kLRT; ++r) acc[r] = fma(wk[q], win[r - q + 7], acc[r]);
+    }
+    double *o = mu + (int64_t)d * T + t0;
+#pragma unroll
+    for (int r = 0; r < kLRT; ++r)
+        if (t0 + r < T) o[r] = acc[r];
+}
+
+__global__ void k_light_pad(const float *__restrict__ ipe, float *__restrict__ xp, int32_t Kp, int32_t T, int32_t n_det) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_det * T) return;
+    const int64_t d = i / T, t = i - d * T;
+    xp[d * (Kp + T) + Kp + t] = ipe[i];
+}
+
+// Photoelectron statistics; writes pe (FP64) and the FP32 copy with Rp zeros in front for the response sum.
+__global__ void k_light_fluct(const double *__restrict__ mu, double *__restrict__ pe, float *__restrict__ pef,
+                              int32_t Rp, int32_t T, int32_t n_det, uint64_t event, uint32_t k0, uint32_t k1,
+                              double normal_above) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_det * T) return;
+    const int64_t d = i / T, t = i - d * T;
+    const uint4 c = make_uint4((uint32_t)d, (uint32_t)t, (uint32_t)event, (uint32_t)((event >> 32) << 4) | kStreamLightPe);
+    const uint4 x = philox4x32_10(c, k0, k1);
+    const double u = ((double)x.x + 0.5) * 0x1p-32;
+    const double m = mu[i];
+    double n;
+    if (m > normal_above) {
+        const double u1 = ((double)x.y + 0.5) * 0x1p-32;
+        n = m + sqrt(m) * (sqrt(-2.0 * log(u)) * cos(6.283185307179586477 * u1));
+    } else {
+        double p = exp(-m), F = p;
+        int32_t k = 0;
+        while (u > F && k < 1000) {
+            ++k;
+            p *= m / k;
+            F += p;
+        }
+        n = (double)k;
+    }
+    pe[i] = n;
+    pef[d * (Rp + T) + Rp + t] = (float)n;
+}
+
+// Noise coefficients per (detector, frequency): A_f cos(phi), A_f sin(phi), phi = 2 pi u.
+__global__ void k_light_noise_coef(const float *__restrict__ amp, int32_t F, int32_t n_det, uint64_t event, uint32_t k0,
+                                   uint32_t k1, float2 *__restrict__ coef) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_det * F) return;
+    const int32_t d = (int32_t)(i / F), f = (int32_t)(i - (int64_t)d * F) + 1;
+    const uint4 c = make_uint4((uint32_t)d, (uint32_t)f, (uint32_t)event, (uint32_t)((event >> 32) << 4) | kStreamLightNoise);
+    const uint4 x = philox4x32_10(c, k0, k1);
+    const double phi = 6.283185307179586477 * (((double)x.x + 0.5) * 0x1p-32);
+    coef[i] = make_float2((float)(amp[f - 1] * cos(phi)), (float)(amp[f - 1] * sin(phi)));
+}
+
+// V for 8 consecutive ticks per thread: the response sum (pef row with Rp zeros in front, r padded to nrb * 8 taps)
+// and the noise sinusoids: cos(2 pi f t / T + phi) = C[m] cos(phi) - S[m] sin(phi), m = f t mod T, with the angle of
+// the following ticks advanced by the rotation (C[f], S[f]).
+__global__ __launch_bounds__(kLWG) void k_light_response(const float *__restrict__ pef, int32_t Rp, int32_t T,
+                                                         const float *__restrict__ r, int32_t nrb, float gain,
+                                                         const float2 *__restrict__ coef, int32_t F,
+                                                         const float *__restrict__ Ct, const float *__restrict__ St,
+                                                         float *__restrict__ V) {
+    const int32_t d = blockIdx.y;
+    const int32_t t0 = blockIdx.x * kLTile + threadIdx.x * kLRT;
+    if (t0 >= T) return;
+    const float *x = pef + (int64_t)d * (Rp + T) + Rp + t0 - 7;
+    cfloat4_ptr rc = (cfloat4_ptr)r;
+    float acc[kLRT];
+#pragma unroll
+    for (int j = 0; j < kLRT; ++j) acc[j] = 0.0f;
+    for (int32_t kb = 0; kb < nrb; ++kb) {
+        float win[kLRT + 7];
+#pragma unroll
+        for (int m = 0; m < kLRT + 7; ++m) win[m] = x[m - 8 * kb];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float rk = rc[8 * kb + q];
+#pragma unroll
+            for (int j = 0; j < kLRT; ++j) acc[j] = fmaf(rk, win[j - q + 7], acc[j]);
+        }
+    }
+    float nz[kLRT];
+#pragma unroll
+    for (int j = 0; j < kLRT; ++j) nz[j] = 0.0f;
+    const float2 *cf = coef + (int64_t)d * F;
+    int32_t m0 = 0;                                    // f * t0 mod T, advanced by t0 per frequency
+    for (int32_t f = 1; f <= F; ++f) {
+        const float2 ab = cf[f - 1];
+        m0 += t0;
+        if (m0 >= T) m0 -= T;
+        float c = Ct[m0], s = St[m0];
+        const float c1 = Ct[f], s1 = St[f];
+#pragma unroll
+        for (int j = 0; j < kLRT; ++j) {
+            nz[j] = fmaf(ab.x, c, fmaf(-ab.y, s, nz[j]));
+            const float cn = fmaf(c, c1, -s * s1);
+            s = fmaf(s, c1, c * s1);
+            c = cn;
+        }
+    }
+    float *o = V + (int64_t)d * T + t0;
+#pragma unroll
+    for (int j = 0; j < kLRT; ++j)
+        if (t0 + j < T) o[j] = fmaf(gain, acc[j], nz[j]);
+}
+
+// One wavefront per detector group: 64 ticks at a time, the group sums in a fixed detector order, the first lane at
+// or after the end of the dead time whose sum reaches the threshold triggers.
+__global__ void k_light_trigger(const float *__restrict__ V, int32_t T, int32_t group, int32_t n_groups, float thr,
+                                int32_t dead, int32_t max_trig, int32_t *__restrict__ trig, int32_t *__restrict__ count) {
+    const int32_t g = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    if (g >= n_groups) return;
+    int32_t ready = 0, n = 0;
+    for (int32_t c0 = 0; c0 < T && n < max_trig; c0 += 64) {
+        const int32_t t = c0 + lane;
+        float s = 0.0f;
+        if (t < T)
+            for (int32_t k = 0; k < group; ++k) s += V[(int64_t)(g * group + k) * T + t];
+        const bool hit = t < T && s >= thr;
+        for (;;) {
+            const uint64_t m = __ballot(hit && t >= ready);
+            if (m == 0 || n >= max_trig) break;
+            const int32_t tf = c0 + __builtin_ctzll(m);
+            if (lane == 0) trig[(int64_t)g * max_trig + n] = tf;
+            ++n;
+            ready = tf + dead;
+        }
+    }
+    for (int32_t i = n + lane; i < max_trig; i += 64) trig[(int64_t)g * max_trig + i] = -1;
+    if (lane == 0) count[g] = n;
+}
+
+template <typename T>
+struct DBuf {
+    T *p = nullptr;
+    ~DBuf() { if (p) (void)hipFree(p); }
+    hipError_t alloc(size_t n) { return hipMalloc((void **)&p, sizeof(T) * std::max<size_t>(n, 1)); }
+};
+
+}  // namespace
+}  // namespace ltsim
+
+using namespace ltsim;
+
+struct lts_light {
+    lts_light_params p{};
+    int device = 0;
+    int32_t K = 0, nkb = 0, Kp = 0, R = 0, nrb = 0, Rp = 0, F = 0;
+    uint32_t k0 = 0, k1 = 0;
+    bool sticky = false;
+    std::string err;
+    DBuf<double> w, mu, pe;
+    DBuf<float> xp, pef, r, amp, Ct, St;
+    DBuf<float2> coef;
+};
+
+namespace {
+lts_status lfail(lts_light *L, lts_status s, const std::string &m) {
+    if (L) {
+        L->err = m;
+        if (s == LTS_ERR_DEVICE) L->sticky = true;
+    }
+    return s;
+}
+#define LHIP(L, call)                                                                                         \
+    do {                                                                                                      \
+        hipError_t e_ = (call);                                                                               \
+        if (e_ != hipSuccess) return lfail(L, e_ == hipErrorOutOfMemory ? LTS_ERR_OOM : LTS_ERR_DEVICE,       \
+                                          std::string(#call) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+}  // namespace
+
+extern "C" {
+
+lts_status lts_light_create(int device, const lts_light_params *p, const float *resp, int32_t n_resp,
+                            const float *noise_amp, int32_t n_freq, lts_light **out) {
+    if (!out) return LTS_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!p || !resp || n_resp < 1 || n_resp > (1 << 16) || (n_freq > 0 && !noise_amp) || n_freq < 0)
+        return LTS_ERR_INVALID_ARG;
+    const lts_light_params &q = *p;
+    if (!(q.tick > 0 && q.tau_p > 0 && q.tau_s > 0 && q.f_prompt >= 0 && q.f_prompt <= 1 && q.trunc > 0 &&
+          std::isfinite(q.gain) && std::isfinite(q.normal_above) && q.normal_above >= 0 && q.n_det >= 1 &&
+          q.n_ticks >= 1 && q.n_ticks <= (1 << 20) && q.group >= 1 && q.n_det % q.group == 0 &&
+          std::isfinite(q.trig_threshold) && q.trig_deadtime >= 1 && q.max_trig >= 0 && n_freq < q.n_ticks / 2))
+        return LTS_ERR_INVALID_ARG;
+    const double kd = std::floor(q.trunc * q.tau_s / q.tick) + 1.0;
+    if (!(kd >= 1.0 && kd <= (double)(1 << 22))) return LTS_ERR_INVALID_ARG;
+    lts_light *L = new lts_light();
+    L->p = q;
+    L->device = device;
+    L->K = (int32_t)kd;
+    L->nkb = (L->K + 7) / 8;
+    L->Kp = 8 * L->nkb + 8;
+    L->R = n_resp;
+    L->nrb = (n_resp + 7) / 8;
+    L->Rp = 8 * L->nrb + 8;
+    L->F = n_freq;
+    L->k0 = (uint32_t)q.seed;
+    L->k1 = (uint32_t)(q.seed >> 32);
+    auto fin = [&](lts_status s) {
+        if (s != LTS_OK) delete L;
+        else *out = L;
+        return s;
+    };
+    if (hipSetDevice(device) != hipSuccess) return fin(LTS_ERR_DEVICE);
+    const size_t nd = (size_t)q.n_det, T = (size_t)q.n_ticks;
+    // scintillation kernel, sampled two-exponential profile (Sec. 4.2), zero past the truncation
+    std::vector<double> w(8 * (size_t)L->nkb, 0.0);
+    for (int32_t k = 0; k < L->K; ++k) {
+        const double t = k * q.tick;
+        w[k] = q.tick * (q.f_prompt / q.tau_p * std::exp(-t / q.tau_p) + (1.0 - q.f_prompt) / q.tau_s * std::exp(-t / q.tau_s));
+    }
+    std::vector<float> r(8 * (size_t)L->nrb, 0.0f);
+    std::copy(resp, resp + n_resp, r.begin());
+    std::vector<float> C(T), S(T);
+    for (size_t m = 0; m < T; ++m) {
+        const double a = 6.283185307179586477 * (double)m / (double)T;
+        C[m] = (float)std::cos(a);
+        S[m] = (float)std::sin(a);
+    }
+    lts_status st = LTS_OK;
+    auto ok = [&](hipError_t e) {
+        if (e != hipSuccess && st == LTS_OK) st = e == hipErrorOutOfMemory ? LTS_ERR_OOM : LTS_ERR_DEVICE;
+        return e == hipSuccess;
+    };
+    ok(L->w.alloc(w.size())) && ok(L->mu.alloc(nd * T)) && ok(L->pe.alloc(nd * T)) &&
+        ok(L->xp.alloc(nd * (L->Kp + T) + 8)) && ok(L->pef.alloc(nd * (L->Rp + T) + 8)) && ok(L->r.alloc(r.size())) &&
+        ok(L->amp.alloc(std::max(n_freq, 1))) && ok(L->Ct.alloc(T)) && ok(L->St.alloc(T)) &&
+        ok(L->coef.alloc(nd * std::max(n_freq, 1))) &&
+        ok(hipMemcpy(L->w.p, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice)) &&
+        ok(hipMemcpy(L->r.p, r.data(), sizeof(float) * r.size(), hipMemcpyHostToDevice)) &&
+        (n_freq == 0 || ok(hipMemcpy(L->amp.p, noise_amp, sizeof(float) * n_freq, hipMemcpyHostToDevice))) &&
+        ok(hipMemcpy(L->Ct.p, C.data(), sizeof(float) * T, hipMemcpyHostToDevice)) &&
+        ok(hipMemcpy(L->St.p, S.data(), sizeof(float) * T, hipMemcpyHostToDevice)) &&
+        ok(hipMemset(L->xp.p, 0, sizeof(float) * (nd * (L->Kp + T) + 8))) &&
+        ok(hipMemset(L->pef.p, 0, sizeof(float) * (nd * (L->Rp + T) + 8))) && ok(hipDeviceSynchronize());
+    return fin(st);
+}
+
+void lts_light_destroy(lts_light *L) {
+    if (!L) return;
+    (void)hipSetDevice(L->device);
+    (void)hipDeviceSynchronize();
+    delete L;
+}
+
+lts_status lts_light_simulate(lts_light *L, uint64_t event_id, const float *ipe, double *mu, double *pe, float *V,
+                              int32_t *trig, int32_t *trig_count, void *stream) {
+    if (!L) return LTS_ERR_INVALID_ARG;
+    if (L->sticky) return lfail(L, LTS_ERR_DEVICE, "a previous device error: destroy and recreate");
+    if (!ipe || !V || (!trig) != (!trig_count)) return lfail(L, LTS_ERR_INVALID_ARG, "null buffer");
+    hipStream_t st = (hipStream_t)stream;
+    LHIP(L, hipSetDevice(L->device));
+    const lts_light_params &q = L->p;
+    const int32_t T = q.n_ticks, nd = q.n_det;
+    const int64_t n = (int64_t)nd * T;
+    double *mu_d = mu ? mu : L->mu.p;
+    double *pe_d = pe ? pe : L->pe.p;
+    const unsigned g1 = (unsigned)((n + 255) / 256);
+    k_light_pad<<<g1, 256, 0, st>>>(ipe, L->xp.p, L->Kp, T, nd);
+    const dim3 gt((unsigned)((T + kLTile - 1) / kLTile), (unsigned)nd);
+    k_light_scint<<<gt, kLWG, 0, st>>>(L->xp.p, L->Kp, T, L->w.p, L->nkb, mu_d);
+    k_light_fluct<<<g1, 256, 0, st>>>(mu_d, pe_d, L->pef.p, L->Rp, T, nd, event_id, L->k0, L->k1, q.normal_above);
+    if (L->F > 0) {
+        const int64_t nc = (int64_t)nd * L->F;
+        k_light_noise_coef<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(L->amp.p, L->F, nd, event_id, L->k0, L->k1,
+                                                                        L->coef.p);
+    }
+    k_light_response<<<gt, kLWG, 0, st>>>(L->pef.p, L->Rp, T, L->r.p, L->nrb, (float)q.gain, L->coef.p, L->F,
+                                         L->Ct.p, L->St.p, V);
+    if (trig) {
+        const int32_t ng = nd / q.group;
+        k_light_trigger<<<(unsigned)((ng + 3) / 4), 256, 0, st>>>(V, T, q.group, ng, (float)q.trig_threshold,
+                                                                 q.trig_deadtime, q.max_trig, trig, trig_count);
+    }
+    LHIP(L, hipGetLastError());
+    return LTS_OK;
+}
+
+const char *lts_light_last_error(const lts_light *L) { return L ? L->err.c_str() : "null light simulator"; }
+
+}  // extern "C"

@@ -79,7 +79,14 @@ EXPORTS = ("lts_server_start", "lts_server_submit", "lts_server_poll", "lts_serv
            "lts_server_stop", "lts_set_timing", "lts_get_timing", "lts_work_stats", "lts_context_create", "lts_context_destroy",
            "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_set_ticks_per_thread", "lts_set_lane_exchange", "lts_set_channel_mask",
            "lts_plan", "lts_simulate", "lts_simulate_batch", "lts_stage_quench_drift", "lts_debug_cells",
-           "lts_stage_electronics", "lts_stage_philox", "lts_status_str", "lts_last_error", "lts_version")
+           "lts_stage_electronics", "lts_stage_philox", "lts_status_str", "lts_last_error", "lts_version",
+           "lts_light_create", "lts_light_destroy", "lts_light_simulate", "lts_light_last_error")
+
+
+class lts_light_params(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("tick", "tau_p", "tau_s", "f_prompt", "trunc", "gain", "normal_above")] + [
+        ("n_det", C.c_int32), ("n_ticks", C.c_int32), ("group", C.c_int32), ("trig_threshold", C.c_double),
+        ("trig_deadtime", C.c_int32), ("max_trig", C.c_int32), ("seed", C.c_uint64)]
 
 _LIB = None
 
@@ -123,6 +130,12 @@ def lib():
             getattr(L, f).restype = C.c_char_p
         L.lts_status_str.argtypes = [C.c_int]
         L.lts_last_error.argtypes = [P]
+        L.lts_light_create.argtypes = [C.c_int, C.POINTER(lts_light_params), P, C.c_int32, P, C.c_int32, C.POINTER(P)]
+        L.lts_light_destroy.argtypes = [P]
+        L.lts_light_destroy.restype = None
+        L.lts_light_simulate.argtypes = [P, C.c_uint64, P, P, P, P, P, P, P]
+        L.lts_light_last_error.argtypes = [P]
+        L.lts_light_last_error.restype = C.c_char_p
         _LIB = L
     return _LIB
 
@@ -427,5 +440,62 @@ class Server:
     def __del__(self):
         try:
             self.stop()
+        except Exception:
+            pass
+
+
+class LightSim:
+    """Light path on given photocurrents (lts_light_*): scintillation, photoelectron statistics, response with
+    noise and group triggers, all on the device."""
+
+    def __init__(self, light, resp, noise_amp, device: int = 0):
+        L = lib()
+        self._p = _fill(lts_light_params, light)
+        self.light = light
+        r = np.ascontiguousarray(resp, dtype=np.float32)
+        a = np.ascontiguousarray(noise_amp, dtype=np.float32)
+        self._h = C.c_void_p()
+        st = L.lts_light_create(device, C.byref(self._p), r.ctypes.data, len(r), a.ctypes.data, len(a),
+                                C.byref(self._h))
+        if st:
+            raise LtsimError(st, "lts_light_create")
+        self.device = device
+
+    def simulate(self, ipe, event_id: int, keep_mu: bool = False, keep_pe: bool = False, stream=None):
+        """ipe: device float32 tensor [n_det, n_ticks].  Returns device tensors V (and mu, pe if asked), trigger ticks
+        [n_groups, max_trig] and counts [n_groups]."""
+        import torch
+        lp = self.light
+        shape = (lp.n_det, lp.n_ticks)
+        if tuple(ipe.shape) != shape or ipe.dtype != torch.float32 or not ipe.is_cuda or not ipe.is_contiguous():
+            raise LtsimError(1, f"photocurrent must be a contiguous float32 device tensor of shape {shape}")
+        dev = ipe.device
+        V = torch.empty(shape, dtype=torch.float32, device=dev)
+        mu = torch.empty(shape, dtype=torch.float64, device=dev) if keep_mu else None
+        pe = torch.empty(shape, dtype=torch.float64, device=dev) if keep_pe else None
+        ng = lp.n_det // lp.group
+        trig = torch.empty((ng, max(lp.max_trig, 1)), dtype=torch.int32, device=dev)
+        cnt = torch.empty(ng, dtype=torch.int32, device=dev)
+        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        st = lib().lts_light_simulate(self._h, event_id, ipe.data_ptr(), mu.data_ptr() if keep_mu else None,
+                                      pe.data_ptr() if keep_pe else None, V.data_ptr(), trig.data_ptr(),
+                                      cnt.data_ptr(), s)
+        if st:
+            raise LtsimError(st, lib().lts_light_last_error(self._h).decode())
+        out = {"V": V, "trig": trig[:, :lp.max_trig], "trig_count": cnt}
+        if keep_mu:
+            out["mu"] = mu
+        if keep_pe:
+            out["pe"] = pe
+        return out
+
+    def close(self):
+        if self._h:
+            lib().lts_light_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass
