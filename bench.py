@@ -108,6 +108,39 @@ def batched_vs_plain(ltsim, W, n_events, mode):
     return res
 
 
+PEAK_FP64_FMA_TFLOPS = PEAK_FP32_FMA_TFLOPS     # gfx950: FP64 vector FMA at the non-packed FP32 rate
+
+
+def light_leg(ltsim, W, reps=10):
+    """The light path (Sec. 4.2-4.3) on the synthetic spill photocurrents: per-event time of one lts_light_simulate
+    (HIP events on its stream, inputs resident), detector-ticks per second, and the FP64 rate of the scintillation
+    convolution's useful multiply-adds over the whole call (a lower bound of that kernel's own rate)."""
+    import torch
+    lp, ipe, r, amp = W.light_workload()
+    sim = ltsim.LightSim(lp, r, amp)
+    x = torch.from_numpy(ipe).cuda()
+    sim.simulate(x, 1)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(reps):
+        sim.simulate(x, 1 + i)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    K = int(lp.trunc * lp.tau_s / lp.tick) + 1
+    T = lp.n_ticks
+    fma = lp.n_det * (min(K, T) * (min(K, T) + 1) // 2 + max(T - K, 0) * K)
+    sim.close()
+    ach = 2.0 * fma / (ms / 1e3) / 1e12
+    return {"workload": f"light spill: {lp.n_det} detectors x {T} ticks of {lp.tick} ns, {K}-tap scintillation kernel, "
+                        f"{len(r)}-tap response, {len(amp)} noise sinusoids, 4 interactions",
+            "ms_per_event": ms, "detector_ticks_per_s": lp.n_det * T / (ms / 1e3),
+            "roofline": {"kernel": "k_light_scint (whole light call timed)", "bound": "alu", "achieved": ach,
+                         "peak": PEAK_FP64_FMA_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_FMA_TFLOPS,
+                         "flops_per_launch": 2.0 * fma, "dtype": "f64"}}
+
+
 def served(ltsim, W, rate_hz, n_events, mode, lanes=2):
     """Poisson arrivals at rate_hz of the batched-spill event mix through the library's request loop."""
     import numpy as np
@@ -184,13 +217,14 @@ def main():
     ap.add_argument("--served", type=float, nargs=2, default=(2.0, 16), metavar=("RATE_HZ", "N"),
                     help="also serve N spill events arriving as a Poisson process at RATE_HZ")
     ap.add_argument("--slices", type=int, default=1)
+    ap.add_argument("--no-light", action="store_true", help="skip the light-path leg")
     ap.add_argument("--also", default=None,
                     help="comma-separated other reduce modes to time on the same event (default: summed; none with --quick)")
     ap.add_argument("--quick", action="store_true", help="only the headline path (no batch or serving, and no other "
                                                          "modes unless --also names them)")
     args = ap.parse_args()
     if args.quick:
-        args.batched, args.served = 0, None
+        args.batched, args.served, args.no_light = 0, None, True
     if args.also is None:
         args.also = "" if args.quick else "summed"
     if args.gpus != 1:
@@ -270,6 +304,8 @@ def main():
         line.setdefault("modes", {})[other] = time_mode(ltsim, w, segs, other, args.steps)
     if args.batched:
         line["batched"] = batched_vs_plain(ltsim, W, args.batched, mode)
+    if not args.no_light:
+        line["light"] = light_leg(ltsim, W)
     if args.served:
         line["served"] = served(ltsim, W, args.served[0], int(args.served[1]), mode)
     if not args.no_cpu_baseline:
