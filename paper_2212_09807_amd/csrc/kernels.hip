@@ -793,38 +793,6 @@ __device__ __forceinline__ void column_stream(const float *col, const float *cc,
     }
 }
 
-// Products of one table column with one cell column for RT = 8, two 8-value blocks in ping-pong: block j of cell
-// ticks needs b_j = R[K0-8j .. +7] and b_{j+1} = R[K0-8j-8 .. -1]; the buffer holding b_j is refilled with b_{j+2}
-// after block j, so each block loads only its 8 new values (no copies, no cross-lane traffic).
-template <bool ALIGNED>
-__device__ __forceinline__ void column_pingpong(const float *col, cfloat_ptr cc, int32_t nblk, float (&acc)[8]) {
-    float X[8], Y[8], cv[kAC];
-    load8<ALIGNED>(col, X);
-    for (int32_t j = 0; j < nblk; j += 2) {
-        load8<ALIGNED>(col - 8 * (j + 1), Y);
-#pragma unroll
-        for (int q = 0; q < kAC; ++q) cv[q] = cc[kAC * j + q];
-#pragma unroll
-        for (int q = 0; q < kAC; ++q)
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int m = r - q + kAC - 1;
-                acc[r] = fmaf(cv[q], m < 7 ? Y[m + 1] : X[m - 7], acc[r]);
-            }
-        if (j + 1 >= nblk) break;
-        load8<ALIGNED>(col - 8 * (j + 2), X);
-#pragma unroll
-        for (int q = 0; q < kAC; ++q) cv[q] = cc[kAC * (j + 1) + q];
-#pragma unroll
-        for (int q = 0; q < kAC; ++q)
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int m = r - q + kAC - 1;
-                acc[r] = fmaf(cv[q], m < 7 ? X[m + 1] : Y[m - 7], acc[r]);
-            }
-    }
-}
-
 // One (segment, pixel) pair through the lane-exchange ring: the columns (u, v) of its charge box inside the pixel's
 // reach, in row order.
 __device__ __forceinline__ void pair_block_ring(const DevParams &P, const float *__restrict__ cc0, int32_t nv, int32_t nap,
@@ -1377,20 +1345,62 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
         };
         int64_t q = pb;
         while (q < pe && !meets(q)) ++q;
-        if constexpr (!SHIFT) {                         // aligned ping-pong per piece, Kahan after each piece
-            for (; q < pe; ++q) {
-                if (!meets(q)) continue;
+        if constexpr (!SHIFT) {
+            // the pixel's (piece, block) sequence with the next block's 15-value window and cell values loaded
+            // while the current block's products run, across piece boundaries; Kahan after each piece
+            if (q < pe) {
                 const float *col, *cc;
-                int32_t nblk;
+                int32_t nblk, j = 0;
                 colof(q, col, cc, nblk);
-                column_pingpong<true>(col, uniform_cptr(cc), nblk, acc);
+                cfloat_ptr ccu = uniform_cptr(cc);
+                bool done = false;
+                auto fetch = [&](float (&w)[8 + kAC - 1], float (&cv)[kAC], bool &last, bool &valid) {
+                    valid = !done;
+                    const float *pw = col - (kAC - 1) - kAC * j;          // R[K0 - 8j - 7 .. K0 - 8j + 7]
 #pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const float y = acc[r] - cmp[r];
-                    const float t = sum[r] + y;
-                    cmp[r] = (t - sum[r]) - y;
-                    sum[r] = t;
-                    acc[r] = 0.0f;
+                    for (int m = 0; m < 8 + kAC - 1; ++m) w[m] = pw[m];
+#pragma unroll
+                    for (int c = 0; c < kAC; ++c) cv[c] = ccu[kAC * j + c];
+                    last = j == nblk - 1;
+                    if (!done && ++j == nblk) {
+                        do { ++q; } while (q < pe && !meets(q));
+                        if (q < pe) {
+                            colof(q, col, cc, nblk);
+                            ccu = uniform_cptr(cc);
+                            j = 0;
+                        } else {
+                            done = true;                        // keep fetching the last block (safe addresses)
+                            j = nblk - 1;
+                        }
+                    }
+                };
+                auto block = [&](const float (&w)[8 + kAC - 1], const float (&cv)[kAC], bool last) {
+#pragma unroll
+                    for (int c = 0; c < kAC; ++c)
+#pragma unroll
+                        for (int r = 0; r < 8; ++r) acc[r] = fmaf(cv[c], w[r - c + kAC - 1], acc[r]);
+                    if (last) {
+#pragma unroll
+                        for (int r = 0; r < 8; ++r) {
+                            const float y = acc[r] - cmp[r];
+                            const float t = sum[r] + y;
+                            cmp[r] = (t - sum[r]) - y;
+                            sum[r] = t;
+                            acc[r] = 0.0f;
+                        }
+                    }
+                };
+                float wa[8 + kAC - 1], ca[kAC], wb[8 + kAC - 1], cb[kAC];
+                bool la, va, lb, vb;
+                fetch(wa, ca, la, va);
+                while (va) {
+                    fetch(wb, cb, lb, vb);
+                    __builtin_amdgcn_sched_barrier(0);
+                    block(wa, ca, la);
+                    if (!vb) break;
+                    fetch(wa, ca, la, va);
+                    __builtin_amdgcn_sched_barrier(0);
+                    block(wb, cb, lb);
                 }
             }
         } else if (q < pe) {
