@@ -638,20 +638,22 @@ struct BlockCursor {
 __device__ __forceinline__ void pair_block_pf(const DevParams &P, const float *__restrict__ cc0, int32_t nv, int32_t nap,
                                               int32_t u0, int32_t v0, int32_t a0, const float *__restrict__ Rpad,
                                               int32_t ulo, int32_t uhi, int32_t vlo, int32_t vhi, int32_t uc,
-                                              int32_t vc, int32_t nb, float (&acc)[8]) {
-    const int32_t K0 = nb - a0 + P.t_r - 1 + kPad;
+                                              int32_t vc, int32_t nb0, int32_t lane_off, float (&acc)[8]) {
+    // table offset of the window's first value for the workgroup's first thread (uniform) and this thread's offset
+    // from it (8 ticks per thread): every load is a uniform base plus a fixed 32-bit lane offset
+    const int32_t K0w = nb0 - a0 + P.t_r - 1 + kPad - (kAC - 1);
     const int32_t nblk = nap / kAC;
-    const int64_t total = (int64_t)(uhi - ulo + 1) * (vhi - vlo + 1) * nblk;
+    const int32_t total = (uhi - ulo + 1) * (vhi - vlo + 1) * nblk;
     BlockCursor f{ulo, vlo, 0};                         // next block to fetch
-    int64_t nf = 0;                                     // blocks fetched so far
+    int32_t nf = 0;                                     // blocks fetched so far
     // Loads are issued unconditionally (past the last block the last block is fetched again), so the number of
     // loads in flight is the same on every path and the waits only cover the block about to be used.
     auto fetch = [&](float (&w)[8 + kAC - 1], float (&cv)[kAC]) {
-        const float *col = Rpad + (int64_t)(fold(f.u - uc) * P.by + fold(f.v - vc)) * P.col_len + K0 - (kAC - 1) -
-                           kAC * f.j;
-        cfloat_ptr cc = uniform_cptr(cc0 + ((int64_t)(f.u - u0) * nv + (f.v - v0)) * nap + kAC * f.j);
+        const int64_t cb = (int64_t)(fold(f.u - uc) * P.by + fold(f.v - vc)) * P.col_len + K0w - kAC * f.j;
+        gfloat_ptr base = (gfloat_ptr)(Rpad + cb);
+        cfloat_ptr cc = (cfloat_ptr)(cc0 + ((int64_t)(f.u - u0) * nv + (f.v - v0)) * nap + kAC * f.j);
 #pragma unroll
-        for (int m = 0; m < 8 + kAC - 1; ++m) w[m] = col[m];
+        for (int m = 0; m < 8 + kAC - 1; ++m) w[m] = base[lane_off + m];
 #pragma unroll
         for (int q = 0; q < kAC; ++q) cv[q] = cc[q];
         if (++nf < total && ++f.j == nblk) {
@@ -667,7 +669,7 @@ __device__ __forceinline__ void pair_block_pf(const DevParams &P, const float *_
     };
     float wa[8 + kAC - 1], ca[kAC], wb[8 + kAC - 1], cb[kAC];
     fetch(wa, ca);
-    for (int64_t b = 0; b < total; b += 2) {
+    for (int32_t b = 0; b < total; b += 2) {
         fetch(wb, cb);
         __builtin_amdgcn_sched_barrier(0);
         block(wa, ca);
@@ -902,7 +904,8 @@ __global__ __launch_bounds__(kWG) void k_induce_sorted(DevParams P, const SegInf
                     pair_block_ring(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, nb <= hi, acc);
                 else if constexpr (RT == 8 && PREFETCH) {
                     if (nb <= hi)
-                        pair_block_pf(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, acc);
+                        pair_block_pf(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb0, tid * RT,
+                                      acc);
                 } else if (nb <= hi)
                     pair_block<RT>(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, acc);
 #pragma unroll
@@ -1349,24 +1352,33 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
             // the pixel's (piece, block) sequence with the next block's 15-value window and cell values loaded
             // while the current block's products run, across piece boundaries; Kahan after each piece
             if (q < pe) {
-                const float *col, *cc;
+                // table offsets: a uniform base per piece (the tile's first tick) plus the lane's 8 * lane
+                const int32_t loff = 8 * lane;
+                int64_t cbase;
+                const float *cc;
                 int32_t nblk, j = 0;
-                colof(q, col, cc, nblk);
-                cfloat_ptr ccu = uniform_cptr(cc);
+                auto piece_at = [&](int64_t k) {
+                    const SegInfo &g = piece[list[k]];
+                    cbase = (int64_t)(fold(g.u0 - uc) * P.by + fold(g.v0 - vc)) * P.col_len + (t0 - g.a0 + TR - 1 + kPad);
+                    cc = S + g.cell_off;
+                    nblk = g.na_pad / kAC;
+                };
+                piece_at(q);
+                cfloat_ptr ccu = (cfloat_ptr)cc;
                 bool done = false;
                 auto fetch = [&](float (&w)[8 + kAC - 1], float (&cv)[kAC], bool &last, bool &valid) {
                     valid = !done;
-                    const float *pw = col - (kAC - 1) - kAC * j;          // R[K0 - 8j - 7 .. K0 - 8j + 7]
+                    gfloat_ptr pw = (gfloat_ptr)(Rpad + cbase - (kAC - 1) - kAC * j);   // R[K0 - 8j - 7 ..]
 #pragma unroll
-                    for (int m = 0; m < 8 + kAC - 1; ++m) w[m] = pw[m];
+                    for (int m = 0; m < 8 + kAC - 1; ++m) w[m] = pw[loff + m];
 #pragma unroll
                     for (int c = 0; c < kAC; ++c) cv[c] = ccu[kAC * j + c];
                     last = j == nblk - 1;
                     if (!done && ++j == nblk) {
                         do { ++q; } while (q < pe && !meets(q));
                         if (q < pe) {
-                            colof(q, col, cc, nblk);
-                            ccu = uniform_cptr(cc);
+                            piece_at(q);
+                            ccu = (cfloat_ptr)cc;
                             j = 0;
                         } else {
                             done = true;                        // keep fetching the last block (safe addresses)
