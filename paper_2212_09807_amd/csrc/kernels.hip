@@ -795,6 +795,39 @@ __device__ __forceinline__ void column_stream(const float *col, const float *cc,
     }
 }
 
+// Products of one table column with one cell column for RT = 8, two 8-value blocks in ping-pong: block j of cell
+// ticks needs b_j = R[K0-8j .. +7] and b_{j+1} = R[K0-8j-8 .. -1]; the buffer holding b_j is refilled with b_{j+2}
+// after block j, so each block loads only its 8 new values (no copies, no cross-lane traffic).
+template <bool ALIGNED>
+__device__ __forceinline__ void column_pingpong(const float *col, cfloat_ptr cc, int32_t nblk, float (&acc)[8]) {
+    float X[8], Y[8], cv[kAC];
+    load8<ALIGNED>(col, X);
+    for (int32_t j = 0; j < nblk; j += 2) {
+        load8<ALIGNED>(col - 8 * (j + 1), Y);
+#pragma unroll
+        for (int q = 0; q < kAC; ++q) cv[q] = cc[kAC * j + q];
+#pragma unroll
+        for (int q = 0; q < kAC; ++q)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int m = r - q + kAC - 1;
+                acc[r] = fmaf(cv[q], m < 7 ? Y[m + 1] : X[m - 7], acc[r]);
+            }
+        if (j + 1 >= nblk) break;
+        load8<ALIGNED>(col - 8 * (j + 2), X);
+#pragma unroll
+        for (int q = 0; q < kAC; ++q) cv[q] = cc[kAC * (j + 1) + q];
+#pragma unroll
+        for (int q = 0; q < kAC; ++q)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int m = r - q + kAC - 1;
+                acc[r] = fmaf(cv[q], m < 7 ? X[m + 1] : Y[m - 7], acc[r]);
+            }
+    }
+}
+
+
 // One (segment, pixel) pair through the lane-exchange ring: the columns (u, v) of its charge box inside the pixel's
 // reach, in row order.
 __device__ __forceinline__ void pair_block_ring(const DevParams &P, const float *__restrict__ cc0, int32_t nv, int32_t nap,
@@ -1348,71 +1381,20 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
         };
         int64_t q = pb;
         while (q < pe && !meets(q)) ++q;
-        if constexpr (!SHIFT) {
-            // the pixel's (piece, block) sequence with the next block's 15-value window and cell values loaded
-            // while the current block's products run, across piece boundaries; Kahan after each piece
-            if (q < pe) {
-                // table offsets: a uniform base per piece (the tile's first tick) plus the lane's 8 * lane
-                const int32_t loff = 8 * lane;
-                int64_t cbase;
-                const float *cc;
-                int32_t nblk, j = 0;
-                auto piece_at = [&](int64_t k) {
-                    const SegInfo &g = piece[list[k]];
-                    cbase = (int64_t)(fold(g.u0 - uc) * P.by + fold(g.v0 - vc)) * P.col_len + (t0 - g.a0 + TR - 1 + kPad);
-                    cc = S + g.cell_off;
-                    nblk = g.na_pad / kAC;
-                };
-                piece_at(q);
-                cfloat_ptr ccu = (cfloat_ptr)cc;
-                bool done = false;
-                auto fetch = [&](float (&w)[8 + kAC - 1], float (&cv)[kAC], bool &last, bool &valid) {
-                    valid = !done;
-                    gfloat_ptr pw = (gfloat_ptr)(Rpad + cbase - (kAC - 1) - kAC * j);   // R[K0 - 8j - 7 ..]
+        if constexpr (!SHIFT) {                         // aligned ping-pong per piece, Kahan after each piece
+            for (; q < pe; ++q) {
+                if (!meets(q)) continue;
+                const float *col, *cc;
+                int32_t nblk;
+                colof(q, col, cc, nblk);
+                column_pingpong<true>(col, uniform_cptr(cc), nblk, acc);
 #pragma unroll
-                    for (int m = 0; m < 8 + kAC - 1; ++m) w[m] = pw[loff + m];
-#pragma unroll
-                    for (int c = 0; c < kAC; ++c) cv[c] = ccu[kAC * j + c];
-                    last = j == nblk - 1;
-                    if (!done && ++j == nblk) {
-                        do { ++q; } while (q < pe && !meets(q));
-                        if (q < pe) {
-                            piece_at(q);
-                            ccu = (cfloat_ptr)cc;
-                            j = 0;
-                        } else {
-                            done = true;                        // keep fetching the last block (safe addresses)
-                            j = nblk - 1;
-                        }
-                    }
-                };
-                auto block = [&](const float (&w)[8 + kAC - 1], const float (&cv)[kAC], bool last) {
-#pragma unroll
-                    for (int c = 0; c < kAC; ++c)
-#pragma unroll
-                        for (int r = 0; r < 8; ++r) acc[r] = fmaf(cv[c], w[r - c + kAC - 1], acc[r]);
-                    if (last) {
-#pragma unroll
-                        for (int r = 0; r < 8; ++r) {
-                            const float y = acc[r] - cmp[r];
-                            const float t = sum[r] + y;
-                            cmp[r] = (t - sum[r]) - y;
-                            sum[r] = t;
-                            acc[r] = 0.0f;
-                        }
-                    }
-                };
-                float wa[8 + kAC - 1], ca[kAC], wb[8 + kAC - 1], cb[kAC];
-                bool la, va, lb, vb;
-                fetch(wa, ca, la, va);
-                while (va) {
-                    fetch(wb, cb, lb, vb);
-                    __builtin_amdgcn_sched_barrier(0);
-                    block(wa, ca, la);
-                    if (!vb) break;
-                    fetch(wa, ca, la, va);
-                    __builtin_amdgcn_sched_barrier(0);
-                    block(wb, cb, lb);
+                for (int r = 0; r < 8; ++r) {
+                    const float y = acc[r] - cmp[r];
+                    const float t = sum[r] + y;
+                    cmp[r] = (t - sum[r]) - y;
+                    sum[r] = t;
+                    acc[r] = 0.0f;
                 }
             }
         } else if (q < pe) {
