@@ -141,6 +141,36 @@ def light_leg(ltsim, W, reps=10):
                          "flops_per_launch": 2.0 * fma, "dtype": "f64"}}
 
 
+def large_spill_leg(ltsim, W, modes):
+    """The large spill (35 tiles of 140 x 140 pixels, 2,000,000 segments plus halo replicas, 5000 ticks, full noise):
+    one plain lts_simulate per tile, device-resident segments, wall time of the whole spill per reduce mode."""
+    import torch
+    w = W.make_workload(5)
+    n_orig = 2_000_000
+    n_all = sum(e.n for e in w.events)
+    dsegs = [ltsim.to_device(e) for e in w.events]
+    out = {"workload": f"large spill: {len(w.events)} tiles of {w.readout.n_x}x{w.readout.n_y} pixels, {n_orig} "
+                       f"segments ({n_all} with halo replicas), {w.readout.n_ticks} ticks, 45x45x1950 table, "
+                       f"noise 900/650/500 e-, one plain call per tile"}
+    for name in modes:
+        mode, shift, rt = MODES[name]
+        ctx = ltsim.Context.from_workload(w, reduce_mode=mode)
+        ctx.set_lane_exchange(shift)
+        ctx.set_ticks_per_thread(rt)
+        big = max(range(len(dsegs)), key=lambda i: w.events[i].n)
+        ctx.simulate(dsegs[big], event_id=w.event_ids[big])            # warm-up: allocations, table upload
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for d, i in zip(dsegs, w.event_ids):
+            ctx.simulate(d, event_id=i)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(f"[bench] large spill {name}: {el:.2f} s", file=sys.stderr, flush=True)
+        out[name] = {"seconds": el, "segments_per_s": n_orig / el}
+        ctx.close()
+    return out
+
+
 def served(ltsim, W, rate_hz, n_events, mode, lanes=2):
     """Poisson arrivals at rate_hz of the batched-spill event mix through the library's request loop."""
     import numpy as np
@@ -218,6 +248,8 @@ def main():
                     help="also serve N spill events arriving as a Poisson process at RATE_HZ")
     ap.add_argument("--slices", type=int, default=1)
     ap.add_argument("--no-light", action="store_true", help="skip the light-path leg")
+    ap.add_argument("--large-spill", default="", help="comma-separated modes to time on the 2M-segment large spill "
+                                                      "(minutes of GPU time; off by default)")
     ap.add_argument("--also", default=None,
                     help="comma-separated other reduce modes to time on the same event (default: summed; none with --quick)")
     ap.add_argument("--quick", action="store_true", help="only the headline path (no batch or serving, and no other "
@@ -306,6 +338,8 @@ def main():
         line["batched"] = batched_vs_plain(ltsim, W, args.batched, mode)
     if not args.no_light:
         line["light"] = light_leg(ltsim, W)
+    if args.large_spill:
+        line["large_spill"] = large_spill_leg(ltsim, W, [m for m in args.large_spill.split(",") if m])
     if args.served:
         line["served"] = served(ltsim, W, args.served[0], int(args.served[1]), mode)
     if not args.no_cpu_baseline:
