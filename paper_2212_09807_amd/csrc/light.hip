@@ -112,6 +112,38 @@ __global__ void k_light_noise_coef(const float *__restrict__ amp, int32_t F, int
     coef[i] = make_float2((float)(amp[f - 1] * cos(phi)), (float)(amp[f - 1] * sin(phi)));
 }
 
+// Noise by FFT (power-of-two windows whose complex spectrum fits in LDS): noise[t] is the real part of
+// y[t] = sum_{f=1}^{F} A_f e^{i phi_f} e^{2 pi i f t / T}, an unnormalised inverse DFT of the one-sided spectrum,
+// computed in place by iterative radix-2 decimation in time (bit-reversed load, log2 T butterfly stages with
+// twiddles e^{2 pi i j / len} read from the cosine / sine tables at index j T / len).  One workgroup per detector.
+__global__ __launch_bounds__(1024) void k_light_noise_fft(const float2 *__restrict__ coef, int32_t F, int32_t T,
+                                                          int32_t log2T, const float *__restrict__ Ct,
+                                                          const float *__restrict__ St, float *__restrict__ nz) {
+    extern __shared__ float2 xs[];
+    const int32_t d = blockIdx.x;
+    const float2 *cf = coef + (int64_t)d * F;
+    for (int32_t i = threadIdx.x; i < T; i += blockDim.x) {
+        const float2 y = (i >= 1 && i <= F) ? cf[i - 1] : make_float2(0.0f, 0.0f);
+        xs[__builtin_bitreverse32((uint32_t)i) >> (32 - log2T)] = y;
+    }
+    __syncthreads();
+    for (int32_t half = 1; half < T; half <<= 1) {
+        const int32_t stride = T / (2 * half);                    // twiddle table step for this stage
+        for (int32_t k = threadIdx.x; k < T / 2; k += blockDim.x) {
+            const int32_t j = k & (half - 1);
+            const int32_t i0 = ((k - j) << 1) + j, i1 = i0 + half;
+            const float wr = Ct[j * stride], wi = St[j * stride];
+            const float2 a = xs[i0], b = xs[i1];
+            const float tr = wr * b.x - wi * b.y, ti = fmaf(wr, b.y, wi * b.x);
+            xs[i0] = make_float2(a.x + tr, a.y + ti);
+            xs[i1] = make_float2(a.x - tr, a.y - ti);
+        }
+        __syncthreads();
+    }
+    float *o = nz + (int64_t)d * T;
+    for (int32_t i = threadIdx.x; i < T; i += blockDim.x) o[i] = xs[i].x;
+}
+
 // V for 8 consecutive ticks per thread: the response sum (pef row with Rp zeros in front, r padded to nrb * 8 taps)
 // and the noise sinusoids: cos(2 pi f t / T + phi) = C[m] cos(phi) - S[m] sin(phi), m = f t mod T, with the angle of
 // the following ticks advanced by the rotation (C[f], S[f]).
@@ -119,7 +151,7 @@ __global__ __launch_bounds__(kLWG) void k_light_response(const float *__restrict
                                                          const float *__restrict__ r, int32_t nrb, float gain,
                                                          const float2 *__restrict__ coef, int32_t F,
                                                          const float *__restrict__ Ct, const float *__restrict__ St,
-                                                         float *__restrict__ V) {
+                                                         const float *__restrict__ nzpre, float *__restrict__ V) {
     const int32_t d = blockIdx.y;
     const int32_t t0 = blockIdx.x * kLTile + threadIdx.x * kLRT;
     if (t0 >= T) return;
@@ -141,10 +173,10 @@ __global__ __launch_bounds__(kLWG) void k_light_response(const float *__restrict
     }
     float nz[kLRT];
 #pragma unroll
-    for (int j = 0; j < kLRT; ++j) nz[j] = 0.0f;
+    for (int j = 0; j < kLRT; ++j) nz[j] = (nzpre && t0 + j < T) ? nzpre[(int64_t)d * T + t0 + j] : 0.0f;
     const float2 *cf = coef + (int64_t)d * F;
     int32_t m0 = 0;                                    // f * t0 mod T, advanced by t0 per frequency
-    for (int32_t f = 1; f <= F; ++f) {
+    for (int32_t f = 1; f <= (nzpre ? 0 : F); ++f) {
         const float2 ab = cf[f - 1];
         m0 += t0;
         if (m0 >= T) m0 -= T;
@@ -213,6 +245,8 @@ struct lts_light {
     DBuf<double> w, mu, pe;
     DBuf<float> xp, pef, r, amp, Ct, St;
     DBuf<float2> coef;
+    DBuf<float> nz;                                  // noise by FFT (when fft_log2 > 0)
+    int32_t fft_log2 = 0;
 };
 
 namespace {
@@ -296,6 +330,18 @@ lts_status lts_light_create(int device, const lts_light_params *p, const float *
         ok(hipMemcpy(L->St.p, S.data(), sizeof(float) * T, hipMemcpyHostToDevice)) &&
         ok(hipMemset(L->xp.p, 0, sizeof(float) * (nd * (L->Kp + T) + 8))) &&
         ok(hipMemset(L->pef.p, 0, sizeof(float) * (nd * (L->Rp + T) + 8))) && ok(hipDeviceSynchronize());
+    // power-of-two windows up to 16384 ticks take the FFT noise path if the device grants the LDS it needs
+    if (st == LTS_OK && n_freq > 0 && T >= 2 && (T & (T - 1)) == 0 && T * sizeof(float2) <= 131072) {
+        if (hipFuncSetAttribute((const void *)k_light_noise_fft, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(T * sizeof(float2))) == hipSuccess &&
+            ok(L->nz.alloc(nd * T))) {
+            int32_t lg = 0;
+            while ((size_t)1 << lg < T) ++lg;
+            L->fft_log2 = lg;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
     return fin(st);
 }
 
@@ -328,8 +374,14 @@ lts_status lts_light_simulate(lts_light *L, uint64_t event_id, const float *ipe,
         k_light_noise_coef<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(L->amp.p, L->F, nd, event_id, L->k0, L->k1,
                                                                         L->coef.p);
     }
+    const float *nzpre = nullptr;
+    if (L->F > 0 && L->fft_log2 > 0) {
+        k_light_noise_fft<<<(unsigned)nd, 1024, (size_t)T * sizeof(float2), st>>>(L->coef.p, L->F, T, L->fft_log2,
+                                                                                L->Ct.p, L->St.p, L->nz.p);
+        nzpre = L->nz.p;
+    }
     k_light_response<<<gt, kLWG, 0, st>>>(L->pef.p, L->Rp, T, L->r.p, L->nrb, (float)q.gain, L->coef.p, L->F,
-                                         L->Ct.p, L->St.p, V);
+                                         L->Ct.p, L->St.p, nzpre, V);
     if (trig) {
         const int32_t ng = nd / q.group;
         k_light_trigger<<<(unsigned)((ng + 3) / 4), 256, 0, st>>>(V, T, q.group, ng, (float)q.trig_threshold,
