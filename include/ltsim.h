@@ -306,7 +306,7 @@ typedef struct lts_light_params {
     double trunc;              /* the scintillation kernel is truncated after trunc * tau_s (5 in Sec. 4.2) */
     double gain;               /* G: ADC counts per photoelectron (Sec. 4.3) */
     double normal_above;       /* mean p.e. per tick above which a normal draw replaces Poisson (30 in Sec. 4.2) */
-    int32_t n_det, n_ticks;    /* detectors; ticks of the window (<= 1 << 20) */
+    int32_t n_det, n_ticks;    /* detectors; ticks of the window (<= 1 << 19) */
     int32_t group;             /* consecutive detectors summed for triggering (divides n_det) */
     double trig_threshold;     /* ADC counts on a group's summed waveform */
     int32_t trig_deadtime;     /* ticks after a trigger before the group can trigger again (>= 1) */

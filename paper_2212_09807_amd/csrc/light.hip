@@ -196,31 +196,41 @@ __global__ __launch_bounds__(kLWG) void k_light_response(const float *__restrict
         if (t0 + j < T) o[j] = fmaf(gain, acc[j], nz[j]);
 }
 
-// One wavefront per detector group: 64 ticks at a time, the group sums in a fixed detector order, the first lane at
-// or after the end of the dead time whose sum reaches the threshold triggers.
-__global__ void k_light_trigger(const float *__restrict__ V, int32_t T, int32_t group, int32_t n_groups, float thr,
-                                int32_t dead, int32_t max_trig, int32_t *__restrict__ trig, int32_t *__restrict__ count) {
-    const int32_t g = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-    const int lane = threadIdx.x & 63;
-    if (g >= n_groups) return;
-    int32_t ready = 0, n = 0;
-    for (int32_t c0 = 0; c0 < T && n < max_trig; c0 += 64) {
-        const int32_t t = c0 + lane;
+// One workgroup per detector group.  First every thread sums the group's waveforms (fixed detector order) for its
+// ticks and each wavefront's ballot records, per 64-tick chunk, which ticks reach the threshold (all chunks at once,
+// into LDS); then one thread scans the chunk masks in time order: the first set bit at or after the end of the dead
+// time triggers, and the dead time restarts from it.
+__global__ __launch_bounds__(256) void k_light_trigger(const float *__restrict__ V, int32_t T, int32_t group, float thr,
+                                                       int32_t dead, int32_t max_trig, int32_t *__restrict__ trig,
+                                                       int32_t *__restrict__ count) {
+    extern __shared__ uint64_t masks[];
+    const int32_t g = blockIdx.x;
+    const int32_t nch = (T + 63) / 64;
+    for (int32_t base = 0; base < nch * 64; base += blockDim.x) {
+        const int32_t t = base + threadIdx.x;
         float s = 0.0f;
         if (t < T)
             for (int32_t k = 0; k < group; ++k) s += V[(int64_t)(g * group + k) * T + t];
-        const bool hit = t < T && s >= thr;
+        const uint64_t m = __ballot(t < T && s >= thr);
+        if ((threadIdx.x & 63) == 0 && t / 64 < nch) masks[t / 64] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    int32_t ready = 0, n = 0;
+    for (int32_t c = 0; c < nch && n < max_trig; ++c) {
+        uint64_t m = masks[c];
         for (;;) {
-            const uint64_t m = __ballot(hit && t >= ready);
+            const int32_t off = ready - 64 * c;                  // ticks of this chunk still in the dead time
+            if (off >= 64) break;
+            if (off > 0) m &= ~((1ull << off) - 1ull);
             if (m == 0 || n >= max_trig) break;
-            const int32_t tf = c0 + __builtin_ctzll(m);
-            if (lane == 0) trig[(int64_t)g * max_trig + n] = tf;
-            ++n;
+            const int32_t tf = 64 * c + __builtin_ctzll(m);
+            trig[(int64_t)g * max_trig + n++] = tf;
             ready = tf + dead;
         }
     }
-    for (int32_t i = n + lane; i < max_trig; i += 64) trig[(int64_t)g * max_trig + i] = -1;
-    if (lane == 0) count[g] = n;
+    for (int32_t i = n; i < max_trig; ++i) trig[(int64_t)g * max_trig + i] = -1;
+    count[g] = n;
 }
 
 template <typename T>
@@ -276,7 +286,7 @@ lts_status lts_light_create(int device, const lts_light_params *p, const float *
     const lts_light_params &q = *p;
     if (!(q.tick > 0 && q.tau_p > 0 && q.tau_s > 0 && q.f_prompt >= 0 && q.f_prompt <= 1 && q.trunc > 0 &&
           std::isfinite(q.gain) && std::isfinite(q.normal_above) && q.normal_above >= 0 && q.n_det >= 1 &&
-          q.n_ticks >= 1 && q.n_ticks <= (1 << 20) && q.group >= 1 && q.n_det % q.group == 0 &&
+          q.n_ticks >= 1 && q.n_ticks <= (1 << 19) && q.group >= 1 && q.n_det % q.group == 0 &&
           std::isfinite(q.trig_threshold) && q.trig_deadtime >= 1 && q.max_trig >= 0 && n_freq < q.n_ticks / 2))
         return LTS_ERR_INVALID_ARG;
     const double kd = std::floor(q.trunc * q.tau_s / q.tick) + 1.0;
@@ -384,8 +394,9 @@ lts_status lts_light_simulate(lts_light *L, uint64_t event_id, const float *ipe,
                                          L->Ct.p, L->St.p, nzpre, V);
     if (trig) {
         const int32_t ng = nd / q.group;
-        k_light_trigger<<<(unsigned)((ng + 3) / 4), 256, 0, st>>>(V, T, q.group, ng, (float)q.trig_threshold,
-                                                                 q.trig_deadtime, q.max_trig, trig, trig_count);
+        const size_t lds = sizeof(uint64_t) * (size_t)((T + 63) / 64);
+        k_light_trigger<<<(unsigned)ng, 256, lds, st>>>(V, T, q.group, (float)q.trig_threshold, q.trig_deadtime,
+                                                       q.max_trig, trig, trig_count);
     }
     LHIP(L, hipGetLastError());
     return LTS_OK;
