@@ -174,6 +174,43 @@ def large_spill_leg(ltsim, W, modes):
     return out
 
 
+def materialised_leg(ltsim, W, steps=3):
+    """The paper's data flow on the module-scale event: every (segment, pixel) pair's current written out as its own
+    n_ticks waveform (lts_stage_induce), then summed per pixel (lts_stage_reduce); wall time per event against the
+    fused per-pair path, and the bytes of the materialised tensor."""
+    import torch
+    w = W.make_workload(2)
+    d = ltsim.to_device(w.events[0])
+    ctx = ltsim.Context.from_workload(w)
+    eid = w.event_ids[0]
+    sg, px, cur = ctx.stage_induce(d, event_id=eid)
+    ctx.stage_reduce(px, cur)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        del sg, px, cur                                # one materialised tensor at a time
+        sg, px, cur = ctx.stage_induce(d, event_id=eid)
+        pid, red = ctx.stage_reduce(px, cur)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    fused = ctx.simulate(d, event_id=eid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fused = ctx.simulate(d, event_id=eid)
+    torch.cuda.synchronize()
+    fe = (time.perf_counter() - t0) / steps
+    n_pairs = int(px.numel())
+    out = {"workload": "module-scale event, materialised (segment, pixel, tick) currents then per-pixel sum",
+           "pairs": n_pairs, "tensor_bytes": 4 * n_pairs * w.readout.n_ticks,
+           "ms_per_event": el * 1e3, "fused_ms_per_event": fe * 1e3,
+           "note": "materialised = stage_induce + stage_reduce (no electronics); fused = whole lts_simulate"}
+    del sg, px, cur, pid, red, fused
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def served(ltsim, W, rate_hz, n_events, mode, lanes=2):
     """Poisson arrivals at rate_hz of the batched-spill event mix through the library's request loop."""
     import numpy as np
@@ -251,6 +288,8 @@ def main():
                     help="also serve N spill events arriving as a Poisson process at RATE_HZ")
     ap.add_argument("--slices", type=int, default=1)
     ap.add_argument("--no-light", action="store_true", help="skip the light-path leg")
+    ap.add_argument("--materialised", action="store_true",
+                    help="also time the paper's data flow: per-pair currents written out, then summed per pixel")
     ap.add_argument("--large-spill", default="", help="comma-separated modes to time on the 2M-segment large spill "
                                                       "(minutes of GPU time; off by default)")
     ap.add_argument("--also", default=None,
@@ -343,6 +382,8 @@ def main():
         line["batched"] = batched_vs_plain(ltsim, W, args.batched, mode)
     if not args.no_light:
         line["light"] = light_leg(ltsim, W)
+    if args.materialised:
+        line["materialised"] = materialised_leg(ltsim, W)
     if args.large_spill:
         line["large_spill"] = large_spill_leg(ltsim, W, [m for m in args.large_spill.split(",") if m])
     if args.served:

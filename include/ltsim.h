@@ -216,6 +216,33 @@ lts_status lts_stage_quench_drift(lts_context *ctx, const lts_segments *segs, fl
  * box[6] = (a0, na, u0, nu, v0, nv) in absolute tick / sub-pixel-bin indices, cells[na][nu][nv] if cap >= size. */
 lts_status lts_debug_cells(lts_context *ctx, int64_t segment, int64_t box[6], float *cells_host, int64_t cap);
 
+/* Rasterisation alone (Sec. 3.3.2: the pixels a segment's charge reaches; Sec. 3.3.1: a pixel reaches the table's
+ * extent of sub-pixel bins around its centre).  Writes the (segment, pixel) pairs of the call, pixel-major with
+ * ascending segment index within a pixel: pair_segment[k] = row of segs, pair_pixel[k] = tile-local pixel id
+ * (both device, cap_pairs entries).  *n_pairs_out (host) receives the pair count; LTS_ERR_CAPACITY if it exceeds
+ * cap_pairs (nothing is written then).  Synchronises the stream once (sizing). */
+lts_status lts_stage_rasterize(lts_context *ctx, const lts_segments *segs, int32_t *pair_segment,
+                               int32_t *pair_pixel, int64_t cap_pairs, int64_t *n_pairs_out, void *stream);
+
+/* Induction per pair, materialised (Sec. 3.3.2, eq. (current), the per-(segment, pixel, tick) waveforms of the
+ * paper's design, Sec. 3.4): pair k of the list lts_stage_rasterize returns gets row k of pair_current
+ * (device, cap_pairs * n_ticks floats), its current over the whole window (zero outside the pair's reach in time).
+ * pair_segment / pair_pixel (device, may be NULL) receive the pair list.  event_id keys the Monte Carlo draws.
+ * Capacity and synchronisation as lts_stage_rasterize.  Memory: 4 * n_ticks bytes per pair. */
+lts_status lts_stage_induce(lts_context *ctx, uint64_t event_id, const lts_segments *segs, int32_t *pair_segment,
+                            int32_t *pair_pixel, float *pair_current, int64_t cap_pairs, int64_t *n_pairs_out,
+                            void *stream);
+
+/* Per-pixel sum of materialised pair waveforms (Sec. 3.4: the current on a pixel is the sum over the segments
+ * reaching it).  pair_pixel[n_pairs] (device) must be grouped by ascending pixel id (as lts_stage_rasterize
+ * returns it; LTS_ERR_INVALID_ARG otherwise); pair_current[n_pairs * n_ticks] (device).  Writes one row per
+ * distinct pixel: pixel_id[k] and current[k * n_ticks ...] (device, cap_pixels rows), each the FP32 Kahan sum of
+ * its pairs in stored order.  *n_pixels_out (host) receives the row count; LTS_ERR_CAPACITY if above cap_pixels.
+ * Synchronises the stream once. */
+lts_status lts_stage_reduce(lts_context *ctx, const int32_t *pair_pixel, const float *pair_current, int64_t n_pairs,
+                            int32_t *pixel_id, float *current, int64_t cap_pixels, int64_t *n_pixels_out,
+                            void *stream);
+
 /* Front end alone on given currents: n_pix pixels with tile-local ids pixel_ids[] (device), currents
  * current[n_pix * n_ticks] (device).  Packets as in lts_outputs (counts and packet arrays). */
 lts_status lts_stage_electronics(lts_context *ctx, uint64_t event_id, const int32_t *pixel_ids, const float *current,

@@ -1173,6 +1173,143 @@ void launch_induce(const DevParams &P, const Work &w, const Table &T, float *wav
     }
 }
 
+// ================================================================================================= stage hooks
+// The paper's own data flow (Sec. 3.3.2, 3.4): the induced current of every (segment, pixel) pair is materialised as
+// its own waveform, then the waveforms of each pixel are summed.  The fused kernels above never write these; the
+// hooks below do, for tests and for comparison with the fused path.
+
+// Pair list in stored order (pixel-major, ascending segment within a pixel): segment index and tile pixel id.
+__global__ __launch_bounds__(kWG) void k_pair_list(DevParams P, const int64_t *__restrict__ slot_off,
+                                                   const int32_t *__restrict__ pairs,
+                                                   const int32_t *__restrict__ slot_gp, const DevHeader *H,
+                                                   int32_t *pair_seg, int32_t *pair_pix) {
+    for (int64_t slot = blockIdx.x; slot < H->n_slots; slot += gridDim.x) {
+        const int32_t gp = slot_gp[slot];
+        const int32_t p = gp - (gp / P.npx) * P.npx;
+        for (int64_t q = slot_off[slot] + threadIdx.x; q < slot_off[slot + 1]; q += kWG) {
+            if (pair_seg) pair_seg[q] = pairs[q];
+            if (pair_pix) pair_pix[q] = p;
+        }
+    }
+}
+
+// Row q of `out` (n_ticks floats) receives pair q's current I_sp[n]: workgroup per active pixel, its pairs in
+// stored order; ticks outside the pair's reach in time are written as zero.
+template <int RT>
+__global__ __launch_bounds__(kWG) void k_induce_pairs(DevParams P, const SegInfo *__restrict__ si,
+                                                      const float *__restrict__ cells, const float *__restrict__ Rpad,
+                                                      const int64_t *__restrict__ slot_off,
+                                                      const int32_t *__restrict__ pairs,
+                                                      const int32_t *__restrict__ slot_gp, const DevHeader *H,
+                                                      float *__restrict__ out) {
+    const int NT = P.nticks;
+    const int tid = threadIdx.x;
+    for (int64_t slot = blockIdx.x; slot < H->n_slots; slot += gridDim.x) {
+        const int32_t gp = slot_gp[slot];
+        const int32_t p = gp - (gp / P.npx) * P.npx;
+        const int32_t ix = p % P.nx, iy = p / P.nx;
+        const int32_t uc = ix * P.nsub + P.nsub / 2, vc = iy * P.nsub + P.nsub / 2;
+        for (int64_t q = slot_off[slot]; q < slot_off[slot + 1]; ++q) {
+            const SegInfo &g = si[__builtin_amdgcn_readfirstlane(pairs[q])];
+            const int32_t u0 = g.u0, v0 = g.v0, a0 = g.a0, nv = g.nv, nap = g.na_pad, na = g.na;
+            const int32_t ulo = max(u0, uc - P.bx), uhi = min(u0 + g.nu - 1, uc + P.bx - 1);
+            const int32_t vlo = max(v0, vc - P.by), vhi = min(v0 + nv - 1, vc + P.by - 1);
+            const bool any = ulo <= uhi && vlo <= vhi;
+            const int32_t lo = any ? max(a0 - (P.t_r - 1), 0) : NT, hi = any ? min(a0 + na - 1, NT - 1) : -1;
+            float *row = out + q * NT;
+            for (int n = tid; n < NT; n += kWG)
+                if (n < lo || n > hi) row[n] = 0.0f;
+            const float *cc0 = cells + g.cell_off;
+            for (int32_t nb0 = lo; nb0 <= hi; nb0 += kWG * RT) {
+                const int32_t nb = nb0 + tid * RT;
+                if (nb > hi) continue;
+                float acc[RT];
+#pragma unroll
+                for (int r = 0; r < RT; ++r) acc[r] = 0.0f;
+                pair_block<RT>(P, cc0, nv, nap, u0, v0, a0, Rpad, ulo, uhi, vlo, vhi, uc, vc, nb, acc);
+#pragma unroll
+                for (int r = 0; r < RT; ++r)
+                    if (nb + r <= hi) row[nb + r] = acc[r];
+            }
+        }
+    }
+}
+
+void launch_pair_list(const DevParams &P, const Work &w, int64_t n_slots, int32_t *pair_seg, int32_t *pair_pix,
+                      hipStream_t st) {
+    if (n_slots <= 0) return;
+    const unsigned g = (unsigned)std::min<int64_t>(n_slots, 65536);
+    k_pair_list<<<g, kWG, 0, st>>>(P, w.slot_off, w.pairs, w.slot_gp, w.hdr, pair_seg, pair_pix);
+}
+
+void launch_induce_pairs(const DevParams &P, const Work &w, const Table &T, int64_t n_slots, float *out,
+                         hipStream_t st) {
+    if (n_slots <= 0) return;
+    const unsigned g = (unsigned)std::min<int64_t>(n_slots, 65536);
+    switch (pick_rt(P, 0)) {
+        case 1: k_induce_pairs<1><<<g, kWG, 0, st>>>(P, w.si, w.cells, T.Rpad, w.slot_off, w.pairs, w.slot_gp, w.hdr, out); break;
+        case 2: k_induce_pairs<2><<<g, kWG, 0, st>>>(P, w.si, w.cells, T.Rpad, w.slot_off, w.pairs, w.slot_gp, w.hdr, out); break;
+        case 4: k_induce_pairs<4><<<g, kWG, 0, st>>>(P, w.si, w.cells, T.Rpad, w.slot_off, w.pairs, w.slot_gp, w.hdr, out); break;
+        default: k_induce_pairs<8><<<g, kWG, 0, st>>>(P, w.si, w.cells, T.Rpad, w.slot_off, w.pairs, w.slot_gp, w.hdr, out); break;
+    }
+}
+
+// Per-pixel sum of pair waveforms grouped by pixel: head[q] = 1 where a run of equal pixel ids starts (q < n),
+// head[n] = 0; a pixel id below its predecessor sets ST_INVALID (the pairs are not grouped in ascending order).
+__global__ void k_run_heads(const int32_t *__restrict__ pix, int64_t n, int64_t *head, DevHeader *H) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > n) return;
+    if (q == n) { head[q] = 0; return; }
+    const int32_t prev = q > 0 ? pix[q - 1] : -1;
+    head[q] = pix[q] != prev ? 1 : 0;
+    if (pix[q] < prev) atomicOr(&H->status, ST_INVALID);
+}
+
+// After the exclusive scan of head: start[k] = first pair of run k, start[n_runs] = n; pixel ids of the runs.
+__global__ void k_run_starts(const int32_t *__restrict__ pix, int64_t n, const int64_t *__restrict__ idx,
+                             int64_t *start, int32_t *pixel_out, int64_t cap) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int64_t k = idx[q];
+    if (q == 0 || pix[q] != pix[q - 1]) {
+        start[k] = q;
+        if (k < cap) pixel_out[k] = pix[q];
+    }
+    if (q == n - 1) start[idx[n]] = n;
+}
+
+// current[k][t] = sum over the run's pairs, in stored order, of their waveforms at tick t (Kahan summation).
+__global__ __launch_bounds__(kWG) void k_reduce_runs(const float *__restrict__ pair_current,
+                                                     const int64_t *__restrict__ start, int32_t NT, float *current) {
+    const int64_t k = blockIdx.x;
+    const int32_t t = blockIdx.y * kWG + threadIdx.x;
+    if (t >= NT) return;
+    float sum = 0.0f, cmp = 0.0f;
+    for (int64_t q = start[k]; q < start[k + 1]; ++q) {
+        const float y = pair_current[q * NT + t] - cmp;
+        const float z = sum + y;
+        cmp = (z - sum) - y;
+        sum = z;
+    }
+    current[k * NT + t] = sum - cmp;
+}
+
+void launch_run_heads(const int32_t *pix, int64_t n, int64_t *head, DevHeader *H, hipStream_t st) {
+    k_run_heads<<<(unsigned)((n + 1 + kWG - 1) / kWG), kWG, 0, st>>>(pix, n, head, H);
+}
+
+void launch_run_starts(const int32_t *pix, int64_t n, const int64_t *idx, int64_t *start, int32_t *pixel_out,
+                       int64_t cap, hipStream_t st) {
+    if (n > 0) k_run_starts<<<(unsigned)((n + kWG - 1) / kWG), kWG, 0, st>>>(pix, n, idx, start, pixel_out, cap);
+}
+
+void launch_reduce_runs(const float *pair_current, const int64_t *start, int64_t n_runs, int32_t NT, float *current,
+                        hipStream_t st) {
+    if (n_runs <= 0 || NT <= 0) return;
+    const dim3 g((unsigned)n_runs, (unsigned)((NT + kWG - 1) / kWG));
+    k_reduce_runs<<<g, kWG, 0, st>>>(pair_current, start, NT, current);
+}
+
 // ================================================================================================= summed induction
 // Sum-then-convolve: by linearity of eq. (current), the current on pixel p is the time convolution of each absolute
 // sub-pixel column's charge, summed over all segments, with that column's folded table column.  The columns are

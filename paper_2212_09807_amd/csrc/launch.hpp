@@ -84,6 +84,15 @@ void launch_induce(const DevParams &P, const Work &w, const Table &T, float *wav
                    int32_t rt, bool shift, hipStream_t st);
 void launch_induce_slices(const DevParams &P, const Work &w, const Table &T, float *wave, int64_t n_slots, int32_t NS,
                           float *part, int64_t chunk, int32_t rt, hipStream_t st);
+void launch_pair_list(const DevParams &P, const Work &w, int64_t n_slots, int32_t *pair_seg, int32_t *pair_pix,
+                      hipStream_t st);
+void launch_induce_pairs(const DevParams &P, const Work &w, const Table &T, int64_t n_slots, float *out,
+                         hipStream_t st);
+void launch_run_heads(const int32_t *pix, int64_t n, int64_t *head, DevHeader *H, hipStream_t st);
+void launch_run_starts(const int32_t *pix, int64_t n, const int64_t *idx, int64_t *start, int32_t *pixel_out,
+                       int64_t cap, hipStream_t st);
+void launch_reduce_runs(const float *pair_current, const int64_t *start, int64_t n_runs, int32_t NT, float *current,
+                        hipStream_t st);
 void launch_electronics(const DevParams &P, const float *wave, const int32_t *slot_gp, const uint64_t *event_ids,
                         int64_t n_slots, const Work &w, hipStream_t st);
 void launch_compact_packets(const DevParams &P, const Work &w, int64_t n_slots, int32_t *pkt_pixel, int32_t *pkt_tick,

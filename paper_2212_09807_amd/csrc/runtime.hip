@@ -51,7 +51,7 @@ struct lts_context {
     int32_t t_r = 0, b_x = 0, b_y = 0;
     // scratch pool
     DevBuf si, cell_off, pix_cnt, cursor, pix_slot, slot_gp, slot_off, pairs_u, pairs, cells, pk_tick, pk_adc,
-        pk_flag, pk_off, hdr, scan_tmp, ev_off, ev_ids, report_tmp, counts_tmp;
+        pk_flag, pk_off, hdr, scan_tmp, ev_off, ev_ids, report_tmp, counts_tmp, red_head, red_start;
     DevHeader *hdr_host = nullptr;   // pinned
     int64_t last_n_seg = -1;
     int64_t last_n_slots = 0;
@@ -531,7 +531,8 @@ void lts_context_destroy(lts_context *c) {
     DevBuf *bufs[] = {&c->mask, &c->col_lo, &c->col_hi, &c->col_seg_off, &c->col_cursor, &c->col_seg, &c->piece_off, &c->s_off,
                       &c->piece, &c->S, &c->list_off, &c->list, &c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off, &c->pix_cnt, &c->cursor, &c->pix_slot, &c->slot_gp,
                       &c->slot_off, &c->pairs_u, &c->pairs, &c->cells, &c->pk_tick, &c->pk_adc, &c->pk_flag,
-                      &c->pk_off, &c->hdr, &c->scan_tmp, &c->ev_off, &c->ev_ids, &c->report_tmp, &c->counts_tmp};
+                      &c->pk_off, &c->hdr, &c->scan_tmp, &c->ev_off, &c->ev_ids, &c->report_tmp, &c->counts_tmp,
+                      &c->red_head, &c->red_start};
     for (DevBuf *b : bufs) free_buf(*b);
     if (c->hdr_host) (void)hipHostFree(c->hdr_host);
     delete c;
@@ -751,6 +752,112 @@ lts_status lts_stage_electronics(lts_context *c, uint64_t event_id, const int32_
     launch_electronics(c->P, current, pixel_ids, as<uint64_t>(c->ev_ids), n_pix, w, st);
     launch_compact_packets(c->P, w, n_pix, out->pkt_pixel, out->pkt_tick, out->pkt_adc, out->pkt_flags, out->cap_packets,
                            nullptr, nullptr, out->counts, st);
+    HIP_TRY(c, hipGetLastError());
+    return LTS_OK;
+}
+
+// Front half of the pipeline for the pair-level hooks: sizing, slots, pixel-major pairs in ascending segment order,
+// and (with_cells) the charge cells.  Returns the header; the pair count is h.n_pairs.
+static lts_status stage_front(lts_context *c, uint64_t event_id, const lts_segments *segs, bool with_cells,
+                              hipStream_t st, Work &w, DevHeader &h) {
+    if (c->sticky) return fail(c, c->sticky, "context is in a failed state: " + c->err);
+    if (!c->has_table) return fail(c, LTS_ERR_STATE, "no response table: call lts_set_response first");
+    lts_status r;
+    if ((r = check_segments(c, segs))) return r;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if ((r = ensure(c, c->report_tmp, sizeof(double) * 5))) return r;
+    const int64_t off[2] = {0, segs->n};
+    if ((r = run_sizing(c, 1, &event_id, off, segs, as<double>(c->report_tmp), st, w, h))) return r;
+    // lts_debug_cells and lts_work_stats describe the last call that computed charge cells
+    if (!with_cells) c->last_n_seg = -1;
+    c->last_mode = LTS_REDUCE_SORTED;
+    c->last_n_slots = h.n_slots;
+    const int64_t n_slots = h.n_slots, n_pairs = h.n_pairs;
+    if ((r = ensure(c, c->slot_gp, sizeof(int32_t) * (size_t)std::max<int64_t>(n_slots, 1)))) return r;
+    if ((r = ensure(c, c->slot_off, sizeof(int64_t) * (size_t)(n_slots + 1)))) return r;
+    if ((r = ensure(c, c->pairs_u, sizeof(int32_t) * (size_t)std::max<int64_t>(n_pairs, 1)))) return r;
+    if ((r = ensure(c, c->pairs, sizeof(int32_t) * (size_t)std::max<int64_t>(n_pairs, 1)))) return r;
+    if (with_cells && (r = ensure(c, c->cells, sizeof(float) * (size_t)(h.n_cells + kCellSlack)))) return r;
+    w.slot_gp = as<int32_t>(c->slot_gp);
+    w.slot_off = as<int64_t>(c->slot_off);
+    w.pairs_unsorted = as<int32_t>(c->pairs_u);
+    w.pairs = as<int32_t>(c->pairs);
+    w.cells = with_cells ? as<float>(c->cells) : nullptr;
+    launch_slots(c->P, w, nullptr, nullptr, st);
+    launch_fill_pairs(c->P, w, st);
+    launch_sort_pairs(w, n_slots, st);
+    if (with_cells) launch_cells(c->P, w, st);
+    HIP_TRY(c, hipGetLastError());
+    return LTS_OK;
+}
+
+static lts_status stage_pairs(lts_context *c, uint64_t event_id, const lts_segments *segs, int32_t *pair_segment,
+                              int32_t *pair_pixel, float *pair_current, int64_t cap_pairs, int64_t *n_pairs_out,
+                              void *stream) {
+    if (!c) return LTS_ERR_INVALID_ARG;
+    if (!n_pairs_out || cap_pairs < 0) return fail(c, LTS_ERR_INVALID_ARG, "n_pairs_out is NULL or cap_pairs < 0");
+    hipStream_t st = to_stream(stream);
+    Work w;
+    DevHeader h;
+    lts_status r;
+    if ((r = stage_front(c, event_id, segs, pair_current != nullptr, st, w, h))) return r;
+    *n_pairs_out = h.n_pairs;
+    if (h.n_pairs > cap_pairs)
+        return fail(c, LTS_ERR_CAPACITY, "cap_pairs " + std::to_string(cap_pairs) + " < " + std::to_string(h.n_pairs));
+    if (pair_segment || pair_pixel) launch_pair_list(c->P, w, h.n_slots, pair_segment, pair_pixel, st);
+    if (pair_current) {
+        Table T{as<float>(c->Rpad), as<double>(c->prefix)};
+        launch_induce_pairs(c->P, w, T, h.n_slots, pair_current, st);
+    }
+    HIP_TRY(c, hipGetLastError());
+    return LTS_OK;
+}
+
+lts_status lts_stage_rasterize(lts_context *c, const lts_segments *segs, int32_t *pair_segment, int32_t *pair_pixel,
+                               int64_t cap_pairs, int64_t *n_pairs_out, void *stream) {
+    if (c && (!pair_segment || !pair_pixel)) return fail(c, LTS_ERR_INVALID_ARG, "NULL pair output");
+    return stage_pairs(c, 0, segs, pair_segment, pair_pixel, nullptr, cap_pairs, n_pairs_out, stream);
+}
+
+lts_status lts_stage_induce(lts_context *c, uint64_t event_id, const lts_segments *segs, int32_t *pair_segment,
+                            int32_t *pair_pixel, float *pair_current, int64_t cap_pairs, int64_t *n_pairs_out,
+                            void *stream) {
+    if (c && !pair_current) return fail(c, LTS_ERR_INVALID_ARG, "NULL pair_current");
+    return stage_pairs(c, event_id, segs, pair_segment, pair_pixel, pair_current, cap_pairs, n_pairs_out, stream);
+}
+
+lts_status lts_stage_reduce(lts_context *c, const int32_t *pair_pixel, const float *pair_current, int64_t n_pairs,
+                            int32_t *pixel_id, float *current, int64_t cap_pixels, int64_t *n_pixels_out,
+                            void *stream) {
+    if (!c) return LTS_ERR_INVALID_ARG;
+    if (!n_pixels_out || n_pairs < 0 || cap_pixels < 0 || (n_pairs > 0 && (!pair_pixel || !pair_current)) ||
+        (cap_pixels > 0 && (!pixel_id || !current)))
+        return fail(c, LTS_ERR_INVALID_ARG, "bad reduce stage arguments");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = to_stream(stream);
+    *n_pixels_out = 0;
+    if (n_pairs == 0) return LTS_OK;
+    lts_status r;
+    if ((r = ensure(c, c->red_head, sizeof(int64_t) * (size_t)(n_pairs + 1)))) return r;
+    if ((r = ensure(c, c->red_start, sizeof(int64_t) * (size_t)(n_pairs + 1)))) return r;
+    if ((r = ensure(c, c->hdr, sizeof(DevHeader)))) return r;
+    if ((r = ensure(c, c->scan_tmp, sizeof(int64_t) * (size_t)scan_tmp_needed(n_pairs + 1)))) return r;
+    int64_t *head = as<int64_t>(c->red_head), *start = as<int64_t>(c->red_start);
+    HIP_TRY(c, hipMemsetAsync(c->hdr.p, 0, sizeof(DevHeader), st));
+    launch_run_heads(pair_pixel, n_pairs, head, as<DevHeader>(c->hdr), st);
+    scan_exclusive_i64(head, n_pairs + 1, nullptr, c->scan_tmp.p, st);
+    launch_run_starts(pair_pixel, n_pairs, head, start, pixel_id, cap_pixels, st);
+    HIP_TRY(c, hipGetLastError());
+    int64_t n_runs = 0;
+    HIP_TRY(c, hipMemcpyAsync(&n_runs, head + n_pairs, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(c->hdr_host, c->hdr.p, sizeof(DevHeader), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (c->hdr_host->status & ST_INVALID)
+        return fail(c, LTS_ERR_INVALID_ARG, "pairs are not grouped by ascending pixel id");
+    *n_pixels_out = n_runs;
+    if (n_runs > cap_pixels)
+        return fail(c, LTS_ERR_CAPACITY, "cap_pixels " + std::to_string(cap_pixels) + " < " + std::to_string(n_runs));
+    launch_reduce_runs(pair_current, start, n_runs, c->P.nticks, current, st);
     HIP_TRY(c, hipGetLastError());
     return LTS_OK;
 }

@@ -79,7 +79,7 @@ EXPORTS = ("lts_server_start", "lts_server_submit", "lts_server_poll", "lts_serv
            "lts_server_stop", "lts_set_timing", "lts_get_timing", "lts_work_stats", "lts_context_create", "lts_context_destroy",
            "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_set_ticks_per_thread", "lts_set_lane_exchange", "lts_set_channel_mask",
            "lts_plan", "lts_simulate", "lts_simulate_batch", "lts_stage_quench_drift", "lts_debug_cells",
-           "lts_stage_electronics", "lts_stage_philox", "lts_status_str", "lts_last_error", "lts_version",
+           "lts_stage_electronics", "lts_stage_philox", "lts_stage_rasterize", "lts_stage_induce", "lts_stage_reduce", "lts_status_str", "lts_last_error", "lts_version",
            "lts_light_create", "lts_light_destroy", "lts_light_simulate", "lts_light_last_error")
 
 
@@ -117,6 +117,10 @@ def lib():
         L.lts_debug_cells.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), P, C.c_int64]
         L.lts_stage_electronics.argtypes = [P, C.c_uint64, P, P, C.c_int64, C.POINTER(lts_outputs), P]
         L.lts_stage_philox.argtypes = [P, C.c_uint32, C.c_uint32, P, C.c_int64, P]
+        L.lts_stage_rasterize.argtypes = [P, C.POINTER(lts_segments), P, P, C.c_int64, C.POINTER(C.c_int64), P]
+        L.lts_stage_induce.argtypes = [P, C.c_uint64, C.POINTER(lts_segments), P, P, P, C.c_int64,
+                                       C.POINTER(C.c_int64), P]
+        L.lts_stage_reduce.argtypes = [P, P, P, C.c_int64, P, P, C.c_int64, C.POINTER(C.c_int64), P]
         L.lts_work_stats.argtypes = [P, C.POINTER(C.c_double)]
         L.lts_server_start.argtypes = [P, C.POINTER(lts_server_cfg), C.POINTER(P)]
         L.lts_server_submit.argtypes = [P, C.c_uint64, C.POINTER(lts_segments), C.POINTER(C.c_uint64)]
@@ -362,6 +366,51 @@ class Context:
         self._check(lib().lts_stage_electronics(self._h, event_id, _ptr(pixel_ids), _ptr(current), n, C.byref(o),
                                                 _stream(stream)))
         return out
+
+    def stage_rasterize(self, segs: DeviceSegments, stream=None):
+        """(segment, pixel) pairs, pixel-major and ascending in segment: int32 tensors (pair_segment, pair_pixel)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        cap = self.plan(segs, stream)["pairs"]
+        seg = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        pix = torch.empty_like(seg)
+        n = C.c_int64(0)
+        s = segs.struct()
+        self._check(lib().lts_stage_rasterize(self._h, C.byref(s), _ptr(seg), _ptr(pix), cap, C.byref(n),
+                                              _stream(stream)))
+        return seg[:n.value], pix[:n.value]
+
+    def stage_induce(self, segs: DeviceSegments, event_id: int = 0, stream=None):
+        """Materialised per-pair currents: (pair_segment, pair_pixel, current [n_pairs, n_ticks] float32)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        cap = self.plan(segs, stream)["pairs"]
+        seg = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        pix = torch.empty_like(seg)
+        cur = torch.empty((max(cap, 1), self.readout.n_ticks), dtype=torch.float32, device=dev)
+        n = C.c_int64(0)
+        s = segs.struct()
+        self._check(lib().lts_stage_induce(self._h, event_id, C.byref(s), _ptr(seg), _ptr(pix), _ptr(cur), cap,
+                                           C.byref(n), _stream(stream)))
+        return seg[:n.value], pix[:n.value], cur[:n.value]
+
+    def stage_reduce(self, pair_pixel, pair_current, stream=None):
+        """Per-pixel sums of pair waveforms grouped by pixel: (pixel_id int32 [k], current float32 [k, n_ticks])."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        n_pairs = int(pair_pixel.numel())
+        assert pair_current.shape == (n_pairs, self.readout.n_ticks) and pair_current.is_contiguous()
+        n = C.c_int64(0)
+        st = lib().lts_stage_reduce(self._h, _ptr(pair_pixel), _ptr(pair_current), n_pairs, None, None, 0,
+                                    C.byref(n), _stream(stream))       # sizing pass: the number of pixels
+        if st != 2:
+            self._check(st)
+        cap = n.value
+        pid = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        cur = torch.empty((max(cap, 1), self.readout.n_ticks), dtype=torch.float32, device=dev)
+        self._check(lib().lts_stage_reduce(self._h, _ptr(pair_pixel), _ptr(pair_current), n_pairs, _ptr(pid),
+                                           _ptr(cur), cap, C.byref(n), _stream(stream)))
+        return pid[:n.value], cur[:n.value]
 
 
 def philox(ctr, k0: int, k1: int, stream=None):

@@ -529,3 +529,87 @@ def test_mc_diffusion_batch_invariant(lt, torch):
     for e, s in enumerate(singles):
         assert np.array_equal(b["pixel_id"][po[e]:po[e + 1]], s["pixel_id"])
         assert np.array_equal(b["current"][po[e]:po[e + 1]], s["current"])
+
+
+# ----------------------------------------------------------------------------------------------- stage hooks
+
+def _stage_workloads():
+    w2 = W.make_workload(2)
+    w2.events[0] = w2.events[0].subset(np.arange(0, 20000, 97))
+    return {"cfg1": W.make_workload(1), "ragged": _ragged_workload(), "cfg2-sub": w2}
+
+
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "cfg2-sub"])
+def test_rasterized_pairs_equal_the_oracle_reach(lt, orc, torch, name):
+    """Pair set (exact): for every segment, the pixels paired with it are the pixels whose table reach meets its
+    truncated charge box in the oracle; pixel-major, ascending segment within a pixel."""
+    w = _stage_workloads()[name]
+    segs = w.events[0]
+    ctx = lt.Context.from_workload(w)
+    sg, px = ctx.stage_rasterize(lt.to_device(segs))
+    sg, px = sg.cpu().numpy(), px.cpu().numpy()
+    key = px.astype(np.int64) * (segs.n + 1) + sg
+    assert np.all(np.diff(key) > 0)
+    for s in range(segs.n):
+        want = orc.active_pixels(w.physics, w.readout, w.table, segs.subset([s]))
+        got = px[sg == s]
+        assert np.array_equal(np.sort(got), want), (name, s)
+    print(f"{name}: {len(sg)} pairs over {segs.n} segments")
+
+
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "cfg2-sub"])
+def test_materialised_pair_currents_vs_oracle(lt, orc, torch, name):
+    """Per-pair currents I_sp (the paper's (segment, pixel, tick) tensor) against the oracle's single-segment
+    waveforms, on a sample of segments; e_p <= 1e-4 per pair."""
+    w = _stage_workloads()[name]
+    segs = w.events[0]
+    table = W.response_table(w.table, w.readout, w.physics.v_drift)
+    ctx = lt.Context.from_workload(w)
+    sg, px, cur = ctx.stage_induce(lt.to_device(segs), event_id=w.event_ids[0])
+    sg, px, cur = sg.cpu().numpy(), px.cpu().numpy(), cur.cpu().numpy().astype(np.float64)
+    worst = 0.0
+    for s in range(0, segs.n, max(1, segs.n // 12)):
+        sel = np.flatnonzero(sg == s)
+        if len(sel) == 0:
+            continue
+        o, _ = orc.waveforms(w.physics, w.readout, table, segs.subset([s]), px[sel])
+        e = per_pixel_errors(cur[sel], o)
+        worst = max(worst, float(e.max()))
+        assert e.max() <= TOL_WAVE, (name, s, e.max())
+    print(f"{name}: {len(sg)} pairs, worst sampled e_p {worst:.2e}")
+
+
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "cfg2-sub"])
+def test_reduce_of_materialised_pairs_equals_fused_path(lt, torch, name):
+    """Materialise-then-sum (the paper's data flow) gives the pixels and currents of the fused sorted path to FP32
+    rounding (both Kahan-sum the same per-pair values in the same order)."""
+    w = _stage_workloads()[name]
+    segs = w.events[0]
+    ctx = lt.Context.from_workload(w)
+    d = lt.to_device(segs)
+    sg, px, cur = ctx.stage_induce(d, event_id=w.event_ids[0])
+    pid, red = ctx.stage_reduce(px, cur)
+    h = ctx.simulate(d, event_id=w.event_ids[0]).host()
+    pid = pid.cpu().numpy()
+    assert np.array_equal(pid, h["pixel_id"])
+    e = per_pixel_errors(red.cpu().numpy().astype(np.float64), h["current"].astype(np.float64))
+    assert e.max() <= 2e-6, (name, e.max())
+
+
+def test_stage_hooks_capacity_and_order_errors(lt, torch):
+    import ctypes as C
+    w = W.make_workload(1)
+    ctx = lt.Context.from_workload(w)
+    d = lt.to_device(w.events[0])
+    s = d.struct()
+    seg = torch.empty(4, dtype=torch.int32, device="cuda")
+    n = C.c_int64(0)
+    st = lt.lib().lts_stage_rasterize(ctx._h, C.byref(s), lt._ptr(seg), lt._ptr(seg), 4, C.byref(n),
+                                      lt._stream(None))
+    assert st == 2 and n.value > 4                                             # LTS_ERR_CAPACITY, need reported
+    pix = torch.tensor([3, 5, 4], dtype=torch.int32, device="cuda")            # not grouped in ascending order
+    cur = torch.zeros((3, w.readout.n_ticks), dtype=torch.float32, device="cuda")
+    with pytest.raises(lt.LtsimError):
+        ctx.stage_reduce(pix, cur)
+    pid, red = ctx.stage_reduce(pix[:0], cur[:0])
+    assert pid.numel() == 0 and red.shape[0] == 0
