@@ -288,6 +288,8 @@ def main():
                     help="also serve N spill events arriving as a Poisson process at RATE_HZ")
     ap.add_argument("--slices", type=int, default=1)
     ap.add_argument("--no-light", action="store_true", help="skip the light-path leg")
+    ap.add_argument("--served-sweep", default="", metavar="RATES",
+                    help="comma-separated arrival rates (events/s) to serve 16 spill events each at, to find saturation")
     ap.add_argument("--materialised", action="store_true",
                     help="also time the paper's data flow: per-pair currents written out, then summed per pixel")
     ap.add_argument("--large-spill", default="", help="comma-separated modes to time on the 2M-segment large spill "
@@ -388,6 +390,8 @@ def main():
         line["large_spill"] = large_spill_leg(ltsim, W, [m for m in args.large_spill.split(",") if m])
     if args.served:
         line["served"] = served(ltsim, W, args.served[0], int(args.served[1]), mode)
+    if args.served_sweep:
+        line["served_sweep"] = [served(ltsim, W, float(r), 16, mode) for r in args.served_sweep.split(",") if r]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -628,9 +628,9 @@ __device__ __forceinline__ void pair_block(const DevParams &P, const float *__re
     }
 }
 
-// pair_block<8> with the loads of the next cell-tick block (its 15-value table window and 8 cell values) issued
+// pair_block<8> with the loads of later cell-tick blocks (each a 15-value table window and 8 cell values) issued
 // before the products of the current one, across column boundaries: the pair's blocks are walked as one sequence
-// (column-major, all columns of a pair have the same number of blocks) with two register buffers in turn.
+// (column-major, all columns of a pair have the same number of blocks) with three register buffers in turn.
 struct BlockCursor {
     int32_t u, v, j;
 };
@@ -667,16 +667,23 @@ __device__ __forceinline__ void pair_block_pf(const DevParams &P, const float *_
 #pragma unroll
             for (int r = 0; r < 8; ++r) acc[r] = fmaf(cv[q], w[r - q + kAC - 1], acc[r]);
     };
-    float wa[8 + kAC - 1], ca[kAC], wb[8 + kAC - 1], cb[kAC];
+    // three register buffers in turn: the loads of block b + 2 are issued before the products of block b, so two
+    // blocks of products cover each load's latency
+    float wa[8 + kAC - 1], ca[kAC], wb[8 + kAC - 1], cb[kAC], wc[8 + kAC - 1], cx[kAC];
     fetch(wa, ca);
-    for (int32_t b = 0; b < total; b += 2) {
-        fetch(wb, cb);
+    fetch(wb, cb);
+    for (int32_t b = 0; b < total; b += 3) {
+        fetch(wc, cx);
         __builtin_amdgcn_sched_barrier(0);
         block(wa, ca);
         if (b + 1 >= total) break;
         fetch(wa, ca);
         __builtin_amdgcn_sched_barrier(0);
         block(wb, cb);
+        if (b + 2 >= total) break;
+        fetch(wb, cb);
+        __builtin_amdgcn_sched_barrier(0);
+        block(wc, cx);
     }
 }
 
