@@ -969,6 +969,197 @@ __global__ __launch_bounds__(kWG) void k_induce_sorted(DevParams P, const SegInf
     }
 }
 
+// ------------------------------------------------------------------------------------------ matrix-core form
+// By eq. (current), a pair's current is I[n] = sum_a sum_col c[col][a] R[col][n - c0 - a] with c0 = a0 - (T_R - 1):
+// a column's cell ticks a against its table column, shifted by a.  Summing over the columns first gives the matrix
+// product Z[a][tau] = sum_col c[col][a] R[col][tau] (cell ticks x table ticks, contracted over the pair's columns),
+// and then I[n] = sum_a Z[a][n - c0 - a], a sum along the anti-diagonals of Z.  The product runs on 32x32x2 FP32
+// MFMA instructions (lane l gives A[l % 32][l / 32] = c[col k0 + l / 32][a] and B[l / 32][l % 32] =
+// R[col k0 + l / 32][tau]): both operands are rows of 32 consecutive floats, and there is no padding beyond
+// rounding the cell ticks to 32 and the columns to 2.  Each 32 x 64 block of Z goes through LDS for the
+// anti-diagonal sums, which each lane adds to its wavefront's output ticks in a fixed order.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+constexpr int32_t kBufferWord3 = 0x00020000;    // raw 32-bit buffer descriptor word 3 (gfx9 family)
+constexpr int32_t kZT = 64;                     // table ticks per block of Z
+constexpr int32_t kZA = 32;                     // cell ticks per block of Z
+constexpr int32_t kZS = kZT + 1;                // LDS row stride of a Z block
+constexpr int32_t kZOut = 512;                  // output ticks per wavefront and pass
+constexpr int32_t kZLds = kZA * kZS + kZOut;    // floats of LDS per wavefront
+
+// One pair's contribution to ticks n_w .. n_w + 511, added to Ow (this wavefront's 512 output sums in LDS).
+__device__ __forceinline__ void pair_zgemm(const DevParams &P, const float *__restrict__ cc0, int32_t nu, int32_t nv,
+                                           int32_t nap, int32_t na, int32_t u0, int32_t v0, int32_t a0,
+                                           __amdgpu_buffer_rsrc_t rt, int32_t ulo, int32_t uhi, int32_t vlo,
+                                           int32_t vhi, int32_t uc, int32_t vc, int32_t n_w, float *Zb, float *Ow) {
+    const int l = lane_id();
+    const int32_t c0 = a0 - (P.t_r - 1);
+    const int32_t nvv = vhi - vlo + 1, ncol = (uhi - ulo + 1) * nvv;
+    // the descriptors must be wavefront-uniform (scalar registers)
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)uniform_ptr(cc0), (short)0, __builtin_amdgcn_readfirstlane(nu * nv * nap * 4), kBufferWord3);
+    for (int32_t ab = 0; ab < na; ab += kZA) {
+        // table ticks that reach this wavefront's outputs from cell ticks ab .. ab + 31
+        const int32_t t_first = max(n_w - c0 - ab - (kZA - 1), 0);
+        const int32_t t_last = min(n_w + kZOut - 1 - c0 - ab, P.t_r - 1);
+        for (int32_t t0 = t_first; t0 <= t_last; t0 += kZT) {
+            floatx16 D[2];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) D[nt][r] = 0.0f;
+            // 32x32x2: lane l gives A[l % 32][l / 32] (cell tick ab + l % 32 of column k0 + l / 32) and
+            // B[l / 32][l % 32] (table tick t0 + 32 nt + l % 32 of that column)
+            const int32_t i32 = l & 31, h = l >> 5;
+            // this lane's columns: k = h, h + 2, ... in row-major (u, v) order; a step of 2 moves du rows and dv
+            // columns, plus at most one wrap; colc (the column's cell offset) follows incrementally
+            int32_t k = h, uu = ulo + h / nvv, vv = vlo + h % nvv;
+            const int32_t du = 2 / nvv, dv = 2 - du * nvv;
+            int32_t colc = ((uu - u0) * nv + (vv - v0)) * nap;
+            const int32_t step_c = (du * nv + dv) * nap, wrap_c = (nv - nvv) * nap;
+            auto fetch = [&](float &A, float (&B)[2]) {
+                const bool valid = k < ncol;
+                const int32_t fu = uu - uc, fv = vv - vc;
+                const int32_t bin = __mul24(fu ^ (fu >> 31), P.by) + (fv ^ (fv >> 31));   // fold(), 24-bit products
+                const int32_t colr = __mul24(bin, P.col_len) + kPad + t0 + i32;
+                const int32_t a = ab + i32;
+                const bool in = valid && a < na;
+                const float cv = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(rc, 4 * (in ? colc + a : 0), 0, 0));
+                A = in ? cv : 0.0f;
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    B[nt] = __builtin_bit_cast(
+                        float, __builtin_amdgcn_raw_buffer_load_b32(rt, 4 * (valid ? colr + 32 * nt : 0), 0, 0));
+                k += 2;
+                vv += dv;
+                uu += du;
+                colc += step_c;
+                const bool wrap = vv > vhi;
+                vv = wrap ? vv - nvv : vv;
+                uu = wrap ? uu + 1 : uu;
+                colc = wrap ? colc + wrap_c : colc;
+            };
+            auto step = [&](float A, const float (&B)[2]) {
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) D[nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(A, B[nt], D[nt], 0, 0, 0);
+            };
+            const int32_t ks2 = (ncol + 1) >> 1;
+            float A0, B0[2], A1, B1[2], A2, B2[2];
+            fetch(A0, B0);
+            fetch(A1, B1);
+            for (int32_t st = 0; st < ks2; st += 3) {
+                fetch(A2, B2);
+                __builtin_amdgcn_sched_barrier(0);
+                step(A0, B0);
+                __builtin_amdgcn_sched_barrier(0);
+                fetch(A0, B0);
+                __builtin_amdgcn_sched_barrier(0);
+                step(A1, B1);
+                __builtin_amdgcn_sched_barrier(0);
+                fetch(A1, B1);
+                __builtin_amdgcn_sched_barrier(0);
+                step(A2, B2);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // Z block to LDS: 32x32 layout, lane l register r holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) Zb[(8 * (r >> 2) + 4 * h + (r & 3)) * kZS + 32 * nt + i32] = D[nt][r];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // anti-diagonal d = t + a' holds the block's part of tick n = t0 + c0 + ab + d
+            for (int32_t d = l; d < kZT + kZA - 1; d += 64) {
+                const int32_t o = t0 + c0 + ab + d - n_w;
+                if (o < 0 || o >= kZOut) continue;
+                float sum = 0.0f;
+                const int32_t alo = max(0, d - (kZT - 1)), ahi = min(kZA - 1, d);
+                for (int32_t ap = alo; ap <= ahi; ++ap) sum += Zb[ap * kZS + (d - ap)];
+                Ow[o] += sum;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+}
+
+// Per-pair induction of the sorted variant on the matrix cores: the same pixel-slot work queue, pair order and
+// Kahan accumulation in LDS as k_induce_sorted; wavefront w of the workgroup owns ticks nb0 + 512 w .. + 511 of
+// each 2048-tick pass over a pair's window, lane l of it ticks + 8 l .. + 7.
+__global__ __launch_bounds__(kWG) void k_induce_mfma(DevParams P, const SegInfo *__restrict__ si,
+                                                     const float *__restrict__ cells, const float *__restrict__ Rpad,
+                                                     const double *__restrict__ prefix,
+                                                     const int64_t *__restrict__ slot_off,
+                                                     const int32_t *__restrict__ pairs,
+                                                     const int32_t *__restrict__ slot_gp, float *__restrict__ wave,
+                                                     DevHeader *H, double *report) {
+    extern __shared__ float sm[];
+    __shared__ int32_t s_slot;
+    __shared__ double red[kWG / 64];
+    const int NT = P.nticks;
+    float *s_sum = sm, *s_cmp = sm + NT;
+    const int tid = threadIdx.x;
+    const int32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;   // wavefront index (uniform)
+    float *Zb = sm + 2 * NT + wv * kZLds, *Ow = Zb + kZA * kZS;
+    const int64_t n_slots = H->n_slots;
+    const __amdgpu_buffer_rsrc_t rt =
+        __builtin_amdgcn_make_buffer_rsrc((void *)Rpad, (short)0, P.bx * P.by * P.col_len * 4, kBufferWord3);
+    for (int o = l; o < kZOut; o += 64) Ow[o] = 0.0f;
+    for (;;) {
+        if (tid == 0) s_slot = (int32_t)atomicAdd(&H->work[0], 1u);
+        __syncthreads();
+        const int64_t slot = s_slot;
+        if (slot >= n_slots) break;
+        for (int n = tid; n < NT; n += kWG) { s_sum[n] = 0.0f; s_cmp[n] = 0.0f; }
+        const int32_t gp = slot_gp[slot];
+        const int32_t e = gp / P.npx, p = gp - e * P.npx;
+        const int32_t ix = p % P.nx, iy = p / P.nx;
+        const int32_t uc = ix * P.nsub + P.nsub / 2, vc = iy * P.nsub + P.nsub / 2;
+        const int64_t pb = slot_off[slot], pe = slot_off[slot + 1];
+        double clip = 0.0;
+        __syncthreads();
+        for (int64_t qq = pb; qq < pe; ++qq) {
+            const int32_t s = __builtin_amdgcn_readfirstlane(pairs[qq]);
+            const SegInfo &g = si[s];
+            const int32_t u0 = g.u0, v0 = g.v0, a0 = g.a0, nv = g.nv, nap = g.na_pad, na = g.na;
+            const int32_t ulo = max(u0, uc - P.bx), uhi = min(u0 + g.nu - 1, uc + P.bx - 1);
+            const int32_t vlo = max(v0, vc - P.by), vhi = min(v0 + nv - 1, vc + P.by - 1);
+            if (ulo > uhi || vlo > vhi) continue;
+            const float *cc0 = cells + g.cell_off;
+            const int32_t wlo = a0 - (P.t_r - 1), whi = a0 + na - 1;
+            if (wlo < 0 || whi >= NT)
+                clip += pair_clipped(P, cc0, nv, nap, na, u0, v0, a0, prefix, ulo, uhi, vlo, vhi, uc, vc);
+            const int32_t lo = max(wlo, 0), hi = min(whi, NT - 1);
+            for (int32_t nb0 = lo; nb0 <= hi; nb0 += 4 * kZOut) {
+                const int32_t n_w = nb0 + kZOut * wv;
+                if (n_w <= hi) {
+                    pair_zgemm(P, cc0, g.nu, nv, nap, na, u0, v0, a0, rt, ulo, uhi, vlo, vhi, uc, vc, n_w, Zb, Ow);
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) {
+                        const int32_t o = 8 * l + r, n = n_w + o;
+                        const float x = Ow[o];
+                        Ow[o] = 0.0f;
+                        if (n <= hi) {                                   // Kahan: s_cmp holds the lost low part
+                            const float y = x - s_cmp[n];
+                            const float z = s_sum[n] + y;
+                            s_cmp[n] = (z - s_sum[n]) - y;
+                            s_sum[n] = z;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        float *wrow = wave + slot * NT;
+        for (int n = tid; n < NT; n += kWG) wrow[n] = s_sum[n] - s_cmp[n];
+        const double c = block_sum_double(clip, red);
+        if (tid == 0 && c != 0.0) atomicAdd(&report[(int64_t)e * 5 + 3], c);
+        __syncthreads();
+    }
+}
+
 // Atomic variant: one workgroup per segment (dynamic work queue); its pairs in pixel order; FP32 atomics.
 template <int RT>
 __global__ __launch_bounds__(kWG) void k_induce_atomic(DevParams P, const SegInfo *__restrict__ si, int64_t n_seg,
@@ -1164,6 +1355,15 @@ static void induce_rt(const DevParams &P, const Work &w, const Table &T, float *
         k_induce_atomic<RT><<<(unsigned)g, kWG, 0, st>>>(P, w.si, w.n_seg, w.cells, T.Rpad, T.prefix, w.pix_slot, wave,
                                                         w.hdr, w.report);
     }
+}
+
+void launch_induce_mfma(const DevParams &P, const Work &w, const Table &T, float *wave, int64_t n_slots,
+                        hipStream_t st) {
+    const int64_t cap = 2048;
+    const int64_t g = n_slots < 1 ? 1 : (n_slots > cap ? cap : n_slots);
+    const size_t lds = ((size_t)2 * P.nticks + (size_t)(kWG / 64) * kZLds) * sizeof(float);
+    k_induce_mfma<<<(unsigned)g, kWG, lds, st>>>(P, w.si, w.cells, T.Rpad, T.prefix, w.slot_off, w.pairs, w.slot_gp,
+                                                  wave, w.hdr, w.report);
 }
 
 void launch_induce(const DevParams &P, const Work &w, const Table &T, float *wave, int mode, int64_t n_slots, int32_t rt,

@@ -82,6 +82,8 @@ void launch_sort_pairs(const Work &w, int64_t n_slots_host, hipStream_t st);
 void launch_cells(const DevParams &P, const Work &w, hipStream_t st);
 void launch_induce(const DevParams &P, const Work &w, const Table &T, float *wave, int mode, int64_t n_slots_host,
                    int32_t rt, bool shift, hipStream_t st);
+void launch_induce_mfma(const DevParams &P, const Work &w, const Table &T, float *wave, int64_t n_slots,
+                        hipStream_t st);
 void launch_induce_slices(const DevParams &P, const Work &w, const Table &T, float *wave, int64_t n_slots, int32_t NS,
                           float *part, int64_t chunk, int32_t rt, hipStream_t st);
 void launch_pair_list(const DevParams &P, const Work &w, int64_t n_slots, int32_t *pair_seg, int32_t *pair_pix,

@@ -40,6 +40,7 @@ struct lts_context {
     int32_t induce_slices = 1;       // sorted variant: table slices (one per XCD); 1 = unsliced kernel
     int32_t ticks_per_thread = 0;    // induction tick tile per thread (0 = chosen from the table length)
     int32_t lane_exchange = 0;       // 8-tick tiles share table windows across lanes (1) or load their own (0)
+    int32_t matrix_cores = 0;        // sorted per-pair induction on the FP32 matrix cores (1) or the vector ALUs (0)
     DevBuf part;                     // per-slice partial waveforms of the sliced sorted variant
     DevBuf mask;                     // disabled-channel mask (npx bytes) when set
     bool has_mask = false;
@@ -450,6 +451,9 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
         StageTimer t(c, st, LTS_STAGE_INDUCE);
         launch_induce_slices(P, w, T, out->current, n_slots, c->induce_slices, as<float>(c->part), chunk,
                              c->ticks_per_thread, st);
+    } else if (c->reduce_mode == LTS_REDUCE_SORTED && c->matrix_cores) {
+        StageTimer t(c, st, LTS_STAGE_INDUCE);
+        launch_induce_mfma(P, w, T, out->current, n_slots, st);
     } else {
         StageTimer t(c, st, LTS_STAGE_INDUCE);
         launch_induce(P, w, T, out->current, c->reduce_mode, n_slots, c->ticks_per_thread, c->lane_exchange != 0, st);
@@ -585,6 +589,13 @@ lts_status lts_set_lane_exchange(lts_context *c, int32_t on) {
     if (!c) return LTS_ERR_INVALID_ARG;
     if (on != 0 && on != 1) return fail(c, LTS_ERR_INVALID_ARG, "lane exchange must be 0 or 1");
     c->lane_exchange = on;
+    return LTS_OK;
+}
+
+lts_status lts_set_matrix_cores(lts_context *c, int32_t on) {
+    if (!c) return LTS_ERR_INVALID_ARG;
+    if (on != 0 && on != 1) return fail(c, LTS_ERR_INVALID_ARG, "matrix cores must be 0 or 1");
+    c->matrix_cores = on;
     return LTS_OK;
 }
 
@@ -1156,6 +1167,7 @@ lts_status lts_server_start(lts_context *ctx, const lts_server_cfg *cfg, lts_ser
         if (r == LTS_OK) r = lts_set_induce_slices(L->ctx, ctx->induce_slices);
         if (r == LTS_OK) r = lts_set_ticks_per_thread(L->ctx, ctx->ticks_per_thread);
         if (r == LTS_OK) r = lts_set_lane_exchange(L->ctx, ctx->lane_exchange);
+        if (r == LTS_OK) r = lts_set_matrix_cores(L->ctx, ctx->matrix_cores);
         if (r == LTS_OK && hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess) r = LTS_ERR_DEVICE;
         if (r != LTS_OK) {
             if (L->ctx) lts_context_destroy(L->ctx);

@@ -77,7 +77,7 @@ STAGES = ("quench_drift", "rasterize", "cells", "induce", "electronics")
 
 EXPORTS = ("lts_server_start", "lts_server_submit", "lts_server_poll", "lts_server_wait", "lts_server_release",
            "lts_server_stop", "lts_set_timing", "lts_get_timing", "lts_work_stats", "lts_context_create", "lts_context_destroy",
-           "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_set_ticks_per_thread", "lts_set_lane_exchange", "lts_set_channel_mask",
+           "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_set_ticks_per_thread", "lts_set_lane_exchange", "lts_set_matrix_cores", "lts_set_channel_mask",
            "lts_plan", "lts_simulate", "lts_simulate_batch", "lts_stage_quench_drift", "lts_debug_cells",
            "lts_stage_electronics", "lts_stage_philox", "lts_stage_rasterize", "lts_stage_induce", "lts_stage_reduce", "lts_status_str", "lts_last_error", "lts_version",
            "lts_light_create", "lts_light_destroy", "lts_light_simulate", "lts_light_last_error")
@@ -109,6 +109,7 @@ def lib():
         L.lts_set_induce_slices.argtypes = [P, C.c_int32]
         L.lts_set_ticks_per_thread.argtypes = [P, C.c_int32]
         L.lts_set_lane_exchange.argtypes = [P, C.c_int32]
+        L.lts_set_matrix_cores.argtypes = [P, C.c_int32]
         L.lts_set_channel_mask.argtypes = [P, P, C.c_int64]
         L.lts_plan.argtypes = [P, C.POINTER(lts_segments), C.POINTER(C.c_int64), P]
         L.lts_simulate.argtypes = [P, C.c_uint64, C.POINTER(lts_segments), C.POINTER(lts_outputs), P]
@@ -269,6 +270,9 @@ class Context:
 
     def set_lane_exchange(self, on: bool):
         self._check(lib().lts_set_lane_exchange(self._h, int(bool(on))))
+
+    def set_matrix_cores(self, on: bool):
+        self._check(lib().lts_set_matrix_cores(self._h, int(bool(on))))
 
     def set_reduce_mode(self, mode: int):
         self._check(lib().lts_set_reduce_mode(self._h, mode))

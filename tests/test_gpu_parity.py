@@ -43,11 +43,12 @@ def per_pixel_errors(g, o):
     return num / den
 
 
-def run_gpu(lt, w, ev=0, mode=0, table=None, slices=1, rt=0, shift=False):
+def run_gpu(lt, w, ev=0, mode=0, table=None, slices=1, rt=0, shift=False, matrix=False):
     ctx = lt.Context.from_workload(w, table=table, reduce_mode=mode)
     ctx.set_induce_slices(slices)
     ctx.set_ticks_per_thread(rt)
     ctx.set_lane_exchange(shift)
+    ctx.set_matrix_cores(matrix)
     segs = lt.to_device(w.events[ev])
     r = ctx.simulate(segs, event_id=w.event_ids[ev])
     h = r.host()
@@ -104,8 +105,8 @@ def compare_packets(h, pixels, orc_pk, ufrom, uncertain_pixels=()):
     return compared, flagged, bad
 
 
-def check_event(lt, orc, w, ev=0, mode=0, table=None, slices=1, rt=0, shift=False):
-    ctx, h = run_gpu(lt, w, ev, mode, table, slices, rt, shift)
+def check_event(lt, orc, w, ev=0, mode=0, table=None, slices=1, rt=0, shift=False, matrix=False):
+    ctx, h = run_gpu(lt, w, ev, mode, table, slices, rt, shift, matrix)
     segs = w.events[ev]
     r = orc.simulate(w, ev, table=table, eps_rel=EPS_REL, eps_abs=EPS_ABS)
     opix = r["pixels"]
@@ -262,12 +263,12 @@ def test_max_window_long_table_parity(lt, orc, torch, mode, rt, shift):
     assert r["report"]["q_clipped"] != 0.0 and cmp_ > 0
 
 
-@pytest.mark.parametrize("mode", [0, 2])
-def test_cfg2_full_size_sampled_pixels(lt, orc, torch, mode):
+@pytest.mark.parametrize("mode,matrix", [(0, False), (2, False), (0, True)])
+def test_cfg2_full_size_sampled_pixels(lt, orc, torch, mode, matrix):
     """The module-scale event at full size, in the launch configurations the benchmark times; the oracle
     recomputes a sample of pixels one by one."""
     w = W.make_workload(2)
-    ctx, h = run_gpu(lt, w, mode=mode)
+    ctx, h = run_gpu(lt, w, mode=mode, matrix=matrix)
     gpix, cur = h["pixel_id"], h["current"]
     tot = np.abs(cur).sum(axis=1)
     rng = np.random.default_rng(11)
@@ -613,3 +614,28 @@ def test_stage_hooks_capacity_and_order_errors(lt, torch):
         ctx.stage_reduce(pix, cur)
     pid, red = ctx.stage_reduce(pix[:0], cur[:0])
     assert pid.numel() == 0 and red.shape[0] == 0
+
+
+# ----------------------------------------------------------------------------------------------- matrix cores
+
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "max-window"])
+def test_matrix_core_induction_parity(lt, orc, torch, name):
+    """The Toeplitz form of the per-pair induction on the FP32 matrix cores meets the same bar against the oracle
+    (cfg1 in full, the ragged multi-tile event, the longest window with ~200-tick charge boxes)."""
+    w = {"cfg1": W.make_workload, "ragged": _ragged_workload, "max-window": _max_window_workload}[name]
+    w = w(1) if name == "cfg1" else w()
+    h, r, e, (cmp_, flg) = check_event(lt, orc, w, matrix=True)
+    print(f"matrix cores {name}: pixels {len(r['pixels'])} max e_p {e.max():.2e} packets compared {cmp_} flagged {flg}")
+
+
+def test_matrix_core_module_event_agrees_with_vector_path(lt, torch):
+    """Full module-scale event: matrix-core and vector-ALU per-pair paths give the same pixels, and currents within
+    the parity bar of each other (the two sum the products in different orders; bipolar currents on non-collecting
+    pixels make the relative difference of FP32 sums reach ~1e-5)."""
+    w = W.make_workload(2)
+    _, a = run_gpu(lt, w)
+    _, b = run_gpu(lt, w, matrix=True)
+    assert np.array_equal(a["pixel_id"], b["pixel_id"])
+    e = per_pixel_errors(b["current"].astype(np.float64), a["current"].astype(np.float64))
+    print(f"module event: matrix vs vector max e_p {e.max():.2e}, p99 {np.percentile(e, 99):.2e}")
+    assert e.max() <= TOL_WAVE
