@@ -1070,13 +1070,19 @@ __device__ __forceinline__ void pair_zgemm(const DevParams &P, const float *__re
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             // anti-diagonal d = t + a' holds the block's part of tick n = t0 + c0 + ab + d
-            for (int32_t d = l; d < kZT + kZA - 1; d += 64) {
+            // (a fixed trip count with clamped indices, so all 32 LDS reads of a diagonal are issued together)
+#pragma unroll
+            for (int32_t half = 0; half < 2; ++half) {
+                const int32_t d = l + 64 * half;
                 const int32_t o = t0 + c0 + ab + d - n_w;
-                if (o < 0 || o >= kZOut) continue;
                 float sum = 0.0f;
-                const int32_t alo = max(0, d - (kZT - 1)), ahi = min(kZA - 1, d);
-                for (int32_t ap = alo; ap <= ahi; ++ap) sum += Zb[ap * kZS + (d - ap)];
-                Ow[o] += sum;
+#pragma unroll
+                for (int32_t ap = 0; ap < kZA; ++ap) {
+                    const int32_t t = d - ap;
+                    const float z = Zb[ap * kZS + min(max(t, 0), kZT - 1)];
+                    sum += (t >= 0 && t < kZT) ? z : 0.0f;
+                }
+                if (d < kZT + kZA - 1 && o >= 0 && o < kZOut) Ow[o] += sum;
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
