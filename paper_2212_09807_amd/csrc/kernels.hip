@@ -1619,21 +1619,33 @@ __global__ void k_sum_pieces(DevParams P, const SegInfo *si, const float *cells,
     const int64_t sb = sw.col_seg_off[c], se = sw.col_seg_off[c + 1];
     float *S = sw.S + sw.s_off[c];
     const int32_t Lpad = (int32_t)(sw.s_off[c + 1] - sw.s_off[c]);
-    for (int32_t a = 0; a < Lpad; ++a) {
-        float sum = 0.0f, cmp = 0.0f;
-        if (a < L) {
-            const int32_t aa = lo + a;
-            for (int64_t q = sb; q < se; ++q) {
-                const SegInfo &g = si[sw.col_seg[q]];
-                if (aa < g.a0 || aa >= g.a0 + g.na) continue;
-                const float x = cells[g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad + (aa - g.a0)];
-                const float y = x - cmp;
-                const float t = sum + y;
-                cmp = (t - sum) - y;
-                sum = t;
+    // 32-tick chunks with their sums in registers; per chunk, every segment of the column that overlaps it adds
+    // its cells, segments in ascending id (the same order per tick as a tick-by-tick scan)
+    constexpr int32_t kCh = 32;
+    for (int32_t a0c = 0; a0c < Lpad; a0c += kCh) {
+        float sum[kCh], cmp[kCh];
+#pragma unroll
+        for (int j = 0; j < kCh; ++j) { sum[j] = 0.0f; cmp[j] = 0.0f; }
+        const int32_t cl = lo + a0c, ch = min(cl + kCh, lo + L) - 1;
+        for (int64_t q = sb; q < se; ++q) {
+            const SegInfo &g = si[sw.col_seg[q]];
+            const int32_t ga = max(g.a0, cl), gb = min(g.a0 + g.na - 1, ch);
+            if (ga > gb) continue;
+            const float *src = cells + g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad - g.a0;
+#pragma unroll
+            for (int j = 0; j < kCh; ++j) {
+                const int32_t aa = cl + j;
+                if (aa >= ga && aa <= gb) {
+                    const float y = src[aa] - cmp[j];
+                    const float t = sum[j] + y;
+                    cmp[j] = (t - sum[j]) - y;
+                    sum[j] = t;
+                }
             }
         }
-        S[a] = sum - cmp;
+#pragma unroll
+        for (int j = 0; j < kCh; ++j)
+            if (a0c + j < Lpad) S[a0c + j] = sum[j] - cmp[j];
     }
     for (int64_t k = 0; k < np; ++k) {
         SegInfo g = {};
