@@ -1704,6 +1704,8 @@ void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw,
 // running sums with Kahan compensation (pieces in list order: deterministic and batch-invariant).  Wavefronts take
 // units from a counter and never synchronise with each other; the first tile of a pixel also accounts the charge
 // that its pieces induce outside the window.
+constexpr int32_t kSumKahanEvery = 4;   // pieces summed in FP32 registers between compensated additions
+
 template <bool SHIFT>
 __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInfo *__restrict__ piece,
                                                        const float *__restrict__ S, const float *__restrict__ Rpad,
@@ -1743,13 +1745,8 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
         };
         int64_t q = pb;
         while (q < pe && !meets(q)) ++q;
-        if constexpr (!SHIFT) {                         // aligned ping-pong per piece, Kahan after each piece
-            for (; q < pe; ++q) {
-                if (!meets(q)) continue;
-                const float *col, *cc;
-                int32_t nblk;
-                colof(q, col, cc, nblk);
-                column_pingpong<true>(col, uniform_cptr(cc), nblk, acc);
+        if constexpr (!SHIFT) {                         // aligned ping-pong per piece, Kahan after every 4 pieces
+            auto kahan = [&] {
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
                     const float y = acc[r] - cmp[r];
@@ -1758,7 +1755,20 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
                     sum[r] = t;
                     acc[r] = 0.0f;
                 }
+            };
+            int32_t pending = 0;
+            for (; q < pe; ++q) {
+                if (!meets(q)) continue;
+                const float *col, *cc;
+                int32_t nblk;
+                colof(q, col, cc, nblk);
+                column_pingpong<true>(col, uniform_cptr(cc), nblk, acc);
+                if (++pending == kSumKahanEvery) {
+                    kahan();
+                    pending = 0;
+                }
             }
+            if (pending) kahan();
         } else if (q < pe) {
             const float *col, *cc;
             int32_t nblk;
