@@ -187,11 +187,12 @@ lts_status lts_set_ticks_per_thread(lts_context *ctx, int32_t rt);
  * Both give the same sums in the same order.  A tuning option (Sec. 3.3.2 sets no kernel design). */
 lts_status lts_set_lane_exchange(lts_context *ctx, int32_t on);
 
-/* Sorted per-pair induction (Sec. 3.3.2, eq. (current)) on the FP32 matrix cores: 1 = each column's products as a
- * Toeplitz-by-table matrix product on 16x16x4 MFMA instructions (cell-tick Toeplitz blocks padded to na + 15
- * lags); 0 (default) = the vector-ALU loop.  Same pair order and Kahan accumulation; the products are summed in a
- * different order, so results agree to FP32 rounding, not bit for bit.  Used only when the reduce mode is
- * LTS_REDUCE_SORTED and induce slices are 1; ignored otherwise. */
+/* Sorted per-pair induction (Sec. 3.3.2, eq. (current)) on the FP32 matrix cores: 1 = per pair, the product of
+ * its cell-tick x column charges with its columns' table rows on 32x32x2 MFMA instructions, then sums along the
+ * product's anti-diagonals (one per output tick); 0 (default, faster on gfx950) = the vector-ALU loop.  Same pair
+ * order and Kahan accumulation; the products are summed in a different order, so results agree to FP32 rounding,
+ * not bit for bit.  Used only when the reduce mode is LTS_REDUCE_SORTED and induce slices are 1; ignored
+ * otherwise. */
 lts_status lts_set_matrix_cores(lts_context *ctx, int32_t on);
 
 /* Sizing pass (synchronous on `stream`): need[4] = (segment-pixel pairs, active pixels, charge cells,
