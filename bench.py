@@ -79,12 +79,13 @@ def cpu_baseline(w, budget_s=15.0):
                       f"3000 ticks, induction + electronics, FP64, {dt:.1f} s"}
 
 
-def batched_vs_plain(ltsim, W, n_events, mode):
-    """The first n_events of the batched-spill workload: one lts_simulate_batch call vs one lts_simulate per event,
-    same results; events/s of each (one untimed pass of each first)."""
+def batched_vs_plain(ltsim, W, n_events, mode, cfg=3):
+    """The first n_events of the batched-spill workload (cfg 3), or n_events single-track events (cfg 1): one
+    lts_simulate_batch call vs one lts_simulate per event, same results; events/s of each (one untimed pass of each
+    first)."""
     import numpy as np
     import torch
-    w = W.make_workload(3, n_events=n_events)
+    w = W.make_workload(cfg, n_events=n_events)
     ctx = ltsim.Context.from_workload(w, reduce_mode=mode)
     allsegs = W.Segments.concat(w.events)
     offs = np.r_[0, np.cumsum([e.n for e in w.events])]
@@ -106,7 +107,8 @@ def batched_vs_plain(ltsim, W, n_events, mode):
         torch.cuda.synchronize()
         tp = time.perf_counter() - t0
         print(f"[bench] batched pass {rep}: batch {tb:.3f} s, plain {tp:.3f} s", file=sys.stderr, flush=True)
-    res = {"events": n_events, "segments": int(allsegs.n), "batched_events_per_s": n_events / tb,
+    res = {"workload": "batched spill (log-normal event sizes)" if cfg == 3 else "single-track events, 200 segments",
+           "events": n_events, "segments": int(allsegs.n), "batched_events_per_s": n_events / tb,
            "plain_events_per_s": n_events / tp, "batched_segments_per_s": allsegs.n / tb,
            "plain_segments_per_s": allsegs.n / tp, "gain": tp / tb}
     return res
@@ -123,15 +125,23 @@ def light_leg(ltsim, W, reps=10):
     lp, ipe, r, amp = W.light_workload()
     sim = ltsim.LightSim(lp, r, amp)
     x = torch.from_numpy(ipe).cuda()
-    sim.simulate(x, 1)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for i in range(reps):
-        sim.simulate(x, 1 + i)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / reps
+
+    def timed(s):
+        out = s.simulate(x, 1)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for i in range(reps):
+            s.simulate(x, 1 + i, out=out)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms = timed(sim)
+    gsim = ltsim.LightSim(lp, r, amp)
+    gsim.set_graph(True)
+    ms_graph = timed(gsim)
+    gsim.close()
     K = int(lp.trunc * lp.tau_s / lp.tick) + 1
     T = lp.n_ticks
     fma = lp.n_det * (min(K, T) * (min(K, T) + 1) // 2 + max(T - K, 0) * K)
@@ -139,7 +149,7 @@ def light_leg(ltsim, W, reps=10):
     ach = 2.0 * fma / (ms / 1e3) / 1e12
     return {"workload": f"light spill: {lp.n_det} detectors x {T} ticks of {lp.tick} ns, {K}-tap scintillation kernel, "
                         f"{len(r)}-tap response, {len(amp)} noise sinusoids, 4 interactions",
-            "ms_per_event": ms, "detector_ticks_per_s": lp.n_det * T / (ms / 1e3),
+            "ms_per_event": ms, "ms_per_event_graph": ms_graph, "detector_ticks_per_s": lp.n_det * T / (ms / 1e3),
             "roofline": {"kernel": "k_light_scint (whole light call timed)", "bound": "alu", "achieved": ach,
                          "peak": PEAK_FP64_FMA_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_FMA_TFLOPS,
                          "flops_per_launch": 2.0 * fma, "dtype": "f64"}}
@@ -386,6 +396,7 @@ def main():
         line.setdefault("modes", {})[other] = time_mode(ltsim, w, segs, other, args.steps)
     if args.batched:
         line["batched"] = batched_vs_plain(ltsim, W, args.batched, mode)
+        line["batched_small"] = batched_vs_plain(ltsim, W, 64, mode, cfg=1)
     if not args.no_light:
         line["light"] = light_leg(ltsim, W)
     if args.materialised:

@@ -371,6 +371,12 @@ void lts_light_destroy(lts_light *L);
  * The event id keys the draws, so results do not depend on call order. */
 lts_status lts_light_simulate(lts_light *L, uint64_t event_id, const float *ipe, double *mu, double *pe, float *V,
                               int32_t *trig, int32_t *trig_count, void *stream);
+
+/* Replay lts_light_simulate through a HIP graph (1) or launch its kernels one by one (0, default).  The graph is
+ * captured on the first call and again whenever the caller's buffers change; later calls only set the event id in
+ * the graph's two random-number kernels and launch it on `stream`.  Results are the same either way.  No memory
+ * is allocated or set by the captured sequence. */
+lts_status lts_light_set_graph(lts_light *L, int32_t on);
 const char *lts_light_last_error(const lts_light *L);
 
 const char *lts_status_str(lts_status s);

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -257,6 +258,14 @@ struct lts_light {
     DBuf<float2> coef;
     DBuf<float> nz;                                  // noise by FFT (when fft_log2 > 0)
     int32_t fft_log2 = 0;
+    // replay through a HIP graph: captured once per set of caller buffers, the event id set per call in the two
+    // kernel nodes that draw random numbers
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t fluct_node = nullptr, coef_node = nullptr;
+    const void *g_ptrs[6] = {};
 };
 
 namespace {
@@ -273,6 +282,105 @@ lts_status lfail(lts_light *L, lts_status s, const std::string &m) {
         if (e_ != hipSuccess) return lfail(L, e_ == hipErrorOutOfMemory ? LTS_ERR_OOM : LTS_ERR_DEVICE,       \
                                           std::string(#call) + ": " + hipGetErrorString(e_));                 \
     } while (0)
+}  // namespace
+
+namespace {
+
+// The kernel sequence of one light event on stream st (shapes fixed by the simulator's parameters).
+void launch_light(lts_light *L, uint64_t event_id, const float *ipe, double *mu_d, double *pe_d, float *V,
+                  int32_t *trig, int32_t *trig_count, hipStream_t st) {
+    const lts_light_params &q = L->p;
+    const int32_t T = q.n_ticks, nd = q.n_det;
+    const int64_t n = (int64_t)nd * T;
+    const unsigned g1 = (unsigned)((n + 255) / 256);
+    k_light_pad<<<g1, 256, 0, st>>>(ipe, L->xp.p, L->Kp, T, nd);
+    const dim3 gt((unsigned)((T + kLTile - 1) / kLTile), (unsigned)nd);
+    k_light_scint<<<gt, kLWG, 0, st>>>(L->xp.p, L->Kp, T, L->w.p, L->nkb, mu_d);
+    k_light_fluct<<<g1, 256, 0, st>>>(mu_d, pe_d, L->pef.p, L->Rp, T, nd, event_id, L->k0, L->k1, q.normal_above);
+    if (L->F > 0) {
+        const int64_t nc = (int64_t)nd * L->F;
+        k_light_noise_coef<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(L->amp.p, L->F, nd, event_id, L->k0, L->k1,
+                                                                        L->coef.p);
+    }
+    const float *nzpre = nullptr;
+    if (L->F > 0 && L->fft_log2 > 0) {
+        k_light_noise_fft<<<(unsigned)nd, 1024, (size_t)T * sizeof(float2), st>>>(L->coef.p, L->F, T, L->fft_log2,
+                                                                                L->Ct.p, L->St.p, L->nz.p);
+        nzpre = L->nz.p;
+    }
+    k_light_response<<<gt, kLWG, 0, st>>>(L->pef.p, L->Rp, T, L->r.p, L->nrb, (float)q.gain, L->coef.p, L->F,
+                                         L->Ct.p, L->St.p, nzpre, V);
+    if (trig) {
+        const int32_t ng = nd / q.group;
+        const size_t lds = sizeof(uint64_t) * (size_t)((T + 63) / 64);
+        k_light_trigger<<<(unsigned)ng, 256, lds, st>>>(V, T, q.group, (float)q.trig_threshold, q.trig_deadtime,
+                                                       q.max_trig, trig, trig_count);
+    }
+}
+
+void free_graph(lts_light *L) {
+    if (L->exec) (void)hipGraphExecDestroy(L->exec);
+    if (L->graph) (void)hipGraphDestroy(L->graph);
+    L->exec = nullptr;
+    L->graph = nullptr;
+    L->fluct_node = L->coef_node = nullptr;
+}
+
+// Capture the sequence for these buffers on the simulator's own stream and find the two event-keyed nodes.
+lts_status capture_light(lts_light *L, const float *ipe, double *mu_d, double *pe_d, float *V, int32_t *trig,
+                         int32_t *trig_count) {
+    free_graph(L);
+    if (!L->cap_stream) LHIP(L, hipStreamCreateWithFlags(&L->cap_stream, hipStreamNonBlocking));
+    LHIP(L, hipStreamBeginCapture(L->cap_stream, hipStreamCaptureModeThreadLocal));
+    launch_light(L, 0, ipe, mu_d, pe_d, V, trig, trig_count, L->cap_stream);
+    hipGraph_t g = nullptr;
+    LHIP(L, hipStreamEndCapture(L->cap_stream, &g));
+    L->graph = g;
+    size_t nn = 0;
+    LHIP(L, hipGraphGetNodes(g, nullptr, &nn));
+    std::vector<hipGraphNode_t> nodes(nn);
+    LHIP(L, hipGraphGetNodes(g, nodes.data(), &nn));
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType ty;
+        LHIP(L, hipGraphNodeGetType(nd, &ty));
+        if (ty != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp;
+        LHIP(L, hipGraphKernelNodeGetParams(nd, &kp));
+        if (kp.func == reinterpret_cast<void *>(k_light_fluct)) L->fluct_node = nd;
+        if (kp.func == reinterpret_cast<void *>(k_light_noise_coef)) L->coef_node = nd;
+    }
+    if (!L->fluct_node || (L->F > 0 && !L->coef_node))
+        return lfail(L, LTS_ERR_DEVICE, "graph capture: event-keyed kernel nodes not found");
+    LHIP(L, hipGraphInstantiate(&L->exec, g, nullptr, nullptr, 0));
+    return LTS_OK;
+}
+
+// Point the two random-number kernel nodes of the instantiated graph at this event.
+lts_status set_event(lts_light *L, uint64_t event_id, double *mu_d, double *pe_d) {
+    const lts_light_params &q = L->p;
+    int32_t T = q.n_ticks, nd = q.n_det, Rp = L->Rp, F = L->F;
+    uint32_t k0 = L->k0, k1 = L->k1;
+    double na = q.normal_above;
+    const double *mu_c = mu_d;
+    float *pef = L->pef.p;
+    hipKernelNodeParams kp;
+    LHIP(L, hipGraphKernelNodeGetParams(L->fluct_node, &kp));
+    void *fa[] = {&mu_c, &pe_d, &pef, &Rp, &T, &nd, &event_id, &k0, &k1, &na};
+    kp.kernelParams = fa;
+    kp.extra = nullptr;
+    LHIP(L, hipGraphExecKernelNodeSetParams(L->exec, L->fluct_node, &kp));
+    if (F > 0) {
+        const float *amp = L->amp.p;
+        float2 *coef = L->coef.p;
+        LHIP(L, hipGraphKernelNodeGetParams(L->coef_node, &kp));
+        void *ca[] = {&amp, &F, &nd, &event_id, &k0, &k1, &coef};
+        kp.kernelParams = ca;
+        kp.extra = nullptr;
+        LHIP(L, hipGraphExecKernelNodeSetParams(L->exec, L->coef_node, &kp));
+    }
+    return LTS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -359,7 +467,16 @@ void lts_light_destroy(lts_light *L) {
     if (!L) return;
     (void)hipSetDevice(L->device);
     (void)hipDeviceSynchronize();
+    free_graph(L);
+    if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
     delete L;
+}
+
+lts_status lts_light_set_graph(lts_light *L, int32_t on) {
+    if (!L) return LTS_ERR_INVALID_ARG;
+    if (on != 0 && on != 1) return lfail(L, LTS_ERR_INVALID_ARG, "graph must be 0 or 1");
+    L->use_graph = on != 0;
+    return LTS_OK;
 }
 
 lts_status lts_light_simulate(lts_light *L, uint64_t event_id, const float *ipe, double *mu, double *pe, float *V,
@@ -374,31 +491,20 @@ lts_status lts_light_simulate(lts_light *L, uint64_t event_id, const float *ipe,
     const int64_t n = (int64_t)nd * T;
     double *mu_d = mu ? mu : L->mu.p;
     double *pe_d = pe ? pe : L->pe.p;
-    const unsigned g1 = (unsigned)((n + 255) / 256);
-    k_light_pad<<<g1, 256, 0, st>>>(ipe, L->xp.p, L->Kp, T, nd);
-    const dim3 gt((unsigned)((T + kLTile - 1) / kLTile), (unsigned)nd);
-    k_light_scint<<<gt, kLWG, 0, st>>>(L->xp.p, L->Kp, T, L->w.p, L->nkb, mu_d);
-    k_light_fluct<<<g1, 256, 0, st>>>(mu_d, pe_d, L->pef.p, L->Rp, T, nd, event_id, L->k0, L->k1, q.normal_above);
-    if (L->F > 0) {
-        const int64_t nc = (int64_t)nd * L->F;
-        k_light_noise_coef<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(L->amp.p, L->F, nd, event_id, L->k0, L->k1,
-                                                                        L->coef.p);
+    if (!L->use_graph) {
+        launch_light(L, event_id, ipe, mu_d, pe_d, V, trig, trig_count, st);
+        LHIP(L, hipGetLastError());
+        return LTS_OK;
     }
-    const float *nzpre = nullptr;
-    if (L->F > 0 && L->fft_log2 > 0) {
-        k_light_noise_fft<<<(unsigned)nd, 1024, (size_t)T * sizeof(float2), st>>>(L->coef.p, L->F, T, L->fft_log2,
-                                                                                L->Ct.p, L->St.p, L->nz.p);
-        nzpre = L->nz.p;
+    const void *ptrs[6] = {ipe, mu_d, pe_d, V, trig, trig_count};
+    if (!L->exec || memcmp(ptrs, L->g_ptrs, sizeof(ptrs)) != 0) {
+        lts_status r = capture_light(L, ipe, mu_d, pe_d, V, trig, trig_count);
+        if (r) return r;
+        memcpy(L->g_ptrs, ptrs, sizeof(ptrs));
     }
-    k_light_response<<<gt, kLWG, 0, st>>>(L->pef.p, L->Rp, T, L->r.p, L->nrb, (float)q.gain, L->coef.p, L->F,
-                                         L->Ct.p, L->St.p, nzpre, V);
-    if (trig) {
-        const int32_t ng = nd / q.group;
-        const size_t lds = sizeof(uint64_t) * (size_t)((T + 63) / 64);
-        k_light_trigger<<<(unsigned)ng, 256, lds, st>>>(V, T, q.group, (float)q.trig_threshold, q.trig_deadtime,
-                                                       q.max_trig, trig, trig_count);
-    }
-    LHIP(L, hipGetLastError());
+    lts_status r = set_event(L, event_id, mu_d, pe_d);
+    if (r) return r;
+    LHIP(L, hipGraphLaunch(L->exec, st));
     return LTS_OK;
 }
 

@@ -80,7 +80,7 @@ EXPORTS = ("lts_server_start", "lts_server_submit", "lts_server_poll", "lts_serv
            "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_set_ticks_per_thread", "lts_set_lane_exchange", "lts_set_matrix_cores", "lts_set_channel_mask",
            "lts_plan", "lts_simulate", "lts_simulate_batch", "lts_stage_quench_drift", "lts_debug_cells",
            "lts_stage_electronics", "lts_stage_philox", "lts_stage_rasterize", "lts_stage_induce", "lts_stage_reduce", "lts_status_str", "lts_last_error", "lts_version",
-           "lts_light_create", "lts_light_destroy", "lts_light_simulate", "lts_light_last_error")
+           "lts_light_create", "lts_light_destroy", "lts_light_simulate", "lts_light_set_graph", "lts_light_last_error")
 
 
 class lts_light_params(C.Structure):
@@ -140,6 +140,7 @@ def lib():
         L.lts_light_destroy.restype = None
         L.lts_light_simulate.argtypes = [P, C.c_uint64, P, P, P, P, P, P, P]
         L.lts_light_last_error.argtypes = [P]
+        L.lts_light_set_graph.argtypes = [P, C.c_int32]
         L.lts_light_last_error.restype = C.c_char_p
         _LIB = L
     return _LIB
@@ -514,33 +515,45 @@ class LightSim:
             raise LtsimError(st, "lts_light_create")
         self.device = device
 
-    def simulate(self, ipe, event_id: int, keep_mu: bool = False, keep_pe: bool = False, stream=None):
+    def set_graph(self, on: bool):
+        """Replay the light kernels through a HIP graph (pass the same `out` buffers each call to reuse it)."""
+        st = lib().lts_light_set_graph(self._h, int(bool(on)))
+        if st:
+            raise LtsimError(st, lib().lts_light_last_error(self._h).decode())
+
+    def simulate(self, ipe, event_id: int, keep_mu: bool = False, keep_pe: bool = False, stream=None, out=None):
         """ipe: device float32 tensor [n_det, n_ticks].  Returns device tensors V (and mu, pe if asked), trigger ticks
-        [n_groups, max_trig] and counts [n_groups]."""
+        [n_groups, max_trig] and counts [n_groups].  `out`, a result of an earlier call with the same keep flags,
+        is written in place."""
         import torch
         lp = self.light
         shape = (lp.n_det, lp.n_ticks)
         if tuple(ipe.shape) != shape or ipe.dtype != torch.float32 or not ipe.is_cuda or not ipe.is_contiguous():
             raise LtsimError(1, f"photocurrent must be a contiguous float32 device tensor of shape {shape}")
         dev = ipe.device
-        V = torch.empty(shape, dtype=torch.float32, device=dev)
-        mu = torch.empty(shape, dtype=torch.float64, device=dev) if keep_mu else None
-        pe = torch.empty(shape, dtype=torch.float64, device=dev) if keep_pe else None
         ng = lp.n_det // lp.group
-        trig = torch.empty((ng, max(lp.max_trig, 1)), dtype=torch.int32, device=dev)
-        cnt = torch.empty(ng, dtype=torch.int32, device=dev)
+        if out is not None:
+            V, mu, pe, trig, cnt = out["V"], out.get("mu"), out.get("pe"), out["_trig"], out["trig_count"]
+            if (mu is not None) != keep_mu or (pe is not None) != keep_pe:
+                raise LtsimError(1, "out was made with other keep_mu / keep_pe flags")
+        else:
+            V = torch.empty(shape, dtype=torch.float32, device=dev)
+            mu = torch.empty(shape, dtype=torch.float64, device=dev) if keep_mu else None
+            pe = torch.empty(shape, dtype=torch.float64, device=dev) if keep_pe else None
+            trig = torch.empty((ng, max(lp.max_trig, 1)), dtype=torch.int32, device=dev)
+            cnt = torch.empty(ng, dtype=torch.int32, device=dev)
         s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
         st = lib().lts_light_simulate(self._h, event_id, ipe.data_ptr(), mu.data_ptr() if keep_mu else None,
                                       pe.data_ptr() if keep_pe else None, V.data_ptr(), trig.data_ptr(),
                                       cnt.data_ptr(), s)
         if st:
             raise LtsimError(st, lib().lts_light_last_error(self._h).decode())
-        out = {"V": V, "trig": trig[:, :lp.max_trig], "trig_count": cnt}
+        res = {"V": V, "trig": trig[:, :lp.max_trig], "_trig": trig, "trig_count": cnt}
         if keep_mu:
-            out["mu"] = mu
+            res["mu"] = mu
         if keep_pe:
-            out["pe"] = pe
-        return out
+            res["pe"] = pe
+        return res
 
     def close(self):
         if self._h:

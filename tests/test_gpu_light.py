@@ -92,3 +92,26 @@ def test_light_invalid_parameters(lt, torch):
             lt.LightSim(bad, r, a)
     with pytest.raises(lt.LtsimError):
         lt.LightSim(dataclasses.replace(lp, n_ticks=64), r, a)            # n_freq >= n_ticks / 2
+
+
+def test_light_graph_replay_equals_eager(lt, torch):
+    """The HIP-graph replay of the light kernels gives the eager results bit for bit, replay after replay with
+    eager calls and host synchronisation between them, for several event ids, and again after the output buffers
+    change (a new capture)."""
+    lp, ipe, r, amp = W.light_workload(n_events=2, light=dataclasses.replace(W.Light(), n_det=16, n_ticks=8192))
+    x = torch.from_numpy(np.ascontiguousarray(ipe, np.float32)).cuda()
+    eager = lt.LightSim(lp, r, amp)
+    graph = lt.LightSim(lp, r, amp)
+    graph.set_graph(True)
+    out = None
+    for rep, ev in enumerate([5, 6, 5, 9, 6]):
+        a = eager.simulate(x, ev, keep_pe=True)
+        out = graph.simulate(x, ev, keep_pe=True, out=out)
+        torch.cuda.synchronize()
+        for k in ("V", "pe", "trig", "trig_count"):
+            assert torch.equal(a[k], out[k]), (rep, ev, k)
+    b = graph.simulate(x, 7, keep_pe=True)                 # new buffers: captured again
+    c = eager.simulate(x, 7, keep_pe=True)
+    torch.cuda.synchronize()
+    assert torch.equal(b["V"], c["V"]) and torch.equal(b["trig"], c["trig"])
+    assert not torch.equal(b["V"], out["V"])                # a different event draws differently
