@@ -263,7 +263,12 @@ struct lts_light {
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // two instances used in turn: an instance is re-parameterised only after its previous launch has finished
+    // (its event), so one call's graph can still run while the next call sets up the other
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipEvent_t done[2] = {nullptr, nullptr};
+    bool launched[2] = {false, false};
+    int32_t turn = 0;
     hipGraphNode_t fluct_node = nullptr, coef_node = nullptr;
     const void *g_ptrs[6] = {};
 };
@@ -319,9 +324,13 @@ void launch_light(lts_light *L, uint64_t event_id, const float *ipe, double *mu_
 }
 
 void free_graph(lts_light *L) {
-    if (L->exec) (void)hipGraphExecDestroy(L->exec);
+    for (int i = 0; i < 2; ++i) {
+        if (L->launched[i]) (void)hipEventSynchronize(L->done[i]);
+        if (L->exec[i]) (void)hipGraphExecDestroy(L->exec[i]);
+        L->exec[i] = nullptr;
+        L->launched[i] = false;
+    }
     if (L->graph) (void)hipGraphDestroy(L->graph);
-    L->exec = nullptr;
     L->graph = nullptr;
     L->fluct_node = L->coef_node = nullptr;
 }
@@ -351,12 +360,15 @@ lts_status capture_light(lts_light *L, const float *ipe, double *mu_d, double *p
     }
     if (!L->fluct_node || (L->F > 0 && !L->coef_node))
         return lfail(L, LTS_ERR_DEVICE, "graph capture: event-keyed kernel nodes not found");
-    LHIP(L, hipGraphInstantiate(&L->exec, g, nullptr, nullptr, 0));
+    for (int i = 0; i < 2; ++i) {
+        LHIP(L, hipGraphInstantiate(&L->exec[i], g, nullptr, nullptr, 0));
+        if (!L->done[i]) LHIP(L, hipEventCreateWithFlags(&L->done[i], hipEventDisableTiming));
+    }
     return LTS_OK;
 }
 
 // Point the two random-number kernel nodes of the instantiated graph at this event.
-lts_status set_event(lts_light *L, uint64_t event_id, double *mu_d, double *pe_d) {
+lts_status set_event(lts_light *L, hipGraphExec_t exec, uint64_t event_id, double *mu_d, double *pe_d) {
     const lts_light_params &q = L->p;
     int32_t T = q.n_ticks, nd = q.n_det, Rp = L->Rp, F = L->F;
     uint32_t k0 = L->k0, k1 = L->k1;
@@ -368,7 +380,7 @@ lts_status set_event(lts_light *L, uint64_t event_id, double *mu_d, double *pe_d
     void *fa[] = {&mu_c, &pe_d, &pef, &Rp, &T, &nd, &event_id, &k0, &k1, &na};
     kp.kernelParams = fa;
     kp.extra = nullptr;
-    LHIP(L, hipGraphExecKernelNodeSetParams(L->exec, L->fluct_node, &kp));
+    LHIP(L, hipGraphExecKernelNodeSetParams(exec, L->fluct_node, &kp));
     if (F > 0) {
         const float *amp = L->amp.p;
         float2 *coef = L->coef.p;
@@ -376,7 +388,7 @@ lts_status set_event(lts_light *L, uint64_t event_id, double *mu_d, double *pe_d
         void *ca[] = {&amp, &F, &nd, &event_id, &k0, &k1, &coef};
         kp.kernelParams = ca;
         kp.extra = nullptr;
-        LHIP(L, hipGraphExecKernelNodeSetParams(L->exec, L->coef_node, &kp));
+        LHIP(L, hipGraphExecKernelNodeSetParams(exec, L->coef_node, &kp));
     }
     return LTS_OK;
 }
@@ -468,6 +480,8 @@ void lts_light_destroy(lts_light *L) {
     (void)hipSetDevice(L->device);
     (void)hipDeviceSynchronize();
     free_graph(L);
+    for (int i = 0; i < 2; ++i)
+        if (L->done[i]) (void)hipEventDestroy(L->done[i]);
     if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
     delete L;
 }
@@ -497,14 +511,19 @@ lts_status lts_light_simulate(lts_light *L, uint64_t event_id, const float *ipe,
         return LTS_OK;
     }
     const void *ptrs[6] = {ipe, mu_d, pe_d, V, trig, trig_count};
-    if (!L->exec || memcmp(ptrs, L->g_ptrs, sizeof(ptrs)) != 0) {
+    if (!L->exec[0] || memcmp(ptrs, L->g_ptrs, sizeof(ptrs)) != 0) {
         lts_status r = capture_light(L, ipe, mu_d, pe_d, V, trig, trig_count);
         if (r) return r;
         memcpy(L->g_ptrs, ptrs, sizeof(ptrs));
     }
-    lts_status r = set_event(L, event_id, mu_d, pe_d);
+    const int i = L->turn;
+    L->turn ^= 1;
+    if (L->launched[i]) LHIP(L, hipEventSynchronize(L->done[i]));
+    lts_status r = set_event(L, L->exec[i], event_id, mu_d, pe_d);
     if (r) return r;
-    LHIP(L, hipGraphLaunch(L->exec, st));
+    LHIP(L, hipGraphLaunch(L->exec[i], st));
+    LHIP(L, hipEventRecord(L->done[i], st));
+    L->launched[i] = true;
     return LTS_OK;
 }
 

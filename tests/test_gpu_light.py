@@ -110,6 +110,18 @@ def test_light_graph_replay_equals_eager(lt, torch):
         torch.cuda.synchronize()
         for k in ("V", "pe", "trig", "trig_count"):
             assert torch.equal(a[k], out[k]), (rep, ev, k)
+    # back to back without host synchronisation: each launch's result is copied in stream order before the next
+    # call re-parameterises a graph instance, and every copy must hold its own event's result
+    evs = [11, 12, 13, 14, 15]
+    copies = []
+    for ev in evs:
+        out = graph.simulate(x, ev, keep_pe=True, out=out)
+        copies.append((out["V"].clone(), out["trig"].clone()))
+    torch.cuda.synchronize()
+    for ev, (v, t) in zip(evs, copies):
+        a = eager.simulate(x, ev, keep_pe=True)
+        torch.cuda.synchronize()
+        assert torch.equal(a["V"], v) and torch.equal(a["trig"], t), ev
     b = graph.simulate(x, 7, keep_pe=True)                 # new buffers: captured again
     c = eager.simulate(x, 7, keep_pe=True)
     torch.cuda.synchronize()
