@@ -500,9 +500,6 @@ lts_status lts_light_simulate(lts_light *L, uint64_t event_id, const float *ipe,
     if (!ipe || !V || (!trig) != (!trig_count)) return lfail(L, LTS_ERR_INVALID_ARG, "null buffer");
     hipStream_t st = (hipStream_t)stream;
     LHIP(L, hipSetDevice(L->device));
-    const lts_light_params &q = L->p;
-    const int32_t T = q.n_ticks, nd = q.n_det;
-    const int64_t n = (int64_t)nd * T;
     double *mu_d = mu ? mu : L->mu.p;
     double *pe_d = pe ? pe : L->pe.p;
     if (!L->use_graph) {
