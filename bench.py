@@ -74,9 +74,24 @@ def cpu_baseline(w, budget_s=15.0):
         if dt >= budget_s / 3 or S >= full.n:
             break
         S = min(full.n, int(S * max(2.0, budget_s / max(dt, 1e-3) * 0.5)))
-    return {"value": S / dt, "unit": "segments/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    # one thread, on a sample 1/cores the size (about the same wall time)
+    S1 = max(1, S // max(cores, 1))
+    sub = full.subset(list(range(S1)))
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        pix1 = oracle.active_pixels(w.physics, w.readout, w.table, sub)
+        wave, _ = oracle.waveforms(w.physics, w.readout, table, sub, pix1)
+        oracle.electronics(w.electronics, w.readout, w.event_ids[0], pix1, wave)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(cores)
+    return {"value": S / dt, "unit": "segments/s", "cores": cores, "kind": "oracle",
             "sample": f"first {S} of {full.n} segments of the module-scale event, all {len(pix)} pixels they reach, "
-                      f"3000 ticks, induction + electronics, FP64, {dt:.1f} s"}
+                      f"3000 ticks, induction + electronics, FP64, {dt:.1f} s",
+            "single_thread": {"value": S1 / dt1, "unit": "segments/s",
+                              "sample": f"first {S1} segments, {len(pix1)} pixels, {dt1:.1f} s"}}
 
 
 def batched_vs_plain(ltsim, W, n_events, mode, cfg=3):

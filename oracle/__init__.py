@@ -128,6 +128,14 @@ def num_threads() -> int:
     return int(lib().orc_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of later oracle calls (for timing only)."""
+    L = lib()
+    L.orc_set_num_threads.argtypes = [C.c_int]
+    L.orc_set_num_threads.restype = None
+    L.orc_set_num_threads(int(n))
+
+
 # --------------------------------------------------------------------------------------------
 # Steps
 # --------------------------------------------------------------------------------------------

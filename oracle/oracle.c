@@ -785,6 +785,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Number of OpenMP threads of later calls (timing of the oracle alone; no effect on its results). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ================================================================================================
  * Light simulation, Sec. 4 (on given photocurrents; the visibility table is an input of the caller).
  * ================================================================================================ */
