@@ -82,8 +82,9 @@ typedef struct lts_readout {
 /* LArPix-like front end (Sec. 3.4). */
 typedef struct lts_electronics {
     double threshold;          /* electrons; a sample is triggered when integral + discriminator noise >= threshold */
-    int32_t hold_ticks;        /* ticks from the threshold crossing to digitisation (1.6 us = 16) */
-    int32_t min_spacing;       /* minimum ticks between consecutive samples (11) */
+    int32_t hold_ticks;        /* ticks from the threshold crossing to digitisation (1.6 us = 16); >= 0, values
+                                  above 2^20 act as 2^20 (every later sample falls past the last tick) */
+    int32_t min_spacing;       /* minimum ticks between consecutive samples (11); >= 0, above 2^20 acts as 2^20 */
     double q_lsb;              /* electrons per ADC count */
     int32_t pedestal;          /* ADC counts added before clamping */
     int32_t adc_bits;          /* ADC resolution (<= 16) */

@@ -193,8 +193,10 @@ lts_status validate_and_derive(lts_context *c) {
     P.sig_reset = (float)el.sigma_reset;
     P.sig_disc = (float)el.sigma_disc;
     P.sig_unc = (float)el.sigma_unc;
-    P.hold = el.hold_ticks;
-    P.spacing = el.min_spacing;
+    // a hold or spacing beyond 2^20 ticks acts as one of 2^20 (every later sample falls past the last tick, and the
+    // "no sample yet" sentinel of -2^28 stays below tick 0); the clamp keeps the tick arithmetic inside int32
+    P.hold = std::min(el.hold_ticks, 1 << 20);
+    P.spacing = std::min(el.min_spacing, 1 << 20);
     P.pedestal = el.pedestal;
     P.adc_max = (1 << el.adc_bits) - 1;
     P.max_packets = el.max_packets;
