@@ -392,6 +392,42 @@ def test_electronics_with_full_noise_vs_oracle(lt, orc, torch, period):
     assert cmp_ > 500 and flg <= 0.01 * (cmp_ + flg)
 
 
+@pytest.mark.parametrize("period,hold,spacing", [(64, 0, 0), (1, 0, 0), (5, 70, 3), (128, 16, 11),
+                                                 (0, 2**31 - 1, 11), (0, 16, 2**31 - 1)])
+def test_electronics_walk_edges_vs_oracle(lt, orc, torch, period, hold, spacing):
+    """Resets on chunk edges and on every tick, samples at the crossing tick, holds that skip several resets, and
+    holds or spacings beyond every tick; 1000 ticks end in a partial 40-tick chunk."""
+    w = W.config(5)
+    w.electronics.reset_period, w.electronics.hold_ticks, w.electronics.min_spacing = period, hold, spacing
+    nt = 1000
+    w.readout = W.Readout(n_x=32, n_y=32, n_ticks=nt)
+    rng = np.random.default_rng(11 + period)
+    n = 200
+    tt = np.arange(nt)
+    cur = np.zeros((n, nt))
+    for q in range(n):
+        for _ in range(rng.integers(1, 6)):
+            t0, amp, wid = rng.integers(0, nt), rng.uniform(200, 6000), rng.uniform(0.5, 20)
+            cur[q] += amp * np.exp(-0.5 * ((tt - t0) / wid) ** 2)
+    cur32 = cur.astype(np.float32)
+    pix = np.sort(rng.choice(32 * 32, n, replace=False)).astype(np.int32)
+    ctx = lt.Context.from_workload(w)
+    h = ctx.stage_electronics(77, torch.tensor(pix, device="cuda"), torch.tensor(cur32, device="cuda")).host()
+    pk, st, uf = orc.electronics(w.electronics, w.readout, 77, pix, cur32.astype(np.float64), EPS_REL, EPS_ABS,
+                                 with_uncertain=True)
+    cmp_, flg, bad = compare_packets(h, pix, pk, uf)
+    print(f"walk edges {period} {hold} {spacing}: compared {cmp_} flagged {flg} dropped {h['counts'][2]} / {st[0]}")
+    assert not bad, bad[:3]
+    n_unc = int((uf < nt).sum())
+    assert abs(int(h["counts"][2]) - int(st[0])) <= n_unc            # dropped samples
+    if hold >= nt:
+        assert len(h["pkt_tick"]) == 0 and int(st[0]) > 0
+    else:
+        assert cmp_ > 20 and flg <= 0.02 * (cmp_ + flg)
+    if spacing >= nt:                                                  # one sample per pixel at most
+        assert len(np.unique(h["pkt_pixel"])) == len(h["pkt_pixel"])
+
+
 # ----------------------------------------------------------------------------------------------- batching
 
 @pytest.mark.parametrize("mode", [0, 2])
