@@ -388,6 +388,27 @@ def test_philox_known_answers(orc):
         assert [int(x) for x in orc.philox4x32_10(v[:4], v[4:6])] == v[6:]
 
 
+def test_philox_matches_rocrand(orc, tmp_path):
+    """The oracle's Philox4x32-10 against rocRAND's engine (an independent implementation of the same published
+    generator), on edge and random counters and keys."""
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
+        pytest.skip("hipcc or the rocRAND headers are not installed")
+    exe = str(tmp_path / "philox_blocks")
+    src = os.path.join(os.path.dirname(__file__), "rocrand_philox_blocks.cpp")
+    subprocess.run([hipcc, "-O1", src, "-o", exe], check=True, capture_output=True, timeout=300)
+    rng = np.random.default_rng(2212)
+    cases = [[0] * 6, [0xFFFFFFFF] * 6, [0xFFFFFFFF, 0xFFFFFFFF, 0, 0, 1, 2], [0, 0, 0xFFFFFFFF, 0, 0, 0]]
+    cases += rng.integers(0, 2**32, size=(300, 6), dtype=np.uint64).tolist()
+    out = subprocess.run([exe], input="\n".join(" ".join(f"{int(x):x}" for x in c) for c in cases) + "\n",
+                         check=True, capture_output=True, text=True, timeout=60).stdout.split("\n")
+    for c, line in zip(cases, out):
+        assert [int(x) for x in orc.philox4x32_10(c[:4], c[4:6])] == [int(x, 16) for x in line.split()], c
+    assert len([ln for ln in out if ln.strip()]) == len(cases)
+
+
 def test_noise_normal_statistics(orc):
     g = np.array([orc.noise_normal(0x2212098070000001, p, t, 7, 2) for p in range(200) for t in range(200)])
     assert abs(g.mean()) < 4 / math.sqrt(g.size)
