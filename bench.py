@@ -31,6 +31,9 @@ PEAK_FP32_MFMA_TFLOPS = 157.3       # dense FP32 matrix-core rate
 HBM_PEAK_GBS = 8000.0
 
 
+INDUCE_KERNEL = {"sorted": "k_induce_sorted", "atomic": "k_induce_atomic", "summed": "k_induce_summed"}
+
+
 def kernel_source_digest():
     """SHA-256 over the device sources (kernels.hip, device.hpp): identifies the kernel build a profile was taken on."""
     import hashlib
@@ -400,10 +403,10 @@ def main():
                      "frac": achieved / PEAK_FP32_FMA_TFLOPS,
                      "peak_basis": "FP32 FMA without packed-FP32 instructions (not emitted by this build)",
                      "frac_of_packed_fp32_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
-                     "traffic": profiled_traffic("k_induce_atomic" if args.mode == "atomic" else "k_induce_sorted"),
+                     "traffic": profiled_traffic(INDUCE_KERNEL[args.mode]),
                      "traffic_unit": "bytes per launch beyond L2 (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel_source": kernel_source_digest(),
-                     "kernel": "k_induce_atomic" if args.mode == "atomic" else "k_induce_sorted",
+                     "kernel": INDUCE_KERNEL[args.mode],
                      "flops_per_launch": 2.0 * stats["fma"], "launch_ms": ind_s * 1e3},
     }
     line["config"]["induce_slices"] = args.slices if args.mode == "sorted" else 1

@@ -1691,17 +1691,39 @@ void launch_sum_lists_count(const DevParams &P, const Work &w, const SumWork &sw
     if (n_slots > 0)
         k_sum_lists<false><<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
 }
-void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, hipStream_t st) {
-    if (n_slots > 0)
-        k_sum_lists<true><<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
+// per list entry: the piece as a record for the summed induction loop (its pixel found by bisection of the list
+// offsets; one thread per entry, so the record writes are coalesced)
+__global__ void k_sum_recs(DevParams P, int64_t n_slots, int64_t n_list, const int32_t *slot_gp, SumWork sw) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_list) return;
+    int64_t lo = 0, hi = n_slots - 1;                   // last slot whose list starts at or before i
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (sw.list_off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    const int32_t gp = slot_gp[lo];
+    const int32_t p = gp - (gp / P.npx) * P.npx;
+    const int32_t uc = (p % P.nx) * P.nsub + P.nsub / 2, vc = (p / P.nx) * P.nsub + P.nsub / 2;
+    const SegInfo &g = sw.piece[sw.list[i]];
+    sw.rec[i] = PieceRef{g.a0, g.na, (uint32_t)(g.cell_off / kAC), fold(g.u0 - uc) * P.by + fold(g.v0 - vc)};
+}
+
+void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, int64_t n_list,
+                           hipStream_t st) {
+    if (n_slots <= 0) return;
+    k_sum_lists<true><<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
+    if (n_list > 0)
+        k_sum_recs<<<(unsigned)((n_list + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, n_list, w.slot_gp, sw);
 }
 
 // Summed induction, one wavefront per work unit (active pixel, tile of kTileTicks ticks): lane t owns ticks
 // t0 + 8t .. +7 of the tile, and the wavefront streams every column piece of the pixel's list whose tick window
-// [a0 - T_R + 1, a0 + na - 1] meets the tile through registers (pieces start at the aligning residue, so every
-// lane's table offset is a multiple of 8).  Lanes whose ticks lie outside a piece's
-// window read the table's zero padding, so they add exact zeros.  Each piece's product is added to the lane's
-// running sums with Kahan compensation (pieces in list order: deterministic and batch-invariant).  Wavefronts take
+// [a0 - T_R + 1, a0 + na - 1] meets the tile through the four-block register ring, three blocks ahead and into the
+// next piece (pieces start at the aligning residue, so every lane's table offset is a multiple of 8 and the loads
+// are aligned 16-byte loads).  The pieces come as 16-byte records (first tick, length, charge offset, folded table
+// column), so the walk needs no dependent loads.  Lanes whose ticks lie outside a piece's window read the table's
+// zero padding, so they add exact zeros.  The products are added to the lane's running sums with Kahan
+// compensation after every 4 pieces (pieces in list order: deterministic and batch-invariant).  Wavefronts take
 // units from a counter and never synchronise with each other; the first tile of a pixel also accounts the charge
 // that its pieces induce outside the window.
 constexpr int32_t kSumKahanEvery = 4;   // pieces summed in FP32 registers between compensated additions
@@ -1712,6 +1734,7 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
                                                        const double *__restrict__ prefix,
                                                        const int64_t *__restrict__ list_off,
                                                        const int32_t *__restrict__ list,
+                                                       const PieceRef *__restrict__ rec,
                                                        const int32_t *__restrict__ slot_gp, float *__restrict__ wave,
                                                        DevHeader *H, double *report) {
     const int lane = threadIdx.x & 63;
@@ -1743,8 +1766,6 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
             cc = S + g.cell_off;
             nblk = g.na_pad / kAC;
         };
-        int64_t q = pb;
-        while (q < pe && !meets(q)) ++q;
         if constexpr (!SHIFT) {                         // aligned ping-pong per piece, Kahan after every 4 pieces
             auto kahan = [&] {
 #pragma unroll
@@ -1756,40 +1777,67 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
                     acc[r] = 0.0f;
                 }
             };
+            // the pixel's pieces that meet the tile, in list order, streamed through the four-block register ring
+            // (three blocks ahead, the next piece's first blocks loaded while the current one runs)
+            auto skip = [&](int64_t q) {
+                while (q < pe) {
+                    const PieceRef r = rec[q];
+                    if (r.a0 + r.na - 1 >= t0 && r.a0 - (TR - 1) <= t1) break;
+                    ++q;
+                }
+                return q;
+            };
             int32_t pending = 0;
-            for (; q < pe; ++q) {
-                if (!meets(q)) continue;
+            int64_t q = skip(pb);
+            if (q < pe) {
+                auto colp = [&](const PieceRef &r) {
+                    return Rpad + (int64_t)r.bin * P.col_len + (nb - r.a0 + TR - 1 + kPad);
+                };
+                const PieceRef r0 = rec[q];
+                auto adv = [&](const float *&ncol, const float *&ncc, int32_t &nn) {
+                    q = skip(q + 1);
+                    if (q >= pe) return false;
+                    const PieceRef r = rec[q];
+                    ncol = colp(r);
+                    ncc = S + (int64_t)r.cell8 * kAC;
+                    nn = (r.na + kAC - 1) / kAC;
+                    return true;
+                };
+                auto done = [&] {
+                    if (++pending == kSumKahanEvery) {
+                        kahan();
+                        pending = 0;
+                    }
+                };
+                column_stream<false, true>(colp(r0), S + (int64_t)r0.cell8 * kAC, (r0.na + kAC - 1) / kAC, adv, done,
+                                           acc);
+            }
+            if (pending) kahan();
+        } else {
+            int64_t q = pb;
+            while (q < pe && !meets(q)) ++q;
+            if (q < pe) {
                 const float *col, *cc;
                 int32_t nblk;
                 colof(q, col, cc, nblk);
-                column_pingpong<true>(col, uniform_cptr(cc), nblk, acc);
-                if (++pending == kSumKahanEvery) {
-                    kahan();
-                    pending = 0;
-                }
-            }
-            if (pending) kahan();
-        } else if (q < pe) {
-            const float *col, *cc;
-            int32_t nblk;
-            colof(q, col, cc, nblk);
-            auto adv = [&](const float *&ncol, const float *&ncc, int32_t &nn) {
-                do { ++q; } while (q < pe && !meets(q));
-                if (q >= pe) return false;
-                colof(q, ncol, ncc, nn);
-                return true;
-            };
-            auto done = [&] {
+                auto adv = [&](const float *&ncol, const float *&ncc, int32_t &nn) {
+                    do { ++q; } while (q < pe && !meets(q));
+                    if (q >= pe) return false;
+                    colof(q, ncol, ncc, nn);
+                    return true;
+                };
+                auto done = [&] {
 #pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const float y = acc[r] - cmp[r];
-                    const float t = sum[r] + y;
-                    cmp[r] = (t - sum[r]) - y;
-                    sum[r] = t;
-                    acc[r] = 0.0f;
-                }
-            };
-            column_stream<SHIFT, false>(col, cc, nblk, adv, done, acc);
+                    for (int r = 0; r < 8; ++r) {
+                        const float y = acc[r] - cmp[r];
+                        const float t = sum[r] + y;
+                        cmp[r] = (t - sum[r]) - y;
+                        sum[r] = t;
+                        acc[r] = 0.0f;
+                    }
+                };
+                column_stream<SHIFT, false>(col, cc, nblk, adv, done, acc);
+            }
         }
         float *wrow = wave + slot * NT;
 #pragma unroll
@@ -1833,10 +1881,10 @@ void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, 
     const int64_t g = std::min<int64_t>((units + kWG / 64 - 1) / (kWG / 64), 256 * 8);
     if (shift)
         k_induce_summed<true><<<(unsigned)g, kWG, 0, st>>>(P, sw.piece, sw.S, T.Rpad, T.prefix, sw.list_off, sw.list,
-                                                           w.slot_gp, wave, w.hdr, w.report);
+                                                           sw.rec, w.slot_gp, wave, w.hdr, w.report);
     else
         k_induce_summed<false><<<(unsigned)g, kWG, 0, st>>>(P, sw.piece, sw.S, T.Rpad, T.prefix, sw.list_off, sw.list,
-                                                            w.slot_gp, wave, w.hdr, w.report);
+                                                            sw.rec, w.slot_gp, wave, w.hdr, w.report);
 }
 
 // ================================================================================================= electronics

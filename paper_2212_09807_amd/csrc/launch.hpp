@@ -46,6 +46,15 @@ struct Table {
 
 // Device buffers of the summed (sum-then-convolve) induction: per event an absolute grid of sub-pixel columns
 // u in [UL, UL + CU) x v in [VL, VL + CV), UL = nsub/2 - bx (the columns some in-grid pixel can reach).
+// One column piece as seen from one active pixel: what the summed induction loop needs, in one 16-byte record
+// (no dependent loads): the piece's first tick and length, its summed charge at S + 8 * cell8, and the folded
+// table column that the pixel sees it through.
+struct alignas(16) PieceRef {
+    int32_t a0, na;
+    uint32_t cell8;
+    int32_t bin;
+};
+
 struct SumWork {
     int32_t CU = 0, CV = 0, UL = 0, VL = 0;
     int64_t n_cols = 0;                      // n_ev * CU * CV
@@ -59,6 +68,7 @@ struct SumWork {
     float *S = nullptr;                      // [n_s] summed charge per column piece (padded to kAC)
     int64_t *list_off = nullptr;             // [n_slots + 1] pieces in reach per active pixel, then offsets
     int32_t *list = nullptr;                 // [n_list] piece ids per active pixel, in column order
+    PieceRef *rec = nullptr;                 // [n_list + 1] the same pieces as records (one spare entry at the end)
 };
 constexpr int32_t kPieceTicks = kPieceMax;   // ticks per column piece (a multiple of kAC, <= kNaMax)
 static_assert(kPieceTicks % kAC == 0 && kPieceTicks <= kNaMax, "piece length");
@@ -67,7 +77,8 @@ void launch_sum_ranges(const DevParams &P, const Work &w, const SumWork &sw, hip
 void launch_sum_fill(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st);     // lists, pieces
 void launch_sum_pieces(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st);   // piece records, S
 void launch_sum_lists_count(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, hipStream_t st);
-void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, hipStream_t st);
+void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, int64_t n_list,
+                           hipStream_t st);                                                    // + records
 void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, const Table &T, float *wave,
                           int64_t n_slots, int32_t rt, bool shift, hipStream_t st);
 

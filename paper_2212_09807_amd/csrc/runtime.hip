@@ -44,7 +44,7 @@ struct lts_context {
     DevBuf part;                     // per-slice partial waveforms of the sliced sorted variant
     DevBuf mask;                     // disabled-channel mask (npx bytes) when set
     bool has_mask = false;
-    DevBuf col_lo, col_hi, col_seg_off, col_cursor, col_seg, piece_off, s_off, piece, S, list_off, list;
+    DevBuf col_lo, col_hi, col_seg_off, col_cursor, col_seg, piece_off, s_off, piece, S, list_off, list, rec;
     DevParams P{};
     bool has_table = false;
     DevBuf Rpad, prefix;
@@ -335,6 +335,8 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     // front and 7 of padding at the end; every column with charge has at least one segment (n_colseg >= columns)
     const int64_t max_pieces = 2 * n_colseg + h.n_cells / kPieceTicks + 1;
     const int64_t max_s = h.n_cells + 2 * (int64_t)kAC * n_colseg + kAC;
+    if (max_s / kAC >= (int64_t)UINT32_MAX)          // piece records hold the charge offset in units of kAC floats
+        return fail(c, LTS_ERR_CAPACITY, "summed induction: too many summed charge values for one call");
     if ((r = ensure(c, c->col_lo, sizeof(int32_t) * (size_t)sw.n_cols))) return r;
     if ((r = ensure(c, c->col_hi, sizeof(int32_t) * (size_t)sw.n_cols))) return r;
     if ((r = ensure(c, c->col_seg_off, sizeof(int64_t) * (size_t)nc1))) return r;
@@ -379,7 +381,10 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
         return fail(c, LTS_ERR_DEVICE, "summed induction: column pieces exceed their bound");
     if ((r = ensure(c, c->list, sizeof(int32_t) * (size_t)std::max<int64_t>(tot[0], 1)))) return r;
     sw.list = as<int32_t>(c->list);
-    launch_sum_lists_fill(P, w, sw, n_slots, st);
+    if ((r = ensure(c, c->rec, sizeof(PieceRef) * (size_t)(tot[0] + 1)))) return r;
+    sw.rec = as<PieceRef>(c->rec);
+    HIP_TRY(c, hipMemsetAsync(sw.rec + tot[0], 0, sizeof(PieceRef), st));   // the spare entry read one ahead
+    launch_sum_lists_fill(P, w, sw, n_slots, tot[0], st);
     Table T{as<float>(c->Rpad), as<double>(c->prefix)};
     launch_induce_summed(P, w, sw, T, wave, n_slots, c->ticks_per_thread, c->lane_exchange != 0, st);
     return LTS_OK;
@@ -535,7 +540,7 @@ void lts_context_destroy(lts_context *c) {
     }
     for (hipEvent_t e : c->free_ev) (void)hipEventDestroy(e);
     DevBuf *bufs[] = {&c->mask, &c->col_lo, &c->col_hi, &c->col_seg_off, &c->col_cursor, &c->col_seg, &c->piece_off, &c->s_off,
-                      &c->piece, &c->S, &c->list_off, &c->list, &c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off, &c->pix_cnt, &c->cursor, &c->pix_slot, &c->slot_gp,
+                      &c->piece, &c->S, &c->list_off, &c->list, &c->rec, &c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off, &c->pix_cnt, &c->cursor, &c->pix_slot, &c->slot_gp,
                       &c->slot_off, &c->pairs_u, &c->pairs, &c->cells, &c->pk_tick, &c->pk_adc, &c->pk_flag,
                       &c->pk_off, &c->hdr, &c->scan_tmp, &c->ev_off, &c->ev_ids, &c->report_tmp, &c->counts_tmp,
                       &c->red_head, &c->red_start};
