@@ -125,10 +125,26 @@ def batched_vs_plain(ltsim, W, n_events, mode, cfg=3):
         torch.cuda.synchronize()
         tp = time.perf_counter() - t0
         print(f"[bench] batched pass {rep}: batch {tb:.3f} s, plain {tp:.3f} s", file=sys.stderr, flush=True)
+    # the same plain calls and batch with each call's launch sequence replayed as a HIP graph
+    ctx.set_graph(True)
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for d, o, i in zip(singles, outs, w.event_ids):
+            ctx.simulate(d, event_id=i, out=o)
+        torch.cuda.synchronize()
+        tpg = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ctx.simulate_batch(dsegs, offs, w.event_ids, out=bout)
+        torch.cuda.synchronize()
+        tbg = time.perf_counter() - t0
+    ctx.set_graph(False)
     res = {"workload": "batched spill (log-normal event sizes)" if cfg == 3 else "single-track events, 200 segments",
            "events": n_events, "segments": int(allsegs.n), "batched_events_per_s": n_events / tb,
            "plain_events_per_s": n_events / tp, "batched_segments_per_s": allsegs.n / tb,
-           "plain_segments_per_s": allsegs.n / tp, "gain": tp / tb}
+           "plain_segments_per_s": allsegs.n / tp, "gain": tp / tb,
+           "graph": {"plain_events_per_s": n_events / tpg, "batched_events_per_s": n_events / tbg,
+                     "updates_instantiations": list(ctx.graph_stats())}}
     return res
 
 

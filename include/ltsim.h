@@ -196,6 +196,17 @@ lts_status lts_set_lane_exchange(lts_context *ctx, int32_t on);
  * otherwise. */
 lts_status lts_set_matrix_cores(lts_context *ctx, int32_t on);
 
+/* HIP-graph replay of each call's launch sequence (Sec. 3.4 pipeline; a launch-overhead option for batched and
+ * small events): 1 = after the sizing read-back that every call makes, the rest of the call (rasterisation,
+ * cells, induction, reduction, electronics, packets) is captured on a capture stream owned by the context and
+ * launched as one graph on the call's stream; the context keeps one executable graph and updates it in place when
+ * the next call has the same launch structure (else instantiates a new one), only after the previous launch has
+ * finished.  Results are identical to 0 (default: direct launches).  Ignored in LTS_REDUCE_SUMMED mode, which reads
+ * sizes back in the middle of the call.  Stage timing (lts_set_timing) records nothing for graph-launched calls. */
+lts_status lts_set_graph(lts_context *ctx, int32_t on);
+/* Number of in-place updates and of instantiations of the context's executable graph so far (host pointers). */
+lts_status lts_graph_stats(lts_context *ctx, int64_t *updates, int64_t *instantiations);
+
 /* Sizing pass (synchronous on `stream`): need[4] = (segment-pixel pairs, active pixels, charge cells,
  * packet upper bound = active pixels * max_packets).  Host pointer need. */
 lts_status lts_plan(lts_context *ctx, const lts_segments *segs, int64_t need[4], void *stream);

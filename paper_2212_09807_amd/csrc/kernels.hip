@@ -395,6 +395,20 @@ __global__ __launch_bounds__(kWG) void k_fill_pairs(DevParams P, SegInfo *si, in
         }
 }
 
+// Zero fill by a kernel (a memset node recorded into a captured graph is avoided: the pipeline's launch sequence
+// may be captured).
+__global__ void k_zero_words(uint32_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+void launch_zero(void *p, int64_t bytes, hipStream_t st) {
+    const int64_t n = bytes / 4;
+    if (n <= 0) return;
+    const int64_t g = std::min<int64_t>((n + kWG - 1) / kWG, 4096);
+    k_zero_words<<<(unsigned)g, kWG, 0, st>>>((uint32_t *)p, n);
+}
+
 void launch_fill_pairs(const DevParams &P, const Work &w, hipStream_t st) {
     if (w.n_seg > 0)
         k_fill_pairs<<<(unsigned)((w.n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.n_seg, w.cell_off, w.pix_cnt,

@@ -41,6 +41,13 @@ struct lts_context {
     int32_t ticks_per_thread = 0;    // induction tick tile per thread (0 = chosen from the table length)
     int32_t lane_exchange = 0;       // 8-tick tiles share table windows across lanes (1) or load their own (0)
     int32_t matrix_cores = 0;        // sorted per-pair induction on the FP32 matrix cores (1) or the vector ALUs (0)
+    // HIP-graph replay of the launch sequence after the sizing read-back (per-pair and atomic modes)
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;  // capture stream (captures never run on the caller's stream)
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t gdone = nullptr;        // recorded behind every graph launch
+    bool glaunched = false;
+    int64_t graph_updates = 0, graph_instantiations = 0;
     DevBuf part;                     // per-slice partial waveforms of the sliced sorted variant
     DevBuf mask;                     // disabled-channel mask (npx bytes) when set
     bool has_mask = false;
@@ -390,6 +397,55 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     return LTS_OK;
 }
 
+// Captures the launch sequence `launch` on the context's capture stream, brings the context's executable graph up
+// to date (an update when the node structure is unchanged, else a new instantiation) and launches it on `st`.  The
+// executable graph is only changed after its previous launch has finished.  Stage timing is not recorded here.
+template <class Launch>
+lts_status run_graph(lts_context *c, hipStream_t st, Launch &launch) {
+    if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    if (!c->gdone) HIP_TRY(c, hipEventCreateWithFlags(&c->gdone, hipEventDisableTiming));
+    if (c->glaunched) HIP_TRY(c, hipEventSynchronize(c->gdone));
+    const bool timing = c->timing;
+    c->timing = false;
+    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    const lts_status r = launch(c->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+    c->timing = timing;
+    if (r) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (ec != hipSuccess || !g) return fail(c, LTS_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+    bool ok = false;
+    if (c->gexec) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+        ok = hipGraphExecUpdate(c->gexec, g, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+        (void)hipGetLastError();                        // a refused update is not an error of this call
+        if (ok) {
+            ++c->graph_updates;
+        } else {
+            (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+        }
+    }
+    if (!ok) {
+        const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            c->gexec = nullptr;
+            (void)hipGraphDestroy(g);
+            return fail(c, LTS_ERR_DEVICE, std::string("graph instantiation: ") + hipGetErrorString(ei));
+        }
+        ++c->graph_instantiations;
+    }
+    (void)hipGraphDestroy(g);
+    HIP_TRY(c, hipGraphLaunch(c->gexec, st));
+    HIP_TRY(c, hipEventRecord(c->gdone, st));
+    c->glaunched = true;
+    return LTS_OK;
+}
+
 lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids, const int64_t *seg_offsets,
                         const lts_segments *segs, const lts_outputs *out, hipStream_t st) {
     if (c->sticky) return fail(c, c->sticky, "context is in a failed state: " + c->err);
@@ -432,44 +488,62 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
     w.pk_flag = as<uint8_t>(c->pk_flag);
     w.pk_off = as<int64_t>(c->pk_off);
     w.scan_tmp = c->scan_tmp.p;
-    HIP_TRY(c, hipMemsetAsync(w.pk_off, 0, sizeof(int64_t) * (size_t)(n_slots + 1), st));
     const DevParams &P = c->P;
-    {
-        StageTimer t(c, st, LTS_STAGE_RASTERIZE);
-        launch_slots(P, w, out->pixel_id, out->event_pixel_offsets, st);
-        launch_fill_pairs(P, w, st);
-        if (c->reduce_mode == LTS_REDUCE_SORTED) launch_sort_pairs(w, n_slots, st);
-    }
-    {
-        StageTimer t(c, st, LTS_STAGE_CELLS);
-        launch_cells(P, w, st);
-    }
     Table T{as<float>(c->Rpad), as<double>(c->prefix)};
-    if (c->reduce_mode == LTS_REDUCE_ATOMIC)
-        HIP_TRY(c, hipMemsetAsync(out->current, 0, sizeof(float) * (size_t)n_slots * P.nticks, st));
-    if (c->reduce_mode == LTS_REDUCE_SUMMED) {
-        StageTimer t(c, st, LTS_STAGE_INDUCE);
-        if ((r = run_summed(c, w, h, n_slots, out->current, st))) return r;
-    } else if (c->reduce_mode == LTS_REDUCE_SORTED && c->induce_slices > 1 && n_slots > 0) {
-        // slices of at most 1 GiB of partial waveforms at a time
+    // The sequence from here to the packets has no host synchronisation in the per-pair and atomic modes, so it can
+    // be captured and replayed as one HIP graph (zero fills are kernels, not memset nodes).
+    const bool graph = c->use_graph && c->reduce_mode != LTS_REDUCE_SUMMED;
+    auto launch_all = [&](hipStream_t s) -> lts_status {
+        launch_zero(w.pk_off, (int64_t)sizeof(int64_t) * (n_slots + 1), s);
+        {
+            StageTimer t(c, s, LTS_STAGE_RASTERIZE);
+            launch_slots(P, w, out->pixel_id, out->event_pixel_offsets, s);
+            launch_fill_pairs(P, w, s);
+            if (c->reduce_mode == LTS_REDUCE_SORTED) launch_sort_pairs(w, n_slots, s);
+        }
+        {
+            StageTimer t(c, s, LTS_STAGE_CELLS);
+            launch_cells(P, w, s);
+        }
+        if (c->reduce_mode == LTS_REDUCE_ATOMIC)
+            launch_zero(out->current, (int64_t)sizeof(float) * n_slots * P.nticks, s);
+        if (c->reduce_mode == LTS_REDUCE_SUMMED) {
+            StageTimer t(c, s, LTS_STAGE_INDUCE);
+            lts_status r2 = run_summed(c, w, h, n_slots, out->current, s);
+            if (r2) return r2;
+        } else if (c->reduce_mode == LTS_REDUCE_SORTED && c->induce_slices > 1 && n_slots > 0) {
+            // slices of at most 1 GiB of partial waveforms at a time
+            const int64_t row_bytes = (int64_t)c->induce_slices * P.nticks * (int64_t)sizeof(float);
+            const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_slots, (1ll << 30) / row_bytes));
+            StageTimer t(c, s, LTS_STAGE_INDUCE);
+            launch_induce_slices(P, w, T, out->current, n_slots, c->induce_slices, as<float>(c->part), chunk,
+                                 c->ticks_per_thread, s);
+        } else if (c->reduce_mode == LTS_REDUCE_SORTED && c->matrix_cores) {
+            StageTimer t(c, s, LTS_STAGE_INDUCE);
+            launch_induce_mfma(P, w, T, out->current, n_slots, s);
+        } else {
+            StageTimer t(c, s, LTS_STAGE_INDUCE);
+            launch_induce(P, w, T, out->current, c->reduce_mode, n_slots, c->ticks_per_thread, c->lane_exchange != 0,
+                          s);
+        }
+        {
+            StageTimer t(c, s, LTS_STAGE_ELECTRONICS);
+            launch_electronics(P, out->current, w.slot_gp, w.event_ids, n_slots, w, s);
+            launch_compact_packets(P, w, n_slots, out->pkt_pixel, out->pkt_tick, out->pkt_adc, out->pkt_flags,
+                                   out->cap_packets, out->event_pixel_offsets, out->event_packet_offsets, out->counts,
+                                   s);
+        }
+        return LTS_OK;
+    };
+    if (c->reduce_mode == LTS_REDUCE_SORTED && c->induce_slices > 1 && n_slots > 0) {
         const int64_t row_bytes = (int64_t)c->induce_slices * P.nticks * (int64_t)sizeof(float);
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_slots, (1ll << 30) / row_bytes));
         if ((r = ensure(c, c->part, (size_t)(row_bytes * chunk)))) return r;
-        StageTimer t(c, st, LTS_STAGE_INDUCE);
-        launch_induce_slices(P, w, T, out->current, n_slots, c->induce_slices, as<float>(c->part), chunk,
-                             c->ticks_per_thread, st);
-    } else if (c->reduce_mode == LTS_REDUCE_SORTED && c->matrix_cores) {
-        StageTimer t(c, st, LTS_STAGE_INDUCE);
-        launch_induce_mfma(P, w, T, out->current, n_slots, st);
-    } else {
-        StageTimer t(c, st, LTS_STAGE_INDUCE);
-        launch_induce(P, w, T, out->current, c->reduce_mode, n_slots, c->ticks_per_thread, c->lane_exchange != 0, st);
     }
-    {
-        StageTimer t(c, st, LTS_STAGE_ELECTRONICS);
-        launch_electronics(P, out->current, w.slot_gp, w.event_ids, n_slots, w, st);
-        launch_compact_packets(P, w, n_slots, out->pkt_pixel, out->pkt_tick, out->pkt_adc, out->pkt_flags,
-                               out->cap_packets, out->event_pixel_offsets, out->event_packet_offsets, out->counts, st);
+    if (!graph) {
+        if ((r = launch_all(st))) return r;
+    } else {
+        if ((r = run_graph(c, st, launch_all))) return r;
     }
     HIP_TRY(c, hipGetLastError());
     if (out->cap_packets < n_slots * mp) {
@@ -534,6 +608,10 @@ lts_status lts_context_create(int device, const lts_physics *physics, const lts_
 void lts_context_destroy(lts_context *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
+    if (c->glaunched) (void)hipEventSynchronize(c->gdone);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->gdone) (void)hipEventDestroy(c->gdone);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto &pe : c->pending_ev) {
         (void)hipEventDestroy(pe.second.first);
         (void)hipEventDestroy(pe.second.second);
@@ -603,6 +681,20 @@ lts_status lts_set_matrix_cores(lts_context *c, int32_t on) {
     if (!c) return LTS_ERR_INVALID_ARG;
     if (on != 0 && on != 1) return fail(c, LTS_ERR_INVALID_ARG, "matrix cores must be 0 or 1");
     c->matrix_cores = on;
+    return LTS_OK;
+}
+
+lts_status lts_set_graph(lts_context *c, int32_t on) {
+    if (!c) return LTS_ERR_INVALID_ARG;
+    if (on != 0 && on != 1) return fail(c, LTS_ERR_INVALID_ARG, "graph must be 0 or 1");
+    c->use_graph = on != 0;
+    return LTS_OK;
+}
+
+lts_status lts_graph_stats(lts_context *c, int64_t *updates, int64_t *instantiations) {
+    if (!c || !updates || !instantiations) return LTS_ERR_INVALID_ARG;
+    *updates = c->graph_updates;
+    *instantiations = c->graph_instantiations;
     return LTS_OK;
 }
 

@@ -77,7 +77,7 @@ STAGES = ("quench_drift", "rasterize", "cells", "induce", "electronics")
 
 EXPORTS = ("lts_server_start", "lts_server_submit", "lts_server_poll", "lts_server_wait", "lts_server_release",
            "lts_server_stop", "lts_set_timing", "lts_get_timing", "lts_work_stats", "lts_context_create", "lts_context_destroy",
-           "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_set_ticks_per_thread", "lts_set_lane_exchange", "lts_set_matrix_cores", "lts_set_channel_mask",
+           "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_set_ticks_per_thread", "lts_set_lane_exchange", "lts_set_matrix_cores", "lts_set_graph", "lts_graph_stats", "lts_set_channel_mask",
            "lts_plan", "lts_simulate", "lts_simulate_batch", "lts_stage_quench_drift", "lts_debug_cells",
            "lts_stage_electronics", "lts_stage_philox", "lts_stage_rasterize", "lts_stage_induce", "lts_stage_reduce", "lts_status_str", "lts_last_error", "lts_version",
            "lts_light_create", "lts_light_destroy", "lts_light_simulate", "lts_light_set_graph", "lts_light_last_error")
@@ -110,6 +110,8 @@ def lib():
         L.lts_set_ticks_per_thread.argtypes = [P, C.c_int32]
         L.lts_set_lane_exchange.argtypes = [P, C.c_int32]
         L.lts_set_matrix_cores.argtypes = [P, C.c_int32]
+        L.lts_set_graph.argtypes = [P, C.c_int32]
+        L.lts_graph_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lts_set_channel_mask.argtypes = [P, P, C.c_int64]
         L.lts_plan.argtypes = [P, C.POINTER(lts_segments), C.POINTER(C.c_int64), P]
         L.lts_simulate.argtypes = [P, C.c_uint64, C.POINTER(lts_segments), C.POINTER(lts_outputs), P]
@@ -277,6 +279,16 @@ class Context:
 
     def set_reduce_mode(self, mode: int):
         self._check(lib().lts_set_reduce_mode(self._h, mode))
+
+    def set_graph(self, on: bool):
+        """Replay each call's launch sequence after the sizing read-back as one HIP graph (lts_set_graph)."""
+        self._check(lib().lts_set_graph(self._h, int(bool(on))))
+
+    def graph_stats(self):
+        """(in-place updates, instantiations) of the context's executable graph."""
+        u, i = C.c_int64(0), C.c_int64(0)
+        self._check(lib().lts_graph_stats(self._h, C.byref(u), C.byref(i)))
+        return int(u.value), int(i.value)
 
     def close(self):
         if self._h:

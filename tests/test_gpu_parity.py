@@ -448,6 +448,46 @@ def test_batch_equals_single_events(lt, torch, mode):
         np.testing.assert_allclose(b["report"][e], s["report"][0], rtol=1e-12, atol=1e-9)
 
 
+def test_graph_replay_equals_direct_launches(lt, torch):
+    """Calls replayed as HIP graphs (updated in place between events of different sizes, re-instantiated when the
+    launch structure changes) give the same results as direct launches, with the program's own GPU work and
+    synchronisations between the calls."""
+    w = W.make_workload(1, n_events=4)
+    for e in range(4):
+        w.events[e] = w.events[e].shifted(dt=0.7 * e)
+    direct = lt.Context.from_workload(w)
+    graph = lt.Context.from_workload(w)
+    graph.set_graph(True)
+    dev = [lt.to_device(x) for x in w.events]
+    ref = [direct.simulate(d, event_id=i).host() for d, i in zip(dev, w.event_ids)]
+    scratch = torch.zeros(1 << 20, device="cuda")
+    for rep in range(3):
+        for d, i, r in zip(dev, w.event_ids, ref):
+            g = graph.simulate(d, event_id=i).host()
+            scratch.add_(1.0)
+            torch.cuda.synchronize()
+            for k in ("pixel_id", "current", "pkt_pixel", "pkt_tick", "pkt_adc", "pkt_flags", "counts"):
+                assert np.array_equal(g[k], r[k]), (rep, k)
+            np.testing.assert_allclose(g["report"], r["report"], rtol=1e-12, atol=1e-9)
+    upd, inst = graph.graph_stats()
+    print(f"graph: {upd} in-place updates, {inst} instantiations over 12 calls")
+    assert upd + inst == 12                                  # every call ran as a graph
+    allsegs = W.Segments.concat(w.events)
+    offs = np.r_[0, np.cumsum([x.n for x in w.events])]
+    bd = direct.simulate_batch(lt.to_device(allsegs), offs, w.event_ids).host()
+    bg = graph.simulate_batch(lt.to_device(allsegs), offs, w.event_ids).host()
+    for k in ("pixel_id", "current", "pkt_tick", "pkt_adc", "event_pixel_offsets", "event_packet_offsets"):
+        assert np.array_equal(bd[k], bg[k]), k
+    assert graph.graph_stats()[1] == inst + 1                # the batch's extra offsets kernel: a new instance
+    for mode in (1, 2):                                      # atomic (graph), summed (direct launches)
+        direct.set_reduce_mode(mode)
+        graph.set_reduce_mode(mode)
+        a = direct.simulate(dev[0], event_id=w.event_ids[0]).host()
+        b = graph.simulate(dev[0], event_id=w.event_ids[0]).host()
+        assert np.array_equal(a["pixel_id"], b["pixel_id"])
+        np.testing.assert_allclose(b["current"], a["current"], rtol=1e-5, atol=1e-3)
+
+
 # ----------------------------------------------------------------------------------------------- serving
 
 def test_served_results_equal_alone(lt, torch):
