@@ -202,7 +202,8 @@ lts_status lts_set_matrix_cores(lts_context *ctx, int32_t on);
  * launched as one graph on the call's stream; the context keeps one executable graph and updates it in place when
  * the next call has the same launch structure (else instantiates a new one), only after the previous launch has
  * finished.  Results are identical to 0 (default: direct launches).  Ignored in LTS_REDUCE_SUMMED mode, which reads
- * sizes back in the middle of the call.  Stage timing (lts_set_timing) records nothing for graph-launched calls. */
+ * sizes back in the middle of the call; the server's lanes always launch directly.  Stage timing (lts_set_timing)
+ * records nothing for graph-launched calls. */
 lts_status lts_set_graph(lts_context *ctx, int32_t on);
 /* Number of in-place updates and of instantiations of the context's executable graph so far (host pointers). */
 lts_status lts_graph_stats(lts_context *ctx, int64_t *updates, int64_t *instantiations);
