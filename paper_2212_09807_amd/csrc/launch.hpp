@@ -68,7 +68,7 @@ struct SumWork {
     float *S = nullptr;                      // [n_s] summed charge per column piece (padded to kAC)
     int64_t *list_off = nullptr;             // [n_slots + 1] pieces in reach per active pixel, then offsets
     int32_t *list = nullptr;                 // [n_list] piece ids per active pixel, in column order
-    PieceRef *rec = nullptr;                 // [n_list + 1] the same pieces as records (one spare entry at the end)
+    PieceRef *rec = nullptr;                 // [n_list] the same pieces as records
 };
 constexpr int32_t kPieceTicks = kPieceMax;   // ticks per column piece (a multiple of kAC, <= kNaMax)
 static_assert(kPieceTicks % kAC == 0 && kPieceTicks <= kNaMax, "piece length");

@@ -388,9 +388,8 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
         return fail(c, LTS_ERR_DEVICE, "summed induction: column pieces exceed their bound");
     if ((r = ensure(c, c->list, sizeof(int32_t) * (size_t)std::max<int64_t>(tot[0], 1)))) return r;
     sw.list = as<int32_t>(c->list);
-    if ((r = ensure(c, c->rec, sizeof(PieceRef) * (size_t)(tot[0] + 1)))) return r;
+    if ((r = ensure(c, c->rec, sizeof(PieceRef) * (size_t)std::max<int64_t>(tot[0], 1)))) return r;
     sw.rec = as<PieceRef>(c->rec);
-    HIP_TRY(c, hipMemsetAsync(sw.rec + tot[0], 0, sizeof(PieceRef), st));   // the spare entry read one ahead
     launch_sum_lists_fill(P, w, sw, n_slots, tot[0], st);
     Table T{as<float>(c->Rpad), as<double>(c->prefix)};
     launch_induce_summed(P, w, sw, T, wave, n_slots, c->ticks_per_thread, c->lane_exchange != 0, st);
