@@ -290,6 +290,33 @@ def test_cfg2_full_size_sampled_pixels(lt, orc, torch, mode, matrix):
     assert not bad
 
 
+@pytest.mark.parametrize("mode", [0, 2])
+def test_large_spill_tile_sampled_pixels(lt, orc, torch, mode):
+    """One tile of the large spill (halo replicas included, 5000 ticks, full reset/discriminator/sample noise), in
+    the launch configuration of the large-spill benchmark; the oracle recomputes a sample of pixels one by one."""
+    w = W.make_workload(5)
+    ev = sorted(range(len(w.events)), key=lambda i: w.events[i].n)[2]        # a cosmic-dominated tile, ~14k segments
+    ctx, h = run_gpu(lt, w, ev=ev, mode=mode)
+    gpix, cur = h["pixel_id"], h["current"]
+    tot = np.abs(cur).sum(axis=1)
+    rng = np.random.default_rng(5)
+    pick = np.unique(np.r_[np.argsort(tot)[-3:], rng.choice(len(gpix), 3, replace=False)])
+    o_wave, _ = orc.waveforms(w.physics, w.readout, W.response_table(w.table, w.readout, w.physics.v_drift),
+                              w.events[ev], gpix[pick])
+    e = per_pixel_errors(cur[pick].astype(np.float64), o_wave)
+    print(f"large-spill tile {ev} ({w.events[ev].n} segments) sampled e_p:", e)
+    assert e.max() <= TOL_WAVE
+    qd = orc.quench_drift(w.physics, w.events[ev])
+    rep = h["report"][0]
+    assert rep[1] == pytest.approx(qd["q_a"].sum(), rel=2e-6)
+    assert rep[2] + rep[3] + rep[4] == pytest.approx(rep[1], rel=2e-5)
+    pk, _, uf = orc.electronics(w.electronics, w.readout, w.event_ids[ev], gpix[pick], o_wave, EPS_REL, EPS_ABS,
+                                with_uncertain=True)
+    cmp_, flg, bad = compare_packets(h, gpix[pick], pk, uf)
+    print(f"large-spill tile packets: compared {cmp_} flagged {flg}")
+    assert not bad and cmp_ > 0
+
+
 def test_sorted_and_atomic_agree(lt, torch):
     w = W.make_workload(1)
     _, a = run_gpu(lt, w, mode=0)
