@@ -285,6 +285,42 @@ def served(ltsim, W, rate_hz, n_events, mode, lanes=2):
             "mean_batch_events": float(np.mean([r["batch_events"] for r in res])), "lanes": lanes}
 
 
+def served_burst(ltsim, W, n_events, mode, lanes=2):
+    """n_events single-track events (200 segments each) submitted to the request loop at once, host segments in:
+    completed events/s and latency, against the same events as plain calls (device-resident segments, one
+    lts_simulate and synchronisation each)."""
+    import numpy as np
+    import torch
+    w = W.make_workload(1, n_events=n_events)
+    ctx = ltsim.Context.from_workload(w, reduce_mode=mode)
+    singles = [ltsim.to_device(e) for e in w.events]
+    for d, i in zip(singles[:4], w.event_ids):                      # warm-up
+        ctx.simulate(d, event_id=i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d, i in zip(singles, w.event_ids):
+        ctx.simulate(d, event_id=i)
+        torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    srv = ltsim.Server(ctx, n_lanes=lanes, max_batch_events=64)
+    try:
+        for _ in range(2):                                            # the second burst is timed
+            t0 = time.perf_counter()
+            tickets = [srv.submit(seg, eid) for seg, eid in zip(w.events, w.event_ids)]
+            res = [srv.wait(t) for t in tickets]
+            t1 = time.perf_counter()
+            for t in tickets:
+                srv.release(t)
+    finally:
+        srv.stop()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+    return {"workload": "single-track events, 200 segments, submitted at once", "events": n_events,
+            "events_per_s": n_events / (t1 - t0), "plain_events_per_s": n_events / t_plain,
+            "gain": t_plain / (t1 - t0), "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                                                         "p99": float(np.percentile(lat, 99) * 1e3)},
+            "mean_batch_events": float(np.mean([r["batch_events"] for r in res])), "lanes": lanes}
+
+
 # name: (reduce mode, lane exchange, ticks per thread)
 MODES = {"sorted": (0, 0, 0), "atomic": (1, 0, 0), "summed": (2, 0, 0), "sorted-shift": (0, 1, 0),
          "sorted-noprefetch": (0, 0, 8), "sorted-mfma": (0, 0, 0)}
@@ -439,6 +475,7 @@ def main():
         line["large_spill"] = large_spill_leg(ltsim, W, [m for m in args.large_spill.split(",") if m])
     if args.served:
         line["served"] = served(ltsim, W, args.served[0], int(args.served[1]), mode)
+        line["served_small"] = served_burst(ltsim, W, 64, mode)
     if args.served_sweep:
         line["served_sweep"] = [served(ltsim, W, float(r), 16, mode) for r in args.served_sweep.split(",") if r]
     if not args.no_cpu_baseline:

@@ -1152,6 +1152,25 @@ void lane_run_batch(Lane *L, std::vector<Request *> &batch) {
             hipStreamSynchronize(L->stream) != hipSuccess)
             st = LTS_ERR_DEVICE;
     }
+    // the whole batch's pixels and packets in one copy per array, then cut per event on the host
+    const int64_t np_all = st == LTS_OK ? evpix[ne] : 0, nk_all = st == LTS_OK ? evpkt[ne] : 0;
+    std::vector<int32_t> h_pix(np_all), h_pkp(nk_all), h_pkt(nk_all);
+    std::vector<uint16_t> h_pka(nk_all);
+    std::vector<uint8_t> h_pkf(nk_all);
+    std::vector<float> h_cur(S->cfg.return_currents ? (size_t)np_all * S->n_ticks : 0);
+    if (st == LTS_OK) {
+        bool ok = true;
+        auto get = [&](void *dst, const void *src, size_t bytes) {
+            if (ok && bytes) ok = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, L->stream) == hipSuccess;
+        };
+        get(h_pix.data(), L->pix.p, sizeof(int32_t) * (size_t)np_all);
+        get(h_pkp.data(), L->pkp.p, sizeof(int32_t) * (size_t)nk_all);
+        get(h_pkt.data(), L->pkt.p, sizeof(int32_t) * (size_t)nk_all);
+        get(h_pka.data(), L->pka.p, sizeof(uint16_t) * (size_t)nk_all);
+        get(h_pkf.data(), L->pkf.p, sizeof(uint8_t) * (size_t)nk_all);
+        get(h_cur.data(), L->cur.p, sizeof(float) * h_cur.size());
+        if (!ok || hipStreamSynchronize(L->stream) != hipSuccess) st = LTS_ERR_DEVICE;
+    }
     for (int32_t e = 0; e < ne; ++e) {
         Finished *f = new Finished();
         fin[e] = f;
@@ -1166,17 +1185,13 @@ void lane_run_batch(Lane *L, std::vector<Request *> &batch) {
             f->pkt_tick.resize(k1 - k0);
             f->pkt_adc.resize(k1 - k0);
             f->pkt_flags.resize(k1 - k0);
-            bool ok = hipMemcpy(f->pixel_id.data(), (int32_t *)L->pix.p + p0, sizeof(int32_t) * (p1 - p0), hipMemcpyDeviceToHost) == hipSuccess &&
-                      hipMemcpy(f->pkt_pixel.data(), (int32_t *)L->pkp.p + k0, sizeof(int32_t) * (k1 - k0), hipMemcpyDeviceToHost) == hipSuccess &&
-                      hipMemcpy(f->pkt_tick.data(), (int32_t *)L->pkt.p + k0, sizeof(int32_t) * (k1 - k0), hipMemcpyDeviceToHost) == hipSuccess &&
-                      hipMemcpy(f->pkt_adc.data(), (uint16_t *)L->pka.p + k0, sizeof(uint16_t) * (k1 - k0), hipMemcpyDeviceToHost) == hipSuccess &&
-                      hipMemcpy(f->pkt_flags.data(), (uint8_t *)L->pkf.p + k0, sizeof(uint8_t) * (k1 - k0), hipMemcpyDeviceToHost) == hipSuccess;
-            if (ok && S->cfg.return_currents) {
-                f->current.resize((size_t)(p1 - p0) * S->n_ticks);
-                ok = hipMemcpy(f->current.data(), (float *)L->cur.p + (size_t)p0 * S->n_ticks,
-                               sizeof(float) * f->current.size(), hipMemcpyDeviceToHost) == hipSuccess;
-            }
-            if (!ok) st = LTS_ERR_DEVICE;
+            std::copy(h_pix.begin() + p0, h_pix.begin() + p1, f->pixel_id.begin());
+            std::copy(h_pkp.begin() + k0, h_pkp.begin() + k1, f->pkt_pixel.begin());
+            std::copy(h_pkt.begin() + k0, h_pkt.begin() + k1, f->pkt_tick.begin());
+            std::copy(h_pka.begin() + k0, h_pka.begin() + k1, f->pkt_adc.begin());
+            std::copy(h_pkf.begin() + k0, h_pkf.begin() + k1, f->pkt_flags.begin());
+            if (S->cfg.return_currents)
+                f->current.assign(h_cur.begin() + (size_t)p0 * S->n_ticks, h_cur.begin() + (size_t)p1 * S->n_ticks);
             f->v.n_pixels = p1 - p0;
             f->v.n_packets = k1 - k0;
             for (int k = 0; k < 5; ++k) f->v.report[k] = rep[5 * (size_t)e + k];
