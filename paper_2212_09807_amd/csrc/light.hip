@@ -32,44 +32,76 @@ constexpr uint32_t kStreamLightPe = 12u, kStreamLightNoise = 13u;
 typedef const double __attribute__((address_space(4))) *cdouble_ptr;
 typedef const float __attribute__((address_space(4))) *cfloat4_ptr;
 
-// mu for 8 consecutive ticks per thread; xp is the photocurrent row with Kp = 8 nkb + 8 zeros in front (index
-// Kp + t), w the kernel padded with zeros to nkb * 8 taps.  Window of block kb: xp[Kp + t0 - 8kb - 7 .. Kp + t0 -
-// 8kb + 7]; past the row end it reads the next row's zeros (the buffer has 8 floats of slack after the last row),
-// which only reach ticks >= T that are not stored.
-__global__ __launch_bounds__(kLWG) void k_light_scint(const float *__restrict__ xp, int32_t Kp, int32_t T,
+// mu for 8 consecutive ticks per lane; xp holds one row per detector with stride Ks (a multiple of 8 floats): Kp =
+// 8 nkb + 8 zeros in front, the photocurrent at Kp + t, zeros up to the stride.  w is the kernel padded with zeros
+// to nkb * 8 taps.  A workgroup covers 512 ticks of one detector; its four wavefronts take a quarter of the tap
+// blocks each, and their partial sums are added in wavefront order through LDS (fixed order: deterministic).  Tap
+// block kb needs x[t0 - 8kb - 7 .. t0 - 8kb + 7]: its 8-value half b_kb = x[t0 - 8kb .. +7] and the upper seven
+// values of b_{kb+1}, so the blocks go in ping-pong through two 8-value register sets, each half loaded (two aligned
+// 16-byte loads) and converted to FP64 once.  Reads past a row's end see its zero tail or the next row's zeros and
+// only reach ticks >= T, which are not stored.
+constexpr int kLScintTicks = 64 * kLRT;   // ticks per workgroup of the scintillation sum
+
+__global__ __launch_bounds__(kLWG) void k_light_scint(const float *__restrict__ xp, int32_t Kp, int32_t Ks, int32_t T,
                                                       const double *__restrict__ w, int32_t nkb, double *__restrict__ mu) {
+    __shared__ double part[kLWG / 64 - 1][64][kLRT + 1];
     const int32_t d = blockIdx.y;
-    const int32_t t0 = blockIdx.x * kLTile + threadIdx.x * kLRT;
-    if (t0 >= T) return;
-    const float *x = xp + (int64_t)d * (Kp + T) + Kp + t0 - 7;
+    const int lane = threadIdx.x & 63;
+    const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+    const int32_t t0 = blockIdx.x * kLScintTicks + lane * kLRT;
+    const float *x = xp + (int64_t)d * Ks + Kp + t0;
     cdouble_ptr wc = (cdouble_ptr)w;
+    auto load = [](const float *p, double (&v)[8]) {
+        const float4 lo = *(const float4 *)p, hi = *(const float4 *)(p + 4);
+        v[0] = lo.x; v[1] = lo.y; v[2] = lo.z; v[3] = lo.w; v[4] = hi.x; v[5] = hi.y; v[6] = hi.z; v[7] = hi.w;
+    };
     double acc[kLRT];
 #pragma unroll
     for (int r = 0; r < kLRT; ++r) acc[r] = 0.0;
-    for (int32_t kb = 0; kb < nkb; ++kb) {
-        double win[kLRT + 7];
-#pragma unroll
-        for (int m = 0; m < kLRT + 7; ++m) win[m] = (double)x[m - 8 * kb];
+    // acc[r] += w[8kb + q] * x[t0 + r - q - 8kb]: from b_kb when r >= q, else from b_{kb+1}
+    auto block = [&](int32_t kb, const double (&B)[8], const double (&N)[8]) {
         double wk[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) wk[q] = wc[8 * kb + q];
-        // acc[r] += w[8kb + q] * x[t0 + r - 8kb - q] = wk[q] * win[r - q + 7]
 #pragma unroll
         for (int q = 0; q < 8; ++q)
 #pragma unroll
-            for (int r = 0; r < kLRT; ++r) acc[r] = fma(wk[q], win[r - q + 7], acc[r]);
+            for (int r = 0; r < kLRT; ++r) acc[r] = fma(wk[q], r >= q ? B[r - q] : N[8 + r - q], acc[r]);
+    };
+    const int32_t nq = (nkb + 3) / 4, kb0 = wv * nq, kb1 = min(kb0 + nq, nkb);
+    if (t0 < T && kb0 < kb1) {
+        double X[8], Y[8];
+        load(x - 8 * kb0, X);
+        for (int32_t kb = kb0; kb < kb1; kb += 2) {
+            load(x - 8 * (kb + 1), Y);
+            block(kb, X, Y);
+            if (kb + 1 >= kb1) break;
+            load(x - 8 * (kb + 2), X);
+            block(kb + 1, Y, X);
+        }
     }
-    double *o = mu + (int64_t)d * T + t0;
+    if (wv > 0)
 #pragma unroll
-    for (int r = 0; r < kLRT; ++r)
-        if (t0 + r < T) o[r] = acc[r];
+        for (int r = 0; r < kLRT; ++r) part[wv - 1][lane][r] = acc[r];
+    __syncthreads();
+    if (wv == 0 && t0 < T) {
+#pragma unroll
+        for (int k = 0; k < kLWG / 64 - 1; ++k)
+#pragma unroll
+            for (int r = 0; r < kLRT; ++r) acc[r] += part[k][lane][r];
+        double *o = mu + (int64_t)d * T + t0;
+#pragma unroll
+        for (int r = 0; r < kLRT; ++r)
+            if (t0 + r < T) o[r] = acc[r];
+    }
 }
 
-__global__ void k_light_pad(const float *__restrict__ ipe, float *__restrict__ xp, int32_t Kp, int32_t T, int32_t n_det) {
+__global__ void k_light_pad(const float *__restrict__ ipe, float *__restrict__ xp, int32_t Kp, int32_t Ks, int32_t T,
+                            int32_t n_det) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)n_det * T) return;
     const int64_t d = i / T, t = i - d * T;
-    xp[d * (Kp + T) + Kp + t] = ipe[i];
+    xp[d * Ks + Kp + t] = ipe[i];
 }
 
 // Photoelectron statistics; writes pe (FP64) and the FP32 copy with Rp zeros in front for the response sum.
@@ -197,29 +229,35 @@ __global__ __launch_bounds__(kLWG) void k_light_response(const float *__restrict
         if (t0 + j < T) o[j] = fmaf(gain, acc[j], nz[j]);
 }
 
-// One workgroup per detector group.  First every thread sums the group's waveforms (fixed detector order) for its
-// ticks and each wavefront's ballot records, per 64-tick chunk, which ticks reach the threshold (all chunks at once,
-// into LDS); then one thread scans the chunk masks in time order: the first set bit at or after the end of the dead
-// time triggers, and the dead time restarts from it.
-__global__ __launch_bounds__(256) void k_light_trigger(const float *__restrict__ V, int32_t T, int32_t group, float thr,
-                                                       int32_t dead, int32_t max_trig, int32_t *__restrict__ trig,
-                                                       int32_t *__restrict__ count) {
-    extern __shared__ uint64_t masks[];
+// Triggers per detector group, in two kernels.  k_light_trigger_masks: one thread per (group, tick) sums the
+// group's waveforms (fixed detector order), and each wavefront's ballot is the mask of that 64-tick chunk's ticks
+// that reach the threshold.  k_light_trigger_scan: one workgroup per group stages the group's chunk masks in LDS,
+// then one thread scans them in time order: the first set bit at or after the end of the dead time triggers, and
+// the dead time restarts from it.
+__global__ __launch_bounds__(256) void k_light_trigger_masks(const float *__restrict__ V, int32_t T, int32_t group,
+                                                             float thr, uint64_t *__restrict__ masks) {
+    const int32_t g = blockIdx.y;
+    const int32_t nch = (T + 63) / 64;
+    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+    float s = 0.0f;
+    if (t < T)
+        for (int32_t k = 0; k < group; ++k) s += V[(int64_t)(g * group + k) * T + t];
+    const uint64_t m = __ballot(t < T && s >= thr);
+    if ((threadIdx.x & 63) == 0 && t / 64 < nch) masks[(int64_t)g * nch + t / 64] = m;
+}
+
+__global__ __launch_bounds__(256) void k_light_trigger_scan(const uint64_t *__restrict__ masks, int32_t T,
+                                                            int32_t dead, int32_t max_trig, int32_t *__restrict__ trig,
+                                                            int32_t *__restrict__ count) {
+    extern __shared__ uint64_t mk[];
     const int32_t g = blockIdx.x;
     const int32_t nch = (T + 63) / 64;
-    for (int32_t base = 0; base < nch * 64; base += blockDim.x) {
-        const int32_t t = base + threadIdx.x;
-        float s = 0.0f;
-        if (t < T)
-            for (int32_t k = 0; k < group; ++k) s += V[(int64_t)(g * group + k) * T + t];
-        const uint64_t m = __ballot(t < T && s >= thr);
-        if ((threadIdx.x & 63) == 0 && t / 64 < nch) masks[t / 64] = m;
-    }
+    for (int32_t c = threadIdx.x; c < nch; c += blockDim.x) mk[c] = masks[(int64_t)g * nch + c];
     __syncthreads();
     if (threadIdx.x != 0) return;
     int32_t ready = 0, n = 0;
     for (int32_t c = 0; c < nch && n < max_trig; ++c) {
-        uint64_t m = masks[c];
+        uint64_t m = mk[c];
         for (;;) {
             const int32_t off = ready - 64 * c;                  // ticks of this chunk still in the dead time
             if (off >= 64) break;
@@ -249,13 +287,14 @@ using namespace ltsim;
 struct lts_light {
     lts_light_params p{};
     int device = 0;
-    int32_t K = 0, nkb = 0, Kp = 0, R = 0, nrb = 0, Rp = 0, F = 0;
+    int32_t K = 0, nkb = 0, Kp = 0, Ks = 0, R = 0, nrb = 0, Rp = 0, F = 0;
     uint32_t k0 = 0, k1 = 0;
     bool sticky = false;
     std::string err;
     DBuf<double> w, mu, pe;
     DBuf<float> xp, pef, r, amp, Ct, St;
     DBuf<float2> coef;
+    DBuf<uint64_t> tmask;                            // trigger chunk masks [group][64-tick chunk]
     DBuf<float> nz;                                  // noise by FFT (when fft_log2 > 0)
     int32_t fft_log2 = 0;
     // replay through a HIP graph: captured once per set of caller buffers, the event id set per call in the two
@@ -298,9 +337,9 @@ void launch_light(lts_light *L, uint64_t event_id, const float *ipe, double *mu_
     const int32_t T = q.n_ticks, nd = q.n_det;
     const int64_t n = (int64_t)nd * T;
     const unsigned g1 = (unsigned)((n + 255) / 256);
-    k_light_pad<<<g1, 256, 0, st>>>(ipe, L->xp.p, L->Kp, T, nd);
-    const dim3 gt((unsigned)((T + kLTile - 1) / kLTile), (unsigned)nd);
-    k_light_scint<<<gt, kLWG, 0, st>>>(L->xp.p, L->Kp, T, L->w.p, L->nkb, mu_d);
+    k_light_pad<<<g1, 256, 0, st>>>(ipe, L->xp.p, L->Kp, L->Ks, T, nd);
+    const dim3 gt((unsigned)((T + kLScintTicks - 1) / kLScintTicks), (unsigned)nd);
+    k_light_scint<<<gt, kLWG, 0, st>>>(L->xp.p, L->Kp, L->Ks, T, L->w.p, L->nkb, mu_d);
     k_light_fluct<<<g1, 256, 0, st>>>(mu_d, pe_d, L->pef.p, L->Rp, T, nd, event_id, L->k0, L->k1, q.normal_above);
     if (L->F > 0) {
         const int64_t nc = (int64_t)nd * L->F;
@@ -313,13 +352,16 @@ void launch_light(lts_light *L, uint64_t event_id, const float *ipe, double *mu_
                                                                                 L->Ct.p, L->St.p, L->nz.p);
         nzpre = L->nz.p;
     }
-    k_light_response<<<gt, kLWG, 0, st>>>(L->pef.p, L->Rp, T, L->r.p, L->nrb, (float)q.gain, L->coef.p, L->F,
+    const dim3 gr((unsigned)((T + kLTile - 1) / kLTile), (unsigned)nd);
+    k_light_response<<<gr, kLWG, 0, st>>>(L->pef.p, L->Rp, T, L->r.p, L->nrb, (float)q.gain, L->coef.p, L->F,
                                          L->Ct.p, L->St.p, nzpre, V);
     if (trig) {
         const int32_t ng = nd / q.group;
+        const dim3 gm((unsigned)((T + 255) / 256), (unsigned)ng);
+        k_light_trigger_masks<<<gm, 256, 0, st>>>(V, T, q.group, (float)q.trig_threshold, L->tmask.p);
         const size_t lds = sizeof(uint64_t) * (size_t)((T + 63) / 64);
-        k_light_trigger<<<(unsigned)ng, 256, lds, st>>>(V, T, q.group, (float)q.trig_threshold, q.trig_deadtime,
-                                                       q.max_trig, trig, trig_count);
+        k_light_trigger_scan<<<(unsigned)ng, 256, lds, st>>>(L->tmask.p, T, q.trig_deadtime, q.max_trig, trig,
+                                                             trig_count);
     }
 }
 
@@ -417,6 +459,7 @@ lts_status lts_light_create(int device, const lts_light_params *p, const float *
     L->K = (int32_t)kd;
     L->nkb = (L->K + 7) / 8;
     L->Kp = 8 * L->nkb + 8;
+    L->Ks = L->Kp + (q.n_ticks + 7) / 8 * 8;              // row stride: rows start 32-byte aligned
     L->R = n_resp;
     L->nrb = (n_resp + 7) / 8;
     L->Rp = 8 * L->nrb + 8;
@@ -450,15 +493,16 @@ lts_status lts_light_create(int device, const lts_light_params *p, const float *
         return e == hipSuccess;
     };
     ok(L->w.alloc(w.size())) && ok(L->mu.alloc(nd * T)) && ok(L->pe.alloc(nd * T)) &&
-        ok(L->xp.alloc(nd * (L->Kp + T) + 8)) && ok(L->pef.alloc(nd * (L->Rp + T) + 8)) && ok(L->r.alloc(r.size())) &&
+        ok(L->xp.alloc(nd * L->Ks + 16)) && ok(L->pef.alloc(nd * (L->Rp + T) + 8)) && ok(L->r.alloc(r.size())) &&
         ok(L->amp.alloc(std::max(n_freq, 1))) && ok(L->Ct.alloc(T)) && ok(L->St.alloc(T)) &&
         ok(L->coef.alloc(nd * std::max(n_freq, 1))) &&
+        ok(L->tmask.alloc(nd / std::max(q.group, 1) * ((T + 63) / 64))) &&
         ok(hipMemcpy(L->w.p, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice)) &&
         ok(hipMemcpy(L->r.p, r.data(), sizeof(float) * r.size(), hipMemcpyHostToDevice)) &&
         (n_freq == 0 || ok(hipMemcpy(L->amp.p, noise_amp, sizeof(float) * n_freq, hipMemcpyHostToDevice))) &&
         ok(hipMemcpy(L->Ct.p, C.data(), sizeof(float) * T, hipMemcpyHostToDevice)) &&
         ok(hipMemcpy(L->St.p, S.data(), sizeof(float) * T, hipMemcpyHostToDevice)) &&
-        ok(hipMemset(L->xp.p, 0, sizeof(float) * (nd * (L->Kp + T) + 8))) &&
+        ok(hipMemset(L->xp.p, 0, sizeof(float) * (nd * L->Ks + 16))) &&
         ok(hipMemset(L->pef.p, 0, sizeof(float) * (nd * (L->Rp + T) + 8))) && ok(hipDeviceSynchronize());
     // power-of-two windows up to 16384 ticks take the FFT noise path if the device grants the LDS it needs
     if (st == LTS_OK && n_freq > 0 && T >= 2 && (T & (T - 1)) == 0 && T * sizeof(float2) <= 131072) {
