@@ -145,27 +145,42 @@ __global__ void k_light_noise_coef(const float *__restrict__ amp, int32_t F, int
     coef[i] = make_float2((float)(amp[f - 1] * cos(phi)), (float)(amp[f - 1] * sin(phi)));
 }
 
-// Noise by FFT (power-of-two windows whose complex spectrum fits in LDS): noise[t] is the real part of
-// y[t] = sum_{f=1}^{F} A_f e^{i phi_f} e^{2 pi i f t / T}, an unnormalised inverse DFT of the one-sided spectrum,
-// computed in place by iterative radix-2 decimation in time (bit-reversed load, log2 T butterfly stages with
-// twiddles e^{2 pi i j / len} read from the cosine / sine tables at index j T / len).  One workgroup per detector.
+// Noise by FFT (power-of-two windows, T >= 4, whose complex spectrum and a quarter-period cosine table fit in LDS):
+// noise[t] is the real part of y[t] = sum_{f=1}^{F} A_f e^{i phi_f} e^{2 pi i f t / T}, an unnormalised inverse DFT of
+// the one-sided spectrum, computed in place by iterative radix-2 decimation in time (bit-reversed load, log2 T
+// butterfly stages).  The twiddles e^{2 pi i m / T}, m < T/2, come from cos(2 pi m / T) for m <= T/4 staged in LDS:
+// sin(2 pi m / T) = cos(2 pi (T/4 - m) / T), and past a quarter period cos and sin follow from the quarter shift.
+// One workgroup per detector.
+inline size_t noise_fft_lds(size_t T) { return sizeof(float2) * T + sizeof(float) * (T / 4 + 1); }
+
 __global__ __launch_bounds__(1024) void k_light_noise_fft(const float2 *__restrict__ coef, int32_t F, int32_t T,
                                                           int32_t log2T, const float *__restrict__ Ct,
-                                                          const float *__restrict__ St, float *__restrict__ nz) {
+                                                          float *__restrict__ nz) {
     extern __shared__ float2 xs[];
+    float *qc = (float *)(xs + T);
     const int32_t d = blockIdx.x;
+    const int32_t Q = T >> 2;
     const float2 *cf = coef + (int64_t)d * F;
     for (int32_t i = threadIdx.x; i < T; i += blockDim.x) {
         const float2 y = (i >= 1 && i <= F) ? cf[i - 1] : make_float2(0.0f, 0.0f);
         xs[__builtin_bitreverse32((uint32_t)i) >> (32 - log2T)] = y;
     }
+    for (int32_t m = threadIdx.x; m <= Q; m += blockDim.x) qc[m] = Ct[m];
     __syncthreads();
     for (int32_t half = 1; half < T; half <<= 1) {
-        const int32_t stride = T / (2 * half);                    // twiddle table step for this stage
+        const int32_t stride = T / (2 * half);                    // twiddle index step for this stage
         for (int32_t k = threadIdx.x; k < T / 2; k += blockDim.x) {
             const int32_t j = k & (half - 1);
             const int32_t i0 = ((k - j) << 1) + j, i1 = i0 + half;
-            const float wr = Ct[j * stride], wi = St[j * stride];
+            const int32_t m = j * stride;                         // < T / 2
+            float wr, wi;
+            if (m <= Q) {
+                wr = qc[m];
+                wi = qc[Q - m];
+            } else {
+                wr = -qc[T / 2 - m];
+                wi = qc[m - Q];
+            }
             const float2 a = xs[i0], b = xs[i1];
             const float tr = wr * b.x - wi * b.y, ti = fmaf(wr, b.y, wi * b.x);
             xs[i0] = make_float2(a.x + tr, a.y + ti);
@@ -348,8 +363,8 @@ void launch_light(lts_light *L, uint64_t event_id, const float *ipe, double *mu_
     }
     const float *nzpre = nullptr;
     if (L->F > 0 && L->fft_log2 > 0) {
-        k_light_noise_fft<<<(unsigned)nd, 1024, (size_t)T * sizeof(float2), st>>>(L->coef.p, L->F, T, L->fft_log2,
-                                                                                L->Ct.p, L->St.p, L->nz.p);
+        k_light_noise_fft<<<(unsigned)nd, 1024, noise_fft_lds((size_t)T), st>>>(L->coef.p, L->F, T, L->fft_log2,
+                                                                              L->Ct.p, L->nz.p);
         nzpre = L->nz.p;
     }
     const dim3 gr((unsigned)((T + kLTile - 1) / kLTile), (unsigned)nd);
@@ -505,9 +520,9 @@ lts_status lts_light_create(int device, const lts_light_params *p, const float *
         ok(hipMemset(L->xp.p, 0, sizeof(float) * (nd * L->Ks + 16))) &&
         ok(hipMemset(L->pef.p, 0, sizeof(float) * (nd * (L->Rp + T) + 8))) && ok(hipDeviceSynchronize());
     // power-of-two windows up to 16384 ticks take the FFT noise path if the device grants the LDS it needs
-    if (st == LTS_OK && n_freq > 0 && T >= 2 && (T & (T - 1)) == 0 && T * sizeof(float2) <= 131072) {
+    if (st == LTS_OK && n_freq > 0 && T >= 4 && (T & (T - 1)) == 0 && noise_fft_lds(T) <= 160 * 1024) {
         if (hipFuncSetAttribute((const void *)k_light_noise_fft, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(T * sizeof(float2))) == hipSuccess &&
+                                (int)noise_fft_lds(T)) == hipSuccess &&
             ok(L->nz.alloc(nd * T))) {
             int32_t lg = 0;
             while ((size_t)1 << lg < T) ++lg;
