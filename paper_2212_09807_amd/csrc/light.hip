@@ -247,8 +247,8 @@ __global__ __launch_bounds__(kLWG) void k_light_response(const float *__restrict
 // Triggers per detector group, in two kernels.  k_light_trigger_masks: one thread per (group, tick) sums the
 // group's waveforms (fixed detector order), and each wavefront's ballot is the mask of that 64-tick chunk's ticks
 // that reach the threshold.  k_light_trigger_scan: one workgroup per group stages the group's chunk masks in LDS,
-// then one thread scans them in time order: the first set bit at or after the end of the dead time triggers, and
-// the dead time restarts from it.
+// then one thread walks the non-empty ones in time order: the first set bit at or after the end of the dead time
+// triggers, and the dead time restarts from it.
 __global__ __launch_bounds__(256) void k_light_trigger_masks(const float *__restrict__ V, int32_t T, int32_t group,
                                                              float thr, uint64_t *__restrict__ masks) {
     const int32_t g = blockIdx.y;
@@ -269,20 +269,33 @@ __global__ __launch_bounds__(256) void k_light_trigger_scan(const uint64_t *__re
     const int32_t nch = (T + 63) / 64;
     for (int32_t c = threadIdx.x; c < nch; c += blockDim.x) mk[c] = masks[(int64_t)g * nch + c];
     __syncthreads();
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x >= 64) return;
+    // the first wavefront finds the chunks with any tick over threshold, 64 chunks per ballot; lane 0 walks only
+    // those, in time order
+    const int lane = threadIdx.x;
     int32_t ready = 0, n = 0;
-    for (int32_t c = 0; c < nch && n < max_trig; ++c) {
-        uint64_t m = mk[c];
-        for (;;) {
-            const int32_t off = ready - 64 * c;                  // ticks of this chunk still in the dead time
-            if (off >= 64) break;
-            if (off > 0) m &= ~((1ull << off) - 1ull);
-            if (m == 0 || n >= max_trig) break;
-            const int32_t tf = 64 * c + __builtin_ctzll(m);
-            trig[(int64_t)g * max_trig + n++] = tf;
-            ready = tf + dead;
+    for (int32_t c0 = 0; c0 < nch && n < max_trig; c0 += 64) {
+        uint64_t any = __ballot(c0 + lane < nch && mk[c0 + lane] != 0);
+        if (lane == 0) {
+            while (any && n < max_trig) {
+                const int32_t c = c0 + __builtin_ctzll(any);
+                any &= any - 1;
+                uint64_t m = mk[c];
+                for (;;) {
+                    const int32_t off = ready - 64 * c;          // ticks of this chunk still in the dead time
+                    if (off >= 64) break;
+                    if (off > 0) m &= ~((1ull << off) - 1ull);
+                    if (m == 0 || n >= max_trig) break;
+                    const int32_t tf = 64 * c + __builtin_ctzll(m);
+                    trig[(int64_t)g * max_trig + n++] = tf;
+                    ready = tf + dead;
+                }
+            }
         }
+        n = __shfl(n, 0);
+        ready = __shfl(ready, 0);
     }
+    if (lane != 0) return;
     for (int32_t i = n; i < max_trig; ++i) trig[(int64_t)g * max_trig + i] = -1;
     count[g] = n;
 }
