@@ -915,7 +915,8 @@ __global__ __launch_bounds__(kWG) void k_induce_sorted(DevParams P, const SegInf
                                                        const double *__restrict__ prefix,
                                                        const int64_t *__restrict__ slot_off,
                                                        const int32_t *__restrict__ pairs,
-                                                       const int32_t *__restrict__ slot_gp, float *__restrict__ wave,
+                                                       const int32_t *__restrict__ slot_gp,
+                                                       const int32_t *__restrict__ order, float *__restrict__ wave,
                                                        DevHeader *H, double *report) {
     extern __shared__ float sm[];
     __shared__ int32_t s_slot;
@@ -927,8 +928,8 @@ __global__ __launch_bounds__(kWG) void k_induce_sorted(DevParams P, const SegInf
     for (;;) {
         if (tid == 0) s_slot = (int32_t)atomicAdd(&H->work[0], 1u);
         __syncthreads();
-        const int64_t slot = s_slot;
-        if (slot >= n_slots) break;
+        if (s_slot >= n_slots) break;
+        const int64_t slot = order ? order[s_slot] : s_slot;           // largest-first when an order is given
         for (int n = tid; n < NT; n += kWG) { s_sum[n] = 0.0f; s_cmp[n] = 0.0f; }
         const int32_t gp = slot_gp[slot];
         const int32_t e = gp / P.npx, p = gp - e * P.npx;
@@ -1328,6 +1329,66 @@ __global__ __launch_bounds__(kWG) void k_sum_slices(int32_t NS, int32_t NT, int6
     }
 }
 
+// Largest-first order of the active pixels for the per-pair induction.  A workgroup owns one pixel at a time and
+// takes the next from a counter, so pixels of very unequal work taken in pixel order leave the chip idle at the end
+// while the last heavy pixels finish; taking them largest first (bucketed by the logarithm of their work, 16 buckets
+// per octave) keeps the tail short.  Work of a pixel = sum over its pairs of the charge-box columns in its reach times
+// the cell-tick blocks.  The order changes only which workgroup computes a pixel, not any sum.
+__global__ void k_slot_work(DevParams P, const SegInfo *__restrict__ si, const int64_t *__restrict__ slot_off,
+                            const int32_t *__restrict__ pairs, const int32_t *__restrict__ slot_gp, int64_t n_slots,
+                            int32_t *__restrict__ bucket, int32_t *__restrict__ hist) {
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= n_slots) return;
+    const int32_t gp = slot_gp[slot];
+    const int32_t p = gp % P.npx;
+    const int32_t uc = (p % P.nx) * P.nsub + P.nsub / 2, vc = (p / P.nx) * P.nsub + P.nsub / 2;
+    double work = 0.0;
+    for (int64_t q = slot_off[slot]; q < slot_off[slot + 1]; ++q) {
+        const SegInfo &g = si[pairs[q]];
+        const int32_t cu = min(g.u0 + g.nu, uc + P.bx) - max(g.u0, uc - P.bx);
+        const int32_t cv = min(g.v0 + g.nv, vc + P.by) - max(g.v0, vc - P.by);
+        if (cu > 0 && cv > 0) work += (double)cu * cv * (g.na_pad / kAC);
+    }
+    const int32_t lg = work >= 1.0 ? (int32_t)(16.0 * log2(work)) : 0;
+    const int32_t b = kOrderBuckets - 1 - min(lg, kOrderBuckets - 1);          // descending work
+    bucket[slot] = b;
+    atomicAdd(&hist[b], 1);
+}
+
+// bucket offsets (exclusive scan of the histogram) into the cursors
+__global__ void k_order_offsets(int32_t *__restrict__ hist, int32_t *__restrict__ cursor) {
+    __shared__ int32_t s[kOrderBuckets];
+    for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) s[i] = hist[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int i = 0; i < kOrderBuckets; ++i) {
+            const int32_t c = s[i];
+            s[i] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) cursor[i] = s[i];
+}
+
+__global__ void k_order_scatter(const int32_t *__restrict__ bucket, int64_t n_slots, int32_t *__restrict__ cursor,
+                                int32_t *__restrict__ order) {
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= n_slots) return;
+    order[atomicAdd(&cursor[bucket[slot]], 1)] = (int32_t)slot;
+}
+
+// w.order holds [order: n_slots][bucket: n_slots][hist: kOrderBuckets][cursor: kOrderBuckets]
+static void launch_slot_order(const DevParams &P, const Work &w, int64_t n_slots, hipStream_t st) {
+    int32_t *order = w.order, *bucket = order + n_slots, *hist = bucket + n_slots, *cursor = hist + kOrderBuckets;
+    launch_zero(hist, (int64_t)sizeof(int32_t) * kOrderBuckets, st);
+    const unsigned g = (unsigned)((n_slots + kWG - 1) / kWG);
+    k_slot_work<<<g, kWG, 0, st>>>(P, w.si, w.slot_off, w.pairs, w.slot_gp, n_slots, bucket, hist);
+    k_order_offsets<<<1, kWG, 0, st>>>(hist, cursor);
+    k_order_scatter<<<g, kWG, 0, st>>>(bucket, n_slots, cursor, order);
+}
+
 template <int RT>
 static void induce_slices_rt(const DevParams &P, const Work &w, const Table &T, float *wave, int64_t n_slots, int32_t NS,
                              float *part, int64_t chunk, hipStream_t st) {
@@ -1368,8 +1429,10 @@ static void induce_rt(const DevParams &P, const Work &w, const Table &T, float *
     if (mode == 0) {
         int64_t g = n_slots < 1 ? 1 : (n_slots > cap ? cap : n_slots);
         size_t lds = (size_t)2 * P.nticks * sizeof(float);
+        if (w.order && n_slots > 0) launch_slot_order(P, w, n_slots, st);
         k_induce_sorted<RT, SHIFT, PREFETCH><<<(unsigned)g, kWG, lds, st>>>(P, w.si, w.cells, T.Rpad, T.prefix, w.slot_off, w.pairs,
-                                                          w.slot_gp, wave, w.hdr, w.report);
+                                                          w.slot_gp, n_slots > 0 ? w.order : nullptr, wave, w.hdr,
+                                                          w.report);
     } else {
         int64_t g = w.n_seg < 1 ? 1 : (w.n_seg > cap ? cap : w.n_seg);
         k_induce_atomic<RT><<<(unsigned)g, kWG, 0, st>>>(P, w.si, w.n_seg, w.cells, T.Rpad, T.prefix, w.pix_slot, wave,

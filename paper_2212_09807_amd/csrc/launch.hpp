@@ -37,7 +37,9 @@ struct Work {
     const uint8_t *disabled = nullptr;       // [npx] disabled-channel mask or null
     void *scan_tmp = nullptr;                // scan partials
     int64_t scan_tmp_elems = 0;
+    int32_t *order = nullptr;                // [2 * cap_slots + 2 * kOrderBuckets] per-pair induction work order
 };
+constexpr int kOrderBuckets = 512;            // log-scale work buckets of the largest-first pixel order
 
 struct Table {
     const float *Rpad = nullptr;             // [bx * by][col_len], zero-padded columns

@@ -59,7 +59,7 @@ struct lts_context {
     int32_t t_r = 0, b_x = 0, b_y = 0;
     // scratch pool
     DevBuf si, cell_off, pix_cnt, cursor, pix_slot, slot_gp, slot_off, pairs_u, pairs, cells, pk_tick, pk_adc,
-        pk_flag, pk_off, hdr, scan_tmp, ev_off, ev_ids, report_tmp, counts_tmp, red_head, red_start;
+        pk_flag, pk_off, hdr, scan_tmp, ev_off, ev_ids, report_tmp, counts_tmp, red_head, red_start, order;
     DevHeader *hdr_host = nullptr;   // pinned
     int64_t last_n_seg = -1;
     int64_t last_n_slots = 0;
@@ -477,6 +477,8 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
     if ((r = ensure(c, c->pk_flag, sizeof(uint8_t) * (size_t)(n_slots * mp)))) return r;
     if ((r = ensure(c, c->pk_off, sizeof(int64_t) * (size_t)(n_slots + 1)))) return r;
     if ((r = ensure(c, c->scan_tmp, sizeof(int64_t) * (size_t)scan_tmp_needed(n_slots + 1)))) return r;
+    if ((r = ensure(c, c->order, sizeof(int32_t) * (size_t)(2 * n_slots + 2 * kOrderBuckets)))) return r;
+    w.order = as<int32_t>(c->order);
     w.slot_gp = as<int32_t>(c->slot_gp);
     w.slot_off = as<int64_t>(c->slot_off);
     w.pairs_unsorted = as<int32_t>(c->pairs_u);
@@ -620,7 +622,7 @@ void lts_context_destroy(lts_context *c) {
                       &c->piece, &c->S, &c->list_off, &c->list, &c->rec, &c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off, &c->pix_cnt, &c->cursor, &c->pix_slot, &c->slot_gp,
                       &c->slot_off, &c->pairs_u, &c->pairs, &c->cells, &c->pk_tick, &c->pk_adc, &c->pk_flag,
                       &c->pk_off, &c->hdr, &c->scan_tmp, &c->ev_off, &c->ev_ids, &c->report_tmp, &c->counts_tmp,
-                      &c->red_head, &c->red_start};
+                      &c->red_head, &c->red_start, &c->order};
     for (DevBuf *b : bufs) free_buf(*b);
     if (c->hdr_host) (void)hipHostFree(c->hdr_host);
     delete c;
