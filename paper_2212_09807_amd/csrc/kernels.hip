@@ -1812,6 +1812,7 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
                                                        const int64_t *__restrict__ list_off,
                                                        const int32_t *__restrict__ list,
                                                        const PieceRef *__restrict__ rec,
+                                                       const int32_t *__restrict__ order,
                                                        const int32_t *__restrict__ slot_gp, float *__restrict__ wave,
                                                        DevHeader *H, double *report) {
     const int lane = threadIdx.x & 63;
@@ -1823,8 +1824,9 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
         if (lane == 0) got = atomicAdd(&H->work[2], 1u);
         const int64_t unit = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
         if (unit >= n_units) break;
-        const int64_t slot = unit / n_tiles;
-        const int32_t t0 = (int32_t)(unit - slot * n_tiles) * kTileTicks, t1 = t0 + kTileTicks - 1;
+        const int64_t ui = unit / n_tiles;
+        const int64_t slot = order ? order[ui] : ui;                    // largest-first when an order is given
+        const int32_t t0 = (int32_t)(unit - ui * n_tiles) * kTileTicks, t1 = t0 + kTileTicks - 1;
         const int32_t gp = slot_gp[slot];
         const int32_t e = gp / P.npx, p = gp - e * P.npx;
         const int32_t uc = (p % P.nx) * P.nsub + P.nsub / 2, vc = (p / P.nx) * P.nsub + P.nsub / 2;
@@ -1942,6 +1944,20 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
     }
 }
 
+// Largest-first order of the pixels for the summed induction (the same log-bucketed order as the per-pair kernel's;
+// all tiles of a pixel stay together): work of a pixel = the cell-tick blocks of its pieces.
+__global__ void k_slot_work_summed(const PieceRef *__restrict__ rec, const int64_t *__restrict__ list_off,
+                                   int64_t n_slots, int32_t *__restrict__ bucket, int32_t *__restrict__ hist) {
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= n_slots) return;
+    double work = 0.0;
+    for (int64_t q = list_off[slot]; q < list_off[slot + 1]; ++q) work += (double)((rec[q].na + kAC - 1) / kAC);
+    const int32_t lg = work >= 1.0 ? (int32_t)(16.0 * log2(work)) : 0;
+    const int32_t b = kOrderBuckets - 1 - min(lg, kOrderBuckets - 1);
+    bucket[slot] = b;
+    atomicAdd(&hist[b], 1);
+}
+
 void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, const Table &T, float *wave,
                           int64_t n_slots, int32_t rt, bool shift, hipStream_t st) {
     if (rt != 0 && rt != 8) {                           // the per-pair kernel on the summed pieces (tuning option)
@@ -1956,12 +1972,22 @@ void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, 
     if (n_slots <= 0) return;
     const int64_t units = n_slots * ((P.nticks + kTileTicks - 1) / kTileTicks);
     const int64_t g = std::min<int64_t>((units + kWG / 64 - 1) / (kWG / 64), 256 * 8);
+    const int32_t *order = nullptr;
+    if (w.order && !shift) {
+        int32_t *ord = w.order, *bucket = ord + n_slots, *hist = bucket + n_slots, *cursor = hist + kOrderBuckets;
+        launch_zero(hist, (int64_t)sizeof(int32_t) * kOrderBuckets, st);
+        const unsigned gs = (unsigned)((n_slots + kWG - 1) / kWG);
+        k_slot_work_summed<<<gs, kWG, 0, st>>>(sw.rec, sw.list_off, n_slots, bucket, hist);
+        k_order_offsets<<<1, kWG, 0, st>>>(hist, cursor);
+        k_order_scatter<<<gs, kWG, 0, st>>>(bucket, n_slots, cursor, ord);
+        order = ord;
+    }
     if (shift)
         k_induce_summed<true><<<(unsigned)g, kWG, 0, st>>>(P, sw.piece, sw.S, T.Rpad, T.prefix, sw.list_off, sw.list,
-                                                           sw.rec, w.slot_gp, wave, w.hdr, w.report);
+                                                           sw.rec, order, w.slot_gp, wave, w.hdr, w.report);
     else
         k_induce_summed<false><<<(unsigned)g, kWG, 0, st>>>(P, sw.piece, sw.S, T.Rpad, T.prefix, sw.list_off, sw.list,
-                                                            sw.rec, w.slot_gp, wave, w.hdr, w.report);
+                                                            sw.rec, order, w.slot_gp, wave, w.hdr, w.report);
 }
 
 // ================================================================================================= electronics
