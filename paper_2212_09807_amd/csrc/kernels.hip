@@ -1741,32 +1741,45 @@ void launch_sum_pieces(const DevParams &P, const Work &w, const SumWork &sw, hip
     k_sum_pieces<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.cells, sw);
 }
 
-// per active pixel: number of column pieces in its table reach, then their ids in column order
+// per active pixel (one wavefront): number of column pieces in its table reach, then their ids in column order (row
+// du, then column dv; pieces of a column in tick order).  The lanes take 64 consecutive columns at a time; a wavefront
+// prefix sum of their piece counts gives each lane its place in the list.
 template <bool FILL>
-__global__ void k_sum_lists(DevParams P, int64_t n_slots, const int32_t *slot_gp, SumWork sw) {
-    int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kWG) void k_sum_lists(DevParams P, int64_t n_slots, const int32_t *slot_gp, SumWork sw) {
+    const int lane = threadIdx.x & 63;
+    const int64_t slot = (int64_t)blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (slot >= n_slots) return;
     const int32_t gp = slot_gp[slot];
     const int32_t e = gp / P.npx, p = gp - e * P.npx;
     const int32_t ix = p % P.nx, iy = p / P.nx;
     const int32_t cu0 = ix * P.nsub + P.nsub / 2 - P.bx - sw.UL, cv0 = iy * P.nsub + P.nsub / 2 - P.by - sw.VL;
     const int64_t base = (int64_t)e * sw.CU * sw.CV;
-    int64_t cnt = 0, pos = FILL ? sw.list_off[slot] : 0;
-    for (int32_t du = 0; du < 2 * P.bx; ++du) {
-        const int64_t row = base + (int64_t)(cu0 + du) * sw.CV + cv0;
-        for (int32_t dv = 0; dv < 2 * P.by; ++dv) {
-            const int64_t pb = sw.piece_off[row + dv], pe = sw.piece_off[row + dv + 1];
-            if (FILL)
-                for (int64_t k = pb; k < pe; ++k) sw.list[pos++] = (int32_t)k;
-            cnt += pe - pb;
+    const int32_t nv = 2 * P.by, ncol = 2 * P.bx * nv;
+    int64_t pos = FILL ? sw.list_off[slot] : 0;
+    for (int32_t c0 = 0; c0 < ncol; c0 += 64) {
+        const int32_t c = c0 + lane;
+        int64_t pb = 0, pe = 0;
+        if (c < ncol) {
+            const int64_t col = base + (int64_t)(cu0 + c / nv) * sw.CV + cv0 + c % nv;
+            pb = sw.piece_off[col];
+            pe = sw.piece_off[col + 1];
         }
+        int64_t x = pe - pb, incl = x;                          // inclusive prefix of the piece counts
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t y = __shfl_up(incl, d);
+            if (lane >= d) incl += y;
+        }
+        if (FILL)
+            for (int64_t k = 0; k < x; ++k) sw.list[pos + incl - x + k] = (int32_t)(pb + k);
+        pos += __shfl(incl, 63);
     }
-    if (!FILL) sw.list_off[slot] = cnt;
+    if (!FILL && lane == 0) sw.list_off[slot] = pos;
 }
 
 void launch_sum_lists_count(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, hipStream_t st) {
     if (n_slots > 0)
-        k_sum_lists<false><<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
+        k_sum_lists<false><<<(unsigned)((n_slots + kWG / 64 - 1) / (kWG / 64)), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
 }
 // per list entry: the piece as a record for the summed induction loop (its pixel found by bisection of the list
 // offsets; one thread per entry, so the record writes are coalesced)
@@ -1788,7 +1801,7 @@ __global__ void k_sum_recs(DevParams P, int64_t n_slots, int64_t n_list, const i
 void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, int64_t n_list,
                            hipStream_t st) {
     if (n_slots <= 0) return;
-    k_sum_lists<true><<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
+    k_sum_lists<true><<<(unsigned)((n_slots + kWG / 64 - 1) / (kWG / 64)), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
     if (n_list > 0)
         k_sum_recs<<<(unsigned)((n_list + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, n_list, w.slot_gp, sw);
 }
