@@ -20,7 +20,7 @@
  *   4. Induced current, Sec. 3.3.2, eq. (current): each charge cell (tick a, bin u, v) adds
  *      q * R[k, i, j] to pixel p at tick a - (T_R - 1) + k, where (i, j) is the bin's mirror-folded offset
  *      from the pixel centre (the table is quadrant-symmetric, Sec. 3.3.1) and the table is arrival-aligned.
- *   5. Per-pixel sum over segments (Sec. 3.4, "after summing the current induced by different tracks").
+ *   5. Per-pixel sum over segments (Sec. 3.4).
  *   6. Electronics, Sec. 3.4: integrate, discriminate (>= threshold), hold, digitise (8-bit ADC), reset,
  *      with reset / discriminator / uncorrelated Gaussian noise drawn from a counter-based Philox4x32-10
  *      generator (Salmon et al., SC'11) through Box-Muller.
