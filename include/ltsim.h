@@ -17,9 +17,16 @@
  *   - Stream arguments are hipStream_t values passed as void* (NULL = the null stream).  Entry points that
  *     take a stream enqueue their work on it and return; results are valid after the stream is synchronised.
  *     lts_simulate / lts_simulate_batch additionally synchronise that stream once (after sizing) to size
- *     scratch and check output capacities, so a capacity error is returned synchronously.
+ *     scratch and check output capacities, so a capacity error is returned synchronously (LTS_REDUCE_SUMMED
+ *     synchronises twice more, to size the summed columns and the pixels' piece lists).  Calls on one context
+ *     that use its scratch pool (lts_plan, lts_simulate, lts_simulate_batch, lts_stage_rasterize, lts_stage_induce,
+ *     lts_stage_reduce, lts_stage_electronics) are ordered on the device whatever streams they are given: each one
+ *     first makes its stream wait for the previous one's completion (a HIP event), so work of consecutive calls on
+ *     different streams never overlaps in the shared scratch.
  *   - No call throws across the ABI.  Every call returns an lts_status; on failure lts_last_error() gives a
- *     message.  A failed device call makes the context's status sticky (LTS_ERR_DEVICE).
+ *     message.  A failed device call makes the context's status sticky (LTS_ERR_DEVICE).  A failed host-memory
+ *     allocation inside a call returns LTS_ERR_OOM and leaves the context usable; any other internal C++
+ *     exception returns LTS_ERR_DEVICE without making it sticky.
  *   - A context is not thread-safe: serialise calls on one context.  The server API is thread-safe.
  */
 #ifndef LTSIM_H
@@ -276,6 +283,13 @@ lts_status lts_stage_electronics(lts_context *ctx, uint64_t event_id, const int3
  * reach summed over pixels in LTS_REDUCE_SUMMED); out[3] charge cells of all segments. */
 lts_status lts_work_stats(lts_context *ctx, double out[4]);
 
+/* Test hook for the error paths: after `after` further host-allocation points inside the library have passed
+ * (0 = the next one), one of them fails as if host memory were exhausted, once; -1 disarms.  The points are the
+ * host-side copies of lts_set_response, lts_server_submit, a server lane's batch set-up and lts_light_create.  The
+ * failing call returns LTS_ERR_OOM (a failing server batch gives its tickets that status) and the object stays
+ * usable.  Process-wide; LTS_ERR_INVALID_ARG for after < -1. */
+lts_status lts_debug_fail_host_alloc(int64_t after);
+
 /* Raw Philox4x32-10 blocks: ctr[n*4] (device) with key (k0, k1) -> out[n*4] (device). */
 lts_status lts_stage_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n, void *stream);
 
@@ -307,7 +321,8 @@ typedef struct lts_result_view {  /* host memory owned by the server, valid unti
     const uint16_t *pkt_adc;
     const uint8_t *pkt_flags;
     double report[5];
-    int64_t counts[4];
+    int64_t counts[4];            /* this event's pixels, packets, samples dropped past the window, packets over
+                                     max_packets (the same as the event alone) */
     double t_submit, t_start, t_done;   /* seconds on a monotonic clock: submission, batch launch, completion */
     int32_t batch_events;         /* events in the batch that carried this one */
 } lts_result_view;

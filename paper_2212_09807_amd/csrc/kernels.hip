@@ -1607,12 +1607,7 @@ void launch_reduce_runs(const float *pair_current, const int64_t *start, int64_t
 // a 1 x 1 x L charge box, and every active pixel's list of pieces in its reach replaces its pair list, so the
 // sorted induction kernel runs unchanged on the summed data.
 
-__global__ void k_sum_init(int32_t *lo, int32_t *hi, int64_t n) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) { lo[i] = INT32_MAX; hi[i] = INT32_MIN; }
-}
-
-// per segment: every column of its charge box that some pixel can reach gets the box's tick range and a count
+// per segment: count the columns of its charge box that some pixel can reach
 __global__ void k_sum_ranges(DevParams P, const SegInfo *si, int64_t n_seg, SumWork sw) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n_seg) return;
@@ -1622,16 +1617,11 @@ __global__ void k_sum_ranges(DevParams P, const SegInfo *si, int64_t n_seg, SumW
     const int32_t v_a = max(g.v0, sw.VL), v_b = min(g.v0 + g.nv - 1, sw.VL + sw.CV - 1);
     const int64_t base = (int64_t)g.event * sw.CU * sw.CV;
     for (int32_t u = u_a; u <= u_b; ++u)
-        for (int32_t v = v_a; v <= v_b; ++v) {
-            const int64_t c = base + (int64_t)(u - sw.UL) * sw.CV + (v - sw.VL);
-            atomicMin(&sw.col_lo[c], g.a0);
-            atomicMax(&sw.col_hi[c], g.a0 + g.na - 1);
-            atomicAdd((unsigned long long *)&sw.col_seg_off[c], 1ull);
-        }
+        for (int32_t v = v_a; v <= v_b; ++v)
+            atomicAdd((unsigned long long *)&sw.col_seg_off[base + (int64_t)(u - sw.UL) * sw.CV + (v - sw.VL)], 1ull);
 }
 
 void launch_sum_ranges(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st) {
-    k_sum_init<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(sw.col_lo, sw.col_hi, sw.n_cols);
     if (w.n_seg > 0) k_sum_ranges<<<(unsigned)((w.n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.n_seg, sw);
 }
 
@@ -1650,29 +1640,64 @@ __global__ void k_sum_fill(DevParams P, const SegInfo *si, int64_t n_seg, SumWor
         }
 }
 
-// per column: sort its segment list (ascending id, insertion sort: lists are short), count its pieces and the
-// padded summed-charge length.  The column's first tick is moved down (zero charge in front) to the residue
-// (T_R - 1 + kPad) mod 8, which makes every lane's table offset in the summed induction a multiple of 8.
-__global__ void k_sum_columns(int32_t align_res, SumWork sw) {
+// A column's charge is cut where none of its segments has charge for more than kSumGap ticks: the zero ticks of
+// such a gap would otherwise be convolved with the whole table column.  A new piece costs less than ~16 zero ticks.
+constexpr int32_t kSumGap = 16;
+
+// The merged tick interval that starts at entry q of a column's segment list [q, se) (sorted by first tick): its
+// segments are [q, return value), its ticks [lo, hi], lo moved down (zero charge in front) to the residue `res`
+// mod 8.  Consecutive intervals are separated by more than kSumGap ticks, so the aligned ones do not overlap.
+__device__ inline int64_t sum_interval(const SegInfo *__restrict__ si, const int32_t *__restrict__ seg, int64_t q,
+                                       int64_t se, int32_t res, int32_t &lo, int32_t &hi) {
+    const SegInfo &g0 = si[seg[q]];
+    lo = g0.a0;
+    hi = g0.a0 + g0.na - 1;
+    int64_t qe = q + 1;
+    for (; qe < se; ++qe) {
+        const SegInfo &g = si[seg[qe]];
+        if (g.a0 - hi - 1 > kSumGap) break;
+        hi = max(hi, g.a0 + g.na - 1);
+    }
+    lo -= ((lo - res) % 8 + 8) % 8;
+    return qe;
+}
+
+// Pieces of kPieceTicks ticks of an interval of L ticks, and their summed-charge length (the last one padded to kAC).
+__device__ inline void sum_interval_size(int32_t L, int64_t &np, int64_t &ns) {
+    np = (L + kPieceTicks - 1) / kPieceTicks;
+    const int32_t last = L - (int32_t)(np - 1) * kPieceTicks;
+    ns = (np - 1) * kPieceTicks + (last + kAC - 1) / kAC * kAC;
+}
+
+// per column: sort its segment list by (first tick, segment id) (insertion sort: lists are short), then count the
+// pieces and the padded summed-charge length of its merged tick intervals.  Every interval's first tick is moved down
+// to the residue (T_R - 1 + kPad) mod 8, which makes every lane's table offset in the summed induction a multiple
+// of 8.  The order depends only on the segments' charge boxes and their order within the event, so the sums are
+// the same in a batch and alone.
+__global__ void k_sum_columns(int32_t align_res, const SegInfo *__restrict__ si, SumWork sw) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= sw.n_cols) return;
     const int64_t b = sw.col_seg_off[c], e = sw.col_seg_off[c + 1];
     for (int64_t i = b + 1; i < e; ++i) {
         const int32_t x = sw.col_seg[i];
+        const int32_t ax = si[x].a0;
         int64_t j = i - 1;
-        while (j >= b && sw.col_seg[j] > x) { sw.col_seg[j + 1] = sw.col_seg[j]; --j; }
+        for (; j >= b; --j) {
+            const int32_t y = sw.col_seg[j];
+            const int32_t ay = si[y].a0;
+            if (ay < ax || (ay == ax && y < x)) break;
+            sw.col_seg[j + 1] = y;
+        }
         sw.col_seg[j + 1] = x;
     }
-    const int32_t hi = sw.col_hi[c];
-    int32_t lo = sw.col_lo[c];
     int64_t np = 0, ns = 0;
-    if (e > b && hi >= lo) {
-        lo -= ((lo - align_res) % 8 + 8) % 8;
-        sw.col_lo[c] = lo;
-        const int32_t L = hi - lo + 1;
-        np = (L + kPieceTicks - 1) / kPieceTicks;
-        const int32_t last = L - (int32_t)(np - 1) * kPieceTicks;
-        ns = (np - 1) * kPieceTicks + (last + kAC - 1) / kAC * kAC;
+    for (int64_t q = b; q < e;) {
+        int32_t lo, hi;
+        q = sum_interval(si, sw.col_seg, q, e, align_res, lo, hi);
+        int64_t n, m;
+        sum_interval_size(hi - lo + 1, n, m);
+        np += n;
+        ns += m;
     }
     sw.piece_off[c] = np;
     sw.s_off[c] = ns;
@@ -1680,60 +1705,71 @@ __global__ void k_sum_columns(int32_t align_res, SumWork sw) {
 
 void launch_sum_fill(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st) {
     if (w.n_seg > 0) k_sum_fill<<<(unsigned)((w.n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.n_seg, sw);
-    k_sum_columns<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(((P.t_r - 1 + kPad) % 8 + 8) % 8, sw);
+    k_sum_columns<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(((P.t_r - 1 + kPad) % 8 + 8) % 8, w.si,
+                                                                            sw);
 }
 
-// per column: piece records, and the summed charge of each tick (segments in ascending id, Kahan)
+// per column: piece records, and the summed charge of each tick (Kahan over the column's segments in list order)
 __global__ void k_sum_pieces(DevParams P, const SegInfo *si, const float *cells, SumWork sw) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= sw.n_cols) return;
-    const int64_t np = sw.piece_off[c + 1] - sw.piece_off[c];
-    if (np == 0) return;
+    if (sw.piece_off[c + 1] == sw.piece_off[c]) return;
     const int32_t e = (int32_t)(c / ((int64_t)sw.CU * sw.CV));
     const int64_t r = c - (int64_t)e * sw.CU * sw.CV;
     const int32_t u = sw.UL + (int32_t)(r / sw.CV), v = sw.VL + (int32_t)(r % sw.CV);
-    const int32_t lo = sw.col_lo[c], L = sw.col_hi[c] - lo + 1;
     const int64_t sb = sw.col_seg_off[c], se = sw.col_seg_off[c + 1];
-    float *S = sw.S + sw.s_off[c];
-    const int32_t Lpad = (int32_t)(sw.s_off[c + 1] - sw.s_off[c]);
-    // 32-tick chunks with their sums in registers; per chunk, every segment of the column that overlaps it adds
-    // its cells, segments in ascending id (the same order per tick as a tick-by-tick scan)
-    constexpr int32_t kCh = 32;
-    for (int32_t a0c = 0; a0c < Lpad; a0c += kCh) {
-        float sum[kCh], cmp[kCh];
+    const int32_t res = ((P.t_r - 1 + kPad) % 8 + 8) % 8;
+    int64_t pk = sw.piece_off[c], so = sw.s_off[c];
+    for (int64_t q = sb; q < se;) {
+        int32_t lo, hi;
+        const int64_t qe = sum_interval(si, sw.col_seg, q, se, res, lo, hi);
+        const int32_t L = hi - lo + 1;
+        int64_t np, Lpad;
+        sum_interval_size(L, np, Lpad);
+        float *S = sw.S + so;
+        // 32-tick chunks with their sums in registers; per chunk, every segment of the interval that overlaps it
+        // adds its cells, in list order (the same order per tick as a tick-by-tick scan)
+        constexpr int32_t kCh = 32;
+        for (int32_t a0c = 0; a0c < Lpad; a0c += kCh) {
+            float sum[kCh], cmp[kCh];
 #pragma unroll
-        for (int j = 0; j < kCh; ++j) { sum[j] = 0.0f; cmp[j] = 0.0f; }
-        const int32_t cl = lo + a0c, ch = min(cl + kCh, lo + L) - 1;
-        for (int64_t q = sb; q < se; ++q) {
-            const SegInfo &g = si[sw.col_seg[q]];
-            const int32_t ga = max(g.a0, cl), gb = min(g.a0 + g.na - 1, ch);
-            if (ga > gb) continue;
-            const float *src = cells + g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad - g.a0;
+            for (int j = 0; j < kCh; ++j) { sum[j] = 0.0f; cmp[j] = 0.0f; }
+            const int32_t cl = lo + a0c, ch = min(cl + kCh, lo + L) - 1;
+            for (int64_t k = q; k < qe; ++k) {
+                const SegInfo &g = si[sw.col_seg[k]];
+                if (g.a0 > ch) break;                   // sorted by first tick
+                const int32_t ga = max(g.a0, cl), gb = min(g.a0 + g.na - 1, ch);
+                if (ga > gb) continue;
+                const float *src = cells + g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad - g.a0;
 #pragma unroll
-            for (int j = 0; j < kCh; ++j) {
-                const int32_t aa = cl + j;
-                if (aa >= ga && aa <= gb) {
-                    const float y = src[aa] - cmp[j];
-                    const float t = sum[j] + y;
-                    cmp[j] = (t - sum[j]) - y;
-                    sum[j] = t;
+                for (int j = 0; j < kCh; ++j) {
+                    const int32_t aa = cl + j;
+                    if (aa >= ga && aa <= gb) {
+                        const float y = src[aa] - cmp[j];
+                        const float t = sum[j] + y;
+                        cmp[j] = (t - sum[j]) - y;
+                        sum[j] = t;
+                    }
                 }
             }
-        }
 #pragma unroll
-        for (int j = 0; j < kCh; ++j)
-            if (a0c + j < Lpad) S[a0c + j] = sum[j] - cmp[j];
-    }
-    for (int64_t k = 0; k < np; ++k) {
-        SegInfo g = {};
-        g.u0 = u; g.nu = 1; g.v0 = v; g.nv = 1;
-        g.a0 = lo + (int32_t)k * kPieceTicks;
-        g.na = min(kPieceTicks, L - (int32_t)k * kPieceTicks);
-        g.na_pad = (g.na + kAC - 1) / kAC * kAC;
-        g.cell_off = sw.s_off[c] + k * kPieceTicks;
-        g.event = e;
-        g.n_pairs = 1;
-        sw.piece[sw.piece_off[c] + k] = g;
+            for (int j = 0; j < kCh; ++j)
+                if (a0c + j < Lpad) S[a0c + j] = sum[j] - cmp[j];
+        }
+        for (int64_t k = 0; k < np; ++k) {
+            SegInfo g = {};
+            g.u0 = u; g.nu = 1; g.v0 = v; g.nv = 1;
+            g.a0 = lo + (int32_t)k * kPieceTicks;
+            g.na = min(kPieceTicks, L - (int32_t)k * kPieceTicks);
+            g.na_pad = (g.na + kAC - 1) / kAC * kAC;
+            g.cell_off = so + k * kPieceTicks;
+            g.event = e;
+            g.n_pairs = 1;
+            sw.piece[pk + k] = g;
+        }
+        pk += np;
+        so += Lpad;
+        q = qe;
     }
 }
 
@@ -2027,7 +2063,8 @@ __global__ __launch_bounds__(kWG) void k_electronics(DevParams P, const float *_
                                                      const uint64_t *__restrict__ ev_ids, int32_t n_ev,
                                                      const uint8_t *__restrict__ disabled, int64_t n_slots_arg,
                                                      int32_t *pk_tick, uint16_t *pk_adc, uint8_t *pk_flag,
-                                                     int64_t *pk_cnt, DevHeader *H, double *report) {
+                                                     int64_t *pk_cnt, DevHeader *H, double *report,
+                                                     int64_t *ev_cnt) {
     const int64_t n_slots = n_slots_arg >= 0 ? n_slots_arg : H->n_slots;
     const int32_t NT = P.nticks, RP = P.reset_period;
     const int lane = lane_id();
@@ -2158,8 +2195,14 @@ __global__ __launch_bounds__(kWG) void k_electronics(DevParams P, const float *_
         }
         if (lane == 0) pk_cnt[slot] = off ? 0 : cnt;
         add_report(report, e, 2, rs, true);
-        if (lane == 0 && dropped) atomicAdd((unsigned long long *)&H->dropped, (unsigned long long)dropped);
-        if (lane == 0 && over) atomicAdd((unsigned long long *)&H->over, (unsigned long long)over);
+        if (lane == 0 && dropped) {
+            atomicAdd((unsigned long long *)&H->dropped, (unsigned long long)dropped);
+            if (ev_cnt) atomicAdd((unsigned long long *)&ev_cnt[2 * e], (unsigned long long)dropped);
+        }
+        if (lane == 0 && over) {
+            atomicAdd((unsigned long long *)&H->over, (unsigned long long)over);
+            if (ev_cnt) atomicAdd((unsigned long long *)&ev_cnt[2 * e + 1], (unsigned long long)over);
+        }
     }
 }
 
@@ -2169,7 +2212,7 @@ void launch_electronics(const DevParams &P, const float *wave, const int32_t *sl
     if (g < 1) g = 1;
     if (g > 65536) g = 65536;
     k_electronics<<<(unsigned)g, kWG, 0, st>>>(P, wave, slot_gp, event_ids, w.n_ev, w.disabled, n_slots, w.pk_tick,
-                                               w.pk_adc, w.pk_flag, w.pk_off, w.hdr, w.report);
+                                               w.pk_adc, w.pk_flag, w.pk_off, w.hdr, w.report, w.ev_cnt);
 }
 
 __global__ void k_compact(int32_t max_packets, int64_t n_slots, const int64_t *pk_off, const int32_t *slot_gp,

@@ -34,6 +34,8 @@ struct Work {
     int64_t *pk_off = nullptr;               // [cap_slots + 1] counts, then exclusive offsets
     DevHeader *hdr = nullptr;
     double *report = nullptr;                // [5 * n_ev]
+    int64_t *ev_cnt = nullptr;               // [2 * n_ev] per event: samples dropped past the window, packets over
+                                             // max_packets (or null)
     const uint8_t *disabled = nullptr;       // [npx] disabled-channel mask or null
     void *scan_tmp = nullptr;                // scan partials
     int64_t scan_tmp_elems = 0;
@@ -60,10 +62,9 @@ struct alignas(16) PieceRef {
 struct SumWork {
     int32_t CU = 0, CV = 0, UL = 0, VL = 0;
     int64_t n_cols = 0;                      // n_ev * CU * CV
-    int32_t *col_lo = nullptr, *col_hi = nullptr;   // [n_cols] tick range of the column's charge
     int64_t *col_seg_off = nullptr;          // [n_cols + 1] segments per column, then offsets
     int32_t *col_cursor = nullptr;           // [n_cols]
-    int32_t *col_seg = nullptr;              // [n_col_seg] segment ids per column (ascending after sorting)
+    int32_t *col_seg = nullptr;              // [n_col_seg] segment ids per column (by first tick after sorting)
     int64_t *piece_off = nullptr;            // [n_cols + 1] pieces per column, then offsets
     int64_t *s_off = nullptr;                // [n_cols + 1] summed-cell floats per column, then offsets
     SegInfo *piece = nullptr;                // [n_pieces] one 1 x 1 x L box per column piece
@@ -75,7 +76,7 @@ struct SumWork {
 constexpr int32_t kPieceTicks = kPieceMax;   // ticks per column piece (a multiple of kAC, <= kNaMax)
 static_assert(kPieceTicks % kAC == 0 && kPieceTicks <= kNaMax, "piece length");
 
-void launch_sum_ranges(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st);   // + counts
+void launch_sum_ranges(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st);   // counts
 void launch_sum_fill(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st);     // lists, pieces
 void launch_sum_pieces(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st);   // piece records, S
 void launch_sum_lists_count(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, hipStream_t st);

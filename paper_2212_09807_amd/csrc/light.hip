@@ -15,11 +15,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "device.hpp"
 #include "../../include/ltsim.h"
+#include "api.hpp"
 
 namespace ltsim {
 namespace {
@@ -469,6 +471,7 @@ extern "C" {
 
 lts_status lts_light_create(int device, const lts_light_params *p, const float *resp, int32_t n_resp,
                             const float *noise_amp, int32_t n_freq, lts_light **out) {
+    LTS_API_BEGIN
     if (!out) return LTS_ERR_INVALID_ARG;
     *out = nullptr;
     if (!p || !resp || n_resp < 1 || n_resp > (1 << 16) || (n_freq > 0 && !noise_amp) || n_freq < 0)
@@ -481,7 +484,8 @@ lts_status lts_light_create(int device, const lts_light_params *p, const float *
         return LTS_ERR_INVALID_ARG;
     const double kd = std::floor(q.trunc * q.tau_s / q.tick) + 1.0;
     if (!(kd >= 1.0 && kd <= (double)(1 << 22))) return LTS_ERR_INVALID_ARG;
-    lts_light *L = new lts_light();
+    std::unique_ptr<lts_light> held(new lts_light());   // freed on every failure, exceptions included
+    lts_light *L = held.get();
     L->p = q;
     L->device = device;
     L->K = (int32_t)kd;
@@ -495,13 +499,13 @@ lts_status lts_light_create(int device, const lts_light_params *p, const float *
     L->k0 = (uint32_t)q.seed;
     L->k1 = (uint32_t)(q.seed >> 32);
     auto fin = [&](lts_status s) {
-        if (s != LTS_OK) delete L;
-        else *out = L;
+        if (s == LTS_OK) *out = held.release();
         return s;
     };
     if (hipSetDevice(device) != hipSuccess) return fin(LTS_ERR_DEVICE);
     const size_t nd = (size_t)q.n_det, T = (size_t)q.n_ticks;
     // scintillation kernel, sampled two-exponential profile (Sec. 4.2), zero past the truncation
+    host_alloc_point();
     std::vector<double> w(8 * (size_t)L->nkb, 0.0);
     for (int32_t k = 0; k < L->K; ++k) {
         const double t = k * q.tick;
@@ -545,6 +549,7 @@ lts_status lts_light_create(int device, const lts_light_params *p, const float *
         }
     }
     return fin(st);
+    LTS_API_END(nullptr)
 }
 
 void lts_light_destroy(lts_light *L) {
@@ -559,14 +564,17 @@ void lts_light_destroy(lts_light *L) {
 }
 
 lts_status lts_light_set_graph(lts_light *L, int32_t on) {
+    LTS_API_BEGIN
     if (!L) return LTS_ERR_INVALID_ARG;
     if (on != 0 && on != 1) return lfail(L, LTS_ERR_INVALID_ARG, "graph must be 0 or 1");
     L->use_graph = on != 0;
     return LTS_OK;
+    LTS_API_END(L)
 }
 
 lts_status lts_light_simulate(lts_light *L, uint64_t event_id, const float *ipe, double *mu, double *pe, float *V,
                               int32_t *trig, int32_t *trig_count, void *stream) {
+    LTS_API_BEGIN
     if (!L) return LTS_ERR_INVALID_ARG;
     if (L->sticky) return lfail(L, LTS_ERR_DEVICE, "a previous device error: destroy and recreate");
     if (!ipe || !V || (!trig) != (!trig_count)) return lfail(L, LTS_ERR_INVALID_ARG, "null buffer");
@@ -594,6 +602,7 @@ lts_status lts_light_simulate(lts_light *L, uint64_t event_id, const float *ipe,
     LHIP(L, hipEventRecord(L->done[i], st));
     L->launched[i] = true;
     return LTS_OK;
+    LTS_API_END(L)
 }
 
 const char *lts_light_last_error(const lts_light *L) { return L ? L->err.c_str() : "null light simulator"; }

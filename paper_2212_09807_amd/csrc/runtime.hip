@@ -17,10 +17,13 @@
 #include <vector>
 
 #include "../../include/ltsim.h"
+#include "api.hpp"
 #include "device.hpp"
 #include "launch.hpp"
 
 using namespace ltsim;
+
+std::atomic<int64_t> ltsim::g_host_alloc_fail{-1};
 
 namespace {
 
@@ -51,7 +54,7 @@ struct lts_context {
     DevBuf part;                     // per-slice partial waveforms of the sliced sorted variant
     DevBuf mask;                     // disabled-channel mask (npx bytes) when set
     bool has_mask = false;
-    DevBuf col_lo, col_hi, col_seg_off, col_cursor, col_seg, piece_off, s_off, piece, S, list_off, list, rec;
+    DevBuf col_seg_off, col_cursor, col_seg, piece_off, s_off, piece, S, list_off, list, rec;
     DevParams P{};
     bool has_table = false;
     DevBuf Rpad, prefix;
@@ -70,6 +73,11 @@ struct lts_context {
     std::vector<hipEvent_t> free_ev;
     double stage_ms[LTS_N_STAGES] = {0};
     int64_t stage_calls[LTS_N_STAGES] = {0};
+    // stream order of the calls on this context: every call that uses the scratch pool waits for the previous one
+    // (an event recorded on the previous call's stream), so calls on different streams never share scratch in flight
+    hipEvent_t call_done = nullptr;
+    bool call_recorded = false;
+    DevBuf ev_cnt;                   // [2 per event] samples dropped past the window, packets over max_packets
     std::string err;
     lts_status sticky = LTS_OK;
 };
@@ -78,8 +86,8 @@ namespace {
 
 lts_status fail(lts_context *c, lts_status s, const std::string &msg) {
     if (c) {
-        c->err = msg;
         if (s == LTS_ERR_DEVICE) c->sticky = LTS_ERR_DEVICE;
+        c->err = msg;
     }
     return s;
 }
@@ -218,6 +226,31 @@ lts_status validate_and_derive(lts_context *c) {
 template <typename T>
 T *as(DevBuf &b) { return (T *)b.p; }
 
+// Orders a call that uses the context's scratch after the previous such call, whatever streams they use: the
+// constructor makes `st` wait for the previous call's completion event, the destructor records it on `st`.
+struct CallOrder {
+    lts_context *c;
+    hipStream_t st;
+    lts_status status = LTS_OK;
+    CallOrder(lts_context *c_, hipStream_t st_) : c(c_), st(st_) {
+        if (!c->call_done && hipEventCreateWithFlags(&c->call_done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            c->call_done = nullptr;
+            status = fail(c, LTS_ERR_DEVICE, "hipEventCreateWithFlags failed");
+            return;
+        }
+        if (c->call_recorded && hipStreamWaitEvent(st, c->call_done, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            status = fail(c, LTS_ERR_DEVICE, "hipStreamWaitEvent failed");
+        }
+    }
+    ~CallOrder() {
+        if (!c->call_done) return;
+        if (hipEventRecord(c->call_done, st) == hipSuccess) c->call_recorded = true;
+        else (void)hipGetLastError();
+    }
+};
+
 hipEvent_t take_event(lts_context *c) {
     if (!c->free_ev.empty()) {
         hipEvent_t e = c->free_ev.back();
@@ -286,6 +319,8 @@ lts_status run_sizing(lts_context *c, int32_t n_ev, const uint64_t *event_ids, c
     if ((r = ensure(c, c->ev_off, sizeof(int64_t) * (size_t)(n_ev + 1)))) return r;
     if ((r = ensure(c, c->ev_ids, sizeof(uint64_t) * (size_t)n_ev))) return r;
     if ((r = ensure(c, c->scan_tmp, sizeof(int64_t) * (size_t)scan_tmp_needed(scan_n)))) return r;
+    if ((r = ensure(c, c->ev_cnt, sizeof(int64_t) * 2 * (size_t)n_ev))) return r;
+    HIP_TRY(c, hipMemsetAsync(c->ev_cnt.p, 0, sizeof(int64_t) * 2 * (size_t)n_ev, st));
     HIP_TRY(c, hipMemcpyAsync(c->ev_off.p, seg_offsets, sizeof(int64_t) * (size_t)(n_ev + 1), hipMemcpyHostToDevice, st));
     HIP_TRY(c, hipMemcpyAsync(c->ev_ids.p, event_ids, sizeof(uint64_t) * (size_t)n_ev, hipMemcpyHostToDevice, st));
     HIP_TRY(c, hipMemsetAsync(c->pix_cnt.p, 0, sizeof(uint64_t) * (size_t)(n_gp + 1), st));
@@ -305,6 +340,7 @@ lts_status run_sizing(lts_context *c, int32_t n_ev, const uint64_t *event_ids, c
     w.pix_slot = as<int32_t>(c->pix_slot);
     w.hdr = as<DevHeader>(c->hdr);
     w.report = report;
+    w.ev_cnt = as<int64_t>(c->ev_cnt);
     w.scan_tmp = c->scan_tmp.p;
     w.disabled = c->has_mask ? as<uint8_t>(c->mask) : nullptr;
     SegArrays S = seg_arrays(segs);
@@ -338,32 +374,18 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     sw.n_cols = (int64_t)w.n_ev * sw.CU * sw.CV;
     const int64_t nc1 = sw.n_cols + 1;
     const int64_t n_colseg = std::max<int64_t>(h.n_colseg, 1);
-    // a column with charge spans at most the sum of its segments' tick extents, plus up to 7 ticks of alignment in
-    // front and 7 of padding at the end; every column with charge has at least one segment (n_colseg >= columns)
-    const int64_t max_pieces = 2 * n_colseg + h.n_cells / kPieceTicks + 1;
-    const int64_t max_s = h.n_cells + 2 * (int64_t)kAC * n_colseg + kAC;
-    if (max_s / kAC >= (int64_t)UINT32_MAX)          // piece records hold the charge offset in units of kAC floats
-        return fail(c, LTS_ERR_CAPACITY, "summed induction: too many summed charge values for one call");
-    if ((r = ensure(c, c->col_lo, sizeof(int32_t) * (size_t)sw.n_cols))) return r;
-    if ((r = ensure(c, c->col_hi, sizeof(int32_t) * (size_t)sw.n_cols))) return r;
     if ((r = ensure(c, c->col_seg_off, sizeof(int64_t) * (size_t)nc1))) return r;
     if ((r = ensure(c, c->col_cursor, sizeof(int32_t) * (size_t)sw.n_cols))) return r;
     if ((r = ensure(c, c->col_seg, sizeof(int32_t) * (size_t)n_colseg))) return r;
     if ((r = ensure(c, c->piece_off, sizeof(int64_t) * (size_t)nc1))) return r;
     if ((r = ensure(c, c->s_off, sizeof(int64_t) * (size_t)nc1))) return r;
-    if ((r = ensure(c, c->piece, sizeof(SegInfo) * (size_t)max_pieces))) return r;
-    if ((r = ensure(c, c->S, sizeof(float) * (size_t)(max_s + kCellSlack)))) return r;
     if ((r = ensure(c, c->list_off, sizeof(int64_t) * (size_t)(n_slots + 1)))) return r;
     if ((r = ensure(c, c->scan_tmp, sizeof(int64_t) * (size_t)scan_tmp_needed(std::max(nc1, n_slots + 1))))) return r;
-    sw.col_lo = as<int32_t>(c->col_lo);
-    sw.col_hi = as<int32_t>(c->col_hi);
     sw.col_seg_off = as<int64_t>(c->col_seg_off);
     sw.col_cursor = as<int32_t>(c->col_cursor);
     sw.col_seg = as<int32_t>(c->col_seg);
     sw.piece_off = as<int64_t>(c->piece_off);
     sw.s_off = as<int64_t>(c->s_off);
-    sw.piece = as<SegInfo>(c->piece);
-    sw.S = as<float>(c->S);
     sw.list_off = as<int64_t>(c->list_off);
     void *tmp = c->scan_tmp.p;
     HIP_TRY(c, hipMemsetAsync(sw.col_seg_off, 0, sizeof(int64_t) * (size_t)nc1, st));
@@ -376,16 +398,23 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     launch_sum_fill(P, w, sw, st);
     scan_exclusive_i64(sw.piece_off, nc1, nullptr, tmp, st);
     scan_exclusive_i64(sw.s_off, nc1, nullptr, tmp, st);
-    launch_sum_pieces(P, w, sw, st);
-    launch_sum_lists_count(P, w, sw, n_slots, st);
-    scan_exclusive_i64(sw.list_off, n_slots + 1, nullptr, tmp, st);
+    // exact sizes of the piece records and the summed charges (a column's merged tick intervals are only known
+    // after its segments are sorted)
     int64_t tot[3] = {0, 0, 0};
-    HIP_TRY(c, hipMemcpyAsync(&tot[0], sw.list_off + n_slots, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipMemcpyAsync(&tot[1], sw.piece_off + sw.n_cols, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipMemcpyAsync(&tot[2], sw.s_off + sw.n_cols, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
-    if (tot[1] > max_pieces || tot[2] > max_s)
-        return fail(c, LTS_ERR_DEVICE, "summed induction: column pieces exceed their bound");
+    if (tot[2] / kAC >= (int64_t)UINT32_MAX)          // piece records hold the charge offset in units of kAC floats
+        return fail(c, LTS_ERR_CAPACITY, "summed induction: too many summed charge values for one call");
+    if ((r = ensure(c, c->piece, sizeof(SegInfo) * (size_t)std::max<int64_t>(tot[1], 1)))) return r;
+    if ((r = ensure(c, c->S, sizeof(float) * (size_t)(tot[2] + kCellSlack)))) return r;
+    sw.piece = as<SegInfo>(c->piece);
+    sw.S = as<float>(c->S);
+    launch_sum_pieces(P, w, sw, st);
+    launch_sum_lists_count(P, w, sw, n_slots, st);
+    scan_exclusive_i64(sw.list_off, n_slots + 1, nullptr, tmp, st);
+    HIP_TRY(c, hipMemcpyAsync(&tot[0], sw.list_off + n_slots, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
     if ((r = ensure(c, c->list, sizeof(int32_t) * (size_t)std::max<int64_t>(tot[0], 1)))) return r;
     sw.list = as<int32_t>(c->list);
     if ((r = ensure(c, c->rec, sizeof(PieceRef) * (size_t)std::max<int64_t>(tot[0], 1)))) return r;
@@ -455,6 +484,8 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
         return fail(c, LTS_ERR_INVALID_ARG, "outputs: pixel_id, current, counts and report are required");
     if (n_ev < 1 || !event_ids || !seg_offsets) return fail(c, LTS_ERR_INVALID_ARG, "bad event list");
     HIP_TRY(c, hipSetDevice(c->device));
+    CallOrder order_(c, st);
+    if (order_.status) return order_.status;
     Work w;
     DevHeader h;
     if ((r = run_sizing(c, n_ev, event_ids, seg_offsets, segs, out->report, st, w, h))) return r;
@@ -581,6 +612,7 @@ const char *lts_last_error(const lts_context *ctx) { return ctx ? ctx->err.c_str
 
 lts_status lts_context_create(int device, const lts_physics *physics, const lts_readout *readout,
                               const lts_electronics *electronics, lts_context **out) {
+    LTS_API_BEGIN
     if (!out || !physics || !readout || !electronics) return LTS_ERR_INVALID_ARG;
     *out = nullptr;
     int n = 0;
@@ -604,6 +636,7 @@ lts_status lts_context_create(int device, const lts_physics *physics, const lts_
     }
     *out = c;
     return LTS_OK;
+    LTS_API_END(nullptr)
 }
 
 void lts_context_destroy(lts_context *c) {
@@ -618,7 +651,11 @@ void lts_context_destroy(lts_context *c) {
         (void)hipEventDestroy(pe.second.second);
     }
     for (hipEvent_t e : c->free_ev) (void)hipEventDestroy(e);
-    DevBuf *bufs[] = {&c->mask, &c->col_lo, &c->col_hi, &c->col_seg_off, &c->col_cursor, &c->col_seg, &c->piece_off, &c->s_off,
+    if (c->call_done) {
+        (void)hipEventSynchronize(c->call_done);
+        (void)hipEventDestroy(c->call_done);
+    }
+    DevBuf *bufs[] = {&c->ev_cnt, &c->mask, &c->col_seg_off, &c->col_cursor, &c->col_seg, &c->piece_off, &c->s_off,
                       &c->piece, &c->S, &c->list_off, &c->list, &c->rec, &c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off, &c->pix_cnt, &c->cursor, &c->pix_slot, &c->slot_gp,
                       &c->slot_off, &c->pairs_u, &c->pairs, &c->cells, &c->pk_tick, &c->pk_adc, &c->pk_flag,
                       &c->pk_off, &c->hdr, &c->scan_tmp, &c->ev_off, &c->ev_ids, &c->report_tmp, &c->counts_tmp,
@@ -629,12 +666,15 @@ void lts_context_destroy(lts_context *c) {
 }
 
 lts_status lts_set_timing(lts_context *c, int32_t enabled) {
+    LTS_API_BEGIN
     if (!c) return LTS_ERR_INVALID_ARG;
     c->timing = enabled != 0;
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_get_timing(lts_context *c, double ms[LTS_N_STAGES], int64_t calls[LTS_N_STAGES]) {
+    LTS_API_BEGIN
     if (!c || !ms) return LTS_ERR_INVALID_ARG;
     HIP_TRY(c, hipSetDevice(c->device));
     for (auto &pe : c->pending_ev) {
@@ -654,52 +694,66 @@ lts_status lts_get_timing(lts_context *c, double ms[LTS_N_STAGES], int64_t calls
         c->stage_calls[i] = 0;
     }
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_set_induce_slices(lts_context *c, int32_t slices) {
+    LTS_API_BEGIN
     if (!c) return LTS_ERR_INVALID_ARG;
     if (slices < 1 || slices > 64) return fail(c, LTS_ERR_INVALID_ARG, "slices must be in [1, 64]");
     c->induce_slices = slices;
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_set_ticks_per_thread(lts_context *c, int32_t rt) {
+    LTS_API_BEGIN
     if (!c) return LTS_ERR_INVALID_ARG;
     if (rt != 0 && rt != 1 && rt != 2 && rt != 4 && rt != 8)
         return fail(c, LTS_ERR_INVALID_ARG, "ticks per thread must be 0 (auto), 1, 2, 4 or 8");
     c->ticks_per_thread = rt;
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_set_lane_exchange(lts_context *c, int32_t on) {
+    LTS_API_BEGIN
     if (!c) return LTS_ERR_INVALID_ARG;
     if (on != 0 && on != 1) return fail(c, LTS_ERR_INVALID_ARG, "lane exchange must be 0 or 1");
     c->lane_exchange = on;
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_set_matrix_cores(lts_context *c, int32_t on) {
+    LTS_API_BEGIN
     if (!c) return LTS_ERR_INVALID_ARG;
     if (on != 0 && on != 1) return fail(c, LTS_ERR_INVALID_ARG, "matrix cores must be 0 or 1");
     c->matrix_cores = on;
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_set_graph(lts_context *c, int32_t on) {
+    LTS_API_BEGIN
     if (!c) return LTS_ERR_INVALID_ARG;
     if (on != 0 && on != 1) return fail(c, LTS_ERR_INVALID_ARG, "graph must be 0 or 1");
     c->use_graph = on != 0;
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_graph_stats(lts_context *c, int64_t *updates, int64_t *instantiations) {
+    LTS_API_BEGIN
     if (!c || !updates || !instantiations) return LTS_ERR_INVALID_ARG;
     *updates = c->graph_updates;
     *instantiations = c->graph_instantiations;
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_set_channel_mask(lts_context *c, const uint8_t *mask, int64_t n) {
+    LTS_API_BEGIN
     if (!c) return LTS_ERR_INVALID_ARG;
     if (!mask || n == 0) {
         c->has_mask = false;
@@ -712,22 +766,27 @@ lts_status lts_set_channel_mask(lts_context *c, const uint8_t *mask, int64_t n) 
     HIP_TRY(c, hipMemcpy(c->mask.p, mask, (size_t)n, hipMemcpyHostToDevice));
     c->has_mask = true;
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_set_reduce_mode(lts_context *c, int32_t mode) {
+    LTS_API_BEGIN
     if (!c) return LTS_ERR_INVALID_ARG;
     if (mode != LTS_REDUCE_SORTED && mode != LTS_REDUCE_ATOMIC && mode != LTS_REDUCE_SUMMED)
         return fail(c, LTS_ERR_INVALID_ARG, "unknown reduce mode");
     c->reduce_mode = mode;
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_set_response(lts_context *c, const float *R, int32_t t_r, int32_t b_x, int32_t b_y) {
+    LTS_API_BEGIN
     if (!c) return LTS_ERR_INVALID_ARG;
     if (!R || t_r < 1 || t_r > 8192 || b_x < 1 || b_x > 256 || b_y < 1 || b_y > 256)
         return fail(c, LTS_ERR_INVALID_ARG, "response table shape must be 1..8192 x 1..256 x 1..256");
     const size_t ncol = (size_t)b_x * b_y;
     const int32_t col_len = kPad + (t_r + 7) / 8 * 8 + kPad;      // a multiple of 8: columns start 32-byte aligned
+    host_alloc_point();
     std::vector<float> pad(ncol * (size_t)col_len, 0.0f);
     std::vector<double> pre(ncol * (size_t)(t_r + 1), 0.0);
     for (int32_t i = 0; i < b_x; ++i)
@@ -759,15 +818,19 @@ lts_status lts_set_response(lts_context *c, const float *R, int32_t t_r, int32_t
     c->P.col_len = col_len;
     c->has_table = true;
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_plan(lts_context *c, const lts_segments *segs, int64_t need[4], void *stream) {
+    LTS_API_BEGIN
     if (!c || !need) return LTS_ERR_INVALID_ARG;
     if (c->sticky) return fail(c, c->sticky, "context is in a failed state: " + c->err);
     if (!c->has_table) return fail(c, LTS_ERR_STATE, "no response table: call lts_set_response first");
     lts_status r;
     if ((r = check_segments(c, segs))) return r;
     HIP_TRY(c, hipSetDevice(c->device));
+    CallOrder order_(c, to_stream(stream));
+    if (order_.status) return order_.status;
     if ((r = ensure(c, c->report_tmp, sizeof(double) * 5))) return r;
     const uint64_t eid = 0;
     const int64_t off[2] = {0, segs->n};
@@ -779,25 +842,31 @@ lts_status lts_plan(lts_context *c, const lts_segments *segs, int64_t need[4], v
     need[2] = h.n_cells;
     need[3] = h.n_slots * c->P.max_packets;
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_simulate(lts_context *c, uint64_t event_id, const lts_segments *segs, const lts_outputs *out,
                         void *stream) {
+    LTS_API_BEGIN
     if (!c) return LTS_ERR_INVALID_ARG;
     if (!segs) return fail(c, LTS_ERR_INVALID_ARG, "segments is NULL");
     const int64_t off[2] = {0, segs->n};
     return run_pipeline(c, 1, &event_id, off, segs, out, to_stream(stream));
+    LTS_API_END(c)
 }
 
 lts_status lts_simulate_batch(lts_context *c, int32_t n_events, const uint64_t *event_ids, const int64_t *seg_offsets,
                               const lts_segments *segs, const lts_outputs *out, void *stream) {
+    LTS_API_BEGIN
     if (!c) return LTS_ERR_INVALID_ARG;
     if (out && (!out->event_pixel_offsets || !out->event_packet_offsets))
         return fail(c, LTS_ERR_INVALID_ARG, "batch outputs need event_pixel_offsets and event_packet_offsets");
     return run_pipeline(c, n_events, event_ids, seg_offsets, segs, out, to_stream(stream));
+    LTS_API_END(c)
 }
 
 lts_status lts_stage_quench_drift(lts_context *c, const lts_segments *segs, float *out_f, int32_t *out_i, void *stream) {
+    LTS_API_BEGIN
     if (!c) return LTS_ERR_INVALID_ARG;
     lts_status r;
     if ((r = check_segments(c, segs))) return r;
@@ -806,9 +875,11 @@ lts_status lts_stage_quench_drift(lts_context *c, const lts_segments *segs, floa
     launch_stage_quench_drift(c->P, seg_arrays(segs), segs->n, out_f, out_i, to_stream(stream));
     HIP_TRY(c, hipGetLastError());
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_debug_cells(lts_context *c, int64_t segment, int64_t box[6], float *cells_host, int64_t cap) {
+    LTS_API_BEGIN
     if (!c || !box) return LTS_ERR_INVALID_ARG;
     if (segment < 0 || segment >= c->last_n_seg) return fail(c, LTS_ERR_STATE, "segment not in the last simulated call");
     HIP_TRY(c, hipSetDevice(c->device));
@@ -825,15 +896,19 @@ lts_status lts_debug_cells(lts_context *c, int64_t segment, int64_t box[6], floa
             for (int32_t v = 0; v < g.nv; ++v)
                 cells_host[((int64_t)a * g.nu + u) * g.nv + v] = tmp[((size_t)u * g.nv + v) * g.na_pad + a];
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_stage_electronics(lts_context *c, uint64_t event_id, const int32_t *pixel_ids, const float *current,
                                  int64_t n_pix, const lts_outputs *out, void *stream) {
+    LTS_API_BEGIN
     if (!c) return LTS_ERR_INVALID_ARG;
     if (!pixel_ids || !current || n_pix < 0 || !out || !out->counts)
         return fail(c, LTS_ERR_INVALID_ARG, "bad electronics stage arguments");
     HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t st = to_stream(stream);
+    CallOrder order_(c, st);
+    if (order_.status) return order_.status;
     lts_status r;
     const int64_t mp = c->P.max_packets;
     if ((r = ensure(c, c->pk_tick, sizeof(int32_t) * (size_t)(n_pix * mp)))) return r;
@@ -865,6 +940,7 @@ lts_status lts_stage_electronics(lts_context *c, uint64_t event_id, const int32_
                            nullptr, nullptr, out->counts, st);
     HIP_TRY(c, hipGetLastError());
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 // Front half of the pipeline for the pair-level hooks: sizing, slots, pixel-major pairs in ascending segment order,
@@ -908,6 +984,9 @@ static lts_status stage_pairs(lts_context *c, uint64_t event_id, const lts_segme
     if (!c) return LTS_ERR_INVALID_ARG;
     if (!n_pairs_out || cap_pairs < 0) return fail(c, LTS_ERR_INVALID_ARG, "n_pairs_out is NULL or cap_pairs < 0");
     hipStream_t st = to_stream(stream);
+    HIP_TRY(c, hipSetDevice(c->device));
+    CallOrder order_(c, st);
+    if (order_.status) return order_.status;
     Work w;
     DevHeader h;
     lts_status r;
@@ -926,26 +1005,33 @@ static lts_status stage_pairs(lts_context *c, uint64_t event_id, const lts_segme
 
 lts_status lts_stage_rasterize(lts_context *c, const lts_segments *segs, int32_t *pair_segment, int32_t *pair_pixel,
                                int64_t cap_pairs, int64_t *n_pairs_out, void *stream) {
+    LTS_API_BEGIN
     if (c && (!pair_segment || !pair_pixel)) return fail(c, LTS_ERR_INVALID_ARG, "NULL pair output");
     return stage_pairs(c, 0, segs, pair_segment, pair_pixel, nullptr, cap_pairs, n_pairs_out, stream);
+    LTS_API_END(c)
 }
 
 lts_status lts_stage_induce(lts_context *c, uint64_t event_id, const lts_segments *segs, int32_t *pair_segment,
                             int32_t *pair_pixel, float *pair_current, int64_t cap_pairs, int64_t *n_pairs_out,
                             void *stream) {
+    LTS_API_BEGIN
     if (c && !pair_current) return fail(c, LTS_ERR_INVALID_ARG, "NULL pair_current");
     return stage_pairs(c, event_id, segs, pair_segment, pair_pixel, pair_current, cap_pairs, n_pairs_out, stream);
+    LTS_API_END(c)
 }
 
 lts_status lts_stage_reduce(lts_context *c, const int32_t *pair_pixel, const float *pair_current, int64_t n_pairs,
                             int32_t *pixel_id, float *current, int64_t cap_pixels, int64_t *n_pixels_out,
                             void *stream) {
+    LTS_API_BEGIN
     if (!c) return LTS_ERR_INVALID_ARG;
     if (!n_pixels_out || n_pairs < 0 || cap_pixels < 0 || (n_pairs > 0 && (!pair_pixel || !pair_current)) ||
         (cap_pixels > 0 && (!pixel_id || !current)))
         return fail(c, LTS_ERR_INVALID_ARG, "bad reduce stage arguments");
     HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t st = to_stream(stream);
+    CallOrder order_(c, st);
+    if (order_.status) return order_.status;
     *n_pixels_out = 0;
     if (n_pairs == 0) return LTS_OK;
     lts_status r;
@@ -971,9 +1057,11 @@ lts_status lts_stage_reduce(lts_context *c, const int32_t *pair_pixel, const flo
     launch_reduce_runs(pair_current, start, n_runs, c->P.nticks, current, st);
     HIP_TRY(c, hipGetLastError());
     return LTS_OK;
+    LTS_API_END(c)
 }
 
 lts_status lts_work_stats(lts_context *c, double out[4]) {
+    LTS_API_BEGIN
     if (!c || !out) return LTS_ERR_INVALID_ARG;
     if (c->last_n_seg < 0) return fail(c, LTS_ERR_STATE, "no pipeline call yet");
     HIP_TRY(c, hipSetDevice(c->device));
@@ -1004,12 +1092,21 @@ lts_status lts_work_stats(lts_context *c, double out[4]) {
     HIP_TRY(c, hipMemcpy(h, c->counts_tmp.p, sizeof(h), hipMemcpyDeviceToHost));
     for (int i = 0; i < 4; ++i) out[i] = (double)h[i];
     return LTS_OK;
+    LTS_API_END(c)
+}
+
+lts_status lts_debug_fail_host_alloc(int64_t after) {
+    if (after < -1) return LTS_ERR_INVALID_ARG;
+    g_host_alloc_fail.store(after);
+    return LTS_OK;
 }
 
 lts_status lts_stage_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n, void *stream) {
+    LTS_API_BEGIN
     if (!ctr || !out || n < 0) return LTS_ERR_INVALID_ARG;
     launch_philox(ctr, k0, k1, out, n, to_stream(stream));
     return hipGetLastError() == hipSuccess ? LTS_OK : LTS_ERR_DEVICE;
+    LTS_API_END(nullptr)
 }
 
 }  // extern "C"
@@ -1099,6 +1196,7 @@ void lane_run_batch(Lane *L, std::vector<Request *> &batch) {
         offs[e + 1] = offs[e] + batch[e]->n;
         ids[e] = batch[e]->event_id;
     }
+    host_alloc_point();
     lts_status st = LTS_OK;
     const size_t colb = sizeof(float) * (size_t)std::max<int64_t>(nseg, 1);
     if (!ensure_pinned(L->stage, 10 * colb)) st = LTS_ERR_OOM;
@@ -1142,12 +1240,14 @@ void lane_run_batch(Lane *L, std::vector<Request *> &batch) {
         st = LTS_OK;
     }
     // results back to host
-    std::vector<Finished *> fin(ne, nullptr);
+    std::vector<std::unique_ptr<Finished>> fin(ne);
     int64_t cnt[4] = {0, 0, 0, 0};
     std::vector<int64_t> evpix(ne + 1, 0), evpkt(ne + 1, 0);
     std::vector<double> rep(5 * (size_t)ne, 0.0);
+    std::vector<int64_t> evc(2 * (size_t)ne, 0);
     if (st == LTS_OK) {
         if (hipMemcpyAsync(cnt, L->counts.p, sizeof(cnt), hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
+            hipMemcpyAsync(evc.data(), c->ev_cnt.p, sizeof(int64_t) * 2 * ne, hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
             hipMemcpyAsync(evpix.data(), L->evpix.p, sizeof(int64_t) * (ne + 1), hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
             hipMemcpyAsync(evpkt.data(), L->evpkt.p, sizeof(int64_t) * (ne + 1), hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
             hipMemcpyAsync(rep.data(), L->report.p, sizeof(double) * 5 * ne, hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
@@ -1174,8 +1274,8 @@ void lane_run_batch(Lane *L, std::vector<Request *> &batch) {
         if (!ok || hipStreamSynchronize(L->stream) != hipSuccess) st = LTS_ERR_DEVICE;
     }
     for (int32_t e = 0; e < ne; ++e) {
-        Finished *f = new Finished();
-        fin[e] = f;
+        fin[e].reset(new Finished());
+        Finished *f = fin[e].get();
         f->v.event_id = batch[e]->event_id;
         f->v.t_submit = batch[e]->t_submit;
         f->v.t_start = t_start;
@@ -1199,8 +1299,8 @@ void lane_run_batch(Lane *L, std::vector<Request *> &batch) {
             for (int k = 0; k < 5; ++k) f->v.report[k] = rep[5 * (size_t)e + k];
             f->v.counts[0] = p1 - p0;
             f->v.counts[1] = k1 - k0;
-            f->v.counts[2] = cnt[2];
-            f->v.counts[3] = cnt[3];
+            f->v.counts[2] = evc[2 * (size_t)e];         // this event's own dropped samples and overflow packets
+            f->v.counts[3] = evc[2 * (size_t)e + 1];
         }
         f->v.status = st;
         f->v.pixel_id = f->pixel_id.data();
@@ -1220,14 +1320,55 @@ void lane_run_batch(Lane *L, std::vector<Request *> &batch) {
         fin[e]->v.t_done = t_done;
         const uint64_t t = batch[e]->ticket;
         auto it = S->state.find(t);
+        bool kept = false;
         if (it != S->state.end()) {
-            S->done[t] = fin[e];
-            it->second = 2;
-        } else {
-            delete fin[e];
+            try {
+                S->done[t] = fin[e].get();
+                it->second = 2;
+                kept = true;
+            } catch (...) {
+                it->second = 3;                          // no room for the result: the ticket reads as cancelled
+            }
         }
+        if (kept) (void)fin[e].release();
         delete batch[e];
     }
+    batch.clear();
+    S->cv_done.notify_all();
+}
+
+// A batch whose host-side work threw before its results were published: every ticket of it finishes with `st`
+// (or reads as cancelled if even that cannot be recorded).  Never throws.
+void lane_fail_batch(Lane *L, std::vector<Request *> &batch, lts_status st) noexcept {
+    lts_server *S = L->srv;
+    const double t = now_s();
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (Request *r : batch) {
+        auto it = S->state.find(r->ticket);
+        if (it != S->state.end()) {
+            Finished *f = new (std::nothrow) Finished();
+            bool kept = false;
+            if (f) {
+                f->v.event_id = r->event_id;
+                f->v.status = st;
+                f->v.t_submit = r->t_submit;
+                f->v.t_start = f->v.t_done = t;
+                f->v.batch_events = (int32_t)batch.size();
+                try {
+                    S->done[r->ticket] = f;
+                    it->second = 2;
+                    kept = true;
+                } catch (...) {
+                }
+            }
+            if (!kept) {
+                delete f;
+                it->second = 3;
+            }
+        }
+        delete r;
+    }
+    batch.clear();
     S->cv_done.notify_all();
 }
 
@@ -1237,6 +1378,12 @@ void lane_loop(Lane *L) {
     const double budget = (double)S->cfg.mem_budget_bytes / (double)S->cfg.n_lanes;
     for (;;) {
         std::vector<Request *> batch;
+        try {
+            batch.reserve((size_t)S->cfg.max_batch_events);
+        } catch (...) {
+            std::this_thread::sleep_for(std::chrono::milliseconds(10));   // host memory is short: try again
+            continue;
+        }
         {
             std::unique_lock<std::mutex> lk(S->mu);
             S->cv_work.wait(lk, [&] { return S->stopping || !S->queue.empty(); });
@@ -1252,7 +1399,13 @@ void lane_loop(Lane *L) {
                 segs += r->n;
             }
         }
-        lane_run_batch(L, batch);
+        try {
+            lane_run_batch(L, batch);
+        } catch (const std::bad_alloc &) {
+            lane_fail_batch(L, batch, LTS_ERR_OOM);
+        } catch (...) {
+            lane_fail_batch(L, batch, LTS_ERR_DEVICE);
+        }
     }
 }
 
@@ -1261,6 +1414,7 @@ void lane_loop(Lane *L) {
 extern "C" {
 
 lts_status lts_server_start(lts_context *ctx, const lts_server_cfg *cfg, lts_server **out) {
+    LTS_API_BEGIN
     if (!ctx || !out) return LTS_ERR_INVALID_ARG;
     *out = nullptr;
     if (!ctx->has_table) return fail(ctx, LTS_ERR_STATE, "no response table: call lts_set_response first");
@@ -1273,40 +1427,68 @@ lts_status lts_server_start(lts_context *ctx, const lts_server_cfg *cfg, lts_ser
     if (S->cfg.mem_budget_bytes <= 0) S->cfg.mem_budget_bytes = 32ll << 30;
     S->device = ctx->device;
     S->n_ticks = ctx->ro.n_ticks;
-    for (int i = 0; i < S->cfg.n_lanes; ++i) {
-        std::unique_ptr<Lane> L(new Lane());
-        L->srv = S;
-        lts_status r = lts_context_create(ctx->device, &ctx->ph, &ctx->ro, &ctx->el, &L->ctx);
-        if (r == LTS_OK) r = lts_set_response(L->ctx, ctx->table_host.data(), ctx->t_r, ctx->b_x, ctx->b_y);
-        if (r == LTS_OK) r = lts_set_reduce_mode(L->ctx, ctx->reduce_mode);
-        if (r == LTS_OK) r = lts_set_induce_slices(L->ctx, ctx->induce_slices);
-        if (r == LTS_OK) r = lts_set_ticks_per_thread(L->ctx, ctx->ticks_per_thread);
-        if (r == LTS_OK) r = lts_set_lane_exchange(L->ctx, ctx->lane_exchange);
-        if (r == LTS_OK) r = lts_set_matrix_cores(L->ctx, ctx->matrix_cores);
-        if (r == LTS_OK && hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess) r = LTS_ERR_DEVICE;
-        if (r != LTS_OK) {
-            if (L->ctx) lts_context_destroy(L->ctx);
-            S->stopping = true;
-            for (auto &l : S->lanes) {
-                lts_context_destroy(l->ctx);
-                (void)hipStreamDestroy(l->stream);
-            }
-            delete S;
-            return fail(ctx, r, "server lane creation failed");
+    auto undo = [&] {                                  // destroys the lanes made so far (no thread started yet)
+        for (auto &l : S->lanes) {
+            if (l->ctx) lts_context_destroy(l->ctx);
+            if (l->stream) (void)hipStreamDestroy(l->stream);
         }
-        S->lanes.push_back(std::move(L));
+        delete S;
+    };
+    try {
+        S->lanes.reserve((size_t)S->cfg.n_lanes);
+        for (int i = 0; i < S->cfg.n_lanes; ++i) {
+            S->lanes.emplace_back(new Lane());
+            Lane *L = S->lanes.back().get();
+            L->srv = S;
+            lts_status r = lts_context_create(ctx->device, &ctx->ph, &ctx->ro, &ctx->el, &L->ctx);
+            if (r == LTS_OK) r = lts_set_response(L->ctx, ctx->table_host.data(), ctx->t_r, ctx->b_x, ctx->b_y);
+            if (r == LTS_OK) r = lts_set_reduce_mode(L->ctx, ctx->reduce_mode);
+            if (r == LTS_OK) r = lts_set_induce_slices(L->ctx, ctx->induce_slices);
+            if (r == LTS_OK) r = lts_set_ticks_per_thread(L->ctx, ctx->ticks_per_thread);
+            if (r == LTS_OK) r = lts_set_lane_exchange(L->ctx, ctx->lane_exchange);
+            if (r == LTS_OK) r = lts_set_matrix_cores(L->ctx, ctx->matrix_cores);
+            if (r == LTS_OK && hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess) {
+                L->stream = nullptr;
+                r = LTS_ERR_DEVICE;
+            }
+            if (r != LTS_OK) {
+                undo();
+                return fail(ctx, r, "server lane creation failed");
+            }
+        }
+    } catch (...) {
+        undo();
+        throw;
     }
-    for (auto &L : S->lanes) L->th = std::thread(lane_loop, L.get());
+    try {
+        for (auto &L : S->lanes) L->th = std::thread(lane_loop, L.get());
+    } catch (...) {                                     // a lane thread could not start: undo the started ones
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stopping = true;
+            S->cv_work.notify_all();
+        }
+        for (auto &L : S->lanes) {
+            if (L->th.joinable()) L->th.join();
+            lts_context_destroy(L->ctx);
+            (void)hipStreamDestroy(L->stream);
+        }
+        delete S;
+        return fail(ctx, LTS_ERR_DEVICE, "server lane thread could not be started");
+    }
     *out = S;
     return LTS_OK;
+    LTS_API_END(ctx)
 }
 
 lts_status lts_server_submit(lts_server *S, uint64_t event_id, const lts_segments *h, uint64_t *ticket) {
+    LTS_API_BEGIN
     if (!S || !h || !ticket || h->n < 0) return LTS_ERR_INVALID_ARG;
     if (h->n > 0 && !(h->x0 && h->y0 && h->z0 && h->t0 && h->x1 && h->y1 && h->z1 && h->t1 && h->energy))
         return LTS_ERR_INVALID_ARG;
-    Request *r = new (std::nothrow) Request();
-    if (!r) return LTS_ERR_OOM;
+    host_alloc_point();
+    std::unique_ptr<Request> held(new Request());     // freed if anything below throws
+    Request *r = held.get();
     r->event_id = event_id;
     r->n = h->n;
     r->t_submit = now_s();
@@ -1318,16 +1500,20 @@ lts_status lts_server_submit(lts_server *S, uint64_t event_id, const lts_segment
         else std::fill(dst, dst + h->n, NAN);
     }
     std::lock_guard<std::mutex> lk(S->mu);
-    if (S->stopping) {
-        delete r;
-        return LTS_ERR_STATE;
-    }
+    if (S->stopping) return LTS_ERR_STATE;
     r->ticket = S->next_ticket++;
     S->state[r->ticket] = 0;
-    S->queue.push_back(r);
+    try {
+        S->queue.push_back(r);
+    } catch (...) {
+        S->state.erase(r->ticket);
+        throw;
+    }
+    held.release();
     *ticket = r->ticket;
     S->cv_work.notify_one();
     return LTS_OK;
+    LTS_API_END(nullptr)
 }
 
 static lts_status server_view(lts_server *S, uint64_t t, lts_result_view *out) {
@@ -1341,12 +1527,15 @@ static lts_status server_view(lts_server *S, uint64_t t, lts_result_view *out) {
 }
 
 lts_status lts_server_poll(lts_server *S, uint64_t t, lts_result_view *out) {
+    LTS_API_BEGIN
     if (!S) return LTS_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(S->mu);
     return server_view(S, t, out);
+    LTS_API_END(nullptr)
 }
 
 lts_status lts_server_wait(lts_server *S, uint64_t t, lts_result_view *out, double timeout_s) {
+    LTS_API_BEGIN
     if (!S) return LTS_ERR_INVALID_ARG;
     std::unique_lock<std::mutex> lk(S->mu);
     auto ready = [&] {
@@ -1356,9 +1545,11 @@ lts_status lts_server_wait(lts_server *S, uint64_t t, lts_result_view *out, doub
     if (timeout_s < 0) S->cv_done.wait(lk, ready);
     else S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready);
     return server_view(S, t, out);
+    LTS_API_END(nullptr)
 }
 
 lts_status lts_server_release(lts_server *S, uint64_t t) {
+    LTS_API_BEGIN
     if (!S) return LTS_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->state.find(t);
@@ -1371,9 +1562,11 @@ lts_status lts_server_release(lts_server *S, uint64_t t) {
     }
     S->state.erase(it);
     return LTS_OK;
+    LTS_API_END(nullptr)
 }
 
 lts_status lts_server_stop(lts_server *S) {
+    LTS_API_BEGIN
     if (!S) return LTS_ERR_INVALID_ARG;
     {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -1403,6 +1596,7 @@ lts_status lts_server_stop(lts_server *S) {
     for (auto &kv : S->done) delete kv.second;
     delete S;
     return LTS_OK;
+    LTS_API_END(nullptr)
 }
 
 }  // extern "C"

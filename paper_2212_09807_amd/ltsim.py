@@ -79,7 +79,7 @@ EXPORTS = ("lts_server_start", "lts_server_submit", "lts_server_poll", "lts_serv
            "lts_server_stop", "lts_set_timing", "lts_get_timing", "lts_work_stats", "lts_context_create", "lts_context_destroy",
            "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_set_ticks_per_thread", "lts_set_lane_exchange", "lts_set_matrix_cores", "lts_set_graph", "lts_graph_stats", "lts_set_channel_mask",
            "lts_plan", "lts_simulate", "lts_simulate_batch", "lts_stage_quench_drift", "lts_debug_cells",
-           "lts_stage_electronics", "lts_stage_philox", "lts_stage_rasterize", "lts_stage_induce", "lts_stage_reduce", "lts_status_str", "lts_last_error", "lts_version",
+           "lts_stage_electronics", "lts_stage_philox", "lts_debug_fail_host_alloc", "lts_stage_rasterize", "lts_stage_induce", "lts_stage_reduce", "lts_status_str", "lts_last_error", "lts_version",
            "lts_light_create", "lts_light_destroy", "lts_light_simulate", "lts_light_set_graph", "lts_light_last_error")
 
 
@@ -125,6 +125,7 @@ def lib():
                                        C.POINTER(C.c_int64), P]
         L.lts_stage_reduce.argtypes = [P, P, P, C.c_int64, P, P, C.c_int64, C.POINTER(C.c_int64), P]
         L.lts_work_stats.argtypes = [P, C.POINTER(C.c_double)]
+        L.lts_debug_fail_host_alloc.argtypes = [C.c_int64]
         L.lts_server_start.argtypes = [P, C.POINTER(lts_server_cfg), C.POINTER(P)]
         L.lts_server_submit.argtypes = [P, C.c_uint64, C.POINTER(lts_segments), C.POINTER(C.c_uint64)]
         L.lts_server_poll.argtypes = [P, C.c_uint64, C.POINTER(lts_result_view)]
@@ -438,6 +439,13 @@ def philox(ctr, k0: int, k1: int, stream=None):
     if st:
         raise LtsimError(st, "lts_stage_philox")
     return out
+
+
+def fail_host_alloc(after: int):
+    """Test hook (lts_debug_fail_host_alloc): the library's `after`-th next host allocation point fails once; -1 off."""
+    st = lib().lts_debug_fail_host_alloc(after)
+    if st:
+        raise LtsimError(st, "lts_debug_fail_host_alloc")
 
 
 def _arr(ptr, n, dtype):

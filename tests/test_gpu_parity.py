@@ -254,6 +254,108 @@ def _max_window_workload():
     return w
 
 
+def _stacked_tracks_workload():
+    """Two parallel 20-segment tracks over the same pixels at 5 and 15 cm of drift (about 600 ticks apart), plus a
+    third one crossing both at 10 cm: the sub-pixel columns under them hold charge in separate tick ranges, which the
+    summed induction must cut into separate pieces (a column's span is far longer than its segments' charge)."""
+    rng = np.random.default_rng(21)
+    w = W.config(1)
+    parts = []
+    for z, (x0, x1), (y0, y1) in ((5.0, (8.0, 20.0), (12.0, 12.3)), (15.0, (8.0, 20.0), (12.0, 12.3)),
+                                  (10.0, (14.0, 14.4), (6.0, 18.0))):
+        n = 20
+        s = np.arange(n + 1) / n
+        pts = np.stack([x0 + s * (x1 - x0), y0 + s * (y1 - y0), np.full(n + 1, z)], 1)
+        L = np.linalg.norm(np.diff(pts, axis=0), axis=1)
+        parts.append(W.make_segments(pts[:-1], pts[1:], W.mip_dedx(rng, n) * L, t0=np.zeros(n), t1=np.zeros(n)))
+    w.events, w.event_ids = [W.Segments.concat(parts)], [31]
+    return w
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_stacked_drift_separated_tracks_parity(lt, orc, torch, mode):
+    h, r, e, (cmp_, flg) = check_event(lt, orc, _stacked_tracks_workload(), mode=mode)
+    print(f"stacked tracks mode={mode}: pixels {len(r['pixels'])} max e_p {e.max():.2e} packets compared {cmp_}")
+    assert cmp_ > 20
+
+
+def test_stacked_tracks_summed_batch_equals_single(lt, torch):
+    """The gap-cut summed columns are batch-invariant: a batch of the stacked event with a shifted copy gives each
+    event's single-call currents bit for bit."""
+    w = _stacked_tracks_workload()
+    evs = [w.events[0], w.events[0].shifted(dt=2.5)]
+    ctx = lt.Context.from_workload(w, reduce_mode=2)
+    singles = [ctx.simulate(lt.to_device(s), event_id=i).host() for s, i in zip(evs, (31, 32))]
+    offs = np.r_[0, np.cumsum([s.n for s in evs])]
+    b = ctx.simulate_batch(lt.to_device(W.Segments.concat(evs)), offs, [31, 32]).host()
+    po = b["event_pixel_offsets"]
+    for e, s in enumerate(singles):
+        assert np.array_equal(b["pixel_id"][po[e]:po[e + 1]], s["pixel_id"])
+        assert np.array_equal(b["current"][po[e]:po[e + 1]], s["current"])
+
+
+def test_calls_on_two_streams_do_not_race(lt, torch):
+    """Consecutive calls on one context given different streams, with no host synchronisation between their
+    device work, give the results of separate synchronised calls (each call waits for the previous one's work on
+    the shared scratch pool)."""
+    w = W.make_workload(1, n_events=2)
+    w.events[1] = w.events[1].shifted(dt=4.0)
+    ctx = lt.Context.from_workload(w)
+    d = [lt.to_device(s) for s in w.events]
+    ref = [ctx.simulate(x, event_id=i).host() for x, i in zip(d, w.event_ids)]
+    outs = [ctx._alloc(ref[k]["counts"][0], ref[k]["counts"][0] * w.electronics.max_packets, 1, False)
+            for k in range(2)]
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for rep in range(3):
+        for k, st in ((0, s1), (1, s2)):
+            ctx.simulate(d[k], event_id=w.event_ids[k], stream=st, out=outs[k])
+        torch.cuda.synchronize()
+        for k in range(2):
+            g = outs[k].host()
+            assert np.array_equal(g["pixel_id"], ref[k]["pixel_id"]), (rep, k)
+            assert np.array_equal(g["current"], ref[k]["current"]), (rep, k)
+            assert np.array_equal(g["pkt_tick"], ref[k]["pkt_tick"]), (rep, k)
+
+
+def test_host_allocation_failure_returns_oom(lt, torch):
+    """A host allocation that fails inside a call comes back as LTS_ERR_OOM (no exception crosses the ABI), and the
+    context and a server keep working: the failed server batch fails only its own tickets."""
+    w = W.make_workload(1, n_events=2)
+    table = W.response_table(w.table, w.readout, w.physics.v_drift)
+    ctx = lt.Context.from_workload(w, table=table)
+    lt.fail_host_alloc(0)
+    try:
+        with pytest.raises(lt.LtsimError) as ei:
+            ctx._check(lt.lib().lts_set_response(ctx._h, np.ascontiguousarray(table).ctypes.data_as(
+                __import__("ctypes").c_void_p), *table.shape))
+        assert ei.value.status == 3
+    finally:
+        lt.fail_host_alloc(-1)
+    h = ctx.simulate(lt.to_device(w.events[0]), event_id=w.event_ids[0]).host()      # still usable
+    assert h["counts"][0] > 0
+    srv = lt.Server(ctx, n_lanes=1, max_batch_events=1)
+    try:
+        lt.fail_host_alloc(0)                       # the next allocation point: the submission's copy
+        with pytest.raises(lt.LtsimError) as ei:
+            srv.submit(w.events[0], w.event_ids[0])
+        assert ei.value.status == 3
+        lt.fail_host_alloc(1)                       # the submission passes, the lane's batch set-up fails
+        t0 = srv.submit(w.events[0], w.event_ids[0])
+        with pytest.raises(lt.LtsimError) as ei:
+            srv.wait(t0, 60.0)
+        assert ei.value.status == 3
+        lt.fail_host_alloc(-1)
+        t1 = srv.submit(w.events[1], w.event_ids[1])
+        g = srv.wait(t1, 60.0)
+        assert g["status"] == 0 and len(g["pixel_id"]) > 0
+        srv.release(t0)
+        srv.release(t1)
+    finally:
+        lt.fail_host_alloc(-1)
+        srv.stop()
+
+
 @pytest.mark.parametrize("mode,rt,shift", [(0, 0, False), (0, 8, False), (0, 0, True), (1, 0, False), (2, 0, False)])
 def test_max_window_long_table_parity(lt, orc, torch, mode, rt, shift):
     w = _max_window_workload()
@@ -520,10 +622,11 @@ def test_graph_replay_equals_direct_launches(lt, torch):
 def test_served_results_equal_alone(lt, torch):
     """Events served in a mix (continuous batching over two lanes) give the same result as each event alone."""
     w = W.make_workload(1, n_events=6)
-    for e in range(6):
-        w.events[e] = w.events[e].shifted(dt=0.5 * e)
+    for e in range(6):                              # the last event arrives late: samples fall past the window
+        w.events[e] = w.events[e].shifted(dt=0.5 * e if e < 5 else 21.5)
     ctx = lt.Context.from_workload(w)
     alone = [ctx.simulate(lt.to_device(s), event_id=i).host() for s, i in zip(w.events, w.event_ids)]
+    assert alone[5]["counts"][2] > 0 and alone[0]["counts"][2] == 0
     srv = lt.Server(ctx, n_lanes=2, max_batch_events=4, return_currents=True)
     try:
         tickets = [srv.submit(s, i) for s, i in zip(w.events, w.event_ids)]
@@ -538,6 +641,8 @@ def test_served_results_equal_alone(lt, torch):
         assert np.array_equal(a["pixel_id"], g["pixel_id"])
         assert np.array_equal(a["current"], g["current"])            # deterministic sorted reduction
         assert np.array_equal(a["pkt_tick"], g["pkt_tick"]) and np.array_equal(a["pkt_adc"], g["pkt_adc"])
+        assert np.array_equal(a["pkt_flags"], g["pkt_flags"])
+        assert np.array_equal(a["counts"], g["counts"])              # per-event dropped / overflow counts
         np.testing.assert_allclose(a["report"][0], g["report"], rtol=1e-12, atol=1e-9)
 
 
