@@ -276,6 +276,18 @@ lts_status lts_stage_reduce(lts_context *ctx, const int32_t *pair_pixel, const f
 lts_status lts_stage_electronics(lts_context *ctx, uint64_t event_id, const int32_t *pixel_ids, const float *current,
                                  int64_t n_pix, const lts_outputs *out, void *stream);
 
+/* The front end of lts_stage_electronics for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and results, but the staging it
+ * needs (per-pixel packet slots, offsets, scan partials, counters, the event id and, when out->report is NULL, the
+ * report) lives in a static device array of 32 MiB that each GPU holds from library load to process end, and the
+ * call enqueues kernels only (no allocation, no memset or host copy), so it may be captured into a graph.  Limit:
+ * about 16 * n_pix + 7 * n_pix * max_packets bytes must fit in 32 MiB (e.g. 35,000 pixels at 128 packets);
+ * larger inputs return LTS_ERR_INVALID_ARG with the sizes in lts_last_error.  Every call on a device shares that
+ * device's array, so calls that overlap on one GPU (other streams, other contexts or threads) race: serialise
+ * them.  Arguments, outputs and stream semantics as lts_stage_electronics. */
+lts_status lts_stage_electronics_noalloc(lts_context *ctx, uint64_t event_id, const int32_t *pixel_ids,
+                                         const float *current, int64_t n_pix, const lts_outputs *out, void *stream);
+
 /* Algorithmic work of the last lts_simulate / lts_simulate_batch / lts_plan call on this context (synchronous):
  * out[0] (segment, pixel) pairs; out[1] products c[a,u,v] * R[k,i,j] of eq. (current) that land in the tick
  * window, summed over pairs (the multiply-adds of the induction; in LTS_REDUCE_SUMMED the products of summed

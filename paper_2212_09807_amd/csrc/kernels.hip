@@ -402,6 +402,10 @@ __global__ void k_zero_words(uint32_t *p, int64_t n) {
         p[i] = 0u;
 }
 
+__global__ void k_store_u64(uint64_t *p, uint64_t v) { *p = v; }
+
+void launch_store_u64(uint64_t *p, uint64_t v, hipStream_t st) { k_store_u64<<<1, 1, 0, st>>>(p, v); }
+
 void launch_zero(void *p, int64_t bytes, hipStream_t st) {
     const int64_t n = bytes / 4;
     if (n <= 0) return;

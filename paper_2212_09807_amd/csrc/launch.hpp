@@ -92,6 +92,7 @@ void scan_exclusive_u64(uint64_t *data, int64_t n, void *tmp, hipStream_t st);
 void launch_quench_drift(const DevParams &P, const SegArrays &S, const Work &w, hipStream_t st);
 void launch_slots(const DevParams &P, const Work &w, int32_t *pixel_id_out, int64_t *ev_pix_off, hipStream_t st);
 void launch_zero(void *p, int64_t bytes, hipStream_t st);   // bytes: a multiple of 4
+void launch_store_u64(uint64_t *p, uint64_t v, hipStream_t st); // one value written by a kernel (capture-safe)
 void launch_fill_pairs(const DevParams &P, const Work &w, hipStream_t st);
 void launch_sort_pairs(const Work &w, int64_t n_slots_host, hipStream_t st);
 void launch_cells(const DevParams &P, const Work &w, hipStream_t st);

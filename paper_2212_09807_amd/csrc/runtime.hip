@@ -78,6 +78,7 @@ struct lts_context {
     hipEvent_t call_done = nullptr;
     bool call_recorded = false;
     DevBuf ev_cnt;                   // [2 per event] samples dropped past the window, packets over max_packets
+    void *noalloc_scratch = nullptr; // this device's copy of the static scratch array (lts_stage_electronics_noalloc)
     std::string err;
     lts_status sticky = LTS_OK;
 };
@@ -284,6 +285,34 @@ struct StageTimer {
 };
 
 hipStream_t to_stream(void *s) { return (hipStream_t)s; }
+
+// Device-resident scratch of lts_stage_electronics_noalloc, for callers that cannot allocate (graph capture, tight
+// serving loops).  Each device holds its own copy from module load to process end.  In host code `scratch` only
+// names the symbol: its device address comes from hipGetSymbolAddress, taken once per device (with that device
+// current) at context creation and kept in g_scratch_dev; only that address is ever passed to kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// The calling thread's current device must be `device`.
+lts_status scratch_address(lts_context *c, int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return LTS_OK;       // the no-alloc entry point then reports STATE
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(c, LTS_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_dev[device] = p;
+    }
+    *out = g_scratch_dev[device];
+    return LTS_OK;
+}
 
 lts_status check_segments(lts_context *c, const lts_segments *s) {
     if (!s) return fail(c, LTS_ERR_INVALID_ARG, "segments is NULL");
@@ -628,6 +657,7 @@ lts_status lts_context_create(int device, const lts_physics *physics, const lts_
     c->el = *electronics;
     lts_status r = validate_and_derive(c);
     if (r == LTS_OK && hipSetDevice(device) != hipSuccess) r = LTS_ERR_DEVICE;
+    if (r == LTS_OK) r = scratch_address(c, device, &c->noalloc_scratch);
     if (r == LTS_OK && hipHostMalloc((void **)&c->hdr_host, sizeof(DevHeader), hipHostMallocDefault) != hipSuccess)
         r = LTS_ERR_OOM;
     if (r != LTS_OK) {
@@ -936,6 +966,55 @@ lts_status lts_stage_electronics(lts_context *c, uint64_t event_id, const int32_
     w.slot_gp = const_cast<int32_t *>(pixel_ids);
     w.disabled = c->has_mask ? as<uint8_t>(c->mask) : nullptr;
     launch_electronics(c->P, current, pixel_ids, as<uint64_t>(c->ev_ids), n_pix, w, st);
+    launch_compact_packets(c->P, w, n_pix, out->pkt_pixel, out->pkt_tick, out->pkt_adc, out->pkt_flags, out->cap_packets,
+                           nullptr, nullptr, out->counts, st);
+    HIP_TRY(c, hipGetLastError());
+    return LTS_OK;
+    LTS_API_END(c)
+}
+
+lts_status lts_stage_electronics_noalloc(lts_context *c, uint64_t event_id, const int32_t *pixel_ids,
+                                         const float *current, int64_t n_pix, const lts_outputs *out, void *stream) {
+    LTS_API_BEGIN
+    if (!c) return LTS_ERR_INVALID_ARG;
+    if (!pixel_ids || !current || n_pix < 0 || !out || !out->counts)
+        return fail(c, LTS_ERR_INVALID_ARG, "bad electronics stage arguments");
+    if (!c->noalloc_scratch) return fail(c, LTS_ERR_STATE, "no static scratch on this device");
+    // layout of the static scratch: header, event id, report, packet offsets, scan partials, per-slot packets
+    const int64_t mp = c->P.max_packets;
+    auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+    const int64_t o_hdr = 0, o_ev = up(sizeof(DevHeader)), o_rep = o_ev + 256, o_off = o_rep + 256;
+    const int64_t o_scan = o_off + up(8 * (n_pix + 1));
+    const int64_t o_tick = o_scan + up(8 * scan_tmp_needed(n_pix + 1));
+    const int64_t o_adc = o_tick + up(4 * n_pix * mp);
+    const int64_t o_flag = o_adc + up(2 * n_pix * mp);
+    const int64_t need = o_flag + up(n_pix * mp);
+    if (n_pix > (int64_t)kNoAllocScratchBytes || need > (int64_t)kNoAllocScratchBytes)
+        return fail(c, LTS_ERR_INVALID_ARG,
+                    "lts_stage_electronics_noalloc: " + std::to_string(n_pix) + " pixels x " + std::to_string(mp) +
+                        " packets need " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                        std::to_string(kNoAllocScratchBytes));
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = to_stream(stream);
+    unsigned char *base = (unsigned char *)c->noalloc_scratch;
+    Work w;
+    w.n_ev = 1;
+    w.hdr = (DevHeader *)(base + o_hdr);
+    w.report = out->report ? out->report : (double *)(base + o_rep);
+    w.pk_off = (int64_t *)(base + o_off);
+    w.scan_tmp = base + o_scan;
+    w.pk_tick = (int32_t *)(base + o_tick);
+    w.pk_adc = (uint16_t *)(base + o_adc);
+    w.pk_flag = (uint8_t *)(base + o_flag);
+    w.slot_gp = const_cast<int32_t *>(pixel_ids);
+    w.disabled = c->has_mask ? as<uint8_t>(c->mask) : nullptr;
+    // the scratch keeps the previous call's contents: clear what is accumulated (by kernels, not memset nodes, so a
+    // caller may capture the call into a graph)
+    launch_zero(w.hdr, sizeof(DevHeader), st);
+    launch_zero(w.report, sizeof(double) * 5, st);
+    launch_zero(w.pk_off, 8 * (n_pix + 1), st);
+    launch_store_u64((uint64_t *)(base + o_ev), event_id, st);
+    launch_electronics(c->P, current, pixel_ids, (const uint64_t *)(base + o_ev), n_pix, w, st);
     launch_compact_packets(c->P, w, n_pix, out->pkt_pixel, out->pkt_tick, out->pkt_adc, out->pkt_flags, out->cap_packets,
                            nullptr, nullptr, out->counts, st);
     HIP_TRY(c, hipGetLastError());

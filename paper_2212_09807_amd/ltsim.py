@@ -79,7 +79,7 @@ EXPORTS = ("lts_server_start", "lts_server_submit", "lts_server_poll", "lts_serv
            "lts_server_stop", "lts_set_timing", "lts_get_timing", "lts_work_stats", "lts_context_create", "lts_context_destroy",
            "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_set_ticks_per_thread", "lts_set_lane_exchange", "lts_set_matrix_cores", "lts_set_graph", "lts_graph_stats", "lts_set_channel_mask",
            "lts_plan", "lts_simulate", "lts_simulate_batch", "lts_stage_quench_drift", "lts_debug_cells",
-           "lts_stage_electronics", "lts_stage_philox", "lts_debug_fail_host_alloc", "lts_stage_rasterize", "lts_stage_induce", "lts_stage_reduce", "lts_status_str", "lts_last_error", "lts_version",
+           "lts_stage_electronics", "lts_stage_electronics_noalloc", "lts_stage_philox", "lts_debug_fail_host_alloc", "lts_stage_rasterize", "lts_stage_induce", "lts_stage_reduce", "lts_status_str", "lts_last_error", "lts_version",
            "lts_light_create", "lts_light_destroy", "lts_light_simulate", "lts_light_set_graph", "lts_light_last_error")
 
 
@@ -119,6 +119,7 @@ def lib():
         L.lts_stage_quench_drift.argtypes = [P, C.POINTER(lts_segments), P, P, P]
         L.lts_debug_cells.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), P, C.c_int64]
         L.lts_stage_electronics.argtypes = [P, C.c_uint64, P, P, C.c_int64, C.POINTER(lts_outputs), P]
+        L.lts_stage_electronics_noalloc.argtypes = [P, C.c_uint64, P, P, C.c_int64, C.POINTER(lts_outputs), P]
         L.lts_stage_philox.argtypes = [P, C.c_uint32, C.c_uint32, P, C.c_int64, P]
         L.lts_stage_rasterize.argtypes = [P, C.POINTER(lts_segments), P, P, C.c_int64, C.POINTER(C.c_int64), P]
         L.lts_stage_induce.argtypes = [P, C.c_uint64, C.POINTER(lts_segments), P, P, P, C.c_int64,
@@ -383,6 +384,15 @@ class Context:
         o = self._out_struct(out)
         self._check(lib().lts_stage_electronics(self._h, event_id, _ptr(pixel_ids), _ptr(current), n, C.byref(o),
                                                 _stream(stream)))
+        return out
+
+    def stage_electronics_noalloc(self, event_id: int, pixel_ids, current, out: Result, stream=None) -> Result:
+        """lts_stage_electronics_noalloc into caller-allocated outputs (`out`, e.g. from an earlier call): the library
+        allocates nothing during the call."""
+        n = int(pixel_ids.numel())
+        o = self._out_struct(out)
+        self._check(lib().lts_stage_electronics_noalloc(self._h, event_id, _ptr(pixel_ids), _ptr(current), n,
+                                                        C.byref(o), _stream(stream)))
         return out
 
     def stage_rasterize(self, segs: DeviceSegments, stream=None):
