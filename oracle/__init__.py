@@ -28,7 +28,7 @@ def build(force: bool = True) -> str:
     """Compile oracle.c with gcc (IEEE double, no FP contraction, OpenMP)."""
     if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
         tmp = LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
                                "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter",
                                SRC_PATH, "-o", tmp, "-lm"])
         os.replace(tmp, LIB_PATH)
