@@ -215,6 +215,18 @@ lts_status lts_set_graph(lts_context *ctx, int32_t on);
 /* Number of in-place updates and of instantiations of the context's executable graph so far (host pointers). */
 lts_status lts_graph_stats(lts_context *ctx, int64_t *updates, int64_t *instantiations);
 
+/* Work-split table chosen by an autotuner (the package's autotune module sweeps it): entry k applies to calls whose
+ * mean segments per event is at least min_segments_per_event of entry k and below that of entry k+1 (entries in
+ * ascending order; calls below the first entry use it too).  For the duration of such a call (lts_simulate,
+ * lts_simulate_batch, and every batch of a server started from this context) the entry's reduce mode, induce
+ * slices, ticks per thread and lane exchange replace the context's own settings.  n = 0 (or entries = NULL) removes
+ * the table.  Copied; LTS_ERR_INVALID_ARG for an unsorted table or invalid knob values. */
+typedef struct lts_tuning {
+    int64_t min_segments_per_event;
+    int32_t reduce_mode, induce_slices, ticks_per_thread, lane_exchange;
+} lts_tuning;
+lts_status lts_set_tuning(lts_context *ctx, const lts_tuning *entries, int32_t n);
+
 /* Sizing pass (synchronous on `stream`): need[4] = (segment-pixel pairs, active pixels, charge cells,
  * packet upper bound = active pixels * max_packets).  Host pointer need. */
 lts_status lts_plan(lts_context *ctx, const lts_segments *segs, int64_t need[4], void *stream);
@@ -308,18 +320,21 @@ lts_status lts_stage_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint3
 /* ---- serving ----------------------------------------------------------------------------------------------
  * A request loop with continuous batching: submitted events (segments in HOST memory, copied at submit) wait in a
  * queue; each of n_lanes worker lanes (own HIP stream, own scratch pool and device buffers, the response table of
- * the parent context) repeatedly takes every waiting event that fits its admission budget (at most
- * max_batch_events events, max_batch_segments segments and an estimated mem_budget_bytes / n_lanes bytes of
- * device memory) and runs them as one batch (lts_simulate_batch), so events that arrive while other batches are on
- * the GPU are admitted as soon as a lane frees up, and the lanes' work overlaps on the device.  Results are copied
- * back to host memory owned by the server until lts_server_release.  Thread-safe. */
+ * the parent context) repeatedly takes the waiting events at the queue's head (at most max_batch_events events and
+ * max_batch_segments segments) and runs them as one batch (lts_simulate_batch), so events that arrive while other
+ * batches are on the GPU are admitted as soon as a lane frees up, and the lanes' work overlaps on the device.
+ * Admission by device memory: a lane sizes its tentative batch on the device and runs it only if its footprint
+ * (scratch pool, segments and outputs, grown to the batch's exact sizes) stays within mem_budget_bytes / n_lanes and
+ * the growth fits the device's free memory (hipMemGetInfo) less 1 GiB; otherwise it halves the batch (the events cut
+ * off go back to the queue front, in order), and an event that alone does not fit finishes with LTS_ERR_OOM.
+ * Results are copied back to host memory owned by the server until lts_server_release.  Thread-safe. */
 typedef struct lts_server lts_server;
 
 typedef struct lts_server_cfg {
     int32_t n_lanes;              /* concurrent batches in flight (>= 1; default 2 if 0) */
     int32_t max_batch_events;     /* events per batch (default 64 if 0) */
     int64_t max_batch_segments;   /* segments per batch (default 4,000,000 if 0) */
-    int64_t mem_budget_bytes;     /* device-memory budget for all lanes (default 32 GiB if 0) */
+    int64_t mem_budget_bytes;     /* device-memory budget for all lanes (default if 0: half the device's memory) */
     int32_t return_currents;      /* copy per-pixel currents back (otherwise only pixel ids, packets, report) */
 } lts_server_cfg;
 
@@ -364,7 +379,9 @@ enum {
     LTS_STAGE_CELLS = 2,          /* diffused charge cells per segment (Sec. 3.3.2, eq. (rho)) */
     LTS_STAGE_INDUCE = 3,         /* induced current and per-pixel sum (Sec. 3.3.2 eq. (current), Sec. 3.4) */
     LTS_STAGE_ELECTRONICS = 4,    /* front end, packets and the FP64 current sum (Sec. 3.4) */
-    LTS_N_STAGES = 5
+    LTS_STAGE_INDUCE_KERNEL = 5,  /* inside LTS_STAGE_INDUCE: the induction kernel itself (with the per-pair kernels'
+                                     work-order sort; without the summed mode's column sums and piece lists) */
+    LTS_N_STAGES = 6
 };
 lts_status lts_set_timing(lts_context *ctx, int32_t enabled);
 lts_status lts_get_timing(lts_context *ctx, double ms[LTS_N_STAGES], int64_t calls[LTS_N_STAGES]);

@@ -1611,6 +1611,12 @@ void launch_reduce_runs(const float *pair_current, const int64_t *start, int64_t
 // a 1 x 1 x L charge box, and every active pixel's list of pieces in its reach replaces its pair list, so the
 // sorted induction kernel runs unchanged on the summed data.
 
+// Sort key of a segment in a column's list: first tick (signed, order-preserving bias) above the segment index.
+__device__ __forceinline__ uint64_t sum_key(int32_t a0, int32_t s) {
+    return ((uint64_t)((uint32_t)a0 ^ 0x80000000u) << 32) | (uint32_t)s;
+}
+__device__ __forceinline__ int32_t key_seg(uint64_t k) { return (int32_t)(uint32_t)k; }
+
 // per segment: count the columns of its charge box that some pixel can reach
 __global__ void k_sum_ranges(DevParams P, const SegInfo *si, int64_t n_seg, SumWork sw) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1640,7 +1646,7 @@ __global__ void k_sum_fill(DevParams P, const SegInfo *si, int64_t n_seg, SumWor
     for (int32_t u = u_a; u <= u_b; ++u)
         for (int32_t v = v_a; v <= v_b; ++v) {
             const int64_t c = base + (int64_t)(u - sw.UL) * sw.CV + (v - sw.VL);
-            sw.col_seg[sw.col_seg_off[c] + atomicAdd(&sw.col_cursor[c], 1)] = (int32_t)s;
+            sw.col_tmp[sw.col_seg_off[c] + atomicAdd(&sw.col_cursor[c], 1)] = sum_key(g.a0, (int32_t)s);
         }
 }
 
@@ -1651,14 +1657,14 @@ constexpr int32_t kSumGap = 16;
 // The merged tick interval that starts at entry q of a column's segment list [q, se) (sorted by first tick): its
 // segments are [q, return value), its ticks [lo, hi], lo moved down (zero charge in front) to the residue `res`
 // mod 8.  Consecutive intervals are separated by more than kSumGap ticks, so the aligned ones do not overlap.
-__device__ inline int64_t sum_interval(const SegInfo *__restrict__ si, const int32_t *__restrict__ seg, int64_t q,
+__device__ inline int64_t sum_interval(const SegInfo *__restrict__ si, const uint64_t *__restrict__ seg, int64_t q,
                                        int64_t se, int32_t res, int32_t &lo, int32_t &hi) {
-    const SegInfo &g0 = si[seg[q]];
+    const SegInfo &g0 = si[key_seg(seg[q])];
     lo = g0.a0;
     hi = g0.a0 + g0.na - 1;
     int64_t qe = q + 1;
     for (; qe < se; ++qe) {
-        const SegInfo &g = si[seg[qe]];
+        const SegInfo &g = si[key_seg(seg[qe])];
         if (g.a0 - hi - 1 > kSumGap) break;
         hi = max(hi, g.a0 + g.na - 1);
     }
@@ -1673,31 +1679,53 @@ __device__ inline void sum_interval_size(int32_t L, int64_t &np, int64_t &ns) {
     ns = (np - 1) * kPieceTicks + (last + kAC - 1) / kAC * kAC;
 }
 
-// per column: sort its segment list by (first tick, segment id) (insertion sort: lists are short), then count the
-// pieces and the padded summed-charge length of its merged tick intervals.  Every interval's first tick is moved down
-// to the residue (T_R - 1 + kPad) mod 8, which makes every lane's table offset in the summed induction a multiple
-// of 8.  The order depends only on the segments' charge boxes and their order within the event, so the sums are
-// the same in a batch and alone.
-__global__ void k_sum_columns(int32_t align_res, const SegInfo *__restrict__ si, SumWork sw) {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= sw.n_cols) return;
-    const int64_t b = sw.col_seg_off[c], e = sw.col_seg_off[c + 1];
-    for (int64_t i = b + 1; i < e; ++i) {
-        const int32_t x = sw.col_seg[i];
-        const int32_t ax = si[x].a0;
-        int64_t j = i - 1;
-        for (; j >= b; --j) {
-            const int32_t y = sw.col_seg[j];
-            const int32_t ay = si[y].a0;
-            if (ay < ax || (ay == ax && y < x)) break;
-            sw.col_seg[j + 1] = y;
-        }
-        sw.col_seg[j + 1] = x;
+// 64-bit value of lane j (j wave-uniform).
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int j) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// per column: sort its segment list by key (first tick, segment index) into col_seg, then count the pieces and the
+// padded summed-charge length of its merged tick intervals.  Every interval's first tick is moved down to the residue
+// (T_R - 1 + kPad) mod 8, which makes every lane's table offset in the summed induction a multiple of 8.  The order
+// depends only on the segments' charge boxes and their order within the event, so the sums are the same in a batch
+// and alone.  One wavefront per 64 consecutive columns; the wavefront sorts its columns' lists one after another by
+// ranks (a key's place is the number of smaller keys; keys are unique): lane i holds key i of a 64-key chunk and
+// compares it with every key of the list, taken chunk by chunk from the lanes' registers.
+__global__ __launch_bounds__(kWG) void k_sum_columns(int32_t align_res, const SegInfo *__restrict__ si, SumWork sw) {
+    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t b = 0, e = 0;
+    if (c < sw.n_cols) {
+        b = sw.col_seg_off[c];
+        e = sw.col_seg_off[c + 1];
     }
+    const uint64_t *__restrict__ in = sw.col_tmp;
+    uint64_t *seg = sw.col_seg;
+    uint64_t todo = __ballot(e > b);
+    while (todo) {
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const int64_t lb = __shfl(b, l), n = __shfl(e, l) - lb;
+        for (int64_t i0 = 0; i0 < n; i0 += 64) {
+            const bool mine = i0 + lane < n;
+            const uint64_t x = mine ? in[lb + i0 + lane] : 0;
+            int64_t rank = 0;
+            for (int64_t j0 = 0; j0 < n; j0 += 64) {
+                const uint64_t y = j0 + lane < n ? in[lb + j0 + lane] : ~0ull;
+                const int jn = (int)min<int64_t>(64, n - j0);
+                for (int j = 0; j < jn; ++j) rank += lane_u64(y, j) < x;
+            }
+            if (mine) seg[lb + rank] = x;
+        }
+    }
+    __threadfence_block();                              // the sorted lists before their own lanes read them
+    if (c >= sw.n_cols) return;
     int64_t np = 0, ns = 0;
     for (int64_t q = b; q < e;) {
         int32_t lo, hi;
-        q = sum_interval(si, sw.col_seg, q, e, align_res, lo, hi);
+        q = sum_interval(si, seg, q, e, align_res, lo, hi);
         int64_t n, m;
         sum_interval_size(hi - lo + 1, n, m);
         np += n;
@@ -1740,7 +1768,7 @@ __global__ void k_sum_pieces(DevParams P, const SegInfo *si, const float *cells,
             for (int j = 0; j < kCh; ++j) { sum[j] = 0.0f; cmp[j] = 0.0f; }
             const int32_t cl = lo + a0c, ch = min(cl + kCh, lo + L) - 1;
             for (int64_t k = q; k < qe; ++k) {
-                const SegInfo &g = si[sw.col_seg[k]];
+                const SegInfo &g = si[key_seg(sw.col_seg[k])];
                 if (g.a0 > ch) break;                   // sorted by first tick
                 const int32_t ga = max(g.a0, cl), gb = min(g.a0 + g.na - 1, ch);
                 if (ga > gb) continue;
@@ -1770,6 +1798,7 @@ __global__ void k_sum_pieces(DevParams P, const SegInfo *si, const float *cells,
             g.event = e;
             g.n_pairs = 1;
             sw.piece[pk + k] = g;
+            sw.pdesc[pk + k] = PieceRef{g.a0, g.na, (uint32_t)(g.cell_off / kAC), 0};
         }
         pk += np;
         so += Lpad;
@@ -1781,9 +1810,11 @@ void launch_sum_pieces(const DevParams &P, const Work &w, const SumWork &sw, hip
     k_sum_pieces<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.cells, sw);
 }
 
-// per active pixel (one wavefront): number of column pieces in its table reach, then their ids in column order (row
-// du, then column dv; pieces of a column in tick order).  The lanes take 64 consecutive columns at a time; a wavefront
-// prefix sum of their piece counts gives each lane its place in the list.
+// per active pixel (one wavefront): number of column pieces in its table reach, then their ids and records in column
+// order (row du, then column dv; pieces of a column in tick order).  The lanes take 64 consecutive columns at a time;
+// a wavefront prefix sum of their piece counts gives each lane its place in the list.  A record is the piece's
+// compact descriptor with the folded table column the pixel sees the column through, fold(du - bx) * by +
+// fold(dv - by) for the column at offset (du, dv) of the pixel's reach.
 template <bool FILL>
 __global__ __launch_bounds__(kWG) void k_sum_lists(DevParams P, int64_t n_slots, const int32_t *slot_gp, SumWork sw) {
     const int lane = threadIdx.x & 63;
@@ -1810,8 +1841,16 @@ __global__ __launch_bounds__(kWG) void k_sum_lists(DevParams P, int64_t n_slots,
             const int64_t y = __shfl_up(incl, d);
             if (lane >= d) incl += y;
         }
-        if (FILL)
-            for (int64_t k = 0; k < x; ++k) sw.list[pos + incl - x + k] = (int32_t)(pb + k);
+        if (FILL && x) {
+            const int32_t bin = fold(c / nv - P.bx) * P.by + fold(c % nv - P.by);
+            for (int64_t k = 0; k < x; ++k) {
+                const int64_t q = pos + incl - x + k;
+                sw.list[q] = (int32_t)(pb + k);
+                PieceRef r = sw.pdesc[pb + k];
+                r.bin = bin;
+                sw.rec[q] = r;
+            }
+        }
         pos += __shfl(incl, 63);
     }
     if (!FILL && lane == 0) sw.list_off[slot] = pos;
@@ -1821,29 +1860,11 @@ void launch_sum_lists_count(const DevParams &P, const Work &w, const SumWork &sw
     if (n_slots > 0)
         k_sum_lists<false><<<(unsigned)((n_slots + kWG / 64 - 1) / (kWG / 64)), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
 }
-// per list entry: the piece as a record for the summed induction loop (its pixel found by bisection of the list
-// offsets; one thread per entry, so the record writes are coalesced)
-__global__ void k_sum_recs(DevParams P, int64_t n_slots, int64_t n_list, const int32_t *slot_gp, SumWork sw) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_list) return;
-    int64_t lo = 0, hi = n_slots - 1;                   // last slot whose list starts at or before i
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (sw.list_off[mid] <= i) lo = mid; else hi = mid - 1;
-    }
-    const int32_t gp = slot_gp[lo];
-    const int32_t p = gp - (gp / P.npx) * P.npx;
-    const int32_t uc = (p % P.nx) * P.nsub + P.nsub / 2, vc = (p / P.nx) * P.nsub + P.nsub / 2;
-    const SegInfo &g = sw.piece[sw.list[i]];
-    sw.rec[i] = PieceRef{g.a0, g.na, (uint32_t)(g.cell_off / kAC), fold(g.u0 - uc) * P.by + fold(g.v0 - vc)};
-}
-
 void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, int64_t n_list,
                            hipStream_t st) {
     if (n_slots <= 0) return;
     k_sum_lists<true><<<(unsigned)((n_slots + kWG / 64 - 1) / (kWG / 64)), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
-    if (n_list > 0)
-        k_sum_recs<<<(unsigned)((n_list + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, n_list, w.slot_gp, sw);
+    (void)n_list;
 }
 
 // Summed induction, one wavefront per work unit (active pixel, tile of kTileTicks ticks): lane t owns ticks
@@ -1978,11 +1999,11 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
         if (t0 == 0) {                                  // charge induced outside [0, NT) by the pixel's pieces
             double clip = 0.0;
             for (int64_t k = pb + lane; k < pe; k += 64) {
-                const SegInfo &g = piece[list[k]];
+                const PieceRef g = rec[k];
                 const int32_t wlo = g.a0 - (TR - 1), whi = g.a0 + g.na - 1;
                 if (wlo >= 0 && whi < NT) continue;
-                const double *pf = prefix + (int64_t)(fold(g.u0 - uc) * P.by + fold(g.v0 - vc)) * (TR + 1);
-                const float *cv = S + g.cell_off;
+                const double *pf = prefix + (int64_t)g.bin * (TR + 1);
+                const float *cv = S + (int64_t)g.cell8 * kAC;
                 for (int32_t a = 0; a < g.na; ++a) {
                     const int32_t aa = g.a0 + a;
                     const int32_t klo = min(max(TR - 1 - aa, 0), TR), khi = min(max(NT + TR - 1 - aa, 0), TR);
@@ -2011,8 +2032,20 @@ __global__ void k_slot_work_summed(const PieceRef *__restrict__ rec, const int64
     atomicAdd(&hist[b], 1);
 }
 
+const int32_t *launch_summed_order(const Work &w, const SumWork &sw, int64_t n_slots, int32_t rt, bool shift,
+                                   hipStream_t st) {
+    if ((rt != 0 && rt != 8) || n_slots <= 0 || !w.order || shift) return nullptr;
+    int32_t *ord = w.order, *bucket = ord + n_slots, *hist = bucket + n_slots, *cursor = hist + kOrderBuckets;
+    launch_zero(hist, (int64_t)sizeof(int32_t) * kOrderBuckets, st);
+    const unsigned gs = (unsigned)((n_slots + kWG - 1) / kWG);
+    k_slot_work_summed<<<gs, kWG, 0, st>>>(sw.rec, sw.list_off, n_slots, bucket, hist);
+    k_order_offsets<<<1, kWG, 0, st>>>(hist, cursor);
+    k_order_scatter<<<gs, kWG, 0, st>>>(bucket, n_slots, cursor, ord);
+    return ord;
+}
+
 void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, const Table &T, float *wave,
-                          int64_t n_slots, int32_t rt, bool shift, hipStream_t st) {
+                          int64_t n_slots, int32_t rt, bool shift, const int32_t *order, hipStream_t st) {
     if (rt != 0 && rt != 8) {                           // the per-pair kernel on the summed pieces (tuning option)
         Work ws = w;
         ws.si = sw.piece;
@@ -2025,16 +2058,6 @@ void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, 
     if (n_slots <= 0) return;
     const int64_t units = n_slots * ((P.nticks + kTileTicks - 1) / kTileTicks);
     const int64_t g = std::min<int64_t>((units + kWG / 64 - 1) / (kWG / 64), 256 * 8);
-    const int32_t *order = nullptr;
-    if (w.order && !shift) {
-        int32_t *ord = w.order, *bucket = ord + n_slots, *hist = bucket + n_slots, *cursor = hist + kOrderBuckets;
-        launch_zero(hist, (int64_t)sizeof(int32_t) * kOrderBuckets, st);
-        const unsigned gs = (unsigned)((n_slots + kWG - 1) / kWG);
-        k_slot_work_summed<<<gs, kWG, 0, st>>>(sw.rec, sw.list_off, n_slots, bucket, hist);
-        k_order_offsets<<<1, kWG, 0, st>>>(hist, cursor);
-        k_order_scatter<<<gs, kWG, 0, st>>>(bucket, n_slots, cursor, ord);
-        order = ord;
-    }
     if (shift)
         k_induce_summed<true><<<(unsigned)g, kWG, 0, st>>>(P, sw.piece, sw.S, T.Rpad, T.prefix, sw.list_off, sw.list,
                                                            sw.rec, order, w.slot_gp, wave, w.hdr, w.report);
@@ -2292,13 +2315,13 @@ void launch_work_stats(const DevParams &P, const SegInfo *si, int64_t n_seg, uns
 }
 
 // Summed induction: per active pixel, the (column-piece tick, table tick) products that land in the window.
-__global__ void k_work_stats_summed(DevParams P, int64_t n_slots, const int64_t *list_off, const int32_t *list,
-                                    const SegInfo *piece, unsigned long long *acc) {
+__global__ void k_work_stats_summed(DevParams P, int64_t n_slots, const int64_t *list_off, const PieceRef *rec,
+                                    unsigned long long *acc) {
     int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= n_slots) return;
     unsigned long long f = 0, cells = 0;
     for (int64_t q = list_off[slot]; q < list_off[slot + 1]; ++q) {
-        const SegInfo &g = piece[list[q]];
+        const PieceRef g = rec[q];
         for (int32_t a = g.a0; a < g.a0 + g.na; ++a) {
             const int32_t lo = max(a - P.t_r + 1, 0), hi = min(a, P.nticks - 1);
             if (hi >= lo) f += (unsigned long long)(hi - lo + 1);
@@ -2310,10 +2333,10 @@ __global__ void k_work_stats_summed(DevParams P, int64_t n_slots, const int64_t 
     atomicAdd(&acc[2], cells);
 }
 
-void launch_work_stats_summed(const DevParams &P, int64_t n_slots, const int64_t *list_off, const int32_t *list,
-                              const SegInfo *piece, unsigned long long *acc, hipStream_t st) {
+void launch_work_stats_summed(const DevParams &P, int64_t n_slots, const int64_t *list_off, const PieceRef *rec,
+                              unsigned long long *acc, hipStream_t st) {
     if (n_slots > 0)
-        k_work_stats_summed<<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, list_off, list, piece, acc);
+        k_work_stats_summed<<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, list_off, rec, acc);
 }
 
 // ================================================================================================= Philox test hook

@@ -64,10 +64,12 @@ struct SumWork {
     int64_t n_cols = 0;                      // n_ev * CU * CV
     int64_t *col_seg_off = nullptr;          // [n_cols + 1] segments per column, then offsets
     int32_t *col_cursor = nullptr;           // [n_cols]
-    int32_t *col_seg = nullptr;              // [n_col_seg] segment ids per column (by first tick after sorting)
+    uint64_t *col_tmp = nullptr;             // [n_col_seg] per column: keys (first tick << 32 | segment index)
+    uint64_t *col_seg = nullptr;             // [n_col_seg] the same keys, ascending per column
     int64_t *piece_off = nullptr;            // [n_cols + 1] pieces per column, then offsets
     int64_t *s_off = nullptr;                // [n_cols + 1] summed-cell floats per column, then offsets
     SegInfo *piece = nullptr;                // [n_pieces] one 1 x 1 x L box per column piece
+    PieceRef *pdesc = nullptr;               // [n_pieces] the same pieces as compact records (bin not set)
     float *S = nullptr;                      // [n_s] summed charge per column piece (padded to kAC)
     int64_t *list_off = nullptr;             // [n_slots + 1] pieces in reach per active pixel, then offsets
     int32_t *list = nullptr;                 // [n_list] piece ids per active pixel, in column order
@@ -82,8 +84,11 @@ void launch_sum_pieces(const DevParams &P, const Work &w, const SumWork &sw, hip
 void launch_sum_lists_count(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, hipStream_t st);
 void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, int64_t n_list,
                            hipStream_t st);                                                    // + records
+// largest-first pixel order of the summed induction (null when the chosen kernel takes pixels in slot order)
+const int32_t *launch_summed_order(const Work &w, const SumWork &sw, int64_t n_slots, int32_t rt, bool shift,
+                                   hipStream_t st);
 void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, const Table &T, float *wave,
-                          int64_t n_slots, int32_t rt, bool shift, hipStream_t st);
+                          int64_t n_slots, int32_t rt, bool shift, const int32_t *order, hipStream_t st);
 
 int64_t scan_tmp_needed(int64_t n);
 void scan_exclusive_i64(int64_t *data, int64_t n, int64_t *total_dst, void *tmp, hipStream_t st);
@@ -119,8 +124,8 @@ void launch_compact_packets(const DevParams &P, const Work &w, int64_t n_slots, 
 void launch_stage_quench_drift(const DevParams &P, const SegArrays &S, int64_t n, float *out_f, int32_t *out_i,
                                hipStream_t st);
 void launch_work_stats(const DevParams &P, const SegInfo *si, int64_t n_seg, unsigned long long *acc, hipStream_t st);
-void launch_work_stats_summed(const DevParams &P, int64_t n_slots, const int64_t *list_off, const int32_t *list,
-                              const SegInfo *piece, unsigned long long *acc, hipStream_t st);
+void launch_work_stats_summed(const DevParams &P, int64_t n_slots, const int64_t *list_off, const PieceRef *rec,
+                              unsigned long long *acc, hipStream_t st);
 void launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n, hipStream_t st);
 
 }  // namespace ltsim

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -17,6 +18,7 @@
 #include <vector>
 
 #include "../../include/ltsim.h"
+#include "admission.hpp"
 #include "api.hpp"
 #include "device.hpp"
 #include "launch.hpp"
@@ -44,6 +46,7 @@ struct lts_context {
     int32_t ticks_per_thread = 0;    // induction tick tile per thread (0 = chosen from the table length)
     int32_t lane_exchange = 0;       // 8-tick tiles share table windows across lanes (1) or load their own (0)
     int32_t matrix_cores = 0;        // sorted per-pair induction on the FP32 matrix cores (1) or the vector ALUs (0)
+    std::vector<lts_tuning> tuning;  // autotuned work split per event-size class (empty = the settings above)
     // HIP-graph replay of the launch sequence after the sizing read-back (per-pair and atomic modes)
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;  // capture stream (captures never run on the caller's stream)
@@ -54,7 +57,7 @@ struct lts_context {
     DevBuf part;                     // per-slice partial waveforms of the sliced sorted variant
     DevBuf mask;                     // disabled-channel mask (npx bytes) when set
     bool has_mask = false;
-    DevBuf col_seg_off, col_cursor, col_seg, piece_off, s_off, piece, S, list_off, list, rec;
+    DevBuf col_seg_off, col_cursor, col_seg, col_tmp, piece_off, s_off, piece, pdesc, S, list_off, list, rec;
     DevParams P{};
     bool has_table = false;
     DevBuf Rpad, prefix;
@@ -77,6 +80,10 @@ struct lts_context {
     // (an event recorded on the previous call's stream), so calls on different streams never share scratch in flight
     hipEvent_t call_done = nullptr;
     bool call_recorded = false;
+    // request-loop lanes only: asked, once the sizes of a call are known, whether the call may grow the context's
+    // pool to `total` bytes (`growth` of them not yet allocated); it also sizes the lane's outputs.  LTS_OK runs the
+    // call, kNotAdmitted abandons it before any further allocation.
+    std::function<lts_status(const DevHeader &, int64_t total, int64_t growth)> admit;
     DevBuf ev_cnt;                   // [2 per event] samples dropped past the window, packets over max_packets
     void *noalloc_scratch = nullptr; // this device's copy of the static scratch array (lts_stage_electronics_noalloc)
     std::string err;
@@ -109,19 +116,14 @@ lts_status ensure(lts_context *c, DevBuf &b, size_t bytes) {
         b.p = nullptr;
         b.bytes = 0;
     }
-    size_t want = std::max(bytes, b.bytes + b.bytes / 2);
-    hipError_t e = hipMalloc(&b.p, want);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        e = hipMalloc(&b.p, bytes);
-        want = bytes;
-    }
+    // buffers grow to exactly the size asked for (the request loop's admission accounts for them byte for byte)
+    const hipError_t e = hipMalloc(&b.p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         b.p = nullptr;
         return fail(c, LTS_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     }
-    b.bytes = want;
+    b.bytes = bytes;
     return LTS_OK;
 }
 
@@ -226,6 +228,42 @@ lts_status validate_and_derive(lts_context *c) {
 
 template <typename T>
 T *as(DevBuf &b) { return (T *)b.p; }
+
+// A call's refusal by the request loop's admission: a status the pipeline returns for nothing else (only the
+// server's poll uses it, for unfinished tickets); the lanes turn it into a smaller batch or LTS_ERR_OOM.
+constexpr lts_status kNotAdmitted = LTS_ERR_NOT_READY;
+
+std::vector<DevBuf *> pool_buffers(lts_context *c) {
+    return {&c->ev_cnt, &c->mask, &c->col_seg_off, &c->col_cursor, &c->col_seg, &c->col_tmp, &c->piece_off, &c->s_off, &c->piece,
+            &c->pdesc, &c->S, &c->list_off, &c->list, &c->rec, &c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off,
+            &c->pix_cnt, &c->cursor, &c->pix_slot, &c->slot_gp, &c->slot_off, &c->pairs_u, &c->pairs, &c->cells,
+            &c->pk_tick, &c->pk_adc, &c->pk_flag, &c->pk_off, &c->hdr, &c->scan_tmp, &c->ev_off, &c->ev_ids,
+            &c->report_tmp, &c->counts_tmp, &c->red_head, &c->red_start, &c->order};
+}
+
+// One buffer and the bytes a call needs in it.
+struct Need {
+    DevBuf *b;
+    size_t bytes;
+};
+
+// Grows the listed buffers to their needs, first asking the admission hook (if any) whether the pool may grow.
+lts_status grow(lts_context *c, const DevHeader &h, const std::vector<Need> &needs) {
+    if (c->admit) {
+        int64_t total = 0, growth = 0;
+        for (DevBuf *b : pool_buffers(c)) total += (int64_t)b->bytes;
+        for (const Need &n : needs) {
+            const size_t want = std::max<size_t>(n.bytes, 16);
+            if (want > n.b->bytes) growth += (int64_t)(want - n.b->bytes);
+        }
+        const lts_status r = c->admit(h, total + growth, growth);
+        if (r) return r;
+    }
+    lts_status r;
+    for (const Need &n : needs)
+        if ((r = ensure(c, *n.b, n.bytes))) return r;
+    return LTS_OK;
+}
 
 // Orders a call that uses the context's scratch after the previous such call, whatever streams they use: the
 // constructor makes `st` wait for the previous call's completion event, the destructor records it on `st`.
@@ -391,28 +429,42 @@ lts_status run_sizing(lts_context *c, int32_t n_ev, const uint64_t *event_ids, c
 
 // Sum-then-convolve induction (exact by linearity): columns summed over segments, then the sorted induction kernel
 // over per-pixel lists of column pieces.
-lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t n_slots, float *wave, hipStream_t st) {
-    const DevParams &P = c->P;
-    lts_status r;
+// Absolute sub-pixel column grid of the summed induction: per event the columns some in-grid pixel can reach.
+SumWork summed_grid(const DevParams &P, int32_t n_ev) {
     SumWork sw;
     const int32_t half = P.nsub / 2;
     sw.UL = half - P.bx;
     sw.VL = half - P.by;
     sw.CU = (P.nx - 1) * P.nsub + 2 * P.bx;
     sw.CV = (P.ny - 1) * P.nsub + 2 * P.by;
-    sw.n_cols = (int64_t)w.n_ev * sw.CU * sw.CV;
+    sw.n_cols = (int64_t)n_ev * sw.CU * sw.CV;
+    return sw;
+}
+
+// Buffers of the summed induction whose sizes the sizing pass already fixes (column lists, offsets, pixel lists).
+void summed_needs(lts_context *c, const DevHeader &h, int64_t n_slots, int32_t n_ev, std::vector<Need> &needs) {
+    const SumWork sw = summed_grid(c->P, n_ev);
     const int64_t nc1 = sw.n_cols + 1;
-    const int64_t n_colseg = std::max<int64_t>(h.n_colseg, 1);
-    if ((r = ensure(c, c->col_seg_off, sizeof(int64_t) * (size_t)nc1))) return r;
-    if ((r = ensure(c, c->col_cursor, sizeof(int32_t) * (size_t)sw.n_cols))) return r;
-    if ((r = ensure(c, c->col_seg, sizeof(int32_t) * (size_t)n_colseg))) return r;
-    if ((r = ensure(c, c->piece_off, sizeof(int64_t) * (size_t)nc1))) return r;
-    if ((r = ensure(c, c->s_off, sizeof(int64_t) * (size_t)nc1))) return r;
-    if ((r = ensure(c, c->list_off, sizeof(int64_t) * (size_t)(n_slots + 1)))) return r;
-    if ((r = ensure(c, c->scan_tmp, sizeof(int64_t) * (size_t)scan_tmp_needed(std::max(nc1, n_slots + 1))))) return r;
+    needs.push_back({&c->col_seg_off, sizeof(int64_t) * (size_t)nc1});
+    needs.push_back({&c->col_cursor, sizeof(int32_t) * (size_t)sw.n_cols});
+    needs.push_back({&c->col_seg, sizeof(uint64_t) * (size_t)std::max<int64_t>(h.n_colseg, 1)});
+    needs.push_back({&c->col_tmp, sizeof(uint64_t) * (size_t)std::max<int64_t>(h.n_colseg, 1)});
+    needs.push_back({&c->piece_off, sizeof(int64_t) * (size_t)nc1});
+    needs.push_back({&c->s_off, sizeof(int64_t) * (size_t)nc1});
+    needs.push_back({&c->list_off, sizeof(int64_t) * (size_t)(n_slots + 1)});
+    needs.push_back({&c->scan_tmp, sizeof(int64_t) * (size_t)scan_tmp_needed(std::max(nc1, n_slots + 1))});
+}
+
+// The buffers of summed_needs are grown by the caller.
+lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t n_slots, float *wave, hipStream_t st) {
+    const DevParams &P = c->P;
+    lts_status r;
+    SumWork sw = summed_grid(P, w.n_ev);
+    const int64_t nc1 = sw.n_cols + 1;
     sw.col_seg_off = as<int64_t>(c->col_seg_off);
     sw.col_cursor = as<int32_t>(c->col_cursor);
-    sw.col_seg = as<int32_t>(c->col_seg);
+    sw.col_seg = as<uint64_t>(c->col_seg);
+    sw.col_tmp = as<uint64_t>(c->col_tmp);
     sw.piece_off = as<int64_t>(c->piece_off);
     sw.s_off = as<int64_t>(c->s_off);
     sw.list_off = as<int64_t>(c->list_off);
@@ -435,22 +487,28 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     HIP_TRY(c, hipStreamSynchronize(st));
     if (tot[2] / kAC >= (int64_t)UINT32_MAX)          // piece records hold the charge offset in units of kAC floats
         return fail(c, LTS_ERR_CAPACITY, "summed induction: too many summed charge values for one call");
-    if ((r = ensure(c, c->piece, sizeof(SegInfo) * (size_t)std::max<int64_t>(tot[1], 1)))) return r;
-    if ((r = ensure(c, c->S, sizeof(float) * (size_t)(tot[2] + kCellSlack)))) return r;
+    if ((r = grow(c, h, {{&c->piece, sizeof(SegInfo) * (size_t)std::max<int64_t>(tot[1], 1)},
+                         {&c->pdesc, sizeof(PieceRef) * (size_t)std::max<int64_t>(tot[1], 1)},
+                         {&c->S, sizeof(float) * (size_t)(tot[2] + kCellSlack)}})))
+        return r;
     sw.piece = as<SegInfo>(c->piece);
+    sw.pdesc = as<PieceRef>(c->pdesc);
     sw.S = as<float>(c->S);
     launch_sum_pieces(P, w, sw, st);
     launch_sum_lists_count(P, w, sw, n_slots, st);
     scan_exclusive_i64(sw.list_off, n_slots + 1, nullptr, tmp, st);
     HIP_TRY(c, hipMemcpyAsync(&tot[0], sw.list_off + n_slots, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
-    if ((r = ensure(c, c->list, sizeof(int32_t) * (size_t)std::max<int64_t>(tot[0], 1)))) return r;
+    if ((r = grow(c, h, {{&c->list, sizeof(int32_t) * (size_t)std::max<int64_t>(tot[0], 1)},
+                         {&c->rec, sizeof(PieceRef) * (size_t)std::max<int64_t>(tot[0], 1)}})))
+        return r;
     sw.list = as<int32_t>(c->list);
-    if ((r = ensure(c, c->rec, sizeof(PieceRef) * (size_t)std::max<int64_t>(tot[0], 1)))) return r;
     sw.rec = as<PieceRef>(c->rec);
     launch_sum_lists_fill(P, w, sw, n_slots, tot[0], st);
     Table T{as<float>(c->Rpad), as<double>(c->prefix)};
-    launch_induce_summed(P, w, sw, T, wave, n_slots, c->ticks_per_thread, c->lane_exchange != 0, st);
+    const int32_t *order = launch_summed_order(w, sw, n_slots, c->ticks_per_thread, c->lane_exchange != 0, st);
+    StageTimer tk(c, st, LTS_STAGE_INDUCE_KERNEL);
+    launch_induce_summed(P, w, sw, T, wave, n_slots, c->ticks_per_thread, c->lane_exchange != 0, order, st);
     return LTS_OK;
 }
 
@@ -503,9 +561,35 @@ lts_status run_graph(lts_context *c, hipStream_t st, Launch &launch) {
     return LTS_OK;
 }
 
+// For the duration of one call: the tuning table's entry for the call's mean event size replaces the context's
+// work-split settings (restored afterwards).
+struct TunedKnobs {
+    lts_context *c;
+    int32_t mode, slices, rt, shift;
+    TunedKnobs(lts_context *c_, int64_t n_seg, int32_t n_ev)
+        : c(c_), mode(c_->reduce_mode), slices(c_->induce_slices), rt(c_->ticks_per_thread), shift(c_->lane_exchange) {
+        if (c->tuning.empty() || n_ev < 1) return;
+        const int64_t mean = n_seg / n_ev;
+        const lts_tuning *t = &c->tuning[0];
+        for (const lts_tuning &e : c->tuning)
+            if (e.min_segments_per_event <= mean) t = &e;
+        c->reduce_mode = t->reduce_mode;
+        c->induce_slices = t->induce_slices;
+        c->ticks_per_thread = t->ticks_per_thread;
+        c->lane_exchange = t->lane_exchange;
+    }
+    ~TunedKnobs() {
+        c->reduce_mode = mode;
+        c->induce_slices = slices;
+        c->ticks_per_thread = rt;
+        c->lane_exchange = shift;
+    }
+};
+
 lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids, const int64_t *seg_offsets,
                         const lts_segments *segs, const lts_outputs *out, hipStream_t st) {
     if (c->sticky) return fail(c, c->sticky, "context is in a failed state: " + c->err);
+    TunedKnobs tuned(c, segs ? segs->n : 0, n_ev);
     if (!c->has_table) return fail(c, LTS_ERR_STATE, "no response table: call lts_set_response first");
     lts_status r;
     if ((r = check_segments(c, segs))) return r;
@@ -522,22 +606,31 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
     c->last_n_slots = n_slots;
     c->last_mode = c->reduce_mode;
     const int64_t mp = c->P.max_packets;
+    std::vector<Need> needs = {
+        {&c->slot_gp, sizeof(int32_t) * (size_t)std::max<int64_t>(n_slots, 1)},
+        {&c->slot_off, sizeof(int64_t) * (size_t)(n_slots + 1)},
+        {&c->pairs_u, sizeof(int32_t) * (size_t)std::max<int64_t>(n_pairs, 1)},
+        {&c->pairs, sizeof(int32_t) * (size_t)std::max<int64_t>(n_pairs, 1)},
+        {&c->cells, sizeof(float) * (size_t)(n_cells + kCellSlack)},
+        {&c->pk_tick, sizeof(int32_t) * (size_t)(n_slots * mp)},
+        {&c->pk_adc, sizeof(uint16_t) * (size_t)(n_slots * mp)},
+        {&c->pk_flag, sizeof(uint8_t) * (size_t)(n_slots * mp)},
+        {&c->pk_off, sizeof(int64_t) * (size_t)(n_slots + 1)},
+        {&c->scan_tmp, sizeof(int64_t) * (size_t)scan_tmp_needed(n_slots + 1)},
+        {&c->order, sizeof(int32_t) * (size_t)(2 * n_slots + 2 * kOrderBuckets)}};
+    if (c->reduce_mode == LTS_REDUCE_SUMMED) summed_needs(c, h, n_slots, n_ev, needs);
+    if (c->reduce_mode == LTS_REDUCE_SORTED && c->induce_slices > 1 && n_slots > 0) {
+        const int64_t row_bytes = (int64_t)c->induce_slices * c->P.nticks * (int64_t)sizeof(float);
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_slots, (1ll << 30) / row_bytes));
+        needs.push_back({&c->part, (size_t)(row_bytes * chunk)});
+    }
+    // the admission hook (request-loop lanes) sizes the outputs: the capacity check comes after it
+    if ((r = grow(c, h, needs))) return r;
     if (n_slots > out->cap_pixels) {
         int64_t need[4] = {n_slots, n_slots * mp, 0, 0};
         HIP_TRY(c, hipMemcpy(out->counts, need, sizeof(need), hipMemcpyHostToDevice));
         return fail(c, LTS_ERR_CAPACITY, "cap_pixels " + std::to_string(out->cap_pixels) + " < " + std::to_string(n_slots));
     }
-    if ((r = ensure(c, c->slot_gp, sizeof(int32_t) * (size_t)std::max<int64_t>(n_slots, 1)))) return r;
-    if ((r = ensure(c, c->slot_off, sizeof(int64_t) * (size_t)(n_slots + 1)))) return r;
-    if ((r = ensure(c, c->pairs_u, sizeof(int32_t) * (size_t)std::max<int64_t>(n_pairs, 1)))) return r;
-    if ((r = ensure(c, c->pairs, sizeof(int32_t) * (size_t)std::max<int64_t>(n_pairs, 1)))) return r;
-    if ((r = ensure(c, c->cells, sizeof(float) * (size_t)(n_cells + kCellSlack)))) return r;
-    if ((r = ensure(c, c->pk_tick, sizeof(int32_t) * (size_t)(n_slots * mp)))) return r;
-    if ((r = ensure(c, c->pk_adc, sizeof(uint16_t) * (size_t)(n_slots * mp)))) return r;
-    if ((r = ensure(c, c->pk_flag, sizeof(uint8_t) * (size_t)(n_slots * mp)))) return r;
-    if ((r = ensure(c, c->pk_off, sizeof(int64_t) * (size_t)(n_slots + 1)))) return r;
-    if ((r = ensure(c, c->scan_tmp, sizeof(int64_t) * (size_t)scan_tmp_needed(n_slots + 1)))) return r;
-    if ((r = ensure(c, c->order, sizeof(int32_t) * (size_t)(2 * n_slots + 2 * kOrderBuckets)))) return r;
     w.order = as<int32_t>(c->order);
     w.slot_gp = as<int32_t>(c->slot_gp);
     w.slot_off = as<int64_t>(c->slot_off);
@@ -581,9 +674,11 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
                                  c->ticks_per_thread, s);
         } else if (c->reduce_mode == LTS_REDUCE_SORTED && c->matrix_cores) {
             StageTimer t(c, s, LTS_STAGE_INDUCE);
+            StageTimer tk(c, s, LTS_STAGE_INDUCE_KERNEL);
             launch_induce_mfma(P, w, T, out->current, n_slots, s);
         } else {
             StageTimer t(c, s, LTS_STAGE_INDUCE);
+            StageTimer tk(c, s, LTS_STAGE_INDUCE_KERNEL);
             launch_induce(P, w, T, out->current, c->reduce_mode, n_slots, c->ticks_per_thread, c->lane_exchange != 0,
                           s);
         }
@@ -596,11 +691,6 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
         }
         return LTS_OK;
     };
-    if (c->reduce_mode == LTS_REDUCE_SORTED && c->induce_slices > 1 && n_slots > 0) {
-        const int64_t row_bytes = (int64_t)c->induce_slices * P.nticks * (int64_t)sizeof(float);
-        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_slots, (1ll << 30) / row_bytes));
-        if ((r = ensure(c, c->part, (size_t)(row_bytes * chunk)))) return r;
-    }
     if (!graph) {
         if ((r = launch_all(st))) return r;
     } else {
@@ -685,12 +775,7 @@ void lts_context_destroy(lts_context *c) {
         (void)hipEventSynchronize(c->call_done);
         (void)hipEventDestroy(c->call_done);
     }
-    DevBuf *bufs[] = {&c->ev_cnt, &c->mask, &c->col_seg_off, &c->col_cursor, &c->col_seg, &c->piece_off, &c->s_off,
-                      &c->piece, &c->S, &c->list_off, &c->list, &c->rec, &c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off, &c->pix_cnt, &c->cursor, &c->pix_slot, &c->slot_gp,
-                      &c->slot_off, &c->pairs_u, &c->pairs, &c->cells, &c->pk_tick, &c->pk_adc, &c->pk_flag,
-                      &c->pk_off, &c->hdr, &c->scan_tmp, &c->ev_off, &c->ev_ids, &c->report_tmp, &c->counts_tmp,
-                      &c->red_head, &c->red_start, &c->order};
-    for (DevBuf *b : bufs) free_buf(*b);
+    for (DevBuf *b : pool_buffers(c)) free_buf(*b);
     if (c->hdr_host) (void)hipHostFree(c->hdr_host);
     delete c;
 }
@@ -795,6 +880,33 @@ lts_status lts_set_channel_mask(lts_context *c, const uint8_t *mask, int64_t n) 
     if ((r = ensure(c, c->mask, (size_t)n))) return r;
     HIP_TRY(c, hipMemcpy(c->mask.p, mask, (size_t)n, hipMemcpyHostToDevice));
     c->has_mask = true;
+    return LTS_OK;
+    LTS_API_END(c)
+}
+
+lts_status lts_set_tuning(lts_context *c, const lts_tuning *entries, int32_t n) {
+    LTS_API_BEGIN
+    if (!c) return LTS_ERR_INVALID_ARG;
+    if (!entries || n <= 0) {
+        c->tuning.clear();
+        return LTS_OK;
+    }
+    std::vector<lts_tuning> t(entries, entries + n);
+    for (int32_t i = 0; i < n; ++i) {
+        const lts_tuning &e = t[i];
+        if (i > 0 && e.min_segments_per_event <= t[i - 1].min_segments_per_event)
+            return fail(c, LTS_ERR_INVALID_ARG, "tuning entries must be in ascending min_segments_per_event");
+        if (e.reduce_mode != LTS_REDUCE_SORTED && e.reduce_mode != LTS_REDUCE_ATOMIC && e.reduce_mode != LTS_REDUCE_SUMMED)
+            return fail(c, LTS_ERR_INVALID_ARG, "tuning entry: unknown reduce mode");
+        if (e.induce_slices < 1 || e.induce_slices > 64)
+            return fail(c, LTS_ERR_INVALID_ARG, "tuning entry: slices must be in [1, 64]");
+        const int32_t rt = e.ticks_per_thread;
+        if (rt != 0 && rt != 1 && rt != 2 && rt != 4 && rt != 8)
+            return fail(c, LTS_ERR_INVALID_ARG, "tuning entry: ticks per thread must be 0, 1, 2, 4 or 8");
+        if (e.lane_exchange != 0 && e.lane_exchange != 1)
+            return fail(c, LTS_ERR_INVALID_ARG, "tuning entry: lane exchange must be 0 or 1");
+    }
+    c->tuning.swap(t);
     return LTS_OK;
     LTS_API_END(c)
 }
@@ -1149,8 +1261,8 @@ lts_status lts_work_stats(lts_context *c, double out[4]) {
     HIP_TRY(c, hipDeviceSynchronize());
     HIP_TRY(c, hipMemset(c->counts_tmp.p, 0, 4 * sizeof(unsigned long long)));
     if (c->last_mode == LTS_REDUCE_SUMMED) {
-        launch_work_stats_summed(c->P, c->last_n_slots, as<int64_t>(c->list_off), as<int32_t>(c->list),
-                                 as<SegInfo>(c->piece), as<unsigned long long>(c->counts_tmp), nullptr);
+        launch_work_stats_summed(c->P, c->last_n_slots, as<int64_t>(c->list_off), as<PieceRef>(c->rec),
+                                 as<unsigned long long>(c->counts_tmp), nullptr);
         HIP_TRY(c, hipGetLastError());
         unsigned long long hs[4];
         HIP_TRY(c, hipMemcpy(hs, c->counts_tmp.p, sizeof(hs), hipMemcpyDeviceToHost));
@@ -1257,7 +1369,7 @@ struct lts_server {
     std::unordered_map<uint64_t, int> state;   // 0 queued, 1 running, 2 finished, 3 cancelled
     uint64_t next_ticket = 1;
     bool stopping = false;
-    double bytes_per_segment = 65536.0;        // admission estimate, refined from finished batches
+    int64_t mem_reserve = int64_t(1) << 30;     // device memory left free by admission decisions
 };
 
 namespace {
@@ -1291,50 +1403,98 @@ void lane_run_batch(Lane *L, std::vector<Request *> &batch) {
             st = LTS_ERR_DEVICE;
     }
     float *d = (float *)L->seg.p;
-    lts_segments segs{d, d + nseg, d + 2 * nseg, d + 3 * nseg, d + 4 * nseg, d + 5 * nseg, d + 6 * nseg, d + 7 * nseg,
-                      d + 8 * nseg, d + 9 * nseg, nseg};
+    // memory-based admission: size the tentative batch (the first k events) on the device; run it if the lane's
+    // footprint after growing to the exact sizes fits its share of the budget and the device's free memory, else
+    // halve it; a single event that does not fit fails alone with LTS_ERR_OOM
+    const int64_t mp = c->P.max_packets;
+    const int64_t share = S->cfg.mem_budget_bytes / S->cfg.n_lanes;
+    DevBuf *outs[] = {&L->pix, &L->cur, &L->pkp, &L->pkt, &L->pka, &L->pkf, &L->counts, &L->report, &L->evpix,
+                      &L->evpkt};
     lts_outputs o{};
-    for (int attempt = 0; st == LTS_OK && attempt < 3; ++attempt) {
-        const int64_t mp = c->P.max_packets;
-        if ((st = ensure(c, L->pix, sizeof(int32_t) * (size_t)std::max<int64_t>(L->cap_pixels, 1)))) break;
-        if ((st = ensure(c, L->cur, sizeof(float) * (size_t)std::max<int64_t>(L->cap_pixels, 1) * S->n_ticks))) break;
-        L->cap_packets = std::max<int64_t>(L->cap_packets, L->cap_pixels * mp / 8 + 1024);
-        if ((st = ensure(c, L->pkp, sizeof(int32_t) * (size_t)L->cap_packets))) break;
-        if ((st = ensure(c, L->pkt, sizeof(int32_t) * (size_t)L->cap_packets))) break;
-        if ((st = ensure(c, L->pka, sizeof(uint16_t) * (size_t)L->cap_packets))) break;
-        if ((st = ensure(c, L->pkf, sizeof(uint8_t) * (size_t)L->cap_packets))) break;
-        if ((st = ensure(c, L->counts, sizeof(int64_t) * 4))) break;
-        if ((st = ensure(c, L->report, sizeof(double) * 5 * (size_t)ne))) break;
-        if ((st = ensure(c, L->evpix, sizeof(int64_t) * (size_t)(ne + 1)))) break;
-        if ((st = ensure(c, L->evpkt, sizeof(int64_t) * (size_t)(ne + 1)))) break;
-        o = lts_outputs{(int32_t *)L->pix.p, (float *)L->cur.p, L->cap_pixels, (int32_t *)L->pkp.p, (int32_t *)L->pkt.p,
-                        (uint16_t *)L->pka.p, (uint8_t *)L->pkf.p, L->cap_packets, (int64_t *)L->counts.p,
+    auto set_outputs = [&](int64_t cap_px) {
+        o = lts_outputs{(int32_t *)L->pix.p, (float *)L->cur.p, cap_px, (int32_t *)L->pkp.p, (int32_t *)L->pkt.p,
+                        (uint16_t *)L->pka.p, (uint8_t *)L->pkf.p, cap_px * mp, (int64_t *)L->counts.p,
                         (double *)L->report.p, (int64_t *)L->evpix.p, (int64_t *)L->evpkt.p};
-        st = run_pipeline(c, ne, ids.data(), offs.data(), &segs, &o, L->stream);
-        if (st != LTS_ERR_CAPACITY) break;
-        int64_t need[4] = {0, 0, 0, 0};
-        if (hipMemcpy(need, L->counts.p, sizeof(need), hipMemcpyDeviceToHost) != hipSuccess) { st = LTS_ERR_DEVICE; break; }
-        L->cap_pixels = std::max(L->cap_pixels, need[0] + need[0] / 4 + 64);
-        L->cap_packets = std::max(L->cap_packets, need[1] + need[1] / 4 + 64);
-        st = LTS_OK;
+    };
+    // the sizing pass already writes the per-event report: counts, report and event offsets are sized for the
+    // whole tentative batch up front, the large outputs (non-null placeholders until then) by the admission hook
+    const size_t small[] = {16, 16, 16, 16, 16, 16, sizeof(int64_t) * 4, sizeof(double) * 5 * (size_t)ne,
+                            sizeof(int64_t) * (size_t)(ne + 1), sizeof(int64_t) * (size_t)(ne + 1)};
+    for (int i = 0; i < 10 && st == LTS_OK; ++i) st = ensure(c, *outs[i], small[i]);
+    set_outputs(0);
+    int32_t ran = 0;
+    if (st == LTS_OK) {
+        ran = admission_loop(ne, [&](int32_t k) -> Admit {
+            lts_segments segs{d, d + nseg, d + 2 * nseg, d + 3 * nseg, d + 4 * nseg, d + 5 * nseg, d + 6 * nseg,
+                              d + 7 * nseg, d + 8 * nseg, d + 9 * nseg, offs[k]};
+            Admit decision = Admit::Run;
+            c->admit = [&](const DevHeader &h, int64_t total, int64_t growth) -> lts_status {
+                const int64_t px = std::max<int64_t>(h.n_slots, 1), pk = std::max<int64_t>(h.n_slots * mp, 1);
+                const size_t want[] = {sizeof(int32_t) * (size_t)px, sizeof(float) * (size_t)px * S->n_ticks,
+                                       sizeof(int32_t) * (size_t)pk, sizeof(int32_t) * (size_t)pk,
+                                       sizeof(uint16_t) * (size_t)pk, sizeof(uint8_t) * (size_t)pk,
+                                       sizeof(int64_t) * 4, sizeof(double) * 5 * (size_t)k,
+                                       sizeof(int64_t) * (size_t)(k + 1), sizeof(int64_t) * (size_t)(k + 1)};
+                int64_t out_total = (int64_t)L->seg.bytes, out_growth = 0;
+                for (int i = 0; i < 10; ++i) {
+                    out_total += (int64_t)std::max(outs[i]->bytes, want[i]);
+                    if (want[i] > outs[i]->bytes) out_growth += (int64_t)(want[i] - outs[i]->bytes);
+                }
+                size_t free_b = 0, total_b = 0;
+                if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+                    (void)hipGetLastError();
+                    free_b = 0;
+                }
+                decision = admit_decision(k, total + out_total, growth + out_growth, share, (int64_t)free_b,
+                                          S->mem_reserve);
+                if (decision != Admit::Run) return kNotAdmitted;
+                lts_status r2 = LTS_OK;
+                for (int i = 0; i < 10 && r2 == LTS_OK; ++i) r2 = ensure(c, *outs[i], want[i]);
+                if (r2) return r2;
+                set_outputs(h.n_slots);
+                return LTS_OK;
+            };
+            struct Unhook {                                       // the hook captures this frame: never outlive it
+                lts_context *c;
+                ~Unhook() { c->admit = nullptr; }
+            } unhook{c};
+            st = run_pipeline(c, k, ids.data(), offs.data(), &segs, &o, L->stream);
+            if (st == kNotAdmitted) {
+                st = LTS_OK;
+                return decision;
+            }
+            return Admit::Run;                                    // ran (or failed with its own status)
+        });
     }
+    // events the batch no longer holds go back to the front of the queue, in order; a rejected head event (it alone
+    // exceeds the lane's share) finishes with LTS_ERR_OOM
+    const bool rejected = st == LTS_OK && ran == 0;
+    const size_t keep = st != LTS_OK ? (size_t)ne : rejected ? 1 : (size_t)ran;
+    if (keep < (size_t)ne) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (size_t e = keep; e < (size_t)ne; ++e) S->state[batch[e]->ticket] = 0;
+        requeue_tail(S->queue, batch, keep);
+        S->cv_work.notify_all();
+    }
+    if (rejected) st = LTS_ERR_OOM;
+    const int32_t nr = (int32_t)batch.size();
     // results back to host
-    std::vector<std::unique_ptr<Finished>> fin(ne);
+    std::vector<std::unique_ptr<Finished>> fin(nr);
     int64_t cnt[4] = {0, 0, 0, 0};
-    std::vector<int64_t> evpix(ne + 1, 0), evpkt(ne + 1, 0);
-    std::vector<double> rep(5 * (size_t)ne, 0.0);
-    std::vector<int64_t> evc(2 * (size_t)ne, 0);
+    std::vector<int64_t> evpix(nr + 1, 0), evpkt(nr + 1, 0);
+    std::vector<double> rep(5 * (size_t)nr, 0.0);
+    std::vector<int64_t> evc(2 * (size_t)nr, 0);
     if (st == LTS_OK) {
         if (hipMemcpyAsync(cnt, L->counts.p, sizeof(cnt), hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
-            hipMemcpyAsync(evc.data(), c->ev_cnt.p, sizeof(int64_t) * 2 * ne, hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
-            hipMemcpyAsync(evpix.data(), L->evpix.p, sizeof(int64_t) * (ne + 1), hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
-            hipMemcpyAsync(evpkt.data(), L->evpkt.p, sizeof(int64_t) * (ne + 1), hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
-            hipMemcpyAsync(rep.data(), L->report.p, sizeof(double) * 5 * ne, hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
+            hipMemcpyAsync(evc.data(), c->ev_cnt.p, sizeof(int64_t) * 2 * nr, hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
+            hipMemcpyAsync(evpix.data(), L->evpix.p, sizeof(int64_t) * (nr + 1), hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
+            hipMemcpyAsync(evpkt.data(), L->evpkt.p, sizeof(int64_t) * (nr + 1), hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
+            hipMemcpyAsync(rep.data(), L->report.p, sizeof(double) * 5 * nr, hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
             hipStreamSynchronize(L->stream) != hipSuccess)
             st = LTS_ERR_DEVICE;
     }
     // the whole batch's pixels and packets in one copy per array, then cut per event on the host
-    const int64_t np_all = st == LTS_OK ? evpix[ne] : 0, nk_all = st == LTS_OK ? evpkt[ne] : 0;
+    const int64_t np_all = st == LTS_OK ? evpix[nr] : 0, nk_all = st == LTS_OK ? evpkt[nr] : 0;
     std::vector<int32_t> h_pix(np_all), h_pkp(nk_all), h_pkt(nk_all);
     std::vector<uint16_t> h_pka(nk_all);
     std::vector<uint8_t> h_pkf(nk_all);
@@ -1352,13 +1512,13 @@ void lane_run_batch(Lane *L, std::vector<Request *> &batch) {
         get(h_cur.data(), L->cur.p, sizeof(float) * h_cur.size());
         if (!ok || hipStreamSynchronize(L->stream) != hipSuccess) st = LTS_ERR_DEVICE;
     }
-    for (int32_t e = 0; e < ne; ++e) {
+    for (int32_t e = 0; e < nr; ++e) {
         fin[e].reset(new Finished());
         Finished *f = fin[e].get();
         f->v.event_id = batch[e]->event_id;
         f->v.t_submit = batch[e]->t_submit;
         f->v.t_start = t_start;
-        f->v.batch_events = ne;
+        f->v.batch_events = nr;
         if (st == LTS_OK) {
             const int64_t p0 = evpix[e], p1 = evpix[e + 1], k0 = evpkt[e], k1 = evpkt[e + 1];
             f->pixel_id.resize(p1 - p0);
@@ -1389,13 +1549,9 @@ void lane_run_batch(Lane *L, std::vector<Request *> &batch) {
         f->v.pkt_adc = f->pkt_adc.data();
         f->v.pkt_flags = f->pkt_flags.data();
     }
-    // refine the admission estimate from the scratch actually used
-    const double used = (double)c->si.bytes + c->cells.bytes + c->pairs.bytes + c->pairs_u.bytes + L->cur.bytes +
-                        L->seg.bytes;
     const double t_done = now_s();
     std::lock_guard<std::mutex> lk(S->mu);
-    if (nseg > 0) S->bytes_per_segment = std::max(0.5 * S->bytes_per_segment + 0.5 * used / nseg, 256.0);
-    for (int32_t e = 0; e < ne; ++e) {
+    for (int32_t e = 0; e < nr; ++e) {
         fin[e]->v.t_done = t_done;
         const uint64_t t = batch[e]->ticket;
         auto it = S->state.find(t);
@@ -1454,7 +1610,6 @@ void lane_fail_batch(Lane *L, std::vector<Request *> &batch, lts_status st) noex
 void lane_loop(Lane *L) {
     lts_server *S = L->srv;
     (void)hipSetDevice(S->device);
-    const double budget = (double)S->cfg.mem_budget_bytes / (double)S->cfg.n_lanes;
     for (;;) {
         std::vector<Request *> batch;
         try {
@@ -1470,8 +1625,7 @@ void lane_loop(Lane *L) {
             int64_t segs = 0;
             while (!S->queue.empty() && (int32_t)batch.size() < S->cfg.max_batch_events) {
                 Request *r = S->queue.front();
-                const double est = (double)(segs + r->n) * S->bytes_per_segment;
-                if (!batch.empty() && (segs + r->n > S->cfg.max_batch_segments || est > budget)) break;
+                if (!batch.empty() && segs + r->n > S->cfg.max_batch_segments) break;
                 S->queue.pop_front();
                 S->state[r->ticket] = 1;
                 batch.push_back(r);
@@ -1497,13 +1651,16 @@ lts_status lts_server_start(lts_context *ctx, const lts_server_cfg *cfg, lts_ser
     if (!ctx || !out) return LTS_ERR_INVALID_ARG;
     *out = nullptr;
     if (!ctx->has_table) return fail(ctx, LTS_ERR_STATE, "no response table: call lts_set_response first");
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipMemGetInfo(&free_b, &total_b));
     lts_server *S = new (std::nothrow) lts_server();
     if (!S) return LTS_ERR_OOM;
     if (cfg) S->cfg = *cfg;
     if (S->cfg.n_lanes <= 0) S->cfg.n_lanes = 2;
     if (S->cfg.max_batch_events <= 0) S->cfg.max_batch_events = 64;
     if (S->cfg.max_batch_segments <= 0) S->cfg.max_batch_segments = 4000000;
-    if (S->cfg.mem_budget_bytes <= 0) S->cfg.mem_budget_bytes = 32ll << 30;
+    if (S->cfg.mem_budget_bytes <= 0) S->cfg.mem_budget_bytes = (int64_t)(total_b / 2);   // half of the device
     S->device = ctx->device;
     S->n_ticks = ctx->ro.n_ticks;
     auto undo = [&] {                                  // destroys the lanes made so far (no thread started yet)
@@ -1526,6 +1683,8 @@ lts_status lts_server_start(lts_context *ctx, const lts_server_cfg *cfg, lts_ser
             if (r == LTS_OK) r = lts_set_ticks_per_thread(L->ctx, ctx->ticks_per_thread);
             if (r == LTS_OK) r = lts_set_lane_exchange(L->ctx, ctx->lane_exchange);
             if (r == LTS_OK) r = lts_set_matrix_cores(L->ctx, ctx->matrix_cores);
+            if (r == LTS_OK)
+                r = lts_set_tuning(L->ctx, ctx->tuning.empty() ? nullptr : ctx->tuning.data(), (int32_t)ctx->tuning.size());
             if (r == LTS_OK && hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess) {
                 L->stream = nullptr;
                 r = LTS_ERR_DEVICE;

@@ -60,6 +60,11 @@ class lts_outputs(C.Structure):
                 ("report", C.c_void_p), ("event_pixel_offsets", C.c_void_p), ("event_packet_offsets", C.c_void_p)]
 
 
+class lts_tuning(C.Structure):
+    _fields_ = [("min_segments_per_event", C.c_int64), ("reduce_mode", C.c_int32), ("induce_slices", C.c_int32),
+                ("ticks_per_thread", C.c_int32), ("lane_exchange", C.c_int32)]
+
+
 class lts_server_cfg(C.Structure):
     _fields_ = [("n_lanes", C.c_int32), ("max_batch_events", C.c_int32), ("max_batch_segments", C.c_int64),
                 ("mem_budget_bytes", C.c_int64), ("return_currents", C.c_int32)]
@@ -73,11 +78,11 @@ class lts_result_view(C.Structure):
                 ("t_start", C.c_double), ("t_done", C.c_double), ("batch_events", C.c_int32)]
 
 
-STAGES = ("quench_drift", "rasterize", "cells", "induce", "electronics")
+STAGES = ("quench_drift", "rasterize", "cells", "induce", "electronics", "induce_kernel")
 
 EXPORTS = ("lts_server_start", "lts_server_submit", "lts_server_poll", "lts_server_wait", "lts_server_release",
            "lts_server_stop", "lts_set_timing", "lts_get_timing", "lts_work_stats", "lts_context_create", "lts_context_destroy",
-           "lts_set_response", "lts_set_reduce_mode", "lts_set_induce_slices", "lts_set_ticks_per_thread", "lts_set_lane_exchange", "lts_set_matrix_cores", "lts_set_graph", "lts_graph_stats", "lts_set_channel_mask",
+           "lts_set_response", "lts_set_reduce_mode", "lts_set_tuning", "lts_set_induce_slices", "lts_set_ticks_per_thread", "lts_set_lane_exchange", "lts_set_matrix_cores", "lts_set_graph", "lts_graph_stats", "lts_set_channel_mask",
            "lts_plan", "lts_simulate", "lts_simulate_batch", "lts_stage_quench_drift", "lts_debug_cells",
            "lts_stage_electronics", "lts_stage_electronics_noalloc", "lts_stage_philox", "lts_debug_fail_host_alloc", "lts_stage_rasterize", "lts_stage_induce", "lts_stage_reduce", "lts_status_str", "lts_last_error", "lts_version",
            "lts_light_create", "lts_light_destroy", "lts_light_simulate", "lts_light_set_graph", "lts_light_last_error")
@@ -106,6 +111,7 @@ def lib():
         L.lts_context_destroy.restype = None
         L.lts_set_response.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32]
         L.lts_set_reduce_mode.argtypes = [P, C.c_int32]
+        L.lts_set_tuning.argtypes = [P, C.POINTER(lts_tuning), C.c_int32]
         L.lts_set_induce_slices.argtypes = [P, C.c_int32]
         L.lts_set_ticks_per_thread.argtypes = [P, C.c_int32]
         L.lts_set_lane_exchange.argtypes = [P, C.c_int32]
@@ -281,6 +287,13 @@ class Context:
 
     def set_reduce_mode(self, mode: int):
         self._check(lib().lts_set_reduce_mode(self._h, mode))
+
+    def set_tuning(self, table):
+        """Install a work-split table: a list of (min_segments_per_event, reduce_mode, slices, ticks_per_thread,
+        lane_exchange) in ascending order (lts_set_tuning); None or [] removes it."""
+        table = list(table or [])
+        arr = (lts_tuning * max(len(table), 1))(*[lts_tuning(*map(int, e)) for e in table])
+        self._check(lib().lts_set_tuning(self._h, arr if table else None, len(table)))
 
     def set_graph(self, on: bool):
         """Replay each call's launch sequence after the sizing read-back as one HIP graph (lts_set_graph)."""

@@ -646,17 +646,81 @@ def test_served_results_equal_alone(lt, torch):
         np.testing.assert_allclose(a["report"][0], g["report"], rtol=1e-12, atol=1e-9)
 
 
+def test_server_admission_by_device_memory(lt, torch):
+    """Memory-based admission on the device: with a budget below one event's footprint every event finishes with
+    LTS_ERR_OOM and the server keeps serving; with a budget that holds a few events the lanes halve their batches
+    (no batch reaches the 8 events submitted together) and every result equals the event alone."""
+    w = W.make_workload(1, n_events=8)
+    for e in range(8):
+        w.events[e] = w.events[e].shifted(dt=0.3 * e)
+    ctx = lt.Context.from_workload(w)
+    alone = [ctx.simulate(lt.to_device(s), event_id=i).host() for s, i in zip(w.events, w.event_ids)]
+    srv = lt.Server(ctx, n_lanes=2, max_batch_events=8, mem_budget_bytes=2 << 20)        # 1 MiB per lane
+    try:
+        tickets = [srv.submit(s, i) for s, i in zip(w.events, w.event_ids)]
+        for t in tickets:
+            with pytest.raises(lt.LtsimError) as ei:
+                srv.wait(t, 60.0)
+            assert ei.value.status == 3
+            srv.release(t)
+    finally:
+        srv.stop()
+    # one event's footprint: table (~0.7 MB), scratch and outputs of a 70x70-pixel, 2000-tick event (a few MB)
+    srv = lt.Server(ctx, n_lanes=1, max_batch_events=8, mem_budget_bytes=40 << 20, return_currents=True)
+    try:
+        tickets = [srv.submit(s, i) for s, i in zip(w.events, w.event_ids)]
+        got = [srv.wait(t, 60.0) for t in tickets]
+        for t in tickets:
+            srv.release(t)
+    finally:
+        srv.stop()
+    sizes = [g["batch_events"] for g in got]
+    print(f"admission under a 40 MiB budget: batch sizes {sizes}")
+    assert max(sizes) < 8
+    for a, g in zip(alone, got):
+        assert g["status"] == 0
+        for k in ("pixel_id", "current", "pkt_tick", "pkt_adc", "counts"):
+            assert np.array_equal(a[k], g[k]), k
+
+
 # ----------------------------------------------------------------------------------------------- autotuner
 
-def test_autotune_picks_an_accurate_candidate(lt, torch, tmp_path):
+def test_autotune_table_is_accurate_and_applied(lt, torch, tmp_path):
+    """The autotuner times its candidates per event-size class, keeps only those within 1e-5 of the sorted
+    reference, caches the table, and the library applies the table's entry per call: a batch under the table gives
+    the results of a context set to that entry's knobs directly."""
     from paper_2212_09807_amd import autotune as AT
     w = W.make_workload(1)
-    cands = [AT.Choice(0, 1, 0), AT.Choice(0, 2, 0), AT.Choice(1, 1, 0), AT.Choice(0, 1, 2)]
-    res = AT.autotune(w, candidates=cands, reps=1, cache=str(tmp_path / "tune.json"))
-    assert res["best"]["max_rel_l2_vs_sorted"] <= 1e-5
-    assert len(res["all"]) == 4 and all(r["ms"] > 0 for r in res["all"])
-    again = AT.autotune(w, candidates=cands, cache=str(tmp_path / "tune.json"))     # served from the cache
-    assert again["best"] == res["best"]
+    cands = [AT.Choice(0, 1, 0), AT.Choice(1, 1, 0), AT.Choice(2, 1, 0), AT.Choice(0, 1, 4)]
+    res = AT.autotune(w, sizes=(200,), candidates=cands, events_per_class=4, cache=str(tmp_path / "tune.json"))
+    (cls,) = res["classes"]
+    assert len(cls["all"]) == 4 and all(r["ms"] > 0 for r in cls["all"])
+    assert cls["best"]["max_rel_l2_vs_sorted"] <= 1e-5
+    again = AT.autotune(w, sizes=(200,), candidates=cands, events_per_class=4, cache=str(tmp_path / "tune.json"))
+    assert again["table"] == res["table"]
+    (entry,) = res["table"]
+    evs = AT.class_events(w, 200, 3, seed=5)
+    offs = np.r_[0, np.cumsum([e.n for e in evs])]
+    ids = [11, 12, 13]
+    tuned = lt.Context.from_workload(w)
+    tuned.set_tuning([entry])
+    direct = lt.Context.from_workload(w)
+    AT.Choice(*entry[1:]).apply(direct)
+    a = tuned.simulate_batch(lt.to_device(W.Segments.concat(evs)), offs, ids).host()
+    b = direct.simulate_batch(lt.to_device(W.Segments.concat(evs)), offs, ids).host()
+    assert np.array_equal(a["pixel_id"], b["pixel_id"])
+    if entry[1] == 1:                       # FP32 atomics: the summation order differs from run to run
+        assert per_pixel_errors(a["current"].astype(np.float64), b["current"].astype(np.float64)).max() < 1e-6
+    else:
+        assert np.array_equal(a["current"], b["current"])
+    # a two-entry table: small calls take the first entry, large ones the second
+    tuned.set_tuning([[0, 2, 1, 0, 0], [100000, 1, 1, 0, 0]])
+    c = tuned.simulate_batch(lt.to_device(W.Segments.concat(evs)), offs, ids).host()
+    summed = lt.Context.from_workload(w, reduce_mode=2).simulate_batch(lt.to_device(W.Segments.concat(evs)), offs,
+                                                                      ids).host()
+    assert np.array_equal(c["current"], summed["current"])
+    with pytest.raises(lt.LtsimError):
+        tuned.set_tuning([[10, 0, 1, 0, 0], [5, 0, 1, 0, 0]])             # not ascending
 
 
 def test_disabled_channels_produce_no_packets(lt, torch):
