@@ -164,7 +164,10 @@ def headline(ltsim, W, args):
         "tiles_per_s": len(w.events) * args.steps / elapsed,
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
         "stage_ms": st,
-        "roofline": roofline(INDUCE_KERNEL[args.mode], "large_spill", stats["fma"], st["induce_kernel"]),
+        "roofline": roofline(INDUCE_KERNEL[args.mode], "large_spill", stats["fma"], st["induce_kernel"],
+                             {"fma_issued_per_launch": stats["fma_issued"] or None,
+                              "useful_fraction_of_issued": stats["fma"] / stats["fma_issued"] if stats["fma_issued"]
+                              else None, "records": stats["records"]}),
     }
     # the report's conservation check at full size: collected = induced in window + clipped + off-grid (per tile)
     rep = h["report"]

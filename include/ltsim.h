@@ -303,9 +303,12 @@ lts_status lts_stage_electronics_noalloc(lts_context *ctx, uint64_t event_id, co
 /* Algorithmic work of the last lts_simulate / lts_simulate_batch / lts_plan call on this context (synchronous):
  * out[0] (segment, pixel) pairs; out[1] products c[a,u,v] * R[k,i,j] of eq. (current) that land in the tick
  * window, summed over pairs (the multiply-adds of the induction; in LTS_REDUCE_SUMMED the products of summed
- * column charges, summed over pixels); out[2] charge cells in reach summed over pairs (summed columns' ticks in
- * reach summed over pixels in LTS_REDUCE_SUMMED); out[3] charge cells of all segments. */
-lts_status lts_work_stats(lts_context *ctx, double out[4]);
+ * column charges, summed over pixels, counting only ticks that hold charge); out[2] charge cells in reach summed over
+ * pairs (summed columns' ticks with charge in reach summed over pixels in LTS_REDUCE_SUMMED); out[3] charge cells of all segments; out[4] (LTS_REDUCE_SUMMED
+ * only, else 0) the products the summed induction kernel computes, zeros included (every 512-tick tile a piece's
+ * window meets, all its lanes, charge ticks rounded up to 8): out[1] / out[4] is the useful fraction of its
+ * multiply-adds; out[5] the (pixel, column piece) records in LTS_REDUCE_SUMMED, else the pairs. */
+lts_status lts_work_stats(lts_context *ctx, double out[6]);
 
 /* Test hook for the error paths: after `after` further host-allocation points inside the library have passed
  * (0 = the next one), one of them fails as if host memory were exhausted, once; -1 disarms.  The points are the

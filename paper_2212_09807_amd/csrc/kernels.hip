@@ -379,12 +379,14 @@ void launch_slots(const DevParams &P, const Work &w, int32_t *pixel_id_out, int6
         k_event_pixel_offsets<<<(w.n_ev + 1 + kWG - 1) / kWG, kWG, 0, st>>>(w.n_ev, P.npx, w.pix_cnt, ev_pix_off);
 }
 
-// Also stores each segment's scanned charge-cell offset in its record (the scan runs after k_quench_drift).
+// Also stores each segment's scanned charge-cell offset in its record (the scan runs after k_quench_drift); with
+// pairs = null only that.
 __global__ __launch_bounds__(kWG) void k_fill_pairs(DevParams P, SegInfo *si, int64_t n_seg, const int64_t *cell_off,
                                                     const uint64_t *pix_off, int32_t *cursor, int32_t *pairs) {
     int64_t s = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (s >= n_seg) return;
     si[s].cell_off = cell_off[s];
+    if (!pairs) return;                                  // the summed induction needs no pair lists
     const SegInfo &g = si[s];
     const int64_t base = (int64_t)g.event * P.npx;
     for (int32_t iy = g.iy0; iy <= g.iy1; ++iy)
@@ -1733,6 +1735,7 @@ __global__ __launch_bounds__(kWG) void k_sum_columns(int32_t align_res, const Se
     }
     sw.piece_off[c] = np;
     sw.s_off[c] = ns;
+    if (np) sw.active[atomicAdd(sw.n_active, 1u)] = (int32_t)c;    // any order: a column's outputs have fixed places
 }
 
 void launch_sum_fill(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st) {
@@ -1741,73 +1744,132 @@ void launch_sum_fill(const DevParams &P, const Work &w, const SumWork &sw, hipSt
                                                                             sw);
 }
 
-// per column: piece records, and the summed charge of each tick (Kahan over the column's segments in list order)
-__global__ void k_sum_pieces(DevParams P, const SegInfo *si, const float *cells, SumWork sw) {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= sw.n_cols) return;
-    if (sw.piece_off[c + 1] == sw.piece_off[c]) return;
-    const int32_t e = (int32_t)(c / ((int64_t)sw.CU * sw.CV));
-    const int64_t r = c - (int64_t)e * sw.CU * sw.CV;
-    const int32_t u = sw.UL + (int32_t)(r / sw.CV), v = sw.VL + (int32_t)(r % sw.CV);
-    const int64_t sb = sw.col_seg_off[c], se = sw.col_seg_off[c + 1];
+// Wave-uniform copies of a 64-bit value held by lane l.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// per column: piece records, and the summed charge of each tick (Kahan over the column's segments in list order).
+// Wavefronts take the columns with pieces from the active list, one column at a time; lane j sums tick
+// lo + 64 m + j of the current interval over the interval's segments, the same additions per tick, in the same
+// order, as a tick-by-tick scan.  For a list of at most 256 segments, lane k first loads the first tick, length and
+// start of the cells in this column of segments k, k + 64, k + 128 and k + 192, so the per-segment loop reads them
+// from registers and only the (coalesced) cell loads go to memory; longer lists read each record in the loop.
+__global__ __launch_bounds__(kWG) void k_sum_pieces(DevParams P, const SegInfo *si, const float *cells, SumWork sw) {
+    const int lane = threadIdx.x & 63;
     const int32_t res = ((P.t_r - 1 + kPad) % 8 + 8) % 8;
-    int64_t pk = sw.piece_off[c], so = sw.s_off[c];
-    for (int64_t q = sb; q < se;) {
-        int32_t lo, hi;
-        const int64_t qe = sum_interval(si, sw.col_seg, q, se, res, lo, hi);
-        const int32_t L = hi - lo + 1;
-        int64_t np, Lpad;
-        sum_interval_size(L, np, Lpad);
-        float *S = sw.S + so;
-        // 32-tick chunks with their sums in registers; per chunk, every segment of the interval that overlaps it
-        // adds its cells, in list order (the same order per tick as a tick-by-tick scan)
-        constexpr int32_t kCh = 32;
-        for (int32_t a0c = 0; a0c < Lpad; a0c += kCh) {
-            float sum[kCh], cmp[kCh];
+    const uint32_t n_act = *sw.n_active;
+    const uint32_t waves = gridDim.x * (kWG / 64);
+    for (uint32_t ia = blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); ia < n_act;
+         ia += waves) {
+        const int64_t cc = __builtin_amdgcn_readfirstlane(sw.active[ia]);
+        const int32_t e = (int32_t)(cc / ((int64_t)sw.CU * sw.CV));
+        const int64_t r = cc - (int64_t)e * sw.CU * sw.CV;
+        const int32_t u = sw.UL + (int32_t)(r / sw.CV), v = sw.VL + (int32_t)(r % sw.CV);
+        const int64_t sb = sw.col_seg_off[cc], se = sw.col_seg_off[cc + 1], n = se - sb;
+        int64_t pk = sw.piece_off[cc], so = sw.s_off[cc];
+        const bool regs = n <= 4 * 64;
+        int32_t my_a0[4] = {0, 0, 0, 0}, my_na[4] = {0, 0, 0, 0};
+        int64_t my_base[4] = {0, 0, 0, 0};                // cells index of tick 0 of the segment in this column
+        if (regs) {
 #pragma unroll
-            for (int j = 0; j < kCh; ++j) { sum[j] = 0.0f; cmp[j] = 0.0f; }
-            const int32_t cl = lo + a0c, ch = min(cl + kCh, lo + L) - 1;
-            for (int64_t k = q; k < qe; ++k) {
-                const SegInfo &g = si[key_seg(sw.col_seg[k])];
-                if (g.a0 > ch) break;                   // sorted by first tick
-                const int32_t ga = max(g.a0, cl), gb = min(g.a0 + g.na - 1, ch);
-                if (ga > gb) continue;
-                const float *src = cells + g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad - g.a0;
-#pragma unroll
-                for (int j = 0; j < kCh; ++j) {
-                    const int32_t aa = cl + j;
-                    if (aa >= ga && aa <= gb) {
-                        const float y = src[aa] - cmp[j];
-                        const float t = sum[j] + y;
-                        cmp[j] = (t - sum[j]) - y;
-                        sum[j] = t;
-                    }
+            for (int w = 0; w < 4; ++w)
+                if (64 * w + lane < n) {
+                    const SegInfo &g = si[key_seg(sw.col_seg[sb + 64 * w + lane])];
+                    my_a0[w] = g.a0;
+                    my_na[w] = g.na;
+                    my_base[w] = g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad - g.a0;
                 }
+        }
+        auto seg_at = [&](int64_t k, int32_t &a0, int32_t &na, int64_t &base) {
+            if (regs) {                                   // entry k is held by lane k % 64 in register set k / 64
+                const int w = (int)(k >> 6), j = (int)(k & 63);
+                const int32_t x0 = w == 0 ? my_a0[0] : w == 1 ? my_a0[1] : w == 2 ? my_a0[2] : my_a0[3];
+                const int32_t x1 = w == 0 ? my_na[0] : w == 1 ? my_na[1] : w == 2 ? my_na[2] : my_na[3];
+                const int64_t x2 = w == 0 ? my_base[0] : w == 1 ? my_base[1] : w == 2 ? my_base[2] : my_base[3];
+                a0 = __builtin_amdgcn_readlane(x0, j);
+                na = __builtin_amdgcn_readlane(x1, j);
+                base = uniform_i64(x2, j);
+            } else {
+                const SegInfo &g = si[key_seg(sw.col_seg[sb + k])];
+                a0 = g.a0;
+                na = g.na;
+                base = g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad - g.a0;
             }
+        };
+        for (int64_t q = 0; q < n;) {
+            // the merged interval starting at list entry q (the same rule as sum_interval)
+            int32_t lo, hi, a0, na;
+            int64_t base;
+            seg_at(q, a0, na, base);
+            lo = a0;
+            hi = a0 + na - 1;
+            int64_t qe = q + 1;
+            for (; qe < n; ++qe) {
+                seg_at(qe, a0, na, base);
+                if (a0 - hi - 1 > kSumGap) break;
+                hi = max(hi, a0 + na - 1);
+            }
+            lo -= ((lo - res) % 8 + 8) % 8;
+            const int32_t L = hi - lo + 1;
+            int64_t np, Lpad;
+            sum_interval_size(L, np, Lpad);
+            float *S = sw.S + so;
+            for (int32_t a0c = 0; a0c < Lpad; a0c += 64) {
+                const int32_t aa = lo + a0c + lane, ch = min(lo + a0c + 63, hi);
+                float sum = 0.0f, cmp = 0.0f;
+                // eight segments at a time: their cell loads are issued together, then added in list order
+                bool past = false;
+                for (int64_t k0 = q; k0 < qe && !past; k0 += 8) {
+                    float val[8];
+                    bool use[8];
 #pragma unroll
-            for (int j = 0; j < kCh; ++j)
-                if (a0c + j < Lpad) S[a0c + j] = sum[j] - cmp[j];
+                    for (int i = 0; i < 8; ++i) {
+                        use[i] = false;
+                        val[i] = 0.0f;
+                        if (k0 + i < qe && !past) {
+                            seg_at(k0 + i, a0, na, base);
+                            if (a0 > ch) past = true;           // sorted by first tick: no later one reaches
+                            else if (aa >= a0 && aa <= a0 + na - 1 && aa <= hi) {
+                                use[i] = true;
+                                val[i] = cells[base + aa];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (use[i]) {
+                            const float y = val[i] - cmp;
+                            const float t = sum + y;
+                            cmp = (t - sum) - y;
+                            sum = t;
+                        }
+                }
+                if (a0c + lane < Lpad) S[a0c + lane] = sum - cmp;
+            }
+            for (int64_t k = lane; k < np; k += 64) {
+                SegInfo g = {};
+                g.u0 = u; g.nu = 1; g.v0 = v; g.nv = 1;
+                g.a0 = lo + (int32_t)k * kPieceTicks;
+                g.na = min(kPieceTicks, L - (int32_t)k * kPieceTicks);
+                g.na_pad = (g.na + kAC - 1) / kAC * kAC;
+                g.cell_off = so + k * kPieceTicks;
+                g.event = e;
+                g.n_pairs = 1;
+                sw.piece[pk + k] = g;
+                sw.pdesc[pk + k] = PieceRef{g.a0, g.na, (uint32_t)(g.cell_off / kAC), 0};
+            }
+            pk += np;
+            so += Lpad;
+            q = qe;
         }
-        for (int64_t k = 0; k < np; ++k) {
-            SegInfo g = {};
-            g.u0 = u; g.nu = 1; g.v0 = v; g.nv = 1;
-            g.a0 = lo + (int32_t)k * kPieceTicks;
-            g.na = min(kPieceTicks, L - (int32_t)k * kPieceTicks);
-            g.na_pad = (g.na + kAC - 1) / kAC * kAC;
-            g.cell_off = so + k * kPieceTicks;
-            g.event = e;
-            g.n_pairs = 1;
-            sw.piece[pk + k] = g;
-            sw.pdesc[pk + k] = PieceRef{g.a0, g.na, (uint32_t)(g.cell_off / kAC), 0};
-        }
-        pk += np;
-        so += Lpad;
-        q = qe;
     }
 }
 
 void launch_sum_pieces(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st) {
-    k_sum_pieces<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.cells, sw);
+    k_sum_pieces<<<256 * 16, kWG, 0, st>>>(P, w.si, w.cells, sw);   // persistent waves over the active columns
 }
 
 // per active pixel (one wavefront): number of column pieces in its table reach, then their ids and records in column
@@ -2315,28 +2377,41 @@ void launch_work_stats(const DevParams &P, const SegInfo *si, int64_t n_seg, uns
 }
 
 // Summed induction: per active pixel, the (column-piece tick, table tick) products that land in the window.
+// Summed mode: a tick of a piece counts only if it holds charge (the ticks a piece adds for alignment, and the short
+// gaps between segments that a piece spans, hold exact zeros and are not algorithmic work).
 __global__ void k_work_stats_summed(DevParams P, int64_t n_slots, const int64_t *list_off, const PieceRef *rec,
-                                    unsigned long long *acc) {
+                                    const float *S, unsigned long long *acc) {
     int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= n_slots) return;
-    unsigned long long f = 0, cells = 0;
+    unsigned long long f = 0, cells = 0, issued = 0;
+    const int32_t n_tiles = (P.nticks + kTileTicks - 1) / kTileTicks;
     for (int64_t q = list_off[slot]; q < list_off[slot + 1]; ++q) {
         const PieceRef g = rec[q];
+        const float *sv = S + (int64_t)g.cell8 * kAC;
         for (int32_t a = g.a0; a < g.a0 + g.na; ++a) {
+            if (sv[a - g.a0] == 0.0f) continue;
             const int32_t lo = max(a - P.t_r + 1, 0), hi = min(a, P.nticks - 1);
             if (hi >= lo) f += (unsigned long long)(hi - lo + 1);
+            ++cells;
         }
-        cells += (unsigned long long)g.na;
+        // products the summed kernel computes for this piece, zeros included: every 512-tick tile its window meets,
+        // all 64 lanes x 8 ticks x every 8-tick charge block
+        const int32_t t_lo = max(floor_div(g.a0 - P.t_r + 1, kTileTicks), 0);
+        const int32_t t_hi = min(floor_div(g.a0 + g.na - 1, kTileTicks), n_tiles - 1);
+        if (t_hi >= t_lo)
+            issued += (unsigned long long)(t_hi - t_lo + 1) * (unsigned long long)((g.na + kAC - 1) / kAC) *
+                      (unsigned long long)(kTileTicks * kAC);
     }
     atomicAdd(&acc[0], (unsigned long long)(list_off[slot + 1] - list_off[slot]));
     atomicAdd(&acc[1], f);
     atomicAdd(&acc[2], cells);
+    atomicAdd(&acc[3], issued);
 }
 
 void launch_work_stats_summed(const DevParams &P, int64_t n_slots, const int64_t *list_off, const PieceRef *rec,
-                              unsigned long long *acc, hipStream_t st) {
+                              const float *S, unsigned long long *acc, hipStream_t st) {
     if (n_slots > 0)
-        k_work_stats_summed<<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, list_off, rec, acc);
+        k_work_stats_summed<<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, list_off, rec, S, acc);
 }
 
 // ================================================================================================= Philox test hook

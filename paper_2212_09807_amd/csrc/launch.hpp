@@ -66,6 +66,8 @@ struct SumWork {
     int32_t *col_cursor = nullptr;           // [n_cols]
     uint64_t *col_tmp = nullptr;             // [n_col_seg] per column: keys (first tick << 32 | segment index)
     uint64_t *col_seg = nullptr;             // [n_col_seg] the same keys, ascending per column
+    int32_t *active = nullptr;               // [n_cols] columns with pieces (any order), n_active of them
+    uint32_t *n_active = nullptr;
     int64_t *piece_off = nullptr;            // [n_cols + 1] pieces per column, then offsets
     int64_t *s_off = nullptr;                // [n_cols + 1] summed-cell floats per column, then offsets
     SegInfo *piece = nullptr;                // [n_pieces] one 1 x 1 x L box per column piece
@@ -125,7 +127,7 @@ void launch_stage_quench_drift(const DevParams &P, const SegArrays &S, int64_t n
                                hipStream_t st);
 void launch_work_stats(const DevParams &P, const SegInfo *si, int64_t n_seg, unsigned long long *acc, hipStream_t st);
 void launch_work_stats_summed(const DevParams &P, int64_t n_slots, const int64_t *list_off, const PieceRef *rec,
-                              unsigned long long *acc, hipStream_t st);
+                              const float *S, unsigned long long *acc, hipStream_t st);
 void launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n, hipStream_t st);
 
 }  // namespace ltsim

@@ -461,10 +461,14 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     lts_status r;
     SumWork sw = summed_grid(P, w.n_ev);
     const int64_t nc1 = sw.n_cols + 1;
+    if (sw.n_cols > (int64_t)INT32_MAX)
+        return fail(c, LTS_ERR_INVALID_ARG, "summed induction: events x sub-pixel columns exceeds 2^31 - 1");
     sw.col_seg_off = as<int64_t>(c->col_seg_off);
     sw.col_cursor = as<int32_t>(c->col_cursor);
     sw.col_seg = as<uint64_t>(c->col_seg);
     sw.col_tmp = as<uint64_t>(c->col_tmp);
+    sw.active = as<int32_t>(c->col_cursor);         // the fill's cursors are free once the lists are filled
+    sw.n_active = &w.hdr->work[3];
     sw.piece_off = as<int64_t>(c->piece_off);
     sw.s_off = as<int64_t>(c->s_off);
     sw.list_off = as<int64_t>(c->list_off);
@@ -606,11 +610,13 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
     c->last_n_slots = n_slots;
     c->last_mode = c->reduce_mode;
     const int64_t mp = c->P.max_packets;
+    const bool summed = c->reduce_mode == LTS_REDUCE_SUMMED;
+    const int64_t pair_cap = summed ? 1 : std::max<int64_t>(n_pairs, 1);   // the summed induction has no pair lists
     std::vector<Need> needs = {
         {&c->slot_gp, sizeof(int32_t) * (size_t)std::max<int64_t>(n_slots, 1)},
         {&c->slot_off, sizeof(int64_t) * (size_t)(n_slots + 1)},
-        {&c->pairs_u, sizeof(int32_t) * (size_t)std::max<int64_t>(n_pairs, 1)},
-        {&c->pairs, sizeof(int32_t) * (size_t)std::max<int64_t>(n_pairs, 1)},
+        {&c->pairs_u, sizeof(int32_t) * (size_t)pair_cap},
+        {&c->pairs, sizeof(int32_t) * (size_t)pair_cap},
         {&c->cells, sizeof(float) * (size_t)(n_cells + kCellSlack)},
         {&c->pk_tick, sizeof(int32_t) * (size_t)(n_slots * mp)},
         {&c->pk_adc, sizeof(uint16_t) * (size_t)(n_slots * mp)},
@@ -634,8 +640,8 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
     w.order = as<int32_t>(c->order);
     w.slot_gp = as<int32_t>(c->slot_gp);
     w.slot_off = as<int64_t>(c->slot_off);
-    w.pairs_unsorted = as<int32_t>(c->pairs_u);
-    w.pairs = as<int32_t>(c->pairs);
+    w.pairs_unsorted = summed ? nullptr : as<int32_t>(c->pairs_u);
+    w.pairs = summed ? nullptr : as<int32_t>(c->pairs);
     w.cells = as<float>(c->cells);
     w.pk_tick = as<int32_t>(c->pk_tick);
     w.pk_adc = as<uint16_t>(c->pk_adc);
@@ -1251,7 +1257,7 @@ lts_status lts_stage_reduce(lts_context *c, const int32_t *pair_pixel, const flo
     LTS_API_END(c)
 }
 
-lts_status lts_work_stats(lts_context *c, double out[4]) {
+lts_status lts_work_stats(lts_context *c, double out[6]) {
     LTS_API_BEGIN
     if (!c || !out) return LTS_ERR_INVALID_ARG;
     if (c->last_n_seg < 0) return fail(c, LTS_ERR_STATE, "no pipeline call yet");
@@ -1262,7 +1268,7 @@ lts_status lts_work_stats(lts_context *c, double out[4]) {
     HIP_TRY(c, hipMemset(c->counts_tmp.p, 0, 4 * sizeof(unsigned long long)));
     if (c->last_mode == LTS_REDUCE_SUMMED) {
         launch_work_stats_summed(c->P, c->last_n_slots, as<int64_t>(c->list_off), as<PieceRef>(c->rec),
-                                 as<unsigned long long>(c->counts_tmp), nullptr);
+                                 as<float>(c->S), as<unsigned long long>(c->counts_tmp), nullptr);
         HIP_TRY(c, hipGetLastError());
         unsigned long long hs[4];
         HIP_TRY(c, hipMemcpy(hs, c->counts_tmp.p, sizeof(hs), hipMemcpyDeviceToHost));
@@ -1275,6 +1281,8 @@ lts_status lts_work_stats(lts_context *c, double out[4]) {
         out[1] = (double)hs[1];
         out[2] = (double)hs[2];
         out[3] = (double)hp[3];
+        out[4] = (double)hs[3];
+        out[5] = (double)hs[0];
         return LTS_OK;
     }
     launch_work_stats(c->P, as<SegInfo>(c->si), c->last_n_seg, as<unsigned long long>(c->counts_tmp), nullptr);
@@ -1282,6 +1290,8 @@ lts_status lts_work_stats(lts_context *c, double out[4]) {
     unsigned long long h[4];
     HIP_TRY(c, hipMemcpy(h, c->counts_tmp.p, sizeof(h), hipMemcpyDeviceToHost));
     for (int i = 0; i < 4; ++i) out[i] = (double)h[i];
+    out[4] = 0.0;
+    out[5] = (double)h[0];
     return LTS_OK;
     LTS_API_END(c)
 }

@@ -260,10 +260,12 @@ class Context:
         return {k: (ms[i], calls[i]) for i, k in enumerate(STAGES)}
 
     def work_stats(self):
-        """Algorithmic work of the last call: pairs, induction multiply-adds, cells in reach, cells."""
-        out = (C.c_double * 4)()
+        """Algorithmic work of the last call: pairs, induction multiply-adds, cells in reach, cells, multiply-adds the
+        summed kernel issues (zeros included), summed records."""
+        out = (C.c_double * 6)()
         self._check(lib().lts_work_stats(self._h, out))
-        return {"pairs": out[0], "fma": out[1], "cells_in_reach": out[2], "cells": out[3]}
+        return {"pairs": out[0], "fma": out[1], "cells_in_reach": out[2], "cells": out[3], "fma_issued": out[4],
+                "records": out[5]}
 
     def set_induce_slices(self, slices: int):
         self._check(lib().lts_set_induce_slices(self._h, slices))
