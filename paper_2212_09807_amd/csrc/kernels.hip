@@ -1877,8 +1877,9 @@ void launch_sum_pieces(const DevParams &P, const Work &w, const SumWork &sw, hip
 // a wavefront prefix sum of their piece counts gives each lane its place in the list.  A record is the piece's
 // compact descriptor with the folded table column the pixel sees the column through, fold(du - bx) * by +
 // fold(dv - by) for the column at offset (du, dv) of the pixel's reach.
-template <bool FILL>
-__global__ __launch_bounds__(kWG) void k_sum_lists(DevParams P, int64_t n_slots, const int32_t *slot_gp, SumWork sw) {
+// per active pixel: the number of column pieces in its reach (the columns of its +-bx x +-by sub-pixel window)
+__global__ __launch_bounds__(kWG) void k_sum_lists_count(DevParams P, int64_t n_slots, const int32_t *slot_gp,
+                                                         SumWork sw) {
     const int lane = threadIdx.x & 63;
     const int64_t slot = (int64_t)blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (slot >= n_slots) return;
@@ -1888,45 +1889,220 @@ __global__ __launch_bounds__(kWG) void k_sum_lists(DevParams P, int64_t n_slots,
     const int32_t cu0 = ix * P.nsub + P.nsub / 2 - P.bx - sw.UL, cv0 = iy * P.nsub + P.nsub / 2 - P.by - sw.VL;
     const int64_t base = (int64_t)e * sw.CU * sw.CV;
     const int32_t nv = 2 * P.by, ncol = 2 * P.bx * nv;
-    int64_t pos = FILL ? sw.list_off[slot] : 0;
-    for (int32_t c0 = 0; c0 < ncol; c0 += 64) {
-        const int32_t c = c0 + lane;
-        int64_t pb = 0, pe = 0;
-        if (c < ncol) {
-            const int64_t col = base + (int64_t)(cu0 + c / nv) * sw.CV + cv0 + c % nv;
-            pb = sw.piece_off[col];
-            pe = sw.piece_off[col + 1];
+    int64_t x = 0;
+    for (int32_t c = lane; c < ncol; c += 64) {
+        const int64_t col = base + (int64_t)(cu0 + c / nv) * sw.CV + cv0 + c % nv;
+        x += sw.piece_off[col + 1] - sw.piece_off[col];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (lane == 0) sw.list_off[slot] = x;
+}
+
+// per active pixel: its reach's column pieces as records, grouped by the folded table column (bin) the pixel sees
+// them through and, within a bin, ascending in first tick (equal first ticks keep the mirror columns in the order
+// du >= 0 before du < 0, then dv likewise).  Lane i merges the four tick-sorted piece lists of bin b0 + i.
+__global__ __launch_bounds__(kWG) void k_sum_lists_fill(DevParams P, int64_t n_slots, const int32_t *slot_gp,
+                                                        SumWork sw) {
+    const int lane = threadIdx.x & 63;
+    const int64_t slot = (int64_t)blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (slot >= n_slots) return;
+    const int32_t gp = slot_gp[slot];
+    const int32_t e = gp / P.npx, p = gp - e * P.npx;
+    const int32_t ix = p % P.nx, iy = p / P.nx;
+    const int32_t cu0 = ix * P.nsub + P.nsub / 2 - sw.UL, cv0 = iy * P.nsub + P.nsub / 2 - sw.VL;   // centre column
+    const int64_t base = (int64_t)e * sw.CU * sw.CV;
+    const int32_t nbin = P.bx * P.by;
+    int64_t pos = sw.list_off[slot];
+    for (int32_t b0 = 0; b0 < nbin; b0 += 64) {
+        const int32_t b = b0 + lane;
+        int64_t h[4] = {0, 0, 0, 0}, he[4] = {0, 0, 0, 0};
+        int64_t x = 0;
+        if (b < nbin) {
+            const int32_t fu = b / P.by, fv = b - fu * P.by;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {                // the four columns whose offsets fold to (fu, fv)
+                const int32_t du = (m & 1) ? -fu - 1 : fu, dv = (m & 2) ? -fv - 1 : fv;
+                const int64_t col = base + (int64_t)(cu0 + du) * sw.CV + (cv0 + dv);
+                h[m] = sw.piece_off[col];
+                he[m] = sw.piece_off[col + 1];
+                x += he[m] - h[m];
+            }
         }
-        int64_t x = pe - pb, incl = x;                          // inclusive prefix of the piece counts
+        int64_t incl = x;                               // inclusive prefix of the lanes' record counts
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const int64_t y = __shfl_up(incl, d);
             if (lane >= d) incl += y;
         }
-        if (FILL && x) {
-            const int32_t bin = fold(c / nv - P.bx) * P.by + fold(c % nv - P.by);
-            for (int64_t k = 0; k < x; ++k) {
-                const int64_t q = pos + incl - x + k;
-                sw.list[q] = (int32_t)(pb + k);
-                PieceRef r = sw.pdesc[pb + k];
-                r.bin = bin;
+        if (x) {
+            int32_t ha[4];                              // first tick at each list's head (INT32_MAX when empty)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) ha[m] = h[m] < he[m] ? sw.pdesc[h[m]].a0 : INT32_MAX;
+            for (int64_t q = pos + incl - x; q < pos + incl; ++q) {
+                int m = 0;
+#pragma unroll
+                for (int j = 1; j < 4; ++j) m = ha[j] < (m == 0 ? ha[0] : m == 1 ? ha[1] : ha[2]) ? j : m;
+                int64_t k = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (j == m) {
+                        k = h[j]++;
+                        ha[j] = h[j] < he[j] ? sw.pdesc[h[j]].a0 : INT32_MAX;
+                    }
+                sw.list[q] = (int32_t)k;
+                PieceRef r = sw.pdesc[k];
+                r.bin = b;
                 sw.rec[q] = r;
             }
         }
         pos += __shfl(incl, 63);
     }
-    if (!FILL && lane == 0) sw.list_off[slot] = pos;
 }
 
 void launch_sum_lists_count(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, hipStream_t st) {
     if (n_slots > 0)
-        k_sum_lists<false><<<(unsigned)((n_slots + kWG / 64 - 1) / (kWG / 64)), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
+        k_sum_lists_count<<<(unsigned)((n_slots + kWG / 64 - 1) / (kWG / 64)), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
 }
 void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, int64_t n_list,
                            hipStream_t st) {
-    if (n_slots <= 0) return;
-    k_sum_lists<true><<<(unsigned)((n_slots + kWG / 64 - 1) / (kWG / 64)), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
+    if (n_slots > 0)
+        k_sum_lists_fill<<<(unsigned)((n_slots + kWG / 64 - 1) / (kWG / 64)), kWG, 0, st>>>(P, n_slots, w.slot_gp, sw);
     (void)n_list;
+}
+
+// Mirror merge.  A pixel convolves every record of one folded table column with the same table column, so a run of
+// its list's records with the same bin whose tick spans overlap or lie at most kMergeGap ticks apart is one record
+// whose charge is the members' sum, taken in list order.  Every record starts at the same residue mod 8 (the
+// alignment of the column intervals), so the union does as well.  Runs are cut at every 64th record of the pixel's
+// list (the lanes of one pass), and a run whose union would exceed kPieceMax ticks is not merged; a run of one record
+// stays as it is.  Count pass: records and merged-charge floats per pixel; fill pass: the merged records (in list
+// order) and their charges.  One wavefront per pixel; the runs of 64 records are found with segmented lane scans.
+constexpr int32_t kMergeGap = 8;
+
+// Inclusive segmented scans over the wavefront (a segment starts at a lane whose flag is set).
+__device__ __forceinline__ int32_t seg_scan_max(int32_t v, bool start) {
+    const int lane = lane_id();
+    int f = start;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t y = __shfl_up(v, d);
+        const int g = __shfl_up(f, d);
+        if (lane >= d && !f) {
+            v = max(v, y);
+            f |= g;
+        }
+    }
+    return v;
+}
+__device__ __forceinline__ int32_t seg_scan_min(int32_t v, bool start) {
+    const int lane = lane_id();
+    int f = start;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t y = __shfl_up(v, d);
+        const int g = __shfl_up(f, d);
+        if (lane >= d && !f) {
+            v = min(v, y);
+            f |= g;
+        }
+    }
+    return v;
+}
+// AND of v from this lane to the end of its segment (a segment ends at a lane whose flag is set).
+__device__ __forceinline__ bool seg_rscan_and(bool v, bool end) {
+    const int lane = lane_id();
+    int f = end, x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_down(x, d);
+        const int g = __shfl_down(f, d);
+        if (lane + d < 64 && !f) {
+            x &= y;
+            f |= g;
+        }
+    }
+    return x != 0;
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(kWG) void k_sum_merge(int64_t n_slots, SumWork sw) {
+    const int lane = threadIdx.x & 63;
+    const int64_t slot = (int64_t)blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (slot >= n_slots) return;
+    const int64_t pb = sw.list_off[slot], pe = sw.list_off[slot + 1];
+    int64_t ng = FILL ? sw.mlist_off[slot] : 0, nm = FILL ? sw.m_off[slot] : 0;
+    for (int64_t c0 = pb; c0 < pe; c0 += 64) {
+        const int32_t n = (int32_t)min<int64_t>(64, pe - c0);
+        const bool in = lane < n;
+        PieceRef r{0, 0, 0, 0};
+        if (in) r = sw.rec[c0 + lane];
+        const int32_t end = r.a0 + r.na - 1;
+        // runs: a new bin, or a first tick beyond the bin's spans so far (first ticks ascend within a bin) + the gap
+        const bool fb = lane == 0 || r.bin != __shfl_up(r.bin, 1);
+        const int32_t mb = seg_scan_max(end, fb);
+        const int32_t mprev = __shfl_up(mb, 1);
+        bool st = fb || r.a0 > mprev + 1 + kMergeGap;
+        const int32_t ghi = seg_scan_max(end, st);       // the run's last tick so far
+        const int32_t glo = seg_scan_min(r.a0, st);      // its first tick
+        const bool last = lane >= n - 1 || __shfl_down((int)st, 1) != 0;
+        const bool ok = seg_rscan_and(!last || ghi - glo + 1 <= kPieceMax, last);
+        st = in && (st || !ok);                         // runs over kPieceMax ticks stay single records
+        const uint64_t starts = __ballot(st);
+        const uint64_t after = lane == 63 ? 0ull : starts >> (lane + 1);
+        const int32_t nxt = after ? lane + 1 + __builtin_ctzll(after) : n;
+        const int32_t rhi = __shfl(ghi, max(nxt - 1, 0));
+        const bool multi = st && nxt - lane > 1;
+        const int32_t L = multi ? rhi - r.a0 + 1 : r.na;
+        const int32_t Lp = multi ? (L + kAC - 1) / kAC * kAC : 0;
+        int64_t incl = Lp;                              // inclusive prefix of the merged-charge floats
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t y = __shfl_up(incl, d);
+            if (lane >= d) incl += y;
+        }
+        if (FILL) {
+            const int64_t moff = nm + incl - Lp;
+            if (st) {
+                const int64_t g = ng + __builtin_popcountll(starts & ((1ull << lane) - 1ull));
+                sw.mrec[g] = multi ? PieceRef{r.a0, L, sw.nS8 + (uint32_t)(moff / kAC), r.bin} : r;
+            }
+            uint64_t mm = __ballot(multi);
+            while (mm) {                                // each merged run: its charge, lanes over its ticks
+                const int i = __builtin_ctzll(mm);
+                mm &= mm - 1ull;
+                const int32_t lo = __builtin_amdgcn_readlane(r.a0, i);
+                const int32_t ke = __builtin_amdgcn_readlane(nxt, i);
+                const int32_t lp = __builtin_amdgcn_readlane(Lp, i);
+                const int64_t off = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(moff >> 32), i) << 32) |
+                                              (uint32_t)__builtin_amdgcn_readlane((int)moff, i));
+                for (int32_t t0 = 0; t0 < lp; t0 += 64) {
+                    float v = 0.0f;
+                    for (int32_t k = i; k < ke; ++k) {  // members in list order
+                        const int32_t ma = __builtin_amdgcn_readlane(r.a0, k);
+                        const int32_t mn = __builtin_amdgcn_readlane(r.na, k);
+                        const uint32_t mc = (uint32_t)__builtin_amdgcn_readlane((int)r.cell8, k);
+                        const int32_t o = lo + t0 + lane - ma;
+                        if (o >= 0 && o < mn) v += sw.S[(int64_t)mc * kAC + o];
+                    }
+                    if (t0 + lane < lp) sw.Sm[off + t0 + lane] = v;
+                }
+            }
+        }
+        ng += __builtin_popcountll(starts);
+        nm += __shfl(incl, 63);
+    }
+    if (!FILL && lane == 0) {
+        sw.mlist_off[slot] = ng;
+        sw.m_off[slot] = nm;
+    }
+}
+
+void launch_sum_merge(const SumWork &sw, int64_t n_slots, bool fill, hipStream_t st) {
+    if (n_slots <= 0) return;
+    const unsigned g = (unsigned)((n_slots + kWG / 64 - 1) / (kWG / 64));
+    if (fill) k_sum_merge<true><<<g, kWG, 0, st>>>(n_slots, sw);
+    else k_sum_merge<false><<<g, kWG, 0, st>>>(n_slots, sw);
 }
 
 // Summed induction, one wavefront per work unit (active pixel, tile of kTileTicks ticks): lane t owns ticks
@@ -1939,11 +2115,17 @@ void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw,
 // compensation after every 4 pieces (pieces in list order: deterministic and batch-invariant).  Wavefronts take
 // units from a counter and never synchronise with each other; the first tile of a pixel also accounts the charge
 // that its pieces induce outside the window.
+// A record's summed charge: in the column pieces' buffer, or in the merged records' one.
+__device__ __forceinline__ const float *cell_ptr(const float *S, const float *Sm, uint32_t nS8, uint32_t cell8) {
+    return cell8 < nS8 ? S + (int64_t)cell8 * kAC : Sm + (int64_t)(cell8 - nS8) * kAC;
+}
+
 constexpr int32_t kSumKahanEvery = 4;   // pieces summed in FP32 registers between compensated additions
 
 template <bool SHIFT>
 __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInfo *__restrict__ piece,
-                                                       const float *__restrict__ S, const float *__restrict__ Rpad,
+                                                       const float *__restrict__ S, const float *__restrict__ Sm,
+                                                       uint32_t nS8, const float *__restrict__ Rpad,
                                                        const double *__restrict__ prefix,
                                                        const int64_t *__restrict__ list_off,
                                                        const int32_t *__restrict__ list,
@@ -2014,7 +2196,7 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
                     if (q >= pe) return false;
                     const PieceRef r = rec[q];
                     ncol = colp(r);
-                    ncc = S + (int64_t)r.cell8 * kAC;
+                    ncc = cell_ptr(S, Sm, nS8, r.cell8);
                     nn = (r.na + kAC - 1) / kAC;
                     return true;
                 };
@@ -2024,8 +2206,8 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
                         pending = 0;
                     }
                 };
-                column_stream<false, true>(colp(r0), S + (int64_t)r0.cell8 * kAC, (r0.na + kAC - 1) / kAC, adv, done,
-                                           acc);
+                column_stream<false, true>(colp(r0), cell_ptr(S, Sm, nS8, r0.cell8), (r0.na + kAC - 1) / kAC, adv,
+                                           done, acc);
             }
             if (pending) kahan();
         } else {
@@ -2065,7 +2247,7 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
                 const int32_t wlo = g.a0 - (TR - 1), whi = g.a0 + g.na - 1;
                 if (wlo >= 0 && whi < NT) continue;
                 const double *pf = prefix + (int64_t)g.bin * (TR + 1);
-                const float *cv = S + (int64_t)g.cell8 * kAC;
+                const float *cv = cell_ptr(S, Sm, nS8, g.cell8);
                 for (int32_t a = 0; a < g.na; ++a) {
                     const int32_t aa = g.a0 + a;
                     const int32_t klo = min(max(TR - 1 - aa, 0), TR), khi = min(max(NT + TR - 1 - aa, 0), TR);
@@ -2100,7 +2282,7 @@ const int32_t *launch_summed_order(const Work &w, const SumWork &sw, int64_t n_s
     int32_t *ord = w.order, *bucket = ord + n_slots, *hist = bucket + n_slots, *cursor = hist + kOrderBuckets;
     launch_zero(hist, (int64_t)sizeof(int32_t) * kOrderBuckets, st);
     const unsigned gs = (unsigned)((n_slots + kWG - 1) / kWG);
-    k_slot_work_summed<<<gs, kWG, 0, st>>>(sw.rec, sw.list_off, n_slots, bucket, hist);
+    k_slot_work_summed<<<gs, kWG, 0, st>>>(sw.mrec, sw.mlist_off, n_slots, bucket, hist);
     k_order_offsets<<<1, kWG, 0, st>>>(hist, cursor);
     k_order_scatter<<<gs, kWG, 0, st>>>(bucket, n_slots, cursor, ord);
     return ord;
@@ -2120,12 +2302,14 @@ void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, 
     if (n_slots <= 0) return;
     const int64_t units = n_slots * ((P.nticks + kTileTicks - 1) / kTileTicks);
     const int64_t g = std::min<int64_t>((units + kWG / 64 - 1) / (kWG / 64), 256 * 8);
-    if (shift)
-        k_induce_summed<true><<<(unsigned)g, kWG, 0, st>>>(P, sw.piece, sw.S, T.Rpad, T.prefix, sw.list_off, sw.list,
-                                                           sw.rec, order, w.slot_gp, wave, w.hdr, w.report);
-    else
-        k_induce_summed<false><<<(unsigned)g, kWG, 0, st>>>(P, sw.piece, sw.S, T.Rpad, T.prefix, sw.list_off, sw.list,
-                                                            sw.rec, order, w.slot_gp, wave, w.hdr, w.report);
+    if (shift)                                          // per piece (the list and the unmerged records)
+        k_induce_summed<true><<<(unsigned)g, kWG, 0, st>>>(P, sw.piece, sw.S, sw.Sm, sw.nS8, T.Rpad, T.prefix,
+                                                           sw.list_off, sw.list, sw.rec, order, w.slot_gp, wave,
+                                                           w.hdr, w.report);
+    else                                                // the merged records
+        k_induce_summed<false><<<(unsigned)g, kWG, 0, st>>>(P, sw.piece, sw.S, sw.Sm, sw.nS8, T.Rpad, T.prefix,
+                                                            sw.mlist_off, sw.list, sw.mrec, order, w.slot_gp, wave,
+                                                            w.hdr, w.report);
 }
 
 // ================================================================================================= electronics
@@ -2380,11 +2564,14 @@ void launch_work_stats(const DevParams &P, const SegInfo *si, int64_t n_seg, uns
 // Summed mode: a tick of a piece counts only if it holds charge (the ticks a piece adds for alignment, and the short
 // gaps between segments that a piece spans, hold exact zeros and are not algorithmic work).
 __global__ void k_work_stats_summed(DevParams P, int64_t n_slots, const int64_t *list_off, const PieceRef *rec,
-                                    const float *S, unsigned long long *acc) {
+                                    const float *S, const int64_t *mlist_off, const PieceRef *mrec,
+                                    unsigned long long *acc) {
     int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= n_slots) return;
     unsigned long long f = 0, cells = 0, issued = 0;
     const int32_t n_tiles = (P.nticks + kTileTicks - 1) / kTileTicks;
+    // algorithmic work: every non-zero summed charge tick of every column piece in reach, times the table ticks
+    // that land inside the readout
     for (int64_t q = list_off[slot]; q < list_off[slot + 1]; ++q) {
         const PieceRef g = rec[q];
         const float *sv = S + (int64_t)g.cell8 * kAC;
@@ -2394,24 +2581,29 @@ __global__ void k_work_stats_summed(DevParams P, int64_t n_slots, const int64_t 
             if (hi >= lo) f += (unsigned long long)(hi - lo + 1);
             ++cells;
         }
-        // products the summed kernel computes for this piece, zeros included: every 512-tick tile its window meets,
-        // all 64 lanes x 8 ticks x every 8-tick charge block
+    }
+    // products the summed kernel computes for the merged records, zeros included: every 512-tick tile a record's
+    // window meets, all 64 lanes x 8 ticks x every 8-tick charge block
+    for (int64_t q = mlist_off[slot]; q < mlist_off[slot + 1]; ++q) {
+        const PieceRef g = mrec[q];
         const int32_t t_lo = max(floor_div(g.a0 - P.t_r + 1, kTileTicks), 0);
         const int32_t t_hi = min(floor_div(g.a0 + g.na - 1, kTileTicks), n_tiles - 1);
         if (t_hi >= t_lo)
             issued += (unsigned long long)(t_hi - t_lo + 1) * (unsigned long long)((g.na + kAC - 1) / kAC) *
                       (unsigned long long)(kTileTicks * kAC);
     }
-    atomicAdd(&acc[0], (unsigned long long)(list_off[slot + 1] - list_off[slot]));
+    atomicAdd(&acc[0], (unsigned long long)(mlist_off[slot + 1] - mlist_off[slot]));
     atomicAdd(&acc[1], f);
     atomicAdd(&acc[2], cells);
     atomicAdd(&acc[3], issued);
 }
 
 void launch_work_stats_summed(const DevParams &P, int64_t n_slots, const int64_t *list_off, const PieceRef *rec,
-                              const float *S, unsigned long long *acc, hipStream_t st) {
+                              const float *S, const int64_t *mlist_off, const PieceRef *mrec, unsigned long long *acc,
+                              hipStream_t st) {
     if (n_slots > 0)
-        k_work_stats_summed<<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, list_off, rec, S, acc);
+        k_work_stats_summed<<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, list_off, rec, S,
+                                                                                  mlist_off, mrec, acc);
 }
 
 // ================================================================================================= Philox test hook

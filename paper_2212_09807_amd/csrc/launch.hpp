@@ -51,8 +51,9 @@ struct Table {
 // Device buffers of the summed (sum-then-convolve) induction: per event an absolute grid of sub-pixel columns
 // u in [UL, UL + CU) x v in [VL, VL + CV), UL = nsub/2 - bx (the columns some in-grid pixel can reach).
 // One column piece as seen from one active pixel: what the summed induction loop needs, in one 16-byte record
-// (no dependent loads): the piece's first tick and length, its summed charge at S + 8 * cell8, and the folded
-// table column that the pixel sees it through.
+// (no dependent loads): the piece's first tick and length, its summed charge at S + 8 * cell8 (at
+// Sm + 8 * (cell8 - nS8) for a merged record, cell8 >= nS8), and the folded table column that the pixel sees it
+// through.
 struct alignas(16) PieceRef {
     int32_t a0, na;
     uint32_t cell8;
@@ -74,8 +75,13 @@ struct SumWork {
     PieceRef *pdesc = nullptr;               // [n_pieces] the same pieces as compact records (bin not set)
     float *S = nullptr;                      // [n_s] summed charge per column piece (padded to kAC)
     int64_t *list_off = nullptr;             // [n_slots + 1] pieces in reach per active pixel, then offsets
-    int32_t *list = nullptr;                 // [n_list] piece ids per active pixel, in column order
+    int32_t *list = nullptr;                 // [n_list] piece ids per active pixel, by folded column, then first tick
     PieceRef *rec = nullptr;                 // [n_list] the same pieces as records
+    int64_t *mlist_off = nullptr;            // [n_slots + 1] records per active pixel after the mirror merge, offsets
+    int64_t *m_off = nullptr;                // [n_slots + 1] merged charge floats per active pixel, then offsets
+    PieceRef *mrec = nullptr;                // [n_mlist] the merged records
+    float *Sm = nullptr;                     // [n_m] charges of the merged records (padded to kAC)
+    uint32_t nS8 = 0;                        // S floats / kAC: cell8 at or above it points into Sm
 };
 constexpr int32_t kPieceTicks = kPieceMax;   // ticks per column piece (a multiple of kAC, <= kNaMax)
 static_assert(kPieceTicks % kAC == 0 && kPieceTicks <= kNaMax, "piece length");
@@ -86,6 +92,7 @@ void launch_sum_pieces(const DevParams &P, const Work &w, const SumWork &sw, hip
 void launch_sum_lists_count(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, hipStream_t st);
 void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw, int64_t n_slots, int64_t n_list,
                            hipStream_t st);                                                    // + records
+void launch_sum_merge(const SumWork &sw, int64_t n_slots, bool fill, hipStream_t st);          // mirror merge
 // largest-first pixel order of the summed induction (null when the chosen kernel takes pixels in slot order)
 const int32_t *launch_summed_order(const Work &w, const SumWork &sw, int64_t n_slots, int32_t rt, bool shift,
                                    hipStream_t st);
@@ -127,7 +134,8 @@ void launch_stage_quench_drift(const DevParams &P, const SegArrays &S, int64_t n
                                hipStream_t st);
 void launch_work_stats(const DevParams &P, const SegInfo *si, int64_t n_seg, unsigned long long *acc, hipStream_t st);
 void launch_work_stats_summed(const DevParams &P, int64_t n_slots, const int64_t *list_off, const PieceRef *rec,
-                              const float *S, unsigned long long *acc, hipStream_t st);
+                              const float *S, const int64_t *mlist_off, const PieceRef *mrec, unsigned long long *acc,
+                              hipStream_t st);
 void launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n, hipStream_t st);
 
 }  // namespace ltsim

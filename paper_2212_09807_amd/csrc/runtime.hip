@@ -58,6 +58,7 @@ struct lts_context {
     DevBuf mask;                     // disabled-channel mask (npx bytes) when set
     bool has_mask = false;
     DevBuf col_seg_off, col_cursor, col_seg, col_tmp, piece_off, s_off, piece, pdesc, S, list_off, list, rec;
+    DevBuf mlist_off, m_off, mrec, Sm;          // the mirror-merged records of the summed induction
     DevParams P{};
     bool has_table = false;
     DevBuf Rpad, prefix;
@@ -234,11 +235,12 @@ T *as(DevBuf &b) { return (T *)b.p; }
 constexpr lts_status kNotAdmitted = LTS_ERR_NOT_READY;
 
 std::vector<DevBuf *> pool_buffers(lts_context *c) {
-    return {&c->ev_cnt, &c->mask, &c->col_seg_off, &c->col_cursor, &c->col_seg, &c->col_tmp, &c->piece_off, &c->s_off, &c->piece,
-            &c->pdesc, &c->S, &c->list_off, &c->list, &c->rec, &c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off,
-            &c->pix_cnt, &c->cursor, &c->pix_slot, &c->slot_gp, &c->slot_off, &c->pairs_u, &c->pairs, &c->cells,
-            &c->pk_tick, &c->pk_adc, &c->pk_flag, &c->pk_off, &c->hdr, &c->scan_tmp, &c->ev_off, &c->ev_ids,
-            &c->report_tmp, &c->counts_tmp, &c->red_head, &c->red_start, &c->order};
+    return {&c->ev_cnt, &c->mask, &c->col_seg_off, &c->col_cursor, &c->col_seg, &c->col_tmp, &c->piece_off,
+            &c->s_off, &c->piece, &c->pdesc, &c->S, &c->list_off, &c->list, &c->rec, &c->mlist_off, &c->m_off,
+            &c->mrec, &c->Sm, &c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off, &c->pix_cnt, &c->cursor,
+            &c->pix_slot, &c->slot_gp, &c->slot_off, &c->pairs_u, &c->pairs, &c->cells, &c->pk_tick, &c->pk_adc,
+            &c->pk_flag, &c->pk_off, &c->hdr, &c->scan_tmp, &c->ev_off, &c->ev_ids, &c->report_tmp, &c->counts_tmp,
+            &c->red_head, &c->red_start, &c->order};
 }
 
 // One buffer and the bytes a call needs in it.
@@ -452,6 +454,8 @@ void summed_needs(lts_context *c, const DevHeader &h, int64_t n_slots, int32_t n
     needs.push_back({&c->piece_off, sizeof(int64_t) * (size_t)nc1});
     needs.push_back({&c->s_off, sizeof(int64_t) * (size_t)nc1});
     needs.push_back({&c->list_off, sizeof(int64_t) * (size_t)(n_slots + 1)});
+    needs.push_back({&c->mlist_off, sizeof(int64_t) * (size_t)(n_slots + 1)});
+    needs.push_back({&c->m_off, sizeof(int64_t) * (size_t)(n_slots + 1)});
     needs.push_back({&c->scan_tmp, sizeof(int64_t) * (size_t)scan_tmp_needed(std::max(nc1, n_slots + 1))});
 }
 
@@ -472,12 +476,16 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     sw.piece_off = as<int64_t>(c->piece_off);
     sw.s_off = as<int64_t>(c->s_off);
     sw.list_off = as<int64_t>(c->list_off);
+    sw.mlist_off = as<int64_t>(c->mlist_off);
+    sw.m_off = as<int64_t>(c->m_off);
     void *tmp = c->scan_tmp.p;
     HIP_TRY(c, hipMemsetAsync(sw.col_seg_off, 0, sizeof(int64_t) * (size_t)nc1, st));
     HIP_TRY(c, hipMemsetAsync(sw.col_cursor, 0, sizeof(int32_t) * (size_t)sw.n_cols, st));
     HIP_TRY(c, hipMemsetAsync(sw.piece_off + sw.n_cols, 0, sizeof(int64_t), st));
     HIP_TRY(c, hipMemsetAsync(sw.s_off + sw.n_cols, 0, sizeof(int64_t), st));
     HIP_TRY(c, hipMemsetAsync(sw.list_off + n_slots, 0, sizeof(int64_t), st));
+    HIP_TRY(c, hipMemsetAsync(sw.mlist_off + n_slots, 0, sizeof(int64_t), st));
+    HIP_TRY(c, hipMemsetAsync(sw.m_off + n_slots, 0, sizeof(int64_t), st));
     launch_sum_ranges(P, w, sw, st);
     scan_exclusive_i64(sw.col_seg_off, nc1, nullptr, tmp, st);
     launch_sum_fill(P, w, sw, st);
@@ -509,6 +517,23 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     sw.list = as<int32_t>(c->list);
     sw.rec = as<PieceRef>(c->rec);
     launch_sum_lists_fill(P, w, sw, n_slots, tot[0], st);
+    // mirror merge: sizes of the merged records and charges, then the records
+    sw.nS8 = (uint32_t)(tot[2] / kAC);
+    launch_sum_merge(sw, n_slots, false, st);
+    scan_exclusive_i64(sw.mlist_off, n_slots + 1, nullptr, tmp, st);
+    scan_exclusive_i64(sw.m_off, n_slots + 1, nullptr, tmp, st);
+    int64_t mt[2] = {0, 0};
+    HIP_TRY(c, hipMemcpyAsync(&mt[0], sw.mlist_off + n_slots, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(&mt[1], sw.m_off + n_slots, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (tot[2] / kAC + mt[1] / kAC >= (int64_t)UINT32_MAX)
+        return fail(c, LTS_ERR_CAPACITY, "summed induction: too many summed charge values for one call");
+    if ((r = grow(c, h, {{&c->mrec, sizeof(PieceRef) * (size_t)std::max<int64_t>(mt[0], 1)},
+                         {&c->Sm, sizeof(float) * (size_t)(mt[1] + kCellSlack)}})))
+        return r;
+    sw.mrec = as<PieceRef>(c->mrec);
+    sw.Sm = as<float>(c->Sm);
+    launch_sum_merge(sw, n_slots, true, st);
     Table T{as<float>(c->Rpad), as<double>(c->prefix)};
     const int32_t *order = launch_summed_order(w, sw, n_slots, c->ticks_per_thread, c->lane_exchange != 0, st);
     StageTimer tk(c, st, LTS_STAGE_INDUCE_KERNEL);
@@ -1268,7 +1293,8 @@ lts_status lts_work_stats(lts_context *c, double out[6]) {
     HIP_TRY(c, hipMemset(c->counts_tmp.p, 0, 4 * sizeof(unsigned long long)));
     if (c->last_mode == LTS_REDUCE_SUMMED) {
         launch_work_stats_summed(c->P, c->last_n_slots, as<int64_t>(c->list_off), as<PieceRef>(c->rec),
-                                 as<float>(c->S), as<unsigned long long>(c->counts_tmp), nullptr);
+                                 as<float>(c->S), as<int64_t>(c->mlist_off), as<PieceRef>(c->mrec),
+                                 as<unsigned long long>(c->counts_tmp), nullptr);
         HIP_TRY(c, hipGetLastError());
         unsigned long long hs[4];
         HIP_TRY(c, hipMemcpy(hs, c->counts_tmp.p, sizeof(hs), hipMemcpyDeviceToHost));
