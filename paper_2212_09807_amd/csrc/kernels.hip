@@ -1690,7 +1690,7 @@ __device__ __forceinline__ uint64_t lane_u64(uint64_t v, int j) {
 
 // per column: sort its segment list by key (first tick, segment index) into col_seg, then count the pieces and the
 // padded summed-charge length of its merged tick intervals.  Every interval's first tick is moved down to the residue
-// (T_R - 1 + kPad) mod 8, which makes every lane's table offset in the summed induction a multiple of 8.  The order
+// chosen by the summed induction kernel (it makes every lane's table offsets aligned there).  The order
 // depends only on the segments' charge boxes and their order within the event, so the sums are the same in a batch
 // and alone.  One wavefront per 64 consecutive columns; the wavefront sorts its columns' lists one after another by
 // ranks (a key's place is the number of smaller keys; keys are unique): lane i holds key i of a 64-key chunk and
@@ -1740,8 +1740,7 @@ __global__ __launch_bounds__(kWG) void k_sum_columns(int32_t align_res, const Se
 
 void launch_sum_fill(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st) {
     if (w.n_seg > 0) k_sum_fill<<<(unsigned)((w.n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.n_seg, sw);
-    k_sum_columns<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(((P.t_r - 1 + kPad) % 8 + 8) % 8, w.si,
-                                                                            sw);
+    k_sum_columns<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(sw.align_res, w.si, sw);
 }
 
 // Wave-uniform copies of a 64-bit value held by lane l.
@@ -1759,7 +1758,7 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v, int l) {
 // from registers and only the (coalesced) cell loads go to memory; longer lists read each record in the loop.
 __global__ __launch_bounds__(kWG) void k_sum_pieces(DevParams P, const SegInfo *si, const float *cells, SumWork sw) {
     const int lane = threadIdx.x & 63;
-    const int32_t res = ((P.t_r - 1 + kPad) % 8 + 8) % 8;
+    const int32_t res = sw.align_res;
     const uint32_t n_act = *sw.n_active;
     const uint32_t waves = gridDim.x * (kWG / 64);
     for (uint32_t ia = blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); ia < n_act;
@@ -2009,22 +2008,6 @@ __device__ __forceinline__ int32_t seg_scan_min(int32_t v, bool start) {
     }
     return v;
 }
-// AND of v from this lane to the end of its segment (a segment ends at a lane whose flag is set).
-__device__ __forceinline__ bool seg_rscan_and(bool v, bool end) {
-    const int lane = lane_id();
-    int f = end, x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_down(x, d);
-        const int g = __shfl_down(f, d);
-        if (lane + d < 64 && !f) {
-            x &= y;
-            f |= g;
-        }
-    }
-    return x != 0;
-}
-
 template <bool FILL>
 __global__ __launch_bounds__(kWG) void k_sum_merge(int64_t n_slots, SumWork sw) {
     const int lane = threadIdx.x & 63;
@@ -2045,8 +2028,11 @@ __global__ __launch_bounds__(kWG) void k_sum_merge(int64_t n_slots, SumWork sw) 
         bool st = fb || r.a0 > mprev + 1 + kMergeGap;
         const int32_t ghi = seg_scan_max(end, st);       // the run's last tick so far
         const int32_t glo = seg_scan_min(r.a0, st);      // its first tick
-        const bool last = lane >= n - 1 || __shfl_down((int)st, 1) != 0;
-        const bool ok = seg_rscan_and(!last || ghi - glo + 1 <= kPieceMax, last);
+        // each record's natural run ends before the next run start; the verdict on the run's span is read there
+        const uint64_t nat = __ballot(in && st);
+        const uint64_t nat_after = lane == 63 ? 0ull : nat >> (lane + 1);
+        const int32_t run_end = nat_after ? lane + __builtin_ctzll(nat_after) : n - 1;
+        const bool ok = __shfl((int)(ghi - glo + 1 <= kPieceMax), max(min(run_end, 63), 0)) != 0;
         st = in && (st || !ok);                         // runs over kPieceMax ticks stay single records
         const uint64_t starts = __ballot(st);
         const uint64_t after = lane == 63 ? 0ull : starts >> (lane + 1);
@@ -2262,6 +2248,163 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
     }
 }
 
+// Summed induction in 256-tick work units (active pixel, tile of kTile4 ticks), one wavefront each: lane t owns
+// ticks t0 + 4t .. +3.  The pixel's records are scanned 64 at a time (a ballot of those whose tick window
+// [a0 - T_R + 1, a0 + na - 1] meets the tile); for each, the wavefront stages the table values the tile needs
+// (index t0 - a0 - nap + 1 .. t0 - a0 + 255 of the column, relative to its lag-0 entry) in its LDS slice with aligned
+// 16-byte copies, then streams the record's 8-tick charge blocks (uniform loads) against a 12-value window that moves
+// down 8 values per block (two aligned LDS reads per block).  Lanes whose ticks lie outside the record's window meet
+// the table's zero padding.  Products go to the lane's running sums with Kahan compensation after every 4 records
+// (records in list order: deterministic and batch-invariant).  The first tile of a pixel also accounts the charge
+// its records induce outside the readout.  Charge intervals start at the residue (T_R + kPad) mod 8, so the staged
+// copies start 32-byte aligned.
+constexpr int32_t kTile4 = 256;                         // ticks of one work unit: 64 lanes x 4
+constexpr int32_t kStage4 = kTile4 + kPieceMax + 8;     // staged table values per record and unit (at most)
+
+// Block of 4 ticks x 8 charge ticks: tick r of the lane against charge tick q uses window value r - q + 7.
+__device__ __forceinline__ void block4(const float (&w)[12], const float (&c)[kAC], float (&acc)[4]) {
+#pragma unroll
+    for (int q = 0; q < kAC; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = fmaf(c[q], w[r - q + 7], acc[r]);
+}
+__device__ __forceinline__ void window4(const float *p, float (&w)[12]) {
+    const float4 x = *(const float4 *)p, y = *(const float4 *)(p + 4), z = *(const float4 *)(p + 8);
+    w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w; w[4] = y.x; w[5] = y.y; w[6] = y.z; w[7] = y.w;
+    w[8] = z.x; w[9] = z.y; w[10] = z.z; w[11] = z.w;
+}
+
+__global__ __launch_bounds__(kWG) void k_induce_summed4(DevParams P, const float *__restrict__ S,
+                                                        const float *__restrict__ Sm, uint32_t nS8,
+                                                        const float *__restrict__ Rpad,
+                                                        const double *__restrict__ prefix,
+                                                        const int64_t *__restrict__ list_off,
+                                                        const PieceRef *__restrict__ rec,
+                                                        const int32_t *__restrict__ order,
+                                                        const int32_t *__restrict__ slot_gp, float *__restrict__ wave,
+                                                        DevHeader *H, double *report) {
+    __shared__ __align__(16) float stage_all[kWG / 64][kStage4];
+    const int lane = threadIdx.x & 63;
+    float *stage = stage_all[threadIdx.x >> 6];
+    const int32_t NT = P.nticks, TR = P.t_r;
+    const int32_t n_tiles = (NT + kTile4 - 1) / kTile4;
+    const int64_t n_units = H->n_slots * n_tiles;
+    for (;;) {
+        uint32_t got = 0;
+        if (lane == 0) got = atomicAdd(&H->work[2], 1u);
+        const int64_t unit = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
+        if (unit >= n_units) break;
+        const int64_t ui = unit / n_tiles;
+        const int64_t slot = order ? order[ui] : ui;                    // largest-first when an order is given
+        const int32_t t0 = (int32_t)(unit - ui * n_tiles) * kTile4, t1 = t0 + kTile4 - 1;
+        const int32_t gp = slot_gp[slot];
+        const int32_t e = gp / P.npx;
+        const int64_t pb = list_off[slot], pe = list_off[slot + 1];
+        float acc[4], sum[4], cmp[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) { acc[r] = 0.0f; sum[r] = 0.0f; cmp[r] = 0.0f; }
+        int32_t pending = 0;
+        for (int64_t c0 = pb; c0 < pe; c0 += 64) {
+            PieceRef rl{0, 0, 0, 0};
+            const bool in = c0 + lane < pe;
+            if (in) rl = rec[c0 + lane];
+            uint64_t mask = __ballot(in && rl.a0 + rl.na - 1 >= t0 && rl.a0 - (TR - 1) <= t1);
+            if (!mask) continue;
+            // record i of the chunk: its fields, and the lane's two staged float4s of it, loaded ahead
+            int32_t a0 = 0, nblk = 0, n4 = 0;
+            uint32_t c8 = 0;
+            float4 g0 = {0, 0, 0, 0}, g1 = {0, 0, 0, 0};
+            auto fetch = [&](int i) {
+                a0 = __builtin_amdgcn_readlane(rl.a0, i);
+                const int32_t na = __builtin_amdgcn_readlane(rl.na, i);
+                const int32_t bin = __builtin_amdgcn_readlane(rl.bin, i);
+                c8 = (uint32_t)__builtin_amdgcn_readlane((int)rl.cell8, i);
+                nblk = (na + kAC - 1) / kAC;
+                n4 = (kTile4 + nblk * kAC) / 4;
+                const float *src = Rpad + (int64_t)bin * P.col_len + (t0 - a0 - nblk * kAC + TR + kPad);
+                g0 = *(const float4 *)(src + 4 * lane);
+                if (lane + 64 < n4) g1 = *(const float4 *)(src + 4 * (lane + 64));
+            };
+            while (mask) {
+                const int i = __builtin_ctzll(mask);
+                mask &= mask - 1ull;
+                fetch(i);
+                // the previous record's window reads are done before the slice is overwritten
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                *(float4 *)(stage + 4 * lane) = g0;
+                if (lane + 64 < n4) *(float4 *)(stage + 4 * (lane + 64)) = g1;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int32_t nb_cur = nblk;
+                cfloat_ptr cc = uniform_cptr(cell_ptr(S, Sm, nS8, c8));
+                // 8-tick charge blocks against the 12-value window that moves down 8 per block (the latency of the
+                // window and charge loads is covered by the other wavefronts of the SIMD)
+                int32_t wb = 4 * lane + nb_cur * kAC - 8;
+                for (int32_t j = 0; j < nb_cur; ++j, wb -= 8) {
+                    float W[12], cv[kAC];
+                    window4(stage + wb, W);
+#pragma unroll
+                    for (int q = 0; q < kAC; ++q) cv[q] = cc[kAC * j + q];
+                    block4(W, cv, acc);
+                }
+                if (++pending == kSumKahanEvery) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float y = acc[r] - cmp[r];
+                        const float t = sum[r] + y;
+                        cmp[r] = (t - sum[r]) - y;
+                        sum[r] = t;
+                        acc[r] = 0.0f;
+                    }
+                    pending = 0;
+                }
+            }
+        }
+        if (pending) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float y = acc[r] - cmp[r];
+                const float t = sum[r] + y;
+                cmp[r] = (t - sum[r]) - y;
+                sum[r] = t;
+            }
+        }
+        float *wrow = wave + slot * NT;
+        const int32_t nb = t0 + 4 * lane;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (nb + r < NT) wrow[nb + r] = sum[r] - cmp[r];
+        if (t0 == 0) {                                  // charge induced outside [0, NT) by the pixel's records
+            double clip = 0.0;
+            for (int64_t k = pb + lane; k < pe; k += 64) {
+                const PieceRef g = rec[k];
+                const int32_t wlo = g.a0 - (TR - 1), whi = g.a0 + g.na - 1;
+                if (wlo >= 0 && whi < NT) continue;
+                const double *pf = prefix + (int64_t)g.bin * (TR + 1);
+                const float *cv = cell_ptr(S, Sm, nS8, g.cell8);
+                for (int32_t a = 0; a < g.na; ++a) {
+                    const int32_t aa = g.a0 + a;
+                    const int32_t klo = min(max(TR - 1 - aa, 0), TR), khi = min(max(NT + TR - 1 - aa, 0), TR);
+                    const double dropped = klo >= khi ? pf[TR] : pf[klo] + (pf[TR] - pf[khi]);
+                    clip += (double)cv[a] * dropped;
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) clip += __shfl_xor(clip, o);
+            if (lane == 0 && clip != 0.0) atomicAdd(&report[(int64_t)e * 5 + 3], clip);
+        }
+    }
+}
+
+bool summed_tile256(int32_t rt, bool shift) { return rt == 0 && !shift; }
+int32_t summed_align_res(const DevParams &P, int32_t rt, bool shift) {
+    const int32_t c = summed_tile256(rt, shift) ? P.t_r + kPad : P.t_r - 1 + kPad;
+    return (c % 8 + 8) % 8;
+}
+
 // Largest-first order of the pixels for the summed induction (the same log-bucketed order as the per-pair kernel's;
 // all tiles of a pixel stay together): work of a pixel = the cell-tick blocks of its pieces.
 __global__ void k_slot_work_summed(const PieceRef *__restrict__ rec, const int64_t *__restrict__ list_off,
@@ -2300,6 +2443,13 @@ void launch_induce_summed(const DevParams &P, const Work &w, const SumWork &sw, 
         return;
     }
     if (n_slots <= 0) return;
+    if (summed_tile256(rt, shift)) {
+        const int64_t units = n_slots * ((P.nticks + kTile4 - 1) / kTile4);
+        const int64_t g = std::min<int64_t>((units + kWG / 64 - 1) / (kWG / 64), 256 * 8);
+        k_induce_summed4<<<(unsigned)g, kWG, 0, st>>>(P, sw.S, sw.Sm, sw.nS8, T.Rpad, T.prefix, sw.mlist_off, sw.mrec,
+                                                      order, w.slot_gp, wave, w.hdr, w.report);
+        return;
+    }
     const int64_t units = n_slots * ((P.nticks + kTileTicks - 1) / kTileTicks);
     const int64_t g = std::min<int64_t>((units + kWG / 64 - 1) / (kWG / 64), 256 * 8);
     if (shift)                                          // per piece (the list and the unmerged records)
@@ -2564,12 +2714,12 @@ void launch_work_stats(const DevParams &P, const SegInfo *si, int64_t n_seg, uns
 // Summed mode: a tick of a piece counts only if it holds charge (the ticks a piece adds for alignment, and the short
 // gaps between segments that a piece spans, hold exact zeros and are not algorithmic work).
 __global__ void k_work_stats_summed(DevParams P, int64_t n_slots, const int64_t *list_off, const PieceRef *rec,
-                                    const float *S, const int64_t *mlist_off, const PieceRef *mrec,
+                                    const float *S, const int64_t *mlist_off, const PieceRef *mrec, int32_t tile,
                                     unsigned long long *acc) {
     int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= n_slots) return;
     unsigned long long f = 0, cells = 0, issued = 0;
-    const int32_t n_tiles = (P.nticks + kTileTicks - 1) / kTileTicks;
+    const int32_t n_tiles = (P.nticks + tile - 1) / tile;
     // algorithmic work: every non-zero summed charge tick of every column piece in reach, times the table ticks
     // that land inside the readout
     for (int64_t q = list_off[slot]; q < list_off[slot + 1]; ++q) {
@@ -2582,15 +2732,15 @@ __global__ void k_work_stats_summed(DevParams P, int64_t n_slots, const int64_t 
             ++cells;
         }
     }
-    // products the summed kernel computes for the merged records, zeros included: every 512-tick tile a record's
-    // window meets, all 64 lanes x 8 ticks x every 8-tick charge block
+    // products the summed kernel computes for the merged records, zeros included: every tile (of `tile` ticks) a
+    // record's window meets, all its ticks x every 8-tick charge block
     for (int64_t q = mlist_off[slot]; q < mlist_off[slot + 1]; ++q) {
         const PieceRef g = mrec[q];
-        const int32_t t_lo = max(floor_div(g.a0 - P.t_r + 1, kTileTicks), 0);
-        const int32_t t_hi = min(floor_div(g.a0 + g.na - 1, kTileTicks), n_tiles - 1);
+        const int32_t t_lo = max(floor_div(g.a0 - P.t_r + 1, tile), 0);
+        const int32_t t_hi = min(floor_div(g.a0 + g.na - 1, tile), n_tiles - 1);
         if (t_hi >= t_lo)
             issued += (unsigned long long)(t_hi - t_lo + 1) * (unsigned long long)((g.na + kAC - 1) / kAC) *
-                      (unsigned long long)(kTileTicks * kAC);
+                      (unsigned long long)(tile * kAC);
     }
     atomicAdd(&acc[0], (unsigned long long)(mlist_off[slot + 1] - mlist_off[slot]));
     atomicAdd(&acc[1], f);
@@ -2599,11 +2749,11 @@ __global__ void k_work_stats_summed(DevParams P, int64_t n_slots, const int64_t 
 }
 
 void launch_work_stats_summed(const DevParams &P, int64_t n_slots, const int64_t *list_off, const PieceRef *rec,
-                              const float *S, const int64_t *mlist_off, const PieceRef *mrec, unsigned long long *acc,
-                              hipStream_t st) {
+                              const float *S, const int64_t *mlist_off, const PieceRef *mrec, bool tile256,
+                              unsigned long long *acc, hipStream_t st) {
     if (n_slots > 0)
-        k_work_stats_summed<<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(P, n_slots, list_off, rec, S,
-                                                                                  mlist_off, mrec, acc);
+        k_work_stats_summed<<<(unsigned)((n_slots + kWG - 1) / kWG), kWG, 0, st>>>(
+            P, n_slots, list_off, rec, S, mlist_off, mrec, tile256 ? kTile4 : kTileTicks, acc);
 }
 
 // ================================================================================================= Philox test hook

@@ -82,7 +82,12 @@ struct SumWork {
     PieceRef *mrec = nullptr;                // [n_mlist] the merged records
     float *Sm = nullptr;                     // [n_m] charges of the merged records (padded to kAC)
     uint32_t nS8 = 0;                        // S floats / kAC: cell8 at or above it points into Sm
+    int32_t align_res = 0;                   // first tick of every column interval, mod 8 (set by the kernel choice)
 };
+// The summed induction kernel a tuning choice runs: the 256-tick LDS-staged one (automatic), the 512-tick register
+// one (8 ticks per thread), or the per-pair kernels over the pieces; and the interval alignment each one wants.
+bool summed_tile256(int32_t rt, bool shift);
+int32_t summed_align_res(const DevParams &P, int32_t rt, bool shift);
 constexpr int32_t kPieceTicks = kPieceMax;   // ticks per column piece (a multiple of kAC, <= kNaMax)
 static_assert(kPieceTicks % kAC == 0 && kPieceTicks <= kNaMax, "piece length");
 
@@ -134,8 +139,8 @@ void launch_stage_quench_drift(const DevParams &P, const SegArrays &S, int64_t n
                                hipStream_t st);
 void launch_work_stats(const DevParams &P, const SegInfo *si, int64_t n_seg, unsigned long long *acc, hipStream_t st);
 void launch_work_stats_summed(const DevParams &P, int64_t n_slots, const int64_t *list_off, const PieceRef *rec,
-                              const float *S, const int64_t *mlist_off, const PieceRef *mrec, unsigned long long *acc,
-                              hipStream_t st);
+                              const float *S, const int64_t *mlist_off, const PieceRef *mrec, bool tile256,
+                              unsigned long long *acc, hipStream_t st);
 void launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out, int64_t n, hipStream_t st);
 
 }  // namespace ltsim

@@ -71,6 +71,8 @@ struct lts_context {
     int64_t last_n_seg = -1;
     int64_t last_n_slots = 0;
     int32_t last_mode = -1;
+    int32_t last_rt = 0;                        // the last summed call's kernel choice (ticks per thread, exchange)
+    bool last_shift = false;
     // optional stage timing: HIP events recorded on the caller's stream around each stage group
     bool timing = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending_ev;
@@ -478,6 +480,7 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     sw.list_off = as<int64_t>(c->list_off);
     sw.mlist_off = as<int64_t>(c->mlist_off);
     sw.m_off = as<int64_t>(c->m_off);
+    sw.align_res = summed_align_res(P, c->ticks_per_thread, c->lane_exchange != 0);
     void *tmp = c->scan_tmp.p;
     HIP_TRY(c, hipMemsetAsync(sw.col_seg_off, 0, sizeof(int64_t) * (size_t)nc1, st));
     HIP_TRY(c, hipMemsetAsync(sw.col_cursor, 0, sizeof(int32_t) * (size_t)sw.n_cols, st));
@@ -634,6 +637,8 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
     const int64_t n_slots = h.n_slots, n_pairs = h.n_pairs, n_cells = h.n_cells;
     c->last_n_slots = n_slots;
     c->last_mode = c->reduce_mode;
+    c->last_rt = c->ticks_per_thread;
+    c->last_shift = c->lane_exchange != 0;
     const int64_t mp = c->P.max_packets;
     const bool summed = c->reduce_mode == LTS_REDUCE_SUMMED;
     const int64_t pair_cap = summed ? 1 : std::max<int64_t>(n_pairs, 1);   // the summed induction has no pair lists
@@ -1294,7 +1299,8 @@ lts_status lts_work_stats(lts_context *c, double out[6]) {
     if (c->last_mode == LTS_REDUCE_SUMMED) {
         launch_work_stats_summed(c->P, c->last_n_slots, as<int64_t>(c->list_off), as<PieceRef>(c->rec),
                                  as<float>(c->S), as<int64_t>(c->mlist_off), as<PieceRef>(c->mrec),
-                                 as<unsigned long long>(c->counts_tmp), nullptr);
+                                 summed_tile256(c->last_rt, c->last_shift), as<unsigned long long>(c->counts_tmp),
+                                 nullptr);
         HIP_TRY(c, hipGetLastError());
         unsigned long long hs[4];
         HIP_TRY(c, hipMemcpy(hs, c->counts_tmp.p, sizeof(hs), hipMemcpyDeviceToHost));
