@@ -564,37 +564,57 @@ def main():
 
     line, (w5, h5) = headline(ltsim, W, args)
     torch.cuda.empty_cache()
+    errors = {}
+
+    def leg(name, fn, *a, **kw):
+        """A secondary leg: its failure is recorded in the line (and logged), never the end of the run."""
+        try:
+            return fn(*a, **kw)
+        except Exception as exc:                      # noqa: BLE001 -- reported, the headline stands
+            log(f"{name} failed: {type(exc).__name__}: {exc}")
+            errors[name] = f"{type(exc).__name__}: {exc}"
+            return None
+        finally:
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+
     for m in [x for x in args.spill_tiles.split(",") if x]:
-        line.setdefault("spill_tile_calls", {})[m] = spill_tiles_leg(ltsim, W, m)
-        torch.cuda.empty_cache()
+        line.setdefault("spill_tile_calls", {})[m] = leg(f"spill_tiles_{m}", spill_tiles_leg, ltsim, W, m)
     mods = [x for x in args.module.split(",") if x]
     if mods:
-        line["module_event"] = module_leg(ltsim, W, mods, args.module_steps)
-        torch.cuda.empty_cache()
+        line["module_event"] = leg("module_event", module_leg, ltsim, W, mods, args.module_steps)
     table = None
     bmodes = [x for x in args.batched_modes.split(",") if x]
     if args.no_tune:
         bmodes = [m for m in bmodes if m != "tuned"]
     elif "tuned" in bmodes or args.served_rates:
-        table, line["tuning"] = tuning_leg(ltsim, W)
-        torch.cuda.empty_cache()
+        tuned = leg("tuning", tuning_leg, ltsim, W)
+        if tuned is not None:
+            table, line["tuning"] = tuned
+        else:
+            bmodes = [m for m in bmodes if m != "tuned"]
     for m in bmodes:
-        line.setdefault("batched", {})[m] = batched_vs_plain(ltsim, W, args.batched, m, table=table)
+        line.setdefault("batched", {})[m] = leg(f"batched_{m}", batched_vs_plain, ltsim, W, args.batched, m,
+                                                 table=table)
         if m != "tuned":
-            line.setdefault("batched_small", {})[m] = batched_vs_plain(ltsim, W, 64, m, cfg=1)
-        torch.cuda.empty_cache()
+            line.setdefault("batched_small", {})[m] = leg(f"batched_small_{m}", batched_vs_plain, ltsim, W, 64, m,
+                                                          cfg=1)
     rates = [float(r) for r in args.served_rates.split(",") if r]
     if rates:
-        line["served"] = [served(ltsim, W, r, 64, "summed") for r in rates]
+        line["served"] = [leg(f"served_{r}", served, ltsim, W, r, 64, "summed") for r in rates]
         if table is not None:
-            line["served"].append(served(ltsim, W, rates[-1], 64, "tuned", table=table))
-        line["served_small"] = served_burst(ltsim, W, 64, "summed")
+            line["served"].append(leg("served_tuned", served, ltsim, W, rates[-1], 64, "tuned", table=table))
+        line["served_small"] = leg("served_small", served_burst, ltsim, W, 64, "summed")
     if args.served_sorted_rate > 0:
-        line.setdefault("served", []).append(served(ltsim, W, args.served_sorted_rate, 32, "sorted"))
+        line.setdefault("served", []).append(leg("served_sorted", served, ltsim, W, args.served_sorted_rate, 32,
+                                                 "sorted"))
     if not args.no_light:
-        line["light"] = light_leg(ltsim, W)
+        line["light"] = leg("light", light_leg, ltsim, W)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"], line["accuracy"] = cpu_baseline_leg(w5, h5, args.cpu_budget, args.err_pixels)
+        cb = leg("cpu_baseline", cpu_baseline_leg, w5, h5, args.cpu_budget, args.err_pixels)
+        line["cpu_baseline"], line["accuracy"] = cb if cb is not None else (None, None)
+    if errors:
+        line["leg_errors"] = errors
     print(json.dumps(line), flush=True)
 
 

@@ -154,7 +154,9 @@ typedef struct lts_context lts_context;
  *   LTS_REDUCE_SUMMED: sum-then-convolve: eq. (current) is linear in the charge, so each sub-pixel column's charge
  *                      is first summed over all segments (fixed order, Kahan) and each pixel then convolves the summed
  *                      columns in its reach once; the same result without per-pair currents, with fewer
- *                      multiply-adds where clouds of neighbouring segments overlap (deterministic). */
+ *                      multiply-adds where clouds of neighbouring segments overlap (deterministic).  Per pixel, the
+ *                      column pieces seen through the same mirror-folded table column that overlap in time (up to
+ *                      248 ticks together) are summed first and convolved once. */
 enum { LTS_REDUCE_SORTED = 0, LTS_REDUCE_ATOMIC = 1, LTS_REDUCE_SUMMED = 2 };
 
 /* Create a context on HIP device `device` with copies of the parameter sets.  Validates them
@@ -186,7 +188,10 @@ lts_status lts_set_induce_slices(lts_context *ctx, int32_t slices);
 /* Induction tick tile: each of the 256 threads of a workgroup computes `rt` consecutive ticks of a pair's window
  * (1, 2, 4 or 8; 0 = the smallest that covers the table length plus a typical charge extent, and for 8 ticks the
  * loop that loads the next cell-tick block's window while computing the current one; an explicit 8 selects the
- * loop without that prefetch).  All choices give the same sums in the same order. */
+ * loop without that prefetch).  All choices give the same sums in the same order.  In LTS_REDUCE_SUMMED: 0 = one
+ * wavefront per (pixel, 256-tick tile) with the table window staged in LDS (default), 8 = one wavefront per
+ * (pixel, 512-tick tile) with register-resident table windows, 1, 2, 4 = the per-pair workgroup kernel over the
+ * summed pieces; these agree to FP32 summation order. */
 lts_status lts_set_ticks_per_thread(lts_context *ctx, int32_t rt);
 
 /* Per-pair induction with 8-tick tiles: 1 = lanes share each table window by shifting it one lane per cell-tick
@@ -305,9 +310,10 @@ lts_status lts_stage_electronics_noalloc(lts_context *ctx, uint64_t event_id, co
  * window, summed over pairs (the multiply-adds of the induction; in LTS_REDUCE_SUMMED the products of summed
  * column charges, summed over pixels, counting only ticks that hold charge); out[2] charge cells in reach summed over
  * pairs (summed columns' ticks with charge in reach summed over pixels in LTS_REDUCE_SUMMED); out[3] charge cells of all segments; out[4] (LTS_REDUCE_SUMMED
- * only, else 0) the products the summed induction kernel computes, zeros included (every 512-tick tile a piece's
- * window meets, all its lanes, charge ticks rounded up to 8): out[1] / out[4] is the useful fraction of its
- * multiply-adds; out[5] the (pixel, column piece) records in LTS_REDUCE_SUMMED, else the pairs. */
+ * only, else 0) the products the summed induction kernel computes, zeros included (every 256- or 512-tick tile,
+ * as the kernel choice sets, that a merged record's window meets, all its lanes, charge ticks rounded up to 8):
+ * out[1] / out[4] is the useful fraction of its multiply-adds; out[5] the (pixel, merged record) records the
+ * kernel walks in LTS_REDUCE_SUMMED, else the pairs. */
 lts_status lts_work_stats(lts_context *ctx, double out[6]);
 
 /* Test hook for the error paths: after `after` further host-allocation points inside the library have passed
@@ -329,7 +335,9 @@ lts_status lts_stage_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint3
  * Admission by device memory: a lane sizes its tentative batch on the device and runs it only if its footprint
  * (scratch pool, segments and outputs, grown to the batch's exact sizes) stays within mem_budget_bytes / n_lanes and
  * the growth fits the device's free memory (hipMemGetInfo) less 1 GiB; otherwise it halves the batch (the events cut
- * off go back to the queue front, in order), and an event that alone does not fit finishes with LTS_ERR_OOM.
+ * off go back to the queue front, in order).  A single event that does not fit is sized once more after the lane
+ * frees its pooled scratch (buffers that earlier, larger batches grew), and finishes with LTS_ERR_OOM only if it
+ * still does not fit.
  * Results are copied back to host memory owned by the server until lts_server_release.  Thread-safe. */
 typedef struct lts_server lts_server;
 

@@ -8,7 +8,8 @@ call's mean segments per event, in lts_simulate, lts_simulate_batch and every ba
   pixel order), or sum-then-convolve (one wavefront per (active pixel, 512-tick tile) unit over the pixel's column
   pieces);
 * tick tile (ticks per thread: 0 = automatic, 1, 2, 4, 8): the per-pair kernels' output ticks per thread; in the
-  summed mode a tile of 1, 2 or 4 runs the pixel-per-workgroup kernel over the pieces instead of the wavefront one;
+  summed mode 0 runs the 256-tick LDS-staged wavefront kernel, 8 the 512-tick register one, and 1, 2 or 4 the
+  pixel-per-workgroup kernel over the pieces;
 * induce slices (sorted mode: workgroups per pixel, one table slice each) and lane exchange (table windows shared
   across lanes).
 
@@ -46,7 +47,7 @@ class Choice:
 
 S, A, M = ltsim.LTS_REDUCE_SORTED, ltsim.LTS_REDUCE_ATOMIC, ltsim.LTS_REDUCE_SUMMED
 DEFAULT_CANDIDATES = (Choice(S, 1, 0), Choice(S, 1, 4), Choice(S, 8, 0), Choice(A, 1, 0), Choice(M, 1, 0),
-                      Choice(M, 1, 4))
+                      Choice(M, 1, 8), Choice(M, 1, 4))
 DEFAULT_SIZES = (500, 2000, 8000, 32000)
 
 

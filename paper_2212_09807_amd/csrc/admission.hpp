@@ -5,8 +5,9 @@
 // (up to the batch limits) as a tentative batch and sizes it on the device; the sizing gives the exact bytes every
 // buffer of the call needs.  The batch runs if the lane's footprint after growing to those sizes stays within its
 // share and the growth fits in the device's free memory less a reserve; otherwise the batch is halved (the events
-// cut off go back to the queue front, in order) and sized again, and a single event that does not fit fails with
-// LTS_ERR_OOM.  The summed induction learns the size of its piece lists only half-way through a call, so a call may
+// cut off go back to the queue front, in order) and sized again.  A single event that does not fit is sized once
+// more after the lane releases its pooled scratch (buffers earlier, larger batches grew), and fails with
+// LTS_ERR_OOM only if it still does not fit.  The summed induction learns the size of its piece lists only half-way through a call, so a call may
 // be sized (and refused) a second time there.
 #pragma once
 
@@ -29,17 +30,30 @@ inline Admit admit_decision(int32_t k, int64_t total, int64_t growth, int64_t sh
 inline int32_t admit_shrink(int32_t k) { return std::max(1, k / 2); }
 
 // Admission of one tentative batch of k0 queued events: attempt(k) sizes the first k events as one call and returns
-// the decision for it (running the call when it is Run).  Returns the number of events that ran, or 0 if the first
-// event alone was rejected.
-template <class Attempt>
-int32_t admission_loop(int32_t k0, Attempt attempt) {
+// the decision for it (running the call when it is Run).  When a single event is refused, release() frees the lane's
+// pooled scratch and returns whether that happened (then the event is sized once more).  Returns the number of
+// events that ran, or 0 if the first event alone was rejected.
+template <class Attempt, class Release>
+int32_t admission_loop(int32_t k0, Attempt attempt, Release release) {
     int32_t k = std::max(k0, 1);
+    bool released = false;
     for (;;) {
         const Admit a = attempt(k);
         if (a == Admit::Run) return k;
-        if (a == Admit::Reject || k == 1) return 0;
+        if (a == Admit::Reject || k == 1) {
+            if (!released && release()) {
+                released = true;
+                k = 1;
+                continue;
+            }
+            return 0;
+        }
         k = admit_shrink(k);
     }
+}
+template <class Attempt>
+int32_t admission_loop(int32_t k0, Attempt attempt) {
+    return admission_loop(k0, attempt, [] { return false; });
 }
 
 // Puts batch[keep ..] back at the front of the queue, in their order, and cuts the batch to `keep` events.

@@ -245,6 +245,14 @@ std::vector<DevBuf *> pool_buffers(lts_context *c) {
             &c->red_head, &c->red_start, &c->order};
 }
 
+// Frees the context's per-call scratch (everything in the pool but the response table and the channel mask, which
+// persist across calls); every buffer is grown again to the exact size the next call needs.  The caller makes sure
+// no queued work still uses them.
+void release_scratch(lts_context *c) {
+    for (DevBuf *b : pool_buffers(c))
+        if (b != &c->Rpad && b != &c->prefix && b != &c->mask) free_buf(*b);
+}
+
 // One buffer and the bytes a call needs in it.
 struct Need {
     DevBuf *b;
@@ -1466,47 +1474,61 @@ void lane_run_batch(Lane *L, std::vector<Request *> &batch) {
     set_outputs(0);
     int32_t ran = 0;
     if (st == LTS_OK) {
-        ran = admission_loop(ne, [&](int32_t k) -> Admit {
-            lts_segments segs{d, d + nseg, d + 2 * nseg, d + 3 * nseg, d + 4 * nseg, d + 5 * nseg, d + 6 * nseg,
-                              d + 7 * nseg, d + 8 * nseg, d + 9 * nseg, offs[k]};
-            Admit decision = Admit::Run;
-            c->admit = [&](const DevHeader &h, int64_t total, int64_t growth) -> lts_status {
-                const int64_t px = std::max<int64_t>(h.n_slots, 1), pk = std::max<int64_t>(h.n_slots * mp, 1);
-                const size_t want[] = {sizeof(int32_t) * (size_t)px, sizeof(float) * (size_t)px * S->n_ticks,
-                                       sizeof(int32_t) * (size_t)pk, sizeof(int32_t) * (size_t)pk,
-                                       sizeof(uint16_t) * (size_t)pk, sizeof(uint8_t) * (size_t)pk,
-                                       sizeof(int64_t) * 4, sizeof(double) * 5 * (size_t)k,
-                                       sizeof(int64_t) * (size_t)(k + 1), sizeof(int64_t) * (size_t)(k + 1)};
-                int64_t out_total = (int64_t)L->seg.bytes, out_growth = 0;
-                for (int i = 0; i < 10; ++i) {
-                    out_total += (int64_t)std::max(outs[i]->bytes, want[i]);
-                    if (want[i] > outs[i]->bytes) out_growth += (int64_t)(want[i] - outs[i]->bytes);
+        ran = admission_loop(
+            ne,
+            [&](int32_t k) -> Admit {
+                lts_segments segs{d, d + nseg, d + 2 * nseg, d + 3 * nseg, d + 4 * nseg, d + 5 * nseg, d + 6 * nseg,
+                                  d + 7 * nseg, d + 8 * nseg, d + 9 * nseg, offs[k]};
+                Admit decision = Admit::Run;
+                c->admit = [&](const DevHeader &h, int64_t total, int64_t growth) -> lts_status {
+                    const int64_t px = std::max<int64_t>(h.n_slots, 1), pk = std::max<int64_t>(h.n_slots * mp, 1);
+                    const size_t want[] = {sizeof(int32_t) * (size_t)px, sizeof(float) * (size_t)px * S->n_ticks,
+                                           sizeof(int32_t) * (size_t)pk, sizeof(int32_t) * (size_t)pk,
+                                           sizeof(uint16_t) * (size_t)pk, sizeof(uint8_t) * (size_t)pk,
+                                           sizeof(int64_t) * 4, sizeof(double) * 5 * (size_t)k,
+                                           sizeof(int64_t) * (size_t)(k + 1), sizeof(int64_t) * (size_t)(k + 1)};
+                    int64_t out_total = (int64_t)L->seg.bytes, out_growth = 0;
+                    for (int i = 0; i < 10; ++i) {
+                        out_total += (int64_t)std::max(outs[i]->bytes, want[i]);
+                        if (want[i] > outs[i]->bytes) out_growth += (int64_t)(want[i] - outs[i]->bytes);
+                    }
+                    size_t free_b = 0, total_b = 0;
+                    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+                        (void)hipGetLastError();
+                        free_b = 0;
+                    }
+                    decision = admit_decision(k, total + out_total, growth + out_growth, share, (int64_t)free_b,
+                                              S->mem_reserve);
+                    if (decision != Admit::Run) return kNotAdmitted;
+                    lts_status r2 = LTS_OK;
+                    for (int i = 0; i < 10 && r2 == LTS_OK; ++i) r2 = ensure(c, *outs[i], want[i]);
+                    if (r2) return r2;
+                    set_outputs(h.n_slots);
+                    return LTS_OK;
+                };
+                struct Unhook {                                   // the hook captures this frame: never outlive it
+                    lts_context *c;
+                    ~Unhook() { c->admit = nullptr; }
+                } unhook{c};
+                st = run_pipeline(c, k, ids.data(), offs.data(), &segs, &o, L->stream);
+                if (st == kNotAdmitted) {
+                    st = LTS_OK;
+                    return decision;
                 }
-                size_t free_b = 0, total_b = 0;
-                if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+                return Admit::Run;                                // ran (or failed with its own status)
+            },
+            [&]() -> bool {                                       // the lane's pooled scratch, before refusing
+                if (hipStreamSynchronize(L->stream) != hipSuccess) {
                     (void)hipGetLastError();
-                    free_b = 0;
+                    st = LTS_ERR_DEVICE;
+                    return false;
                 }
-                decision = admit_decision(k, total + out_total, growth + out_growth, share, (int64_t)free_b,
-                                          S->mem_reserve);
-                if (decision != Admit::Run) return kNotAdmitted;
-                lts_status r2 = LTS_OK;
-                for (int i = 0; i < 10 && r2 == LTS_OK; ++i) r2 = ensure(c, *outs[i], want[i]);
-                if (r2) return r2;
-                set_outputs(h.n_slots);
-                return LTS_OK;
-            };
-            struct Unhook {                                       // the hook captures this frame: never outlive it
-                lts_context *c;
-                ~Unhook() { c->admit = nullptr; }
-            } unhook{c};
-            st = run_pipeline(c, k, ids.data(), offs.data(), &segs, &o, L->stream);
-            if (st == kNotAdmitted) {
-                st = LTS_OK;
-                return decision;
-            }
-            return Admit::Run;                                    // ran (or failed with its own status)
-        });
+                release_scratch(c);
+                for (int i = 0; i < 10; ++i) free_buf(*outs[i]);
+                for (int i = 0; i < 10 && st == LTS_OK; ++i) st = ensure(c, *outs[i], small[i]);
+                set_outputs(0);
+                return st == LTS_OK;
+            });
     }
     // events the batch no longer holds go back to the front of the queue, in order; a rejected head event (it alone
     // exceeds the lane's share) finishes with LTS_ERR_OOM

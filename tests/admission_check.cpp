@@ -3,6 +3,7 @@
 // head events (batch limit 16), "sizes" a tentative batch with a fake need model (fixed pool + bytes per event) and
 // runs it through the same decision, shrink and requeue code the library's lanes use.  Prints one line per scenario:
 // name, then the batches run (event ids) and the rejected events, for the Python test to check.
+#include <algorithm>
 #include <cstdio>
 #include <deque>
 #include <string>
@@ -51,6 +52,57 @@ static void run(const Scenario &sc) {
     std::printf("\n");
 }
 
+// Two kinds of buffer (e.g. charge cells and summed columns): an event needs (a, b) bytes of them, the lane's pool
+// keeps each kind at the largest size a batch needed, and a batch's footprint is fixed + max(pool_a, sum a) +
+// max(pool_b, sum b).  release() empties the pool.  Prints the batches run (event ids) and rejected events.
+static void run_pool(const char *name, const std::vector<std::pair<long long, long long>> &ev, long long fixed,
+                     long long share) {
+    std::deque<int> q;
+    for (int i = 0; i < (int)ev.size(); ++i) q.push_back(i);
+    long long pool_a = 0, pool_b = 0;
+    int releases = 0;
+    std::printf("%s", name);
+    while (!q.empty()) {
+        std::vector<int> batch;
+        while (!q.empty() && batch.size() < 16) {
+            batch.push_back(q.front());
+            q.pop_front();
+        }
+        const int ran = admission_loop(
+            (int32_t)batch.size(),
+            [&](int32_t k) {
+                long long a = 0, b = 0;
+                for (int e = 0; e < k; ++e) {
+                    a += ev[batch[e]].first;
+                    b += ev[batch[e]].second;
+                }
+                const long long na = std::max(pool_a, a), nb = std::max(pool_b, b);
+                const Admit d = admit_decision(k, fixed + na + nb, 0, share, 1ll << 50, 0);
+                if (d == Admit::Run) {
+                    pool_a = na;
+                    pool_b = nb;
+                }
+                return d;
+            },
+            [&] {
+                if (pool_a == 0 && pool_b == 0) return false;
+                pool_a = pool_b = 0;
+                ++releases;
+                return true;
+            });
+        if (ran == 0) {
+            std::printf(" reject:%d", batch[0]);
+            requeue_tail(q, batch, 1);
+            continue;
+        }
+        requeue_tail(q, batch, (size_t)ran);
+        std::printf(" run:");
+        for (size_t e = 0; e < batch.size(); ++e) std::printf("%s%d", e ? "," : "", batch[e]);
+        std::printf("@%lld", fixed + pool_a + pool_b);
+    }
+    std::printf(" released:%d\n", releases);
+}
+
 int main() {
     const long long MB = 1 << 20;
     std::vector<long long> uniform(20, 100 * MB);
@@ -65,5 +117,12 @@ int main() {
                                     60 * MB, 400 * MB, 2 * MB, 800 * MB};
     run({"mixed", mixed, 50 * MB, 1000 * MB, 64000 * MB, 1000 * MB});
     run({"nothing_fits", uniform, 50 * MB, 100 * MB, 64000 * MB, 1000 * MB});
+    // 16 events heavy in kind a grow the pool to 3200 MB of it; the next event needs 2000 MB of kind b and fits the
+    // 4000 MB share only once the pool is released; the last one needs 5000 MB and is rejected after the release
+    std::vector<std::pair<long long, long long>> two;
+    for (int i = 0; i < 16; ++i) two.push_back({200 * MB, 0});
+    two.push_back({0, 2000 * MB});
+    two.push_back({0, 5000 * MB});
+    run_pool("pool_release", two, 50 * MB, 4000 * MB);
     return 0;
 }

@@ -27,6 +27,8 @@ def scenarios(tmp_path_factory):
             if s.startswith("run:"):
                 ids, total = s[4:].split("@")
                 parsed.append(("run", [int(x) for x in ids.split(",")], int(total)))
+            elif s.startswith("released:"):
+                parsed.append(("released", [], int(s.split(":")[1])))
             else:
                 parsed.append(("reject", [int(s.split(":")[1])], 0))
         res[name] = parsed
@@ -34,7 +36,7 @@ def scenarios(tmp_path_factory):
 
 
 def _order(steps):
-    return [e for _, ids, _ in steps for e in ids]
+    return [e for kind, ids, _ in steps if kind != "released" for e in ids]
 
 
 def test_everything_fits_in_one_batch_of_16(scenarios):
@@ -77,3 +79,14 @@ def test_mixed_sizes_every_event_exactly_once(scenarios):
 def test_nothing_fits(scenarios):
     s = scenarios["nothing_fits"]
     assert [kind for kind, _, _ in s] == ["reject"] * 20 and _order(s) == list(range(20))
+
+
+def test_pool_release_admits_an_event_the_grown_pool_refused(scenarios):
+    """A lane's pool keeps every buffer at its largest size; a single event refused because of that pool is sized
+    again after the lane releases it, and only an event that alone exceeds the share is rejected."""
+    MB = 1 << 20
+    steps = scenarios["pool_release"]
+    assert steps[0] == ("run", list(range(16)), 50 * MB + 3200 * MB)
+    assert steps[1] == ("run", [16], 50 * MB + 2000 * MB)      # only after the pool was released
+    assert steps[2] == ("reject", [17], 0)
+    assert steps[3] == ("released", [], 2)

@@ -356,7 +356,8 @@ def test_host_allocation_failure_returns_oom(lt, torch):
         srv.stop()
 
 
-@pytest.mark.parametrize("mode,rt,shift", [(0, 0, False), (0, 8, False), (0, 0, True), (1, 0, False), (2, 0, False)])
+@pytest.mark.parametrize("mode,rt,shift", [(0, 0, False), (0, 8, False), (0, 0, True), (1, 0, False), (2, 0, False),
+                                           (2, 8, False), (2, 0, True)])
 def test_max_window_long_table_parity(lt, orc, torch, mode, rt, shift):
     w = _max_window_workload()
     h, r, e, (cmp_, flg) = check_event(lt, orc, w, mode=mode, rt=rt, shift=shift)
@@ -417,6 +418,26 @@ def test_large_spill_tile_sampled_pixels(lt, orc, torch, mode):
     cmp_, flg, bad = compare_packets(h, gpix[pick], pk, uf)
     print(f"large-spill tile packets: compared {cmp_} flagged {flg}")
     assert not bad and cmp_ > 0
+
+
+def test_summed_kernels_reproducible_and_agree(lt, torch):
+    """Summed induction on a spill-mix event whose pixels have long runs of same-bin pieces (merged records up to
+    the 248-tick cap): the 256-tick kernel gives bit-identical currents call after call, and agrees with the
+    512-tick kernel to FP32 summation order."""
+    w = W.make_workload(3, n_events=8)
+    ev, eid = w.events[2], w.event_ids[2]
+    runs = {}
+    for rt in (0, 0, 8):
+        ctx = lt.Context.from_workload(w, reduce_mode=2)
+        ctx.set_ticks_per_thread(rt)
+        runs.setdefault(rt, []).append(ctx.simulate(lt.to_device(ev), event_id=eid).host())
+        ctx.close()
+    a, b, c = runs[0][0], runs[0][1], runs[8][0]
+    assert np.array_equal(a["pixel_id"], b["pixel_id"]) and np.array_equal(a["current"], b["current"])
+    assert np.array_equal(a["pixel_id"], c["pixel_id"])
+    e = per_pixel_errors(a["current"].astype(np.float64), c["current"].astype(np.float64))
+    print(f"summed 256 vs 512 kernel: max e_p {e.max():.2e}")
+    assert e.max() <= 1e-5
 
 
 def test_sorted_and_atomic_agree(lt, torch):
