@@ -34,7 +34,7 @@ PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 PEAK_FP64_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
-INDUCE_KERNEL = {"sorted": "k_induce_sorted", "atomic": "k_induce_atomic", "summed": "k_induce_summed"}
+INDUCE_KERNEL = {"sorted": "k_induce_sorted", "atomic": "k_induce_atomic", "summed": "k_induce_summed4"}
 MODE_ID = {"sorted": 0, "atomic": 1, "summed": 2}
 SPILL_SEGMENTS = 2_000_000
 

@@ -49,6 +49,7 @@ S, A, M = ltsim.LTS_REDUCE_SORTED, ltsim.LTS_REDUCE_ATOMIC, ltsim.LTS_REDUCE_SUM
 DEFAULT_CANDIDATES = (Choice(S, 1, 0), Choice(S, 1, 4), Choice(S, 8, 0), Choice(A, 1, 0), Choice(M, 1, 0),
                       Choice(M, 1, 8), Choice(M, 1, 4))
 DEFAULT_SIZES = (500, 2000, 8000, 32000)
+ACCEPT_REL_L2 = 1e-4
 
 
 def shape_key(w) -> str:
@@ -114,7 +115,7 @@ def autotune(w, sizes: Sequence[int] = DEFAULT_SIZES, candidates: Sequence[Choic
             rows.append({"choice": asdict(c), "ms": ms, "max_rel_l2_vs_sorted": err})
             if verbose:
                 print(f"[autotune] {n} segments/event {asdict(c)}: {ms:.2f} ms, err {err:.1e}", flush=True)
-        best = min((r for r in rows if r["max_rel_l2_vs_sorted"] <= 1e-5), key=lambda r: r["ms"])
+        best = min((r for r in rows if r["max_rel_l2_vs_sorted"] <= ACCEPT_REL_L2), key=lambda r: r["ms"])
         b = best["choice"]
         # a class's entry starts at the geometric midpoint between its size and the previous class's
         lo = 0 if not table else int(np.sqrt(float(sizes[len(table) - 1]) * n))
