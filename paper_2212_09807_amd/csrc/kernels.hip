@@ -518,6 +518,72 @@ __device__ void mc_cells(const DevParams &P, const SegInfo &g, uint32_t seg, uin
     __syncthreads();
 }
 
+// The charge box of one pass over np sample points as a matrix product on the FP32 matrix cores: with the point index
+// m as the contraction, cells[(u, v)][a] = sum_m (fx[m][u] fy[m][v]) ft[m][a], times q (the point charge when every
+// point carries the same charge, else 1: ft then already holds it).  16x16x4 MFMA tiles: rows are 16 (u, v) columns
+// of the box, columns 16 ticks, each instruction takes 4 points (lane l gives A[l % 16][l / 16] = fx fy of its row's
+// column at point l / 16 and B[l / 16][l % 16] = ft of that point at its tick).  Each wavefront of the workgroup takes
+// 2 x 2 blocks of tiles in turn, so every A value serves two tiles and every B value two; out-of-box rows, ticks and
+// points contribute zeros and are not written.  `first` writes the pass's sums, otherwise they are added.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void cells_mfma(const float *fx, const float *fy, const float *ft, int32_t nu, int32_t nv,
+                                           int32_t nap, int32_t np, float q, bool first, float *out) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int32_t ncol = nu * nv, tm = (ncol + 15) / 16, tn = (nap + 15) / 16;
+    const int32_t bm = (tm + 1) / 2, bn = (tn + 1) / 2;
+    const int32_t il = lane & 15, kl = lane >> 4;
+    for (int32_t blk = wv; blk < bm * bn; blk += kWG / 64) {
+        const int32_t mi0 = (blk / bn) * 2, nj0 = (blk % bn) * 2;
+        int32_t cu[2], cv[2], ta[2];
+        bool cok[2], tok[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int32_t c = (mi0 + t) * 16 + il;
+            cok[t] = c < ncol;
+            cu[t] = cok[t] ? c / nv : 0;
+            cv[t] = cok[t] ? c - (c / nv) * nv : 0;
+            ta[t] = (nj0 + t) * 16 + il;
+            tok[t] = ta[t] < nap;
+        }
+        floatx4 D[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) D[i][j] = (floatx4){0.0f, 0.0f, 0.0f, 0.0f};
+        for (int32_t m0 = 0; m0 < np; m0 += 4) {
+            const int32_t m = m0 + kl;
+            const bool mok = m < np;
+            float A[2], B[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const bool ka = mok && cok[t], kb = mok && tok[t];
+                const float x = fx[ka ? m * nu + cu[t] : 0], y = fy[ka ? m * nv + cv[t] : 0];
+                A[t] = ka ? x * y : 0.0f;
+                const float z = ft[kb ? m * nap + ta[t] : 0];
+                B[t] = kb ? z : 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) D[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[i], B[j], D[i][j], 0, 0, 0);
+        }
+        // lane l holds rows 4 (l / 16) + r of each tile (a box column) at column l % 16 (a tick)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int32_t c = (mi0 + i) * 16 + 4 * kl + r, a = (nj0 + j) * 16 + il;
+                    if (c < ncol && a < nap) {
+                        const float v = D[i][j][r] * q;
+                        float *o = out + (int64_t)c * nap + a;
+                        if (first) *o = v; else *o += v;
+                    }
+                }
+    }
+}
+
 __global__ __launch_bounds__(kWG) void k_cells(DevParams P, const SegInfo *si, int64_t n_seg, float *cells,
                                                const int64_t *seg_ev_off, const uint64_t *event_ids, double *report) {
     __shared__ float sm[kCellLds];
@@ -528,7 +594,7 @@ __global__ __launch_bounds__(kWG) void k_cells(DevParams P, const SegInfo *si, i
         if (g.flags & (SEG_INVALID | SEG_TOO_LONG)) continue;
         const int32_t nu = g.nu, nv = g.nv, na = g.na, nap = g.na_pad, N = g.n_points;
         const int32_t row = nu + nv + nap;
-        const int32_t pc = min(64, kCellLds / row);
+        const int32_t pc = min(256, kCellLds / row);
         float *fx = sm, *fy = sm + pc * nu, *ft = fy + pc * nv;
         const int64_t ncell = (int64_t)nu * nv * nap;
         float *out = cells + g.cell_off;
@@ -554,15 +620,7 @@ __global__ __launch_bounds__(kWG) void k_cells(DevParams P, const SegInfo *si, i
                 }
             }
             __syncthreads();
-            for (int64_t c = tid; c < ncell; c += kWG) {
-                const int32_t a = (int32_t)(c % nap);
-                const int32_t uv = (int32_t)(c / nap);
-                const int32_t v = uv % nv, u = uv / nv;
-                float acc = 0.0f;
-                for (int32_t m = 0; m < np; ++m) acc = fmaf(ft[m * nap + a] * fx[m * nu + u], fy[m * nv + v], acc);
-                if (!P.per_point) acc *= g.q_pt;
-                if (mu0 == 0) out[c] = acc; else out[c] += acc;
-            }
+            cells_mfma(fx, fy, ft, nu, nv, nap, np, P.per_point ? 1.0f : g.q_pt, mu0 == 0, out);
             __syncthreads();
         }
         // charge whose cells lie outside the pixel grid
