@@ -1716,7 +1716,8 @@ constexpr int32_t kSumGap = 16;
 
 // The merged tick interval that starts at entry q of a column's segment list [q, se) (sorted by first tick): its
 // segments are [q, return value), its ticks [lo, hi], lo moved down (zero charge in front) to the residue `res`
-// mod 8.  Consecutive intervals are separated by more than kSumGap ticks, so the aligned ones do not overlap.
+// mod 8 when res >= 0.  Consecutive intervals are separated by more than kSumGap ticks, so the aligned ones do not
+// overlap.
 __device__ inline int64_t sum_interval(const SegInfo *__restrict__ si, const uint64_t *__restrict__ seg, int64_t q,
                                        int64_t se, int32_t res, int32_t &lo, int32_t &hi) {
     const SegInfo &g0 = si[key_seg(seg[q])];
@@ -1728,7 +1729,7 @@ __device__ inline int64_t sum_interval(const SegInfo *__restrict__ si, const uin
         if (g.a0 - hi - 1 > kSumGap) break;
         hi = max(hi, g.a0 + g.na - 1);
     }
-    lo -= ((lo - res) % 8 + 8) % 8;
+    if (res >= 0) lo -= ((lo - res) % 8 + 8) % 8;
     return qe;
 }
 
@@ -1747,8 +1748,9 @@ __device__ __forceinline__ uint64_t lane_u64(uint64_t v, int j) {
 }
 
 // per column: sort its segment list by key (first tick, segment index) into col_seg, then count the pieces and the
-// padded summed-charge length of its merged tick intervals.  Every interval's first tick is moved down to the residue
-// chosen by the summed induction kernel (it makes every lane's table offsets aligned there).  The order
+// padded summed-charge length of its merged tick intervals.  For the 512-tick summed induction kernel every
+// interval's first tick is moved down to the residue it chooses (it makes every lane's table offsets aligned there);
+// the 256-tick kernel takes intervals as they are (align_res < 0).  The order
 // depends only on the segments' charge boxes and their order within the event, so the sums are the same in a batch
 // and alone.  One wavefront per 64 consecutive columns; the wavefront sorts its columns' lists one after another by
 // ranks (a key's place is the number of smaller keys; keys are unique): lane i holds key i of a 64-key chunk and
@@ -1869,7 +1871,7 @@ __global__ __launch_bounds__(kWG) void k_sum_pieces(DevParams P, const SegInfo *
                 if (a0 - hi - 1 > kSumGap) break;
                 hi = max(hi, a0 + na - 1);
             }
-            lo -= ((lo - res) % 8 + 8) % 8;
+            if (res >= 0) lo -= ((lo - res) % 8 + 8) % 8;
             const int32_t L = hi - lo + 1;
             int64_t np, Lpad;
             sum_interval_size(L, np, Lpad);
@@ -2030,8 +2032,8 @@ void launch_sum_lists_fill(const DevParams &P, const Work &w, const SumWork &sw,
 
 // Mirror merge.  A pixel convolves every record of one folded table column with the same table column, so a run of
 // its list's records with the same bin whose tick spans overlap or lie at most kMergeGap ticks apart is one record
-// whose charge is the members' sum, taken in list order.  Every record starts at the same residue mod 8 (the
-// alignment of the column intervals), so the union does as well.  Runs are cut at every 64th record of the pixel's
+// whose charge is the members' sum, taken in list order (a member's charge sits at its first tick's offset from the
+// union's first tick).  Runs are cut at every 64th record of the pixel's
 // list (the lanes of one pass), and a run whose union would exceed kPieceMax ticks is not merged; a run of one record
 // stays as it is.  Count pass: records and merged-charge floats per pixel; fill pass: the merged records (in list
 // order) and their charges.  One wavefront per pixel; the runs of 64 records are found with segmented lane scans.
@@ -2314,8 +2316,8 @@ __global__ __launch_bounds__(kWG) void k_induce_summed(DevParams P, const SegInf
 // down 8 values per block (two aligned LDS reads per block).  Lanes whose ticks lie outside the record's window meet
 // the table's zero padding.  Products go to the lane's running sums with Kahan compensation after every 4 records
 // (records in list order: deterministic and batch-invariant).  The first tile of a pixel also accounts the charge
-// its records induce outside the readout.  Charge intervals start at the residue (T_R + kPad) mod 8, so the staged
-// copies start 32-byte aligned.
+// its records induce outside the readout.  Charge intervals start at any tick: the staged copy is loaded from the
+// 16-byte aligned column entry at or below its first value and written to LDS shifted down by the difference.
 constexpr int32_t kTile4 = 256;                         // ticks of one work unit: 64 lanes x 4
 constexpr int32_t kStage4 = kTile4 + kPieceMax + 8;     // staged table values per record and unit (at most)
 
@@ -2341,9 +2343,9 @@ __global__ __launch_bounds__(kWG) void k_induce_summed4(DevParams P, const float
                                                         const int32_t *__restrict__ order,
                                                         const int32_t *__restrict__ slot_gp, float *__restrict__ wave,
                                                         DevHeader *H, double *report) {
-    __shared__ __align__(16) float stage_all[kWG / 64][kStage4];
+    __shared__ __align__(16) float stage_all[kWG / 64][4 + kStage4];
     const int lane = threadIdx.x & 63;
-    float *stage = stage_all[threadIdx.x >> 6];
+    float *stage = stage_all[threadIdx.x >> 6] + 4;     // 4 head floats take the unneeded values of a shifted copy
     const int32_t NT = P.nticks, TR = P.t_r;
     const int32_t n_tiles = (NT + kTile4 - 1) / kTile4;
     const int64_t n_units = H->n_slots * n_tiles;
@@ -2369,7 +2371,7 @@ __global__ __launch_bounds__(kWG) void k_induce_summed4(DevParams P, const float
             uint64_t mask = __ballot(in && rl.a0 + rl.na - 1 >= t0 && rl.a0 - (TR - 1) <= t1);
             if (!mask) continue;
             // record i of the chunk: its fields, and the lane's two staged float4s of it, loaded ahead
-            int32_t a0 = 0, nblk = 0, n4 = 0;
+            int32_t a0 = 0, nblk = 0, n4 = 0, dl = 0;
             uint32_t c8 = 0;
             float4 g0 = {0, 0, 0, 0}, g1 = {0, 0, 0, 0};
             auto fetch = [&](int i) {
@@ -2378,8 +2380,12 @@ __global__ __launch_bounds__(kWG) void k_induce_summed4(DevParams P, const float
                 const int32_t bin = __builtin_amdgcn_readlane(rl.bin, i);
                 c8 = (uint32_t)__builtin_amdgcn_readlane((int)rl.cell8, i);
                 nblk = (na + kAC - 1) / kAC;
-                n4 = (kTile4 + nblk * kAC) / 4;
-                const float *src = Rpad + (int64_t)bin * P.col_len + (t0 - a0 - nblk * kAC + TR + kPad);
+                // the values staged are column entries idx0 .. idx0 + 255 + 8 nblk; they are loaded from the
+                // 16-byte aligned entry idx0 - dl below (table columns start 32-byte aligned)
+                const int32_t idx0 = t0 - a0 - nblk * kAC + TR + kPad;
+                dl = idx0 & 3;
+                n4 = (kTile4 + nblk * kAC + dl + 3) / 4;
+                const float *src = Rpad + (int64_t)bin * P.col_len + (idx0 - dl);
                 g0 = *(const float4 *)(src + 4 * lane);
                 if (lane + 64 < n4) g1 = *(const float4 *)(src + 4 * (lane + 64));
             };
@@ -2391,8 +2397,17 @@ __global__ __launch_bounds__(kWG) void k_induce_summed4(DevParams P, const float
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                *(float4 *)(stage + 4 * lane) = g0;
-                if (lane + 64 < n4) *(float4 *)(stage + 4 * (lane + 64)) = g1;
+                if (dl == 0) {
+                    *(float4 *)(stage + 4 * lane) = g0;
+                    if (lane + 64 < n4) *(float4 *)(stage + 4 * (lane + 64)) = g1;
+                } else {                                // dl entries down: lane 0's first ones land in the head
+                    float *d0 = stage + 4 * lane - dl;
+                    d0[0] = g0.x; d0[1] = g0.y; d0[2] = g0.z; d0[3] = g0.w;
+                    if (lane + 64 < n4) {
+                        float *d1 = d0 + 256;
+                        d1[0] = g1.x; d1[1] = g1.y; d1[2] = g1.z; d1[3] = g1.w;
+                    }
+                }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -2459,8 +2474,8 @@ __global__ __launch_bounds__(kWG) void k_induce_summed4(DevParams P, const float
 
 bool summed_tile256(int32_t rt, bool shift) { return rt == 0 && !shift; }
 int32_t summed_align_res(const DevParams &P, int32_t rt, bool shift) {
-    const int32_t c = summed_tile256(rt, shift) ? P.t_r + kPad : P.t_r - 1 + kPad;
-    return (c % 8 + 8) % 8;
+    if (summed_tile256(rt, shift)) return -1;          // its staging copy realigns the table values itself
+    return ((P.t_r - 1 + kPad) % 8 + 8) % 8;
 }
 
 // Largest-first order of the pixels for the summed induction (the same log-bucketed order as the per-pair kernel's;
