@@ -456,31 +456,6 @@ void launch_sort_pairs(const Work &w, int64_t n_slots_host, hipStream_t st) {
 }
 
 // ================================================================================================= charge cells
-// Masses of nk consecutive bins (edges (k0 + k) * width relative to the reference edge) for a point at local
-// offset l with width sigma, truncated at +-n sigma and renormalised.
-__device__ void axis_masses(float l, float sigma, int32_t k0, int32_t nk, float wh, float wl, const DevParams &P,
-                            float *out) {
-    if (!(sigma > 0.0f)) {
-        const int32_t kk = (int32_t)floorf(__fdiv_rn(l, wh)) - k0;
-        for (int32_t k = 0; k < nk; ++k) out[k] = (k == kk) ? 1.0f : 0.0f;
-        return;
-    }
-    const float inv = 1.0f / sigma;
-    float kf = (float)k0;
-    float e = __fadd_rn(fmaf(kf, wh, -l), __fmul_rn(kf, wl));
-    float za = fminf(fmaxf(e * inv, -P.nsig), P.nsig);
-    float ta = tail(za);
-    for (int32_t k = 0; k < nk; ++k) {
-        kf = (float)(k0 + k + 1);
-        e = __fadd_rn(fmaf(kf, wh, -l), __fmul_rn(kf, wl));
-        const float zb = fminf(fmaxf(e * inv, -P.nsig), P.nsig);
-        const float tb = tail(zb);
-        out[k] = tmass(za, ta, zb, tb, P.inv_norm);
-        za = zb;
-        ta = tb;
-    }
-}
-
 constexpr int kCellLds = 12288;   // floats (48 KB)
 
 // Monte Carlo cells of one segment (the paper's estimator of eq. (rho) with M = P.mc_draws perturbations per point):
@@ -593,31 +568,72 @@ __global__ __launch_bounds__(kWG) void k_cells(DevParams P, const SegInfo *si, i
         const SegInfo g = si[s];
         if (g.flags & (SEG_INVALID | SEG_TOO_LONG)) continue;
         const int32_t nu = g.nu, nv = g.nv, na = g.na, nap = g.na_pad, N = g.n_points;
-        const int32_t row = nu + nv + nap;
-        const int32_t pc = min(256, kCellLds / row);
+        const int32_t row = nu + nv + nap, ne = nu + nv + na + 3;      // bins and bin edges of a point's three axes
+        const int32_t pc = min(256, kCellLds / (row + ne + 6));
         float *fx = sm, *fy = sm + pc * nu, *ft = fy + pc * nv;
+        float *tl = ft + pc * nap;                      // [point][edge]: the edge's tail, negated below the mean
+        float *pl = tl + pc * ne;                       // [point][6]: local x, y, t, widths, charge
         const int64_t ncell = (int64_t)nu * nv * nap;
         float *out = cells + g.cell_off;
         if (P.mc_draws > 0)
             mc_cells(P, g, (uint32_t)(s - seg_ev_off[g.event]), event_ids[g.event], out, (uint32_t *)sm, ncell);
         for (int32_t mu0 = 0; mu0 < (P.mc_draws > 0 ? 0 : N); mu0 += pc) {
             const int32_t np = min(pc, N - mu0);
-            for (int r = tid; r < np * 3; r += kWG) {
-                const int32_t m = r / 3, ax = r - 3 * (r / 3);
-                float lx, ly, lt;
-                point_local(g, P, mu0 + m, lx, ly, lt);
+            // Per point and axis, the masses of consecutive bins (edges (k0 + j) * width from the reference edge)
+            // of the point's Gaussian of width sigma, truncated at +-n sigma and renormalised, each taken as a
+            // difference of tails on the side away from the mean.  Spread over the workgroup: each point's frame,
+            // then every edge's tail, then every bin's mass from its two edges.
+            for (int m = tid; m < np; m += kWG) {
                 float q = 1.0f, sT = g.sigma_t, sL = g.sigma_time;
+                point_local(g, P, mu0 + m, pl[6 * m], pl[6 * m + 1], pl[6 * m + 2]);
                 if (P.per_point) point_drift(g, P, mu0 + m, q, sT, sL);
-                if (ax == 0) {
-                    axis_masses(lx, sT, g.u0 - g.u_ref, nu, P.b_hi, P.b_lo, P, fx + m * nu);
-                } else if (ax == 1) {
-                    axis_masses(ly, sT, g.v0 - g.v_ref, nv, P.b_hi, P.b_lo, P, fy + m * nv);
-                } else {                                // per point: its charge rides on the time masses
-                    axis_masses(lt, sL, g.a0 - g.a_ref, na, P.tick_hi, P.tick_lo, P, ft + m * nap);
-                    if (P.per_point)
-                        for (int32_t a = 0; a < na; ++a) ft[m * nap + a] *= q;
-                    for (int32_t a = na; a < nap; ++a) ft[m * nap + a] = 0.0f;
+                pl[6 * m + 3] = sT;
+                pl[6 * m + 4] = sL;
+                pl[6 * m + 5] = q;
+            }
+            __syncthreads();
+            for (int r = tid; r < np * ne; r += kWG) {
+                const int32_t m = r / ne, k = r - m * ne;
+                const int ax = k <= nu ? 0 : k <= nu + nv + 1 ? 1 : 2;
+                const int32_t j = ax == 0 ? k : ax == 1 ? k - nu - 1 : k - nu - nv - 2;
+                const float l = pl[6 * m + ax], sg = pl[6 * m + (ax == 2 ? 4 : 3)];
+                const int32_t k0 = ax == 0 ? g.u0 - g.u_ref : ax == 1 ? g.v0 - g.v_ref : g.a0 - g.a_ref;
+                const float wh = ax == 2 ? P.tick_hi : P.b_hi, wl = ax == 2 ? P.tick_lo : P.b_lo;
+                float t = 0.0f;
+                if (sg > 0.0f) {
+                    const float kf = (float)(k0 + j);
+                    const float e = __fadd_rn(fmaf(kf, wh, -l), __fmul_rn(kf, wl));
+                    const float z = fminf(fmaxf(e * (1.0f / sg), -P.nsig), P.nsig);
+                    t = tail(z);
+                    if (!(z >= 0.0f)) t = -t;               // the sign bit keeps the side of the mean
                 }
+                tl[r] = t;
+            }
+            __syncthreads();
+            for (int r = tid; r < np * row; r += kWG) {
+                const int32_t m = r / row, k = r - m * row;
+                const int ax = k < nu ? 0 : k < nu + nv ? 1 : 2;
+                const int32_t j = ax == 0 ? k : ax == 1 ? k - nu : k - nu - nv;
+                const int32_t eo = ax == 0 ? 0 : ax == 1 ? nu + 1 : nu + nv + 2;
+                float mass = 0.0f;
+                if (ax < 2 || j < na) {
+                    const float sg = pl[6 * m + (ax == 2 ? 4 : 3)];
+                    if (sg > 0.0f) {
+                        // tmass only asks on which side of the mean each edge lies; an edge at z = 0 counted as
+                        // above it gives the same value, (1 - 1/2) - ta = 1/2 - ta
+                        const float a = tl[m * ne + eo + j], b = tl[m * ne + eo + j + 1];
+                        mass = tmass(__builtin_signbit(a) ? -1.0f : 1.0f, fabsf(a), __builtin_signbit(b) ? -1.0f : 1.0f,
+                                     fabsf(b), P.inv_norm);
+                    } else {                            // no spread: all of the point in the bin that holds it
+                        const float l = pl[6 * m + ax];
+                        const float wh = ax == 2 ? P.tick_hi : P.b_hi;
+                        const int32_t k0 = ax == 0 ? g.u0 - g.u_ref : ax == 1 ? g.v0 - g.v_ref : g.a0 - g.a_ref;
+                        mass = j == (int32_t)floorf(__fdiv_rn(l, wh)) - k0 ? 1.0f : 0.0f;
+                    }
+                    if (ax == 2 && P.per_point) mass *= pl[6 * m + 5];   // per point: its charge rides on the time masses
+                }
+                float *dst = ax == 0 ? fx + m * nu : ax == 1 ? fy + m * nv : ft + m * nap;
+                dst[j] = mass;
             }
             __syncthreads();
             cells_mfma(fx, fy, ft, nu, nv, nap, np, P.per_point ? 1.0f : g.q_pt, mu0 == 0, out);
