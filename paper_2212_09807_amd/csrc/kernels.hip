@@ -1730,25 +1730,6 @@ __global__ void k_sum_fill(DevParams P, const SegInfo *si, int64_t n_seg, SumWor
 // such a gap would otherwise be convolved with the whole table column.  A new piece costs less than ~16 zero ticks.
 constexpr int32_t kSumGap = 16;
 
-// The merged tick interval that starts at entry q of a column's segment list [q, se) (sorted by first tick): its
-// segments are [q, return value), its ticks [lo, hi], lo moved down (zero charge in front) to the residue `res`
-// mod 8 when res >= 0.  Consecutive intervals are separated by more than kSumGap ticks, so the aligned ones do not
-// overlap.
-__device__ inline int64_t sum_interval(const SegInfo *__restrict__ si, const uint64_t *__restrict__ seg, int64_t q,
-                                       int64_t se, int32_t res, int32_t &lo, int32_t &hi) {
-    const SegInfo &g0 = si[key_seg(seg[q])];
-    lo = g0.a0;
-    hi = g0.a0 + g0.na - 1;
-    int64_t qe = q + 1;
-    for (; qe < se; ++qe) {
-        const SegInfo &g = si[key_seg(seg[qe])];
-        if (g.a0 - hi - 1 > kSumGap) break;
-        hi = max(hi, g.a0 + g.na - 1);
-    }
-    if (res >= 0) lo -= ((lo - res) % 8 + 8) % 8;
-    return qe;
-}
-
 // Pieces of kPieceTicks ticks of an interval of L ticks, and their summed-charge length (the last one padded to kAC).
 __device__ inline void sum_interval_size(int32_t L, int64_t &np, int64_t &ns) {
     np = (L + kPieceTicks - 1) / kPieceTicks;
@@ -1766,11 +1747,21 @@ __device__ __forceinline__ uint64_t lane_u64(uint64_t v, int j) {
 // per column: sort its segment list by key (first tick, segment index) into col_seg, then count the pieces and the
 // padded summed-charge length of its merged tick intervals.  For the 512-tick summed induction kernel every
 // interval's first tick is moved down to the residue it chooses (it makes every lane's table offsets aligned there);
-// the 256-tick kernel takes intervals as they are (align_res < 0).  The order
-// depends only on the segments' charge boxes and their order within the event, so the sums are the same in a batch
-// and alone.  One wavefront per 64 consecutive columns; the wavefront sorts its columns' lists one after another by
-// ranks (a key's place is the number of smaller keys; keys are unique): lane i holds key i of a 64-key chunk and
-// compares it with every key of the list, taken chunk by chunk from the lanes' registers.
+// the 256-tick kernel takes intervals as they are (align_res < 0).  The order depends only on the segments' charge
+// boxes and their order within the event, so the sums are the same in a batch and alone.  One wavefront per 64
+// consecutive columns; the wavefront takes its non-empty columns one after another.  Sort by ranks (a key's place is
+// the number of smaller keys; keys are unique): lane i holds key i of a 64-key chunk and compares it with every key
+// of the list, taken chunk by chunk from the lanes' registers.  Intervals from the sorted list, 64 entries at a time:
+// an entry starts an interval when its first tick lies more than kSumGap ticks beyond the last tick of every earlier
+// entry (a prefix maximum over the lanes), and the interval before it ends at that maximum.
+__device__ __forceinline__ int32_t key_a0(uint64_t k) { return (int32_t)((uint32_t)(k >> 32) ^ 0x80000000u); }
+__device__ __forceinline__ void interval_count(int32_t lo, int32_t hi, int32_t res, int64_t &np, int64_t &ns) {
+    if (res >= 0) lo -= ((lo - res) % 8 + 8) % 8;
+    int64_t n, m;
+    sum_interval_size(hi - lo + 1, n, m);
+    np += n;
+    ns += m;
+}
 __global__ __launch_bounds__(kWG) void k_sum_columns(int32_t align_res, const SegInfo *__restrict__ si, SumWork sw) {
     const int lane = threadIdx.x & 63;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1782,36 +1773,99 @@ __global__ __launch_bounds__(kWG) void k_sum_columns(int32_t align_res, const Se
     const uint64_t *__restrict__ in = sw.col_tmp;
     uint64_t *seg = sw.col_seg;
     uint64_t todo = __ballot(e > b);
+    uint64_t act = 0;                                   // the wavefront's columns with pieces
     while (todo) {
         const int l = __ffsll((unsigned long long)todo) - 1;
         todo &= todo - 1;
         const int64_t lb = __shfl(b, l), n = __shfl(e, l) - lb;
-        for (int64_t i0 = 0; i0 < n; i0 += 64) {
-            const bool mine = i0 + lane < n;
-            const uint64_t x = mine ? in[lb + i0 + lane] : 0;
-            int64_t rank = 0;
-            for (int64_t j0 = 0; j0 < n; j0 += 64) {
-                const uint64_t y = j0 + lane < n ? in[lb + j0 + lane] : ~0ull;
-                const int jn = (int)min<int64_t>(64, n - j0);
-                for (int j = 0; j < jn; ++j) rank += lane_u64(y, j) < x;
+        int32_t run_hi = 0, cur_lo = 0;                 // last tick of every entry so far; first tick of the open interval
+        int64_t np = 0, ns = 0;                         // this lane's share of the column's counts
+        // one 64-entry chunk of the sorted list: (first tick, last tick) of entry i0 + lane where `mine`
+        auto chunk = [&](int64_t i0, bool mine, int32_t a0, int32_t end) {
+            if (!mine) end = INT32_MIN;
+            int32_t incl = end;                         // inclusive prefix maximum of the last ticks
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int32_t y = __shfl_up(incl, d);
+                if (lane >= d) incl = max(incl, y);
             }
+            int32_t excl = __shfl_up(incl, 1);
+            if (lane == 0) excl = INT32_MIN;
+            if (i0 > 0) excl = max(excl, run_hi);
+            const bool st = mine && i0 + lane > 0 && (int64_t)a0 - excl - 1 > kSumGap;
+            const uint64_t starts = __ballot(st);
+            // the interval that ends before start lane s began at the previous start (or the open one)
+            const uint64_t below = starts & ((1ull << lane) - 1ull);
+            const int pl = below ? 63 - __builtin_clzll(below) : -1;
+            const int32_t prev_lo = __shfl(a0, max(pl, 0));
+            if (i0 == 0) cur_lo = __shfl(a0, 0);        // (shuffles in uniform control flow: every lane is a source)
+            if (st) interval_count(pl >= 0 ? prev_lo : cur_lo, excl, align_res, np, ns);
+            if (starts) cur_lo = __shfl(a0, 63 - __builtin_clzll(starts));
+            run_hi = i0 == 0 ? __shfl(incl, 63) : max(run_hi, __shfl(incl, 63));
+        };
+        if (n <= 64) {
+            // the lengths are loaded before the sort and travel with their keys to the lanes of their ranks
+            const bool mine = lane < n;
+            const uint64_t x = mine ? in[lb + lane] : ~0ull;
+            const int32_t na = mine ? si[key_seg(x)].na : 0;
+            int32_t rank = 0;
+            for (int j = 0; j < (int)n; ++j) rank += lane_u64(x, j) < x;
+            if (!mine) rank = lane;
             if (mine) seg[lb + rank] = x;
+            const uint32_t xs_lo = (uint32_t)__builtin_amdgcn_ds_permute(rank * 4, (int)(uint32_t)x);
+            const uint32_t xs_hi = (uint32_t)__builtin_amdgcn_ds_permute(rank * 4, (int)(uint32_t)(x >> 32));
+            const int32_t nas = __builtin_amdgcn_ds_permute(rank * 4, na);
+            const int32_t a0 = key_a0(((uint64_t)xs_hi << 32) | xs_lo);
+            chunk(0, mine, a0, a0 + nas - 1);
+        } else {
+            for (int64_t i0 = 0; i0 < n; i0 += 64) {
+                const bool mine = i0 + lane < n;
+                const uint64_t x = mine ? in[lb + i0 + lane] : 0;
+                int64_t rank = 0;
+                for (int64_t j0 = 0; j0 < n; j0 += 64) {
+                    const uint64_t y = j0 + lane < n ? in[lb + j0 + lane] : ~0ull;
+                    const int jn = (int)min<int64_t>(64, n - j0);
+                    for (int j = 0; j < jn; ++j) rank += lane_u64(y, j) < x;
+                }
+                if (mine) seg[lb + rank] = x;
+            }
+            // the sorted list before the wavefront reads it back
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            for (int64_t i0 = 0; i0 < n; i0 += 64) {
+                const bool mine = i0 + lane < n;
+                int32_t a0 = 0, end = 0;
+                if (mine) {
+                    const uint64_t x = seg[lb + i0 + lane];
+                    a0 = key_a0(x);
+                    end = a0 + si[key_seg(x)].na - 1;
+                }
+                chunk(i0, mine, a0, end);
+            }
         }
+        if (lane == 0) interval_count(cur_lo, run_hi, align_res, np, ns);     // the last interval
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            np += __shfl_xor(np, o);
+            ns += __shfl_xor(ns, o);
+        }
+        if (lane == l) {
+            sw.piece_off[c] = np;
+            sw.s_off[c] = ns;
+        }
+        if (np) act |= 1ull << l;
     }
-    __threadfence_block();                              // the sorted lists before their own lanes read them
-    if (c >= sw.n_cols) return;
-    int64_t np = 0, ns = 0;
-    for (int64_t q = b; q < e;) {
-        int32_t lo, hi;
-        q = sum_interval(si, seg, q, e, align_res, lo, hi);
-        int64_t n, m;
-        sum_interval_size(hi - lo + 1, n, m);
-        np += n;
-        ns += m;
+    // columns without segments
+    if (c < sw.n_cols && e <= b) {
+        sw.piece_off[c] = 0;
+        sw.s_off[c] = 0;
     }
-    sw.piece_off[c] = np;
-    sw.s_off[c] = ns;
-    if (np) sw.active[atomicAdd(sw.n_active, 1u)] = (int32_t)c;    // any order: a column's outputs have fixed places
+    // the active list, one atomic per wavefront (any order: a column's outputs have fixed places)
+    uint32_t base = 0;
+    if (act && lane == 0) base = atomicAdd(sw.n_active, (uint32_t)__builtin_popcountll(act));
+    base = __shfl(base, 0);
+    if ((act >> lane) & 1ull) sw.active[base + __builtin_popcountll(act & ((1ull << lane) - 1ull))] = (int32_t)c;
 }
 
 void launch_sum_fill(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st) {
@@ -1829,11 +1883,19 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v, int l) {
 // per column: piece records, and the summed charge of each tick (Kahan over the column's segments in list order).
 // Wavefronts take the columns with pieces from the active list, one column at a time; lane j sums tick
 // lo + 64 m + j of the current interval over the interval's segments, the same additions per tick, in the same
-// order, as a tick-by-tick scan.  For a list of at most 256 segments, lane k first loads the first tick, length and
-// start of the cells in this column of segments k, k + 64, k + 128 and k + 192, so the per-segment loop reads them
-// from registers and only the (coalesced) cell loads go to memory; longer lists read each record in the loop.
+// order, as a tick-by-tick scan.  For a list of at most kPieceStage segments, the lanes first stage each segment's
+// first tick, length and cell base in this column in the wavefront's LDS slice, so the per-segment loops read them
+// with one broadcast LDS read into scalar registers and only the (coalesced) cell loads go to memory; longer lists
+// read each record in the loop.
+constexpr int kPieceStage = 256;
+struct SumRec {
+    int32_t a0, na;
+    int64_t base;                                       // cells index of tick 0 of the segment in this column
+};
 __global__ __launch_bounds__(kWG) void k_sum_pieces(DevParams P, const SegInfo *si, const float *cells, SumWork sw) {
+    __shared__ SumRec stage_all[kWG / 64][kPieceStage];
     const int lane = threadIdx.x & 63;
+    SumRec *rs = stage_all[threadIdx.x >> 6];
     const int32_t res = sw.align_res;
     const uint32_t n_act = *sw.n_active;
     const uint32_t waves = gridDim.x * (kWG / 64);
@@ -1845,101 +1907,103 @@ __global__ __launch_bounds__(kWG) void k_sum_pieces(DevParams P, const SegInfo *
         const int32_t u = sw.UL + (int32_t)(r / sw.CV), v = sw.VL + (int32_t)(r % sw.CV);
         const int64_t sb = sw.col_seg_off[cc], se = sw.col_seg_off[cc + 1], n = se - sb;
         int64_t pk = sw.piece_off[cc], so = sw.s_off[cc];
-        const bool regs = n <= 4 * 64;
-        int32_t my_a0[4] = {0, 0, 0, 0}, my_na[4] = {0, 0, 0, 0};
-        int64_t my_base[4] = {0, 0, 0, 0};                // cells index of tick 0 of the segment in this column
-        if (regs) {
-#pragma unroll
-            for (int w = 0; w < 4; ++w)
-                if (64 * w + lane < n) {
-                    const SegInfo &g = si[key_seg(sw.col_seg[sb + 64 * w + lane])];
-                    my_a0[w] = g.a0;
-                    my_na[w] = g.na;
-                    my_base[w] = g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad - g.a0;
-                }
-        }
-        auto seg_at = [&](int64_t k, int32_t &a0, int32_t &na, int64_t &base) {
-            if (regs) {                                   // entry k is held by lane k % 64 in register set k / 64
-                const int w = (int)(k >> 6), j = (int)(k & 63);
-                const int32_t x0 = w == 0 ? my_a0[0] : w == 1 ? my_a0[1] : w == 2 ? my_a0[2] : my_a0[3];
-                const int32_t x1 = w == 0 ? my_na[0] : w == 1 ? my_na[1] : w == 2 ? my_na[2] : my_na[3];
-                const int64_t x2 = w == 0 ? my_base[0] : w == 1 ? my_base[1] : w == 2 ? my_base[2] : my_base[3];
-                a0 = __builtin_amdgcn_readlane(x0, j);
-                na = __builtin_amdgcn_readlane(x1, j);
-                base = uniform_i64(x2, j);
-            } else {
+        const bool staged = n <= kPieceStage;
+        // the previous column's reads of the slice are done before it is overwritten
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (staged) {
+            for (int64_t k = lane; k < n; k += 64) {
                 const SegInfo &g = si[key_seg(sw.col_seg[sb + k])];
-                a0 = g.a0;
-                na = g.na;
-                base = g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad - g.a0;
+                rs[k] = SumRec{g.a0, g.na, g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad - g.a0};
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        auto from_lds = [&](int64_t k, int32_t &a0, int32_t &na, int64_t &base) {
+            const SumRec x = rs[k];                         // the same address in every lane: a broadcast read
+            a0 = __builtin_amdgcn_readfirstlane(x.a0);
+            na = __builtin_amdgcn_readfirstlane(x.na);
+            base = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)((uint64_t)x.base >> 32)) << 32) |
+                             (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x.base));
         };
-        for (int64_t q = 0; q < n;) {
-            // the merged interval starting at list entry q (the same rule as sum_interval)
-            int32_t lo, hi, a0, na;
-            int64_t base;
-            seg_at(q, a0, na, base);
-            lo = a0;
-            hi = a0 + na - 1;
-            int64_t qe = q + 1;
-            for (; qe < n; ++qe) {
-                seg_at(qe, a0, na, base);
-                if (a0 - hi - 1 > kSumGap) break;
-                hi = max(hi, a0 + na - 1);
-            }
-            if (res >= 0) lo -= ((lo - res) % 8 + 8) % 8;
-            const int32_t L = hi - lo + 1;
-            int64_t np, Lpad;
-            sum_interval_size(L, np, Lpad);
-            float *S = sw.S + so;
-            for (int32_t a0c = 0; a0c < Lpad; a0c += 64) {
-                const int32_t aa = lo + a0c + lane, ch = min(lo + a0c + 63, hi);
-                float sum = 0.0f, cmp = 0.0f;
-                // eight segments at a time: their cell loads are issued together, then added in list order
-                bool past = false;
-                for (int64_t k0 = q; k0 < qe && !past; k0 += 8) {
-                    float val[8];
-                    bool use[8];
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        use[i] = false;
-                        val[i] = 0.0f;
-                        if (k0 + i < qe && !past) {
-                            seg_at(k0 + i, a0, na, base);
-                            if (a0 > ch) past = true;           // sorted by first tick: no later one reaches
-                            else if (aa >= a0 && aa <= a0 + na - 1 && aa <= hi) {
-                                use[i] = true;
-                                val[i] = cells[base + aa];
+        auto from_global = [&](int64_t k, int32_t &a0, int32_t &na, int64_t &base) {
+            const SegInfo &g = si[key_seg(sw.col_seg[sb + k])];
+            a0 = g.a0;
+            na = g.na;
+            base = g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad - g.a0;
+        };
+        auto column = [&](auto seg_at) {
+            for (int64_t q = 0; q < n;) {
+                // the merged interval starting at list entry q (the rule k_sum_columns counts by)
+                int32_t lo, hi, a0, na;
+                int64_t base;
+                seg_at(q, a0, na, base);
+                lo = a0;
+                hi = a0 + na - 1;
+                int64_t qe = q + 1;
+                for (; qe < n; ++qe) {
+                    seg_at(qe, a0, na, base);
+                    if (a0 - hi - 1 > kSumGap) break;
+                    hi = max(hi, a0 + na - 1);
+                }
+                if (res >= 0) lo -= ((lo - res) % 8 + 8) % 8;
+                const int32_t L = hi - lo + 1;
+                int64_t np, Lpad;
+                sum_interval_size(L, np, Lpad);
+                float *S = sw.S + so;
+                for (int32_t a0c = 0; a0c < Lpad; a0c += 64) {
+                    const int32_t aa = lo + a0c + lane, ch = min(lo + a0c + 63, hi);
+                    float sum = 0.0f, cmp = 0.0f;
+                    // eight segments at a time: their cell loads are issued together, then added in list order
+                    bool past = false;
+                    for (int64_t k0 = q; k0 < qe && !past; k0 += 8) {
+                        float val[8];
+                        bool use[8];
+    #pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            use[i] = false;
+                            val[i] = 0.0f;
+                            if (k0 + i < qe && !past) {
+                                seg_at(k0 + i, a0, na, base);
+                                if (a0 > ch) past = true;           // sorted by first tick: no later one reaches
+                                else if (aa >= a0 && aa <= a0 + na - 1 && aa <= hi) {
+                                    use[i] = true;
+                                    val[i] = cells[base + aa];
+                                }
                             }
                         }
+    #pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            if (use[i]) {
+                                const float y = val[i] - cmp;
+                                const float t = sum + y;
+                                cmp = (t - sum) - y;
+                                sum = t;
+                            }
                     }
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (use[i]) {
-                            const float y = val[i] - cmp;
-                            const float t = sum + y;
-                            cmp = (t - sum) - y;
-                            sum = t;
-                        }
+                    if (a0c + lane < Lpad) S[a0c + lane] = sum - cmp;
                 }
-                if (a0c + lane < Lpad) S[a0c + lane] = sum - cmp;
+                for (int64_t k = lane; k < np; k += 64) {
+                    SegInfo g = {};
+                    g.u0 = u; g.nu = 1; g.v0 = v; g.nv = 1;
+                    g.a0 = lo + (int32_t)k * kPieceTicks;
+                    g.na = min(kPieceTicks, L - (int32_t)k * kPieceTicks);
+                    g.na_pad = (g.na + kAC - 1) / kAC * kAC;
+                    g.cell_off = so + k * kPieceTicks;
+                    g.event = e;
+                    g.n_pairs = 1;
+                    sw.piece[pk + k] = g;
+                    sw.pdesc[pk + k] = PieceRef{g.a0, g.na, (uint32_t)(g.cell_off / kAC), 0};
+                }
+                pk += np;
+                so += Lpad;
+                q = qe;
             }
-            for (int64_t k = lane; k < np; k += 64) {
-                SegInfo g = {};
-                g.u0 = u; g.nu = 1; g.v0 = v; g.nv = 1;
-                g.a0 = lo + (int32_t)k * kPieceTicks;
-                g.na = min(kPieceTicks, L - (int32_t)k * kPieceTicks);
-                g.na_pad = (g.na + kAC - 1) / kAC * kAC;
-                g.cell_off = so + k * kPieceTicks;
-                g.event = e;
-                g.n_pairs = 1;
-                sw.piece[pk + k] = g;
-                sw.pdesc[pk + k] = PieceRef{g.a0, g.na, (uint32_t)(g.cell_off / kAC), 0};
-            }
-            pk += np;
-            so += Lpad;
-            q = qe;
-        }
+        };
+        if (staged) column(from_lds);
+        else column(from_global);
     }
 }
 
