@@ -1693,7 +1693,9 @@ __device__ __forceinline__ uint64_t sum_key(int32_t a0, int32_t s) {
 }
 __device__ __forceinline__ int32_t key_seg(uint64_t k) { return (int32_t)(uint32_t)k; }
 
-// per segment: count the columns of its charge box that some pixel can reach
+// Segments per column.  A segment's reachable columns form a rectangle of the event's column grid, so the counts
+// come from a two-dimensional difference array: per segment +1 at the rectangle's first corner and -1 / -1 / +1 at the
+// corners one past it (those outside the grid dropped), then prefix sums along each row and down each grid column.
 __global__ void k_sum_ranges(DevParams P, const SegInfo *si, int64_t n_seg, SumWork sw) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n_seg) return;
@@ -1701,29 +1703,88 @@ __global__ void k_sum_ranges(DevParams P, const SegInfo *si, int64_t n_seg, SumW
     if (g.flags & (SEG_INVALID | SEG_TOO_LONG)) return;
     const int32_t u_a = max(g.u0, sw.UL), u_b = min(g.u0 + g.nu - 1, sw.UL + sw.CU - 1);
     const int32_t v_a = max(g.v0, sw.VL), v_b = min(g.v0 + g.nv - 1, sw.VL + sw.CV - 1);
-    const int64_t base = (int64_t)g.event * sw.CU * sw.CV;
-    for (int32_t u = u_a; u <= u_b; ++u)
-        for (int32_t v = v_a; v <= v_b; ++v)
-            atomicAdd((unsigned long long *)&sw.col_seg_off[base + (int64_t)(u - sw.UL) * sw.CV + (v - sw.VL)], 1ull);
+    if (u_a > u_b || v_a > v_b) return;
+    unsigned long long *cnt = (unsigned long long *)sw.col_seg_off + (int64_t)g.event * sw.CU * sw.CV;
+    const int32_t ua = u_a - sw.UL, ub = u_b - sw.UL + 1, va = v_a - sw.VL, vb = v_b - sw.VL + 1;
+    atomicAdd(&cnt[(int64_t)ua * sw.CV + va], 1ull);
+    if (vb < sw.CV) atomicAdd(&cnt[(int64_t)ua * sw.CV + vb], ~0ull);          // -1
+    if (ub < sw.CU) {
+        atomicAdd(&cnt[(int64_t)ub * sw.CV + va], ~0ull);
+        if (vb < sw.CV) atomicAdd(&cnt[(int64_t)ub * sw.CV + vb], 1ull);
+    }
+}
+
+// inclusive prefix sums along each row of the column grids (one wavefront per row of len values)
+__global__ __launch_bounds__(kWG) void k_prefix_rows(int64_t *a, int64_t n_rows, int32_t len) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (row >= n_rows) return;
+    int64_t *r = a + row * len, carry = 0;
+    for (int32_t c0 = 0; c0 < len; c0 += 64) {
+        int64_t x = c0 + lane < len ? r[c0 + lane] : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t y = __shfl_up(x, d);
+            if (lane >= d) x += y;
+        }
+        x += carry;
+        if (c0 + lane < len) r[c0 + lane] = x;
+        carry = __shfl(x, 63);
+    }
+}
+
+// inclusive prefix sums down each grid column (thread per (event, v); eight rows loaded ahead)
+__global__ void k_prefix_cols(int64_t *a, int32_t n_ev, int32_t CU, int32_t CV) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n_ev * CV) return;
+    const int64_t ev = t / CV, v = t - ev * CV;
+    int64_t *p = a + ev * CU * CV + v, run = 0;
+    int32_t u = 0;
+    for (; u + 8 <= CU; u += 8) {
+        int64_t x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = p[(int64_t)(u + i) * CV];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            run += x[i];
+            p[(int64_t)(u + i) * CV] = run;
+        }
+    }
+    for (; u < CU; ++u) {
+        run += p[(int64_t)u * CV];
+        p[(int64_t)u * CV] = run;
+    }
 }
 
 void launch_sum_ranges(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st) {
     if (w.n_seg > 0) k_sum_ranges<<<(unsigned)((w.n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.n_seg, sw);
+    const int64_t n_ev = sw.n_cols / ((int64_t)sw.CU * sw.CV);
+    const int64_t rows = n_ev * sw.CU;
+    if (rows > 0) {
+        k_prefix_rows<<<(unsigned)((rows + kWG / 64 - 1) / (kWG / 64)), kWG, 0, st>>>(sw.col_seg_off, rows, sw.CV);
+        k_prefix_cols<<<(unsigned)((n_ev * sw.CV + kWG - 1) / kWG), kWG, 0, st>>>(sw.col_seg_off, (int32_t)n_ev, sw.CU,
+                                                                                  sw.CV);
+    }
 }
 
-__global__ void k_sum_fill(DevParams P, const SegInfo *si, int64_t n_seg, SumWork sw) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// per segment (one wavefront, lanes over its reachable columns: every atomic instruction meets distinct cursors)
+__global__ __launch_bounds__(kWG) void k_sum_fill(DevParams P, const SegInfo *si, int64_t n_seg, SumWork sw) {
+    const int lane = threadIdx.x & 63;
+    const int64_t s = (int64_t)blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (s >= n_seg) return;
     const SegInfo &g = si[s];
     if (g.flags & (SEG_INVALID | SEG_TOO_LONG)) return;
     const int32_t u_a = max(g.u0, sw.UL), u_b = min(g.u0 + g.nu - 1, sw.UL + sw.CU - 1);
     const int32_t v_a = max(g.v0, sw.VL), v_b = min(g.v0 + g.nv - 1, sw.VL + sw.CV - 1);
-    const int64_t base = (int64_t)g.event * sw.CU * sw.CV;
-    for (int32_t u = u_a; u <= u_b; ++u)
-        for (int32_t v = v_a; v <= v_b; ++v) {
-            const int64_t c = base + (int64_t)(u - sw.UL) * sw.CV + (v - sw.VL);
-            sw.col_tmp[sw.col_seg_off[c] + atomicAdd(&sw.col_cursor[c], 1)] = sum_key(g.a0, (int32_t)s);
-        }
+    if (u_a > u_b || v_a > v_b) return;
+    const int32_t wv = v_b - v_a + 1, nc = (u_b - u_a + 1) * wv;
+    const int64_t base = (int64_t)g.event * sw.CU * sw.CV + (int64_t)(u_a - sw.UL) * sw.CV + (v_a - sw.VL);
+    const uint64_t key = sum_key(g.a0, (int32_t)s);
+    for (int32_t i = lane; i < nc; i += 64) {
+        const int32_t du = i / wv;
+        const int64_t c = base + (int64_t)du * sw.CV + (i - du * wv);
+        sw.col_tmp[sw.col_seg_off[c] + atomicAdd(&sw.col_cursor[c], 1)] = key;
+    }
 }
 
 // A column's charge is cut where none of its segments has charge for more than kSumGap ticks: the zero ticks of
@@ -1869,7 +1930,8 @@ __global__ __launch_bounds__(kWG) void k_sum_columns(int32_t align_res, const Se
 }
 
 void launch_sum_fill(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st) {
-    if (w.n_seg > 0) k_sum_fill<<<(unsigned)((w.n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, w.si, w.n_seg, sw);
+    if (w.n_seg > 0)
+        k_sum_fill<<<(unsigned)((w.n_seg + kWG / 64 - 1) / (kWG / 64)), kWG, 0, st>>>(P, w.si, w.n_seg, sw);
     k_sum_columns<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(sw.align_res, w.si, sw);
 }
 
