@@ -294,6 +294,32 @@ def test_stacked_tracks_summed_batch_equals_single(lt, torch):
         assert np.array_equal(b["current"][po[e]:po[e + 1]], s["current"])
 
 
+def _drift_parallel_track_workload():
+    """A track along the drift direction (10 cm of drift at almost fixed x and y, 834 segments of 120 um) plus a short
+    one beside it: each sub-pixel column under the long track holds several hundred segments whose charge forms one
+    interval of ~625 ticks, cut into several pieces; the column sort, the interval scan and the summed charges take
+    their long-list paths there (more than 64 and more than 256 segments per column)."""
+    rng = np.random.default_rng(47)
+    w = W.config(1)
+    parts = []
+    for (x0, x1), (y0, y1), (z0, z1), n in (((15.30, 15.34), (15.10, 15.13), (4.0, 14.0), 834),
+                                            ((17.0, 17.6), (15.1, 15.2), (6.0, 6.05), 6)):
+        s = np.arange(n + 1) / n
+        pts = np.stack([x0 + s * (x1 - x0), y0 + s * (y1 - y0), z0 + s * (z1 - z0)], 1)
+        L = np.linalg.norm(np.diff(pts, axis=0), axis=1)
+        parts.append(W.make_segments(pts[:-1], pts[1:], W.mip_dedx(rng, n) * L, t0=np.zeros(n), t1=np.zeros(n)))
+    w.events, w.event_ids = [W.Segments.concat(parts)], [33]
+    return w
+
+
+@pytest.mark.parametrize("mode,rt", [(0, 0), (2, 0), (2, 8)])
+def test_drift_parallel_track_parity(lt, orc, torch, mode, rt):
+    h, r, e, (cmp_, flg) = check_event(lt, orc, _drift_parallel_track_workload(), mode=mode, rt=rt)
+    print(f"drift-parallel track mode={mode} rt={rt}: pixels {len(r['pixels'])} max e_p {e.max():.2e} "
+          f"packets compared {cmp_}")
+    assert cmp_ > 20
+
+
 def test_calls_on_two_streams_do_not_race(lt, torch):
     """Consecutive calls on one context given different streams, with no host synchronisation between their
     device work, give the results of separate synchronised calls (each call waits for the previous one's work on
