@@ -1701,6 +1701,7 @@ __global__ void k_sum_ranges(DevParams P, const SegInfo *si, int64_t n_seg, SumW
     if (s >= n_seg) return;
     const SegInfo &g = si[s];
     if (g.flags & (SEG_INVALID | SEG_TOO_LONG)) return;
+    sw.segc[s] = SumSeg{g.a0, g.na, g.u0, g.v0, g.nv, g.na_pad, g.cell_off};
     const int32_t u_a = max(g.u0, sw.UL), u_b = min(g.u0 + g.nu - 1, sw.UL + sw.CU - 1);
     const int32_t v_a = max(g.v0, sw.VL), v_b = min(g.v0 + g.nv - 1, sw.VL + sw.CV - 1);
     if (u_a > u_b || v_a > v_b) return;
@@ -1868,7 +1869,7 @@ __global__ __launch_bounds__(kWG) void k_sum_columns(int32_t align_res, const Se
             // the lengths are loaded before the sort and travel with their keys to the lanes of their ranks
             const bool mine = lane < n;
             const uint64_t x = mine ? in[lb + lane] : ~0ull;
-            const int32_t na = mine ? si[key_seg(x)].na : 0;
+            const int32_t na = mine ? sw.segc[key_seg(x)].na : 0;
             int32_t rank = 0;
             for (int j = 0; j < (int)n; ++j) rank += lane_u64(x, j) < x;
             if (!mine) rank = lane;
@@ -1900,7 +1901,7 @@ __global__ __launch_bounds__(kWG) void k_sum_columns(int32_t align_res, const Se
                 if (mine) {
                     const uint64_t x = seg[lb + i0 + lane];
                     a0 = key_a0(x);
-                    end = a0 + si[key_seg(x)].na - 1;
+                    end = a0 + sw.segc[key_seg(x)].na - 1;
                 }
                 chunk(i0, mine, a0, end);
             }
@@ -1956,8 +1957,10 @@ struct SumRec {
 };
 __global__ __launch_bounds__(kWG) void k_sum_pieces(DevParams P, const SegInfo *si, const float *cells, SumWork sw) {
     __shared__ SumRec stage_all[kWG / 64][kPieceStage];
+    __shared__ int32_t rmax_all[kWG / 64][kPieceStage];
     const int lane = threadIdx.x & 63;
     SumRec *rs = stage_all[threadIdx.x >> 6];
+    int32_t *rmax = rmax_all[threadIdx.x >> 6];       // last tick of entries 0 .. k (a running maximum)
     const int32_t res = sw.align_res;
     const uint32_t n_act = *sw.n_active;
     const uint32_t waves = gridDim.x * (kWG / 64);
@@ -1974,15 +1977,52 @@ __global__ __launch_bounds__(kWG) void k_sum_pieces(DevParams P, const SegInfo *
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint64_t smask[kPieceStage / 64] = {};            // interval starts among the staged entries
         if (staged) {
-            for (int64_t k = lane; k < n; k += 64) {
-                const SegInfo &g = si[key_seg(sw.col_seg[sb + k])];
-                rs[k] = SumRec{g.a0, g.na, g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad - g.a0};
+            // records, and the interval starts by the rule k_sum_columns counts by (first tick more than kSumGap
+            // beyond the running maximum of the earlier last ticks)
+            int32_t carry = INT32_MIN;
+#pragma unroll
+            for (int w = 0; w < kPieceStage / 64; ++w) {
+                if (64 * w >= n) break;
+                const int64_t k = 64 * w + lane;
+                const bool mine = k < n;
+                int32_t a0 = 0, end = INT32_MIN;
+                if (mine) {
+                    const SumSeg g = sw.segc[key_seg(sw.col_seg[sb + k])];
+                    a0 = g.a0;
+                    end = g.a0 + g.na - 1;
+                    rs[k] = SumRec{g.a0, g.na, g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad - g.a0};
+                }
+                int32_t incl = end;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int32_t y = __shfl_up(incl, d);
+                    if (lane >= d) incl = max(incl, y);
+                }
+                incl = max(incl, carry);
+                int32_t excl = __shfl_up(incl, 1);
+                if (lane == 0) excl = carry;
+                smask[w] = __ballot(mine && (k == 0 || (int64_t)a0 - excl - 1 > kSumGap));
+                if (mine) rmax[k] = incl;
+                carry = __shfl(incl, 63);
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+        // the interval starting at entry q of a staged list: its end entry qe (the next start) and last tick
+        auto staged_interval = [&](int64_t q, int64_t &qe, int32_t &hi) {
+            qe = n;
+            for (int w = (int)((q + 1) >> 6); w < kPieceStage / 64 && 64 * w < n; ++w) {
+                const uint64_t m = smask[w] & (((q + 1) >> 6) == w ? ~0ull << ((q + 1) & 63) : ~0ull);
+                if (m) {
+                    qe = 64 * w + __builtin_ctzll(m);
+                    break;
+                }
+            }
+            hi = __builtin_amdgcn_readfirstlane(rmax[qe - 1]);
+        };
         auto from_lds = [&](int64_t k, int32_t &a0, int32_t &na, int64_t &base) {
             const SumRec x = rs[k];                         // the same address in every lane: a broadcast read
             a0 = __builtin_amdgcn_readfirstlane(x.a0);
@@ -1991,12 +2031,12 @@ __global__ __launch_bounds__(kWG) void k_sum_pieces(DevParams P, const SegInfo *
                              (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x.base));
         };
         auto from_global = [&](int64_t k, int32_t &a0, int32_t &na, int64_t &base) {
-            const SegInfo &g = si[key_seg(sw.col_seg[sb + k])];
+            const SumSeg g = sw.segc[key_seg(sw.col_seg[sb + k])];
             a0 = g.a0;
             na = g.na;
             base = g.cell_off + ((int64_t)(u - g.u0) * g.nv + (v - g.v0)) * g.na_pad - g.a0;
         };
-        auto column = [&](auto seg_at) {
+        auto column = [&](auto seg_at, bool scanned) {
             for (int64_t q = 0; q < n;) {
                 // the merged interval starting at list entry q (the rule k_sum_columns counts by)
                 int32_t lo, hi, a0, na;
@@ -2005,10 +2045,14 @@ __global__ __launch_bounds__(kWG) void k_sum_pieces(DevParams P, const SegInfo *
                 lo = a0;
                 hi = a0 + na - 1;
                 int64_t qe = q + 1;
-                for (; qe < n; ++qe) {
-                    seg_at(qe, a0, na, base);
-                    if (a0 - hi - 1 > kSumGap) break;
-                    hi = max(hi, a0 + na - 1);
+                if (scanned) {
+                    staged_interval(q, qe, hi);
+                } else {
+                    for (; qe < n; ++qe) {
+                        seg_at(qe, a0, na, base);
+                        if (a0 - hi - 1 > kSumGap) break;
+                        hi = max(hi, a0 + na - 1);
+                    }
                 }
                 if (res >= 0) lo -= ((lo - res) % 8 + 8) % 8;
                 const int32_t L = hi - lo + 1;
@@ -2023,7 +2067,7 @@ __global__ __launch_bounds__(kWG) void k_sum_pieces(DevParams P, const SegInfo *
                     for (int64_t k0 = q; k0 < qe && !past; k0 += 8) {
                         float val[8];
                         bool use[8];
-    #pragma unroll
+#pragma unroll
                         for (int i = 0; i < 8; ++i) {
                             use[i] = false;
                             val[i] = 0.0f;
@@ -2036,7 +2080,7 @@ __global__ __launch_bounds__(kWG) void k_sum_pieces(DevParams P, const SegInfo *
                                 }
                             }
                         }
-    #pragma unroll
+#pragma unroll
                         for (int i = 0; i < 8; ++i)
                             if (use[i]) {
                                 const float y = val[i] - cmp;
@@ -2064,8 +2108,8 @@ __global__ __launch_bounds__(kWG) void k_sum_pieces(DevParams P, const SegInfo *
                 q = qe;
             }
         };
-        if (staged) column(from_lds);
-        else column(from_global);
+        if (staged) column(from_lds, true);
+        else column(from_global, false);
     }
 }
 
@@ -2266,12 +2310,20 @@ __global__ __launch_bounds__(kWG) void k_sum_merge(int64_t n_slots, SumWork sw) 
                                               (uint32_t)__builtin_amdgcn_readlane((int)moff, i));
                 for (int32_t t0 = 0; t0 < lp; t0 += 64) {
                     float v = 0.0f;
-                    for (int32_t k = i; k < ke; ++k) {  // members in list order
-                        const int32_t ma = __builtin_amdgcn_readlane(r.a0, k);
-                        const int32_t mn = __builtin_amdgcn_readlane(r.na, k);
-                        const uint32_t mc = (uint32_t)__builtin_amdgcn_readlane((int)r.cell8, k);
-                        const int32_t o = lo + t0 + lane - ma;
-                        if (o >= 0 && o < mn) v += sw.S[(int64_t)mc * kAC + o];
+                    for (int32_t k0 = i; k0 < ke; k0 += 4) {  // members in list order, four loads in flight
+                        float x[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            x[q] = 0.0f;
+                            const int32_t k = min(k0 + q, 63);
+                            const int32_t ma = __builtin_amdgcn_readlane(r.a0, k);
+                            const int32_t mn = __builtin_amdgcn_readlane(r.na, k);
+                            const uint32_t mc = (uint32_t)__builtin_amdgcn_readlane((int)r.cell8, k);
+                            const int32_t o = lo + t0 + lane - ma;
+                            if (k0 + q < ke && o >= 0 && o < mn) x[q] = sw.S[(int64_t)mc * kAC + o];
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) v += x[q];  // adding an exact zero leaves v unchanged
                     }
                     if (t0 + lane < lp) sw.Sm[off + t0 + lane] = v;
                 }
@@ -2622,16 +2674,23 @@ int32_t summed_align_res(const DevParams &P, int32_t rt, bool shift) {
 
 // Largest-first order of the pixels for the summed induction (the same log-bucketed order as the per-pair kernel's;
 // all tiles of a pixel stay together): work of a pixel = the cell-tick blocks of its pieces.
-__global__ void k_slot_work_summed(const PieceRef *__restrict__ rec, const int64_t *__restrict__ list_off,
-                                   int64_t n_slots, int32_t *__restrict__ bucket, int32_t *__restrict__ hist) {
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kWG) void k_slot_work_summed(const PieceRef *__restrict__ rec,
+                                                          const int64_t *__restrict__ list_off, int64_t n_slots,
+                                                          int32_t *__restrict__ bucket, int32_t *__restrict__ hist) {
+    const int lane = threadIdx.x & 63;                  // one wavefront per pixel, lanes over its records
+    const int64_t slot = (int64_t)blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (slot >= n_slots) return;
-    double work = 0.0;
-    for (int64_t q = list_off[slot]; q < list_off[slot + 1]; ++q) work += (double)((rec[q].na + kAC - 1) / kAC);
-    const int32_t lg = work >= 1.0 ? (int32_t)(16.0 * log2(work)) : 0;
-    const int32_t b = kOrderBuckets - 1 - min(lg, kOrderBuckets - 1);
-    bucket[slot] = b;
-    atomicAdd(&hist[b], 1);
+    int64_t blocks = 0;                                 // an integer sum: the same in any order
+    for (int64_t q = list_off[slot] + lane; q < list_off[slot + 1]; q += 64) blocks += (rec[q].na + kAC - 1) / kAC;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) blocks += __shfl_xor(blocks, o);
+    if (lane == 0) {
+        const double work = (double)blocks;
+        const int32_t lg = work >= 1.0 ? (int32_t)(16.0 * log2(work)) : 0;
+        const int32_t b = kOrderBuckets - 1 - min(lg, kOrderBuckets - 1);
+        bucket[slot] = b;
+        atomicAdd(&hist[b], 1);
+    }
 }
 
 const int32_t *launch_summed_order(const Work &w, const SumWork &sw, int64_t n_slots, int32_t rt, bool shift,
@@ -2640,7 +2699,8 @@ const int32_t *launch_summed_order(const Work &w, const SumWork &sw, int64_t n_s
     int32_t *ord = w.order, *bucket = ord + n_slots, *hist = bucket + n_slots, *cursor = hist + kOrderBuckets;
     launch_zero(hist, (int64_t)sizeof(int32_t) * kOrderBuckets, st);
     const unsigned gs = (unsigned)((n_slots + kWG - 1) / kWG);
-    k_slot_work_summed<<<gs, kWG, 0, st>>>(sw.mrec, sw.mlist_off, n_slots, bucket, hist);
+    k_slot_work_summed<<<(unsigned)((n_slots + kWG / 64 - 1) / (kWG / 64)), kWG, 0, st>>>(sw.mrec, sw.mlist_off, n_slots,
+                                                                                         bucket, hist);
     k_order_offsets<<<1, kWG, 0, st>>>(hist, cursor);
     k_order_scatter<<<gs, kWG, 0, st>>>(bucket, n_slots, cursor, ord);
     return ord;

@@ -60,9 +60,18 @@ struct alignas(16) PieceRef {
     int32_t bin;
 };
 
+// The fields of a segment that the column passes read for every (segment, column) entry, 32 bytes (the full record is
+// 176): a spill's array stays in the last-level cache.
+struct alignas(16) SumSeg {
+    int32_t a0, na, u0, v0, nv, na_pad;
+    int64_t cell_off;
+};
+static_assert(sizeof(SumSeg) == 32, "SumSeg layout");
+
 struct SumWork {
     int32_t CU = 0, CV = 0, UL = 0, VL = 0;
     int64_t n_cols = 0;                      // n_ev * CU * CV
+    SumSeg *segc = nullptr;                  // [n_seg] written by the count pass
     int64_t *col_seg_off = nullptr;          // [n_cols + 1] segments per column, then offsets
     int32_t *col_cursor = nullptr;           // [n_cols]
     uint64_t *col_tmp = nullptr;             // [n_col_seg] per column: keys (first tick << 32 | segment index)

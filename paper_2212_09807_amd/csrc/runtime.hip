@@ -59,6 +59,7 @@ struct lts_context {
     bool has_mask = false;
     DevBuf col_seg_off, col_cursor, col_seg, col_tmp, piece_off, s_off, piece, pdesc, S, list_off, list, rec;
     DevBuf mlist_off, m_off, mrec, Sm;          // the mirror-merged records of the summed induction
+    DevBuf segc;                                // compact segment fields for the column passes
     DevParams P{};
     bool has_table = false;
     DevBuf Rpad, prefix;
@@ -239,7 +240,7 @@ constexpr lts_status kNotAdmitted = LTS_ERR_NOT_READY;
 std::vector<DevBuf *> pool_buffers(lts_context *c) {
     return {&c->ev_cnt, &c->mask, &c->col_seg_off, &c->col_cursor, &c->col_seg, &c->col_tmp, &c->piece_off,
             &c->s_off, &c->piece, &c->pdesc, &c->S, &c->list_off, &c->list, &c->rec, &c->mlist_off, &c->m_off,
-            &c->mrec, &c->Sm, &c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off, &c->pix_cnt, &c->cursor,
+            &c->mrec, &c->Sm, &c->segc, &c->part, &c->Rpad, &c->prefix, &c->si, &c->cell_off, &c->pix_cnt, &c->cursor,
             &c->pix_slot, &c->slot_gp, &c->slot_off, &c->pairs_u, &c->pairs, &c->cells, &c->pk_tick, &c->pk_adc,
             &c->pk_flag, &c->pk_off, &c->hdr, &c->scan_tmp, &c->ev_off, &c->ev_ids, &c->report_tmp, &c->counts_tmp,
             &c->red_head, &c->red_start, &c->order};
@@ -454,9 +455,11 @@ SumWork summed_grid(const DevParams &P, int32_t n_ev) {
 }
 
 // Buffers of the summed induction whose sizes the sizing pass already fixes (column lists, offsets, pixel lists).
-void summed_needs(lts_context *c, const DevHeader &h, int64_t n_slots, int32_t n_ev, std::vector<Need> &needs) {
+void summed_needs(lts_context *c, const DevHeader &h, int64_t n_slots, int32_t n_ev, int64_t n_seg,
+                  std::vector<Need> &needs) {
     const SumWork sw = summed_grid(c->P, n_ev);
     const int64_t nc1 = sw.n_cols + 1;
+    needs.push_back({&c->segc, sizeof(SumSeg) * (size_t)std::max<int64_t>(n_seg, 1)});
     needs.push_back({&c->col_seg_off, sizeof(int64_t) * (size_t)nc1});
     needs.push_back({&c->col_cursor, sizeof(int32_t) * (size_t)sw.n_cols});
     needs.push_back({&c->col_seg, sizeof(uint64_t) * (size_t)std::max<int64_t>(h.n_colseg, 1)});
@@ -477,6 +480,7 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     const int64_t nc1 = sw.n_cols + 1;
     if (sw.n_cols > (int64_t)INT32_MAX)
         return fail(c, LTS_ERR_INVALID_ARG, "summed induction: events x sub-pixel columns exceeds 2^31 - 1");
+    sw.segc = as<SumSeg>(c->segc);
     sw.col_seg_off = as<int64_t>(c->col_seg_off);
     sw.col_cursor = as<int32_t>(c->col_cursor);
     sw.col_seg = as<uint64_t>(c->col_seg);
@@ -662,7 +666,7 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
         {&c->pk_off, sizeof(int64_t) * (size_t)(n_slots + 1)},
         {&c->scan_tmp, sizeof(int64_t) * (size_t)scan_tmp_needed(n_slots + 1)},
         {&c->order, sizeof(int32_t) * (size_t)(2 * n_slots + 2 * kOrderBuckets)}};
-    if (c->reduce_mode == LTS_REDUCE_SUMMED) summed_needs(c, h, n_slots, n_ev, needs);
+    if (c->reduce_mode == LTS_REDUCE_SUMMED) summed_needs(c, h, n_slots, n_ev, w.n_seg, needs);
     if (c->reduce_mode == LTS_REDUCE_SORTED && c->induce_slices > 1 && n_slots > 0) {
         const int64_t row_bytes = (int64_t)c->induce_slices * c->P.nticks * (int64_t)sizeof(float);
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_slots, (1ll << 30) / row_bytes));
