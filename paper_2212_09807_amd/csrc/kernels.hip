@@ -293,9 +293,18 @@ __global__ __launch_bounds__(kWG) void k_quench_drift(DevParams P, SegArrays S, 
         if (!skip) atomicAdd((unsigned long long *)&H->n_colseg, (unsigned long long)g.nu * g.nv);
         if (g.flags & SEG_INVALID) atomicOr(&H->status, ST_INVALID);
         if (g.flags & SEG_TOO_LONG) atomicOr(&H->status, ST_TOO_LONG);
-        uint64_t *pc = pix_cnt + (int64_t)e * P.npx;
-        for (int32_t iy = g.iy0; iy <= g.iy1; ++iy)
-            for (int32_t ix = g.ix0; ix <= g.ix1; ++ix) atomicAdd((unsigned long long *)&pc[iy * P.nx + ix], 1ull);
+        // pairs per pixel: the reach is a rectangle of the event's pixel grid, counted by a difference array (+1 at
+        // its first corner, -1 / -1 / +1 one past it; prefix sums along the rows and down the columns follow)
+        if (g.ix1 >= g.ix0 && g.iy1 >= g.iy0) {
+            unsigned long long *pc = (unsigned long long *)pix_cnt + (int64_t)e * P.npx;
+            const int32_t xb = g.ix1 + 1, yb = g.iy1 + 1;
+            atomicAdd(&pc[g.iy0 * P.nx + g.ix0], 1ull);
+            if (xb < P.nx) atomicAdd(&pc[g.iy0 * P.nx + xb], ~0ull);
+            if (yb < P.ny) {
+                atomicAdd(&pc[yb * P.nx + g.ix0], ~0ull);
+                if (xb < P.nx) atomicAdd(&pc[yb * P.nx + xb], 1ull);
+            }
+        }
     }
     add_report(report, e, 0, valid ? (double)g.q_r : 0.0, valid);
     add_report(report, e, 1, valid ? (double)g.q_a : 0.0, valid);
@@ -317,11 +326,60 @@ __global__ void k_totals(const uint64_t *pix_off, int64_t n_gp, const int64_t *c
     H->n_cells = cell_off[n_seg];
 }
 
+// inclusive prefix sums along each row of a set of grids (one wavefront per row of len values)
+__global__ __launch_bounds__(kWG) void k_prefix_rows(int64_t *a, int64_t n_rows, int32_t len) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (row >= n_rows) return;
+    int64_t *r = a + row * len, carry = 0;
+    for (int32_t c0 = 0; c0 < len; c0 += 64) {
+        int64_t x = c0 + lane < len ? r[c0 + lane] : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t y = __shfl_up(x, d);
+            if (lane >= d) x += y;
+        }
+        x += carry;
+        if (c0 + lane < len) r[c0 + lane] = x;
+        carry = __shfl(x, 63);
+    }
+}
+
+// inclusive prefix sums down each column of n_ev grids of CU rows x CV values (thread per (grid, v); eight
+// rows loaded ahead)
+__global__ void k_prefix_cols(int64_t *a, int32_t n_ev, int32_t CU, int32_t CV) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n_ev * CV) return;
+    const int64_t ev = t / CV, v = t - ev * CV;
+    int64_t *p = a + ev * CU * CV + v, run = 0;
+    int32_t u = 0;
+    for (; u + 8 <= CU; u += 8) {
+        int64_t x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = p[(int64_t)(u + i) * CV];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            run += x[i];
+            p[(int64_t)(u + i) * CV] = run;
+        }
+    }
+    for (; u < CU; ++u) {
+        run += p[(int64_t)u * CV];
+        p[(int64_t)u * CV] = run;
+    }
+}
+
 void launch_quench_drift(const DevParams &P, const SegArrays &S, const Work &w, hipStream_t st) {
     const int64_t n_gp = (int64_t)w.n_ev * P.npx;
     if (w.n_seg > 0)
         k_quench_drift<<<(unsigned)((w.n_seg + kWG - 1) / kWG), kWG, 0, st>>>(P, S, w.n_seg, w.seg_ev_off, w.n_ev, w.si,
                                                                             w.cell_off, w.pix_cnt, w.hdr, w.report);
+    if (n_gp > 0) {
+        const int64_t rows = (int64_t)w.n_ev * P.ny;
+        k_prefix_rows<<<(unsigned)((rows + kWG / 64 - 1) / (kWG / 64)), kWG, 0, st>>>((int64_t *)w.pix_cnt, rows, P.nx);
+        k_prefix_cols<<<(unsigned)(((int64_t)w.n_ev * P.nx + kWG - 1) / kWG), kWG, 0, st>>>((int64_t *)w.pix_cnt,
+                                                                                           w.n_ev, P.ny, P.nx);
+    }
     k_mark_active<<<(unsigned)((n_gp + kWG - 1) / kWG), kWG, 0, st>>>(w.pix_cnt, n_gp);
     scan_exclusive<unsigned long long>((unsigned long long *)w.pix_cnt, n_gp + 1, w.scan_tmp, st);
     scan_exclusive<int64_t>(w.cell_off, w.n_seg + 1, w.scan_tmp, st);
@@ -1712,48 +1770,6 @@ __global__ void k_sum_ranges(DevParams P, const SegInfo *si, int64_t n_seg, SumW
     if (ub < sw.CU) {
         atomicAdd(&cnt[(int64_t)ub * sw.CV + va], ~0ull);
         if (vb < sw.CV) atomicAdd(&cnt[(int64_t)ub * sw.CV + vb], 1ull);
-    }
-}
-
-// inclusive prefix sums along each row of the column grids (one wavefront per row of len values)
-__global__ __launch_bounds__(kWG) void k_prefix_rows(int64_t *a, int64_t n_rows, int32_t len) {
-    const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    if (row >= n_rows) return;
-    int64_t *r = a + row * len, carry = 0;
-    for (int32_t c0 = 0; c0 < len; c0 += 64) {
-        int64_t x = c0 + lane < len ? r[c0 + lane] : 0;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int64_t y = __shfl_up(x, d);
-            if (lane >= d) x += y;
-        }
-        x += carry;
-        if (c0 + lane < len) r[c0 + lane] = x;
-        carry = __shfl(x, 63);
-    }
-}
-
-// inclusive prefix sums down each grid column (thread per (event, v); eight rows loaded ahead)
-__global__ void k_prefix_cols(int64_t *a, int32_t n_ev, int32_t CU, int32_t CV) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)n_ev * CV) return;
-    const int64_t ev = t / CV, v = t - ev * CV;
-    int64_t *p = a + ev * CU * CV + v, run = 0;
-    int32_t u = 0;
-    for (; u + 8 <= CU; u += 8) {
-        int64_t x[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) x[i] = p[(int64_t)(u + i) * CV];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            run += x[i];
-            p[(int64_t)(u + i) * CV] = run;
-        }
-    }
-    for (; u < CU; ++u) {
-        run += p[(int64_t)u * CV];
-        p[(int64_t)u * CV] = run;
     }
 }
 
