@@ -1826,8 +1826,8 @@ __device__ __forceinline__ uint64_t lane_u64(uint64_t v, int j) {
 // padded summed-charge length of its merged tick intervals.  For the 512-tick summed induction kernel every
 // interval's first tick is moved down to the residue it chooses (it makes every lane's table offsets aligned there);
 // the 256-tick kernel takes intervals as they are (align_res < 0).  The order depends only on the segments' charge
-// boxes and their order within the event, so the sums are the same in a batch and alone.  One wavefront per 64
-// consecutive columns; the wavefront takes its non-empty columns one after another.  Sort by ranks (a key's place is
+// boxes and their order within the event, so the sums are the same in a batch and alone.  The columns with segments
+// are listed first (k_sum_active); persistent wavefronts take them one at a time.  Sort by ranks (a key's place is
 // the number of smaller keys; keys are unique): lane i holds key i of a 64-key chunk and compares it with every key
 // of the list, taken chunk by chunk from the lanes' registers.  Intervals from the sorted list, 64 entries at a time:
 // an entry starts an interval when its first tick lies more than kSumGap ticks beyond the last tick of every earlier
@@ -1840,22 +1840,49 @@ __device__ __forceinline__ void interval_count(int32_t lo, int32_t hi, int32_t r
     np += n;
     ns += m;
 }
+// columns with segments, listed in any order (one atomic per wavefront of kActiveSpan columns); the others get zero
+// counts
+constexpr int kActiveSpan = 512;
+__global__ __launch_bounds__(kWG) void k_sum_active(SumWork sw) {
+    const int lane = threadIdx.x & 63;
+    const int64_t c0 = ((int64_t)blockIdx.x * (kWG / 64) + (threadIdx.x >> 6)) * kActiveSpan;
+    uint64_t act[kActiveSpan / 64];
+    uint32_t total = 0;
+#pragma unroll
+    for (int i = 0; i < kActiveSpan / 64; ++i) {
+        const int64_t c = c0 + 64 * i + lane;
+        bool has = false;
+        if (c < sw.n_cols) {
+            has = sw.col_seg_off[c + 1] > sw.col_seg_off[c];
+            if (!has) {
+                sw.piece_off[c] = 0;
+                sw.s_off[c] = 0;
+            }
+        }
+        act[i] = __ballot(has);
+        total += (uint32_t)__builtin_popcountll(act[i]);
+    }
+    uint32_t base = 0;
+    if (total && lane == 0) base = atomicAdd(sw.n_active, total);
+    base = __shfl(base, 0);
+#pragma unroll
+    for (int i = 0; i < kActiveSpan / 64; ++i) {
+        if ((act[i] >> lane) & 1ull)
+            sw.active[base + __builtin_popcountll(act[i] & ((1ull << lane) - 1ull))] = (int32_t)(c0 + 64 * i + lane);
+        base += (uint32_t)__builtin_popcountll(act[i]);
+    }
+}
+
 __global__ __launch_bounds__(kWG) void k_sum_columns(int32_t align_res, const SegInfo *__restrict__ si, SumWork sw) {
     const int lane = threadIdx.x & 63;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t b = 0, e = 0;
-    if (c < sw.n_cols) {
-        b = sw.col_seg_off[c];
-        e = sw.col_seg_off[c + 1];
-    }
     const uint64_t *__restrict__ in = sw.col_tmp;
     uint64_t *seg = sw.col_seg;
-    uint64_t todo = __ballot(e > b);
-    uint64_t act = 0;                                   // the wavefront's columns with pieces
-    while (todo) {
-        const int l = __ffsll((unsigned long long)todo) - 1;
-        todo &= todo - 1;
-        const int64_t lb = __shfl(b, l), n = __shfl(e, l) - lb;
+    const uint32_t n_act = *sw.n_active;
+    const uint32_t waves = gridDim.x * (kWG / 64);
+    for (uint32_t ia = blockIdx.x * (kWG / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); ia < n_act;
+         ia += waves) {
+        const int64_t cc = __builtin_amdgcn_readfirstlane(sw.active[ia]);
+        const int64_t lb = sw.col_seg_off[cc], n = sw.col_seg_off[cc + 1] - lb;
         int32_t run_hi = 0, cur_lo = 0;                 // last tick of every entry so far; first tick of the open interval
         int64_t np = 0, ns = 0;                         // this lane's share of the column's counts
         // one 64-entry chunk of the sorted list: (first tick, last tick) of entry i0 + lane where `mine`
@@ -1928,28 +1955,19 @@ __global__ __launch_bounds__(kWG) void k_sum_columns(int32_t align_res, const Se
             np += __shfl_xor(np, o);
             ns += __shfl_xor(ns, o);
         }
-        if (lane == l) {
-            sw.piece_off[c] = np;
-            sw.s_off[c] = ns;
+        if (lane == 0) {
+            sw.piece_off[cc] = np;
+            sw.s_off[cc] = ns;
         }
-        if (np) act |= 1ull << l;
     }
-    // columns without segments
-    if (c < sw.n_cols && e <= b) {
-        sw.piece_off[c] = 0;
-        sw.s_off[c] = 0;
-    }
-    // the active list, one atomic per wavefront (any order: a column's outputs have fixed places)
-    uint32_t base = 0;
-    if (act && lane == 0) base = atomicAdd(sw.n_active, (uint32_t)__builtin_popcountll(act));
-    base = __shfl(base, 0);
-    if ((act >> lane) & 1ull) sw.active[base + __builtin_popcountll(act & ((1ull << lane) - 1ull))] = (int32_t)c;
 }
 
 void launch_sum_fill(const DevParams &P, const Work &w, const SumWork &sw, hipStream_t st) {
     if (w.n_seg > 0)
         k_sum_fill<<<(unsigned)((w.n_seg + kWG / 64 - 1) / (kWG / 64)), kWG, 0, st>>>(P, w.si, w.n_seg, sw);
-    k_sum_columns<<<(unsigned)((sw.n_cols + kWG - 1) / kWG), kWG, 0, st>>>(sw.align_res, w.si, sw);
+    const int64_t span = (int64_t)(kWG / 64) * kActiveSpan;
+    k_sum_active<<<(unsigned)((sw.n_cols + span - 1) / span), kWG, 0, st>>>(sw);
+    k_sum_columns<<<256 * 16, kWG, 0, st>>>(sw.align_res, w.si, sw);   // persistent waves over the listed columns
 }
 
 // Wave-uniform copies of a 64-bit value held by lane l.
