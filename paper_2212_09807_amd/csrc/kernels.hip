@@ -2134,7 +2134,7 @@ __global__ __launch_bounds__(kWG) void k_sum_pieces(DevParams P, const SegInfo *
                     g.cell_off = so + k * kPieceTicks;
                     g.event = e;
                     g.n_pairs = 1;
-                    sw.piece[pk + k] = g;
+                    if (sw.piece_lists) sw.piece[pk + k] = g;
                     sw.pdesc[pk + k] = PieceRef{g.a0, g.na, (uint32_t)(g.cell_off / kAC), 0};
                 }
                 pk += np;
@@ -2229,7 +2229,7 @@ __global__ __launch_bounds__(kWG) void k_sum_lists_fill(DevParams P, int64_t n_s
                         k = h[j]++;
                         ha[j] = h[j] < he[j] ? sw.pdesc[h[j]].a0 : INT32_MAX;
                     }
-                sw.list[q] = (int32_t)k;
+                if (sw.piece_lists) sw.list[q] = (int32_t)k;
                 PieceRef r = sw.pdesc[k];
                 r.bin = b;
                 sw.rec[q] = r;

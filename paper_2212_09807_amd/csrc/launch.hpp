@@ -92,6 +92,8 @@ struct SumWork {
     float *Sm = nullptr;                     // [n_m] charges of the merged records (padded to kAC)
     uint32_t nS8 = 0;                        // S floats / kAC: cell8 at or above it points into Sm
     int32_t align_res = 0;                   // first tick of every column interval, mod 8 (set by the kernel choice)
+    bool piece_lists = true;                 // write `piece` and `list` (read only by the lane-exchange kernel and the
+                                             // per-pair kernels over the pieces)
 };
 // The summed induction kernel a tuning choice runs: the 256-tick LDS-staged one (automatic), the 512-tick register
 // one (8 ticks per thread), or the per-pair kernels over the pieces; and the interval alignment each one wants.

@@ -493,6 +493,7 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     sw.mlist_off = as<int64_t>(c->mlist_off);
     sw.m_off = as<int64_t>(c->m_off);
     sw.align_res = summed_align_res(P, c->ticks_per_thread, c->lane_exchange != 0);
+    sw.piece_lists = !((c->ticks_per_thread == 0 || c->ticks_per_thread == 8) && c->lane_exchange == 0);
     void *tmp = c->scan_tmp.p;
     HIP_TRY(c, hipMemsetAsync(sw.col_seg_off, 0, sizeof(int64_t) * (size_t)nc1, st));
     HIP_TRY(c, hipMemsetAsync(sw.col_cursor, 0, sizeof(int32_t) * (size_t)sw.n_cols, st));
@@ -514,11 +515,13 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     HIP_TRY(c, hipStreamSynchronize(st));
     if (tot[2] / kAC >= (int64_t)UINT32_MAX)          // piece records hold the charge offset in units of kAC floats
         return fail(c, LTS_ERR_CAPACITY, "summed induction: too many summed charge values for one call");
-    if ((r = grow(c, h, {{&c->piece, sizeof(SegInfo) * (size_t)std::max<int64_t>(tot[1], 1)},
-                         {&c->pdesc, sizeof(PieceRef) * (size_t)std::max<int64_t>(tot[1], 1)},
+    if ((r = grow(c, h, {{&c->pdesc, sizeof(PieceRef) * (size_t)std::max<int64_t>(tot[1], 1)},
                          {&c->S, sizeof(float) * (size_t)(tot[2] + kCellSlack)}})))
         return r;
-    sw.piece = as<SegInfo>(c->piece);
+    if (sw.piece_lists) {
+        if ((r = grow(c, h, {{&c->piece, sizeof(SegInfo) * (size_t)std::max<int64_t>(tot[1], 1)}}))) return r;
+        sw.piece = as<SegInfo>(c->piece);
+    }
     sw.pdesc = as<PieceRef>(c->pdesc);
     sw.S = as<float>(c->S);
     launch_sum_pieces(P, w, sw, st);
@@ -526,10 +529,11 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     scan_exclusive_i64(sw.list_off, n_slots + 1, nullptr, tmp, st);
     HIP_TRY(c, hipMemcpyAsync(&tot[0], sw.list_off + n_slots, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
-    if ((r = grow(c, h, {{&c->list, sizeof(int32_t) * (size_t)std::max<int64_t>(tot[0], 1)},
-                         {&c->rec, sizeof(PieceRef) * (size_t)std::max<int64_t>(tot[0], 1)}})))
-        return r;
-    sw.list = as<int32_t>(c->list);
+    if ((r = grow(c, h, {{&c->rec, sizeof(PieceRef) * (size_t)std::max<int64_t>(tot[0], 1)}}))) return r;
+    if (sw.piece_lists) {
+        if ((r = grow(c, h, {{&c->list, sizeof(int32_t) * (size_t)std::max<int64_t>(tot[0], 1)}}))) return r;
+        sw.list = as<int32_t>(c->list);
+    }
     sw.rec = as<PieceRef>(c->rec);
     launch_sum_lists_fill(P, w, sw, n_slots, tot[0], st);
     // mirror merge: sizes of the merged records and charges, then the records
