@@ -514,7 +514,7 @@ void launch_sort_pairs(const Work &w, int64_t n_slots_host, hipStream_t st) {
 }
 
 // ================================================================================================= charge cells
-constexpr int kCellLds = 12288;   // floats (48 KB)
+constexpr int kCellLds = 6144;    // floats (24 KB: several workgroups per CU; long segments take several passes)
 
 // Monte Carlo cells of one segment (the paper's estimator of eq. (rho) with M = P.mc_draws perturbations per point):
 // every moved copy of a sample point adds one hit to the cell that contains it (integer counts, in LDS when the box
