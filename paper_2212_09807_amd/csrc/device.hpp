@@ -43,6 +43,8 @@ struct DevParams {
     float birks_ab, birks_kb_eps, box_alpha, box_beta_eps, inv_w_ion;
     float inv_vd_hi, inv_vd_lo, inv_lifetime, two_dl, two_dt, za_hi, za_lo;
     float step, nsig, inv_norm;             // inv_norm = 1 / P(|g| <= n_sigma)
+    int32_t cell_pad;                       // charge-cell rows rounded up to a multiple of this many ticks (kAC for
+                                            // the per-pair kernels' 8-tick blocks, 1 for the summed columns)
     int32_t mc_draws;                       // 0: expectation over the diffusion draws; M > 0: M draws per point
     int32_t per_point;                      // lifetime and diffusion at each sample point (1) or the midpoint (0)
     // grid
@@ -66,7 +68,7 @@ struct alignas(16) SegInfo {
     float dz, dt, _f3, _f4;
     int32_t u_ref, v_ref, a_ref, n_points;  // reference bin / tick of the start point
     int32_t u0, nu, v0, nv;                 // charge box, absolute sub-pixel bin indices
-    int32_t a0, na, na_pad, flags;          // charge box, absolute tick indices (na_pad = na rounded up to kAC)
+    int32_t a0, na, na_pad, flags;          // charge box, absolute tick indices (na_pad = na rounded up to cell_pad)
     int32_t ix0, ix1, iy0, iy1;             // pixel rectangle reached (clipped to the grid; empty if ix1 < ix0)
     int32_t event, n_pairs, _i0, _i1;
     int64_t cell_off, _l0;

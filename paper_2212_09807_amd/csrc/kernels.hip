@@ -261,7 +261,7 @@ __device__ __forceinline__ void segment_box(const DevParams &P, SegInfo &g) {
     g.u0 = g.u_ref + ulo; g.nu = uhi - ulo + 1;
     g.v0 = g.v_ref + vlo; g.nv = vhi - vlo + 1;
     g.a0 = g.a_ref + alo; g.na = ahi - alo + 1;
-    g.na_pad = (g.na + kAC - 1) / kAC * kAC;
+    g.na_pad = (g.na + P.cell_pad - 1) / P.cell_pad * P.cell_pad;
     if (!(g.nu >= 1 && g.nu <= kBoxMax && g.nv >= 1 && g.nv <= kBoxMax && g.na >= 1 && g.na <= kNaMax))
         g.flags |= SEG_TOO_LONG;
     // pixel ix reaches sub-pixel bins u in [ix*nsub + nsub/2 - bx, ix*nsub + nsub/2 + bx - 1]
@@ -2167,11 +2167,12 @@ __global__ __launch_bounds__(kWG) void k_sum_lists_count(DevParams P, int64_t n_
     const int32_t ix = p % P.nx, iy = p / P.nx;
     const int32_t cu0 = ix * P.nsub + P.nsub / 2 - P.bx - sw.UL, cv0 = iy * P.nsub + P.nsub / 2 - P.by - sw.VL;
     const int64_t base = (int64_t)e * sw.CU * sw.CV;
-    const int32_t nv = 2 * P.by, ncol = 2 * P.bx * nv;
+    // piece_off is the exclusive prefix over the columns in row order: a row's 2 by columns of the reach count
+    // piece_off[end] - piece_off[start]
     int64_t x = 0;
-    for (int32_t c = lane; c < ncol; c += 64) {
-        const int64_t col = base + (int64_t)(cu0 + c / nv) * sw.CV + cv0 + c % nv;
-        x += sw.piece_off[col + 1] - sw.piece_off[col];
+    for (int32_t du = lane; du < 2 * P.bx; du += 64) {
+        const int64_t row = base + (int64_t)(cu0 + du) * sw.CV + cv0;
+        x += sw.piece_off[row + 2 * P.by] - sw.piece_off[row];
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);

@@ -200,6 +200,7 @@ lts_status validate_and_derive(lts_context *c) {
     P.inv_norm = (float)(1.0 / std::erf(ph.n_sigma / std::sqrt(2.0)));
     P.mc_draws = ph.mc_draws;
     P.per_point = ph.per_point;
+    P.cell_pad = kAC;                              // set per call by the sizing pass
     split(ro.pitch / ro.n_sub, P.b_hi, P.b_lo);
     split(ro.x0, P.x0_hi, P.x0_lo);
     split(ro.y0, P.y0_hi, P.y0_lo);
@@ -379,9 +380,12 @@ SegArrays seg_arrays(const lts_segments *s) {
 
 // Sizing half of the pipeline: quench / drift / rasterisation counts and scans; synchronises the stream and
 // returns the header on the host.
+// padded: charge-cell rows in whole 8-tick blocks (the per-pair kernels read them in blocks); the summed mode reads
+// each row's ticks only, unpadded.
 lts_status run_sizing(lts_context *c, int32_t n_ev, const uint64_t *event_ids, const int64_t *seg_offsets,
-                      const lts_segments *segs, double *report, hipStream_t st, Work &w, DevHeader &h) {
+                      const lts_segments *segs, double *report, hipStream_t st, Work &w, DevHeader &h, bool padded) {
     lts_status r;
+    c->P.cell_pad = padded ? kAC : 1;
     const int64_t n_seg = segs->n;
     const int64_t n_gp = (int64_t)n_ev * c->P.npx;
     if (n_gp + 1 >= (1ll << 24)) return fail(c, LTS_ERR_INVALID_ARG, "events x pixels exceeds 2^24 - 1");
@@ -649,7 +653,9 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
     if (order_.status) return order_.status;
     Work w;
     DevHeader h;
-    if ((r = run_sizing(c, n_ev, event_ids, seg_offsets, segs, out->report, st, w, h))) return r;
+    if ((r = run_sizing(c, n_ev, event_ids, seg_offsets, segs, out->report, st, w, h,
+                        c->reduce_mode != LTS_REDUCE_SUMMED)))
+        return r;
     const int64_t n_slots = h.n_slots, n_pairs = h.n_pairs, n_cells = h.n_cells;
     c->last_n_slots = n_slots;
     c->last_mode = c->reduce_mode;
@@ -1030,7 +1036,9 @@ lts_status lts_plan(lts_context *c, const lts_segments *segs, int64_t need[4], v
     const int64_t off[2] = {0, segs->n};
     Work w;
     DevHeader h;
-    if ((r = run_sizing(c, 1, &eid, off, segs, as<double>(c->report_tmp), to_stream(stream), w, h))) return r;
+    if ((r = run_sizing(c, 1, &eid, off, segs, as<double>(c->report_tmp), to_stream(stream), w, h,
+                        c->reduce_mode != LTS_REDUCE_SUMMED)))
+        return r;
     need[0] = h.n_pairs;
     need[1] = h.n_slots;
     need[2] = h.n_cells;
@@ -1197,7 +1205,7 @@ static lts_status stage_front(lts_context *c, uint64_t event_id, const lts_segme
     HIP_TRY(c, hipSetDevice(c->device));
     if ((r = ensure(c, c->report_tmp, sizeof(double) * 5))) return r;
     const int64_t off[2] = {0, segs->n};
-    if ((r = run_sizing(c, 1, &event_id, off, segs, as<double>(c->report_tmp), st, w, h))) return r;
+    if ((r = run_sizing(c, 1, &event_id, off, segs, as<double>(c->report_tmp), st, w, h, true))) return r;
     // lts_debug_cells and lts_work_stats describe the last call that computed charge cells
     if (!with_cells) c->last_n_seg = -1;
     c->last_mode = LTS_REDUCE_SORTED;
