@@ -2,7 +2,8 @@
 //
 // Stage map (one event, or a batch of events whose pixel spaces are concatenated):
 //   k_quench_drift   Sec. 3.1-3.2: recombination, lifetime, diffusion widths per segment; charge box in
-//                    (tick, sub-pixel bin) space; pixel rectangle the box reaches; per-pixel pair counts.
+//                    (tick, sub-pixel bin) space; pixel rectangle the box reaches; per-pixel pair counts (a
+//                    difference array over the pixel grid, k_prefix_rows / k_prefix_cols).
 //   scans            pair / cell offsets (exclusive scans), active-pixel compaction (slots).
 //   k_fill_pairs     pixel-major (pixel, segment) pair lists; k_sort_pairs orders each list by segment id.
 //   k_cells          Sec. 3.3.2 eq. (rho), expectation over the Gaussian perturbations: charge per
@@ -12,6 +13,9 @@
 //                    reach convolved in time with the field-response column of their mirror-folded bin; summed
 //                    over the pixel's segments (Sec. 3.4) either in a fixed order with Kahan compensation
 //                    (sorted variant) or with FP32 atomics (atomic variant).
+//   k_sum_*          the same sum by linearity as sum-then-convolve: segments' charges summed per sub-pixel
+//                    column (column lists, sort, intervals, summed charges), per-pixel records by folded table
+//                    column, the mirror merge, then k_induce_summed4 / k_induce_summed over the records.
 //   k_electronics    Sec. 3.4: integrate, threshold (with discriminator noise), hold, digitise, reset, with
 //                    Philox4x32-10 noise; also the FP64 per-event sum of the currents.
 //   k_compact        packets of all pixels into the caller's arrays.
