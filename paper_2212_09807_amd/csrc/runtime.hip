@@ -50,6 +50,9 @@ struct lts_context {
     // HIP-graph replay of the launch sequence after the sizing read-back (per-pair and atomic modes)
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;  // capture stream (captures never run on the caller's stream)
+    // summed mode: the charge cells run on a side stream beside the column lists (which need only the boxes)
+    hipStream_t side_stream = nullptr;
+    hipEvent_t side_fork = nullptr, side_join = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipEvent_t gdone = nullptr;        // recorded behind every graph launch
     bool glaunched = false;
@@ -477,7 +480,9 @@ void summed_needs(lts_context *c, const DevHeader &h, int64_t n_slots, int32_t n
 }
 
 // The buffers of summed_needs are grown by the caller.
-lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t n_slots, float *wave, hipStream_t st) {
+// cells_ready (may be null): recorded behind the charge cells on another stream; awaited before the column sums.
+lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t n_slots, float *wave, hipStream_t st,
+                      hipEvent_t cells_ready) {
     const DevParams &P = c->P;
     lts_status r;
     SumWork sw = summed_grid(P, w.n_ev);
@@ -528,6 +533,7 @@ lts_status run_summed(lts_context *c, const Work &w, const DevHeader &h, int64_t
     }
     sw.pdesc = as<PieceRef>(c->pdesc);
     sw.S = as<float>(c->S);
+    if (cells_ready) HIP_TRY(c, hipStreamWaitEvent(st, cells_ready, 0));
     launch_sum_pieces(P, w, sw, st);
     launch_sum_lists_count(P, w, sw, n_slots, st);
     scan_exclusive_i64(sw.list_off, n_slots + 1, nullptr, tmp, st);
@@ -713,15 +719,34 @@ lts_status run_pipeline(lts_context *c, int32_t n_ev, const uint64_t *event_ids,
             launch_fill_pairs(P, w, s);
             if (c->reduce_mode == LTS_REDUCE_SORTED) launch_sort_pairs(w, n_slots, s);
         }
-        {
+        // summed mode: the cells on the side stream, beside the column lists (forked after everything queued so far,
+        // joined before the column sums and before anything this call leaves behind)
+        hipEvent_t cells_ready = nullptr;
+        if (summed && !graph) {
+            if (!c->side_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+            if (!c->side_fork) HIP_TRY(c, hipEventCreateWithFlags(&c->side_fork, hipEventDisableTiming));
+            if (!c->side_join) HIP_TRY(c, hipEventCreateWithFlags(&c->side_join, hipEventDisableTiming));
+            HIP_TRY(c, hipEventRecord(c->side_fork, s));
+            HIP_TRY(c, hipStreamWaitEvent(c->side_stream, c->side_fork, 0));
+            {
+                StageTimer t(c, c->side_stream, LTS_STAGE_CELLS);
+                launch_cells(P, w, c->side_stream);
+            }
+            HIP_TRY(c, hipEventRecord(c->side_join, c->side_stream));
+            cells_ready = c->side_join;
+        } else {
             StageTimer t(c, s, LTS_STAGE_CELLS);
             launch_cells(P, w, s);
         }
         if (c->reduce_mode == LTS_REDUCE_ATOMIC)
             launch_zero(out->current, (int64_t)sizeof(float) * n_slots * P.nticks, s);
         if (c->reduce_mode == LTS_REDUCE_SUMMED) {
-            StageTimer t(c, s, LTS_STAGE_INDUCE);
-            lts_status r2 = run_summed(c, w, h, n_slots, out->current, s);
+            lts_status r2;
+            {
+                StageTimer t(c, s, LTS_STAGE_INDUCE);
+                r2 = run_summed(c, w, h, n_slots, out->current, s, cells_ready);
+            }
+            if (cells_ready) HIP_TRY(c, hipStreamWaitEvent(s, cells_ready, 0));   // also on an early return
             if (r2) return r2;
         } else if (c->reduce_mode == LTS_REDUCE_SORTED && c->induce_slices > 1 && n_slots > 0) {
             // slices of at most 1 GiB of partial waveforms at a time
@@ -824,6 +849,12 @@ void lts_context_destroy(lts_context *c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->gdone) (void)hipEventDestroy(c->gdone);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side_stream) {
+        (void)hipStreamSynchronize(c->side_stream);
+        (void)hipStreamDestroy(c->side_stream);
+    }
+    if (c->side_fork) (void)hipEventDestroy(c->side_fork);
+    if (c->side_join) (void)hipEventDestroy(c->side_join);
     for (auto &pe : c->pending_ev) {
         (void)hipEventDestroy(pe.second.first);
         (void)hipEventDestroy(pe.second.second);
