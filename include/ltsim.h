@@ -18,8 +18,10 @@
  *     take a stream enqueue their work on it and return; results are valid after the stream is synchronised.
  *     lts_simulate / lts_simulate_batch additionally synchronise that stream once (after sizing) to size
  *     scratch and check output capacities, so a capacity error is returned synchronously (LTS_REDUCE_SUMMED
- *     synchronises twice more, to size the summed columns and the pixels' piece lists).  Calls on one context
- *     that use its scratch pool (lts_plan, lts_simulate, lts_simulate_batch, lts_stage_rasterize, lts_stage_induce,
+ *     synchronises three times more, to size the summed columns, the pixels' piece lists and the merged records;
+ *     it also runs the charge cells on a stream of the context's own, forked from the call's stream and joined back
+ *     to it before anything the call leaves behind, so the call's stream still orders all of its work).  Calls on
+ *     one context that use its scratch pool (lts_plan, lts_simulate, lts_simulate_batch, lts_stage_rasterize, lts_stage_induce,
  *     lts_stage_reduce, lts_stage_electronics) are ordered on the device whatever streams they are given: each one
  *     first makes its stream wait for the previous one's completion (a HIP event), so work of consecutive calls on
  *     different streams never overlaps in the shared scratch.
@@ -382,8 +384,9 @@ lts_status lts_server_stop(lts_server *srv);
 /* ---- stage timing --------------------------------------------------------------------------------------
  * When enabled, the library records HIP events on the caller's stream around each stage group of every
  * pipeline call.  lts_get_timing waits for the recorded events, returns the summed elapsed milliseconds and the
- * number of timed calls per stage since the previous lts_get_timing, and resets them.  Host arrays of
- * LTS_N_STAGES entries; calls may be NULL. */
+ * number of timed calls per stage since the previous lts_get_timing, and resets them (in LTS_REDUCE_SUMMED the
+ * charge-cell stage is timed on the context's own stream, where it runs beside the start of LTS_STAGE_INDUCE).
+ * Host arrays of LTS_N_STAGES entries; calls may be NULL. */
 enum {
     LTS_STAGE_QUENCH_DRIFT = 0,   /* recombination, drift, charge boxes, pair counts, scans (Sec. 3.1-3.2) */
     LTS_STAGE_RASTERIZE = 1,      /* active-pixel compaction, pair lists, per-pixel ordering */
